@@ -1,0 +1,308 @@
+// Whole-lattice oracle time stepping -- TEST INFRASTRUCTURE ONLY.
+//
+// One step n -> n+1, phase by phase over the whole grid (the order of the
+// algorithm of Sec. 3.2, read for a pull scheme):
+//   1. geometry of every rotor at step n (porosity, tag, normal, wall distance)
+//   2. pre-collision populations f(x,n) = f*(x - c_i, n-1) with the outer
+//      boundaries (periodic y,z; periodic or inflow/outflow in x)
+//   3. moments rho, j, P of f(x,n)
+//   4. wall model on the wall cells
+//   5. collision of every cell, momentum handed to each tagged solid
+//   6. the post-collision populations become the new state.
+// The state is f*(x) of the previous step, held as h = f* - w.
+#pragma once
+#include "hlbm_oracle.hpp"
+
+namespace oracle {
+
+constexpr int NTAG = 16;         // tags 0..15; tag 0 means "no solid element"
+constexpr int HIST = 1 + 15 * 6; // per step: mass, then (F, T) for tags 1..15
+
+template <class T>
+struct Sim {
+  int nx = 0, ny = 0, nz = 0, bc_x = 0;  // bc_x: 0 periodic, 1 inflow at x=0 / outflow at x=nx-1
+  int64_t N = 0;
+  Params p{};
+  std::vector<Rotor> rotors;
+  std::vector<Frame> frames;
+  std::vector<double> d_static, uB_static;
+  std::vector<uint8_t> tag_static;
+  std::vector<T> dd;                      // porosity control added to d
+  double tag_center[NTAG][3]{}, tag_axis[NTAG][3]{};
+  std::vector<T> h;                       // [27][N] post-collision state minus weights
+  std::vector<T> utau;                    // wall state per cell
+  std::vector<uint8_t> active;
+  int64_t step = 0;
+  std::vector<double> hist;               // HIST doubles per recorded step
+  WallStats wstats;
+  int nthreads = 1;
+
+  // objective: J += sum over steps in [t0,t1) of axial torque of obj_tag (0 = all tags), / (t1-t0)
+  bool obj_on = false;
+  int64_t obj_t0 = 0, obj_t1 = 0;
+  int obj_tag = 0;
+  T J = T(0.0);
+
+  // per-step work arrays
+  std::vector<double> g_phi, g_n, g_uB, g_dbase;
+  std::vector<int> g_rot;
+  std::vector<uint8_t> g_tag, g_wall;
+  std::vector<T> f, mom, u, uwm, Swm, dP, d;
+  std::vector<double> sigma;
+
+  Sim(int nx_, int ny_, int nz_, int bcx) : nx(nx_), ny(ny_), nz(nz_), bc_x(bcx) {
+    N = (int64_t)nx * ny * nz;
+    h.assign((size_t)Q * N, T(0.0));
+    utau.assign(N, T(0.0));
+    active.assign(N, 0);
+    for (int t = 0; t < NTAG; ++t) {
+      tag_center[t][0] = 0.5 * (nx - 1); tag_center[t][1] = 0.5 * (ny - 1); tag_center[t][2] = 0.5 * (nz - 1);
+      tag_axis[t][0] = 1; tag_axis[t][1] = 0; tag_axis[t][2] = 0;
+    }
+  }
+
+  int64_t idx(int x, int y, int z) const { return ((int64_t)z * ny + y) * nx + x; }
+  static int wrap(int a, int n) { a %= n; return a < 0 ? a + n : a; }
+
+  void set_rotors(const Rotor* r, int n) {
+    rotors.assign(r, r + n);
+    frames.clear();
+    for (auto& ro : rotors) {
+      frames.push_back(rotor_frame(ro));
+      const Frame& F = frames.back();
+      for (int a = 0; a < 3; ++a) { tag_center[ro.tag][a] = ro.center[a]; tag_axis[ro.tag][a] = F.e[a]; }
+    }
+  }
+
+  // -------------------------------------------------- 1. geometry
+  void geometry(int64_t n) {
+    g_phi.assign(N, -1e300); g_n.assign(3 * N, 0.0); g_uB.assign(3 * N, 0.0); g_dbase.assign(N, 0.0);
+    g_rot.assign(N, -1); g_tag.assign(N, 0); g_wall.assign(N, 0);
+    d.assign(N, T(0.0));
+    const double eps = p.eps_h;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t c = idx(x, y, z);
+          const double X[3] = {double(x), double(y), double(z)};
+          double best = -1e300, bgrad[3] = {0, 0, 0};
+          int brot = -1;
+          for (size_t k = 0; k < rotors.size(); ++k) {
+            double gr[3];
+            double ph = rotor_phi(rotors[k], frames[k], X, n, gr);
+            if (ph > best) { best = ph; brot = (int)k; for (int a = 0; a < 3; ++a) bgrad[a] = gr[a]; }
+          }
+          double drot = brot >= 0 ? transition_s(best, eps, p.transition) : 0.0;
+          double ds = d_static.empty() ? 0.0 : d_static[c];
+          g_dbase[c] = ds > drot ? ds : drot;
+          g_phi[c] = best;
+          if (drot > 0.0) {
+            const Rotor& R = rotors[brot];
+            const Frame& F = frames[brot];
+            g_rot[c] = brot;
+            g_tag[c] = (uint8_t)R.tag;
+            double rel[3] = {X[0] - R.center[0], X[1] - R.center[1], X[2] - R.center[2]};
+            // uB = Omega e x (x - x_c)
+            g_uB[3 * c + 0] = R.omega * (F.e[1] * rel[2] - F.e[2] * rel[1]);
+            g_uB[3 * c + 1] = R.omega * (F.e[2] * rel[0] - F.e[0] * rel[2]);
+            g_uB[3 * c + 2] = R.omega * (F.e[0] * rel[1] - F.e[1] * rel[0]);
+            double gn = std::sqrt(bgrad[0] * bgrad[0] + bgrad[1] * bgrad[1] + bgrad[2] * bgrad[2]);
+            if (gn > 0) for (int a = 0; a < 3; ++a) g_n[3 * c + a] = -bgrad[a] / gn;
+            if (p.wall_model && best > -0.5 * eps && best < 0.0 && gn > 0) g_wall[c] = 1;
+          } else {
+            g_tag[c] = tag_static.empty() ? 0 : tag_static[c];
+            if (!uB_static.empty())
+              for (int a = 0; a < 3; ++a) g_uB[3 * c + a] = uB_static[(size_t)a * N + c];
+          }
+          d[c] = T(g_dbase[c]) + (dd.empty() ? T(0.0) : dd[c]);
+        }
+  }
+
+  // -------------------------------------------------- 2. pull with boundaries
+  void inflow_velocity(int64_t n, int y, int z, double uin[3]) const {
+    double mag = std::sqrt(p.u_in[0] * p.u_in[0] + p.u_in[1] * p.u_in[1] + p.u_in[2] * p.u_in[2]);
+    for (int a = 0; a < 3; ++a) {
+      uin[a] = p.u_in[a];
+      if (p.turb_I != 0.0) uin[a] += p.turb_I * mag * inflow_gaussian(p.seed, n, y, z, a, ny, nz);
+    }
+  }
+
+  void pull(int64_t n) {
+    const Lattice27& L = lat();
+    f.assign((size_t)Q * N, T(0.0));
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t c = idx(x, y, z);
+          for (int i = 0; i < Q; ++i) {
+            int xs = x - L.c[i][0];
+            int ys = wrap(y - L.c[i][1], ny), zs = wrap(z - L.c[i][2], nz);
+            if (bc_x == 0) {
+              xs = wrap(xs, nx);
+            } else if (xs < 0) {
+              double uin[3];
+              inflow_velocity(n, ys, zs, uin);
+              T ui[3] = {T(uin[0]), T(uin[1]), T(uin[2])};
+              T feq[Q];
+              equilibrium(T(1.0), ui, feq);
+              f[(size_t)i * N + c] = feq[i];
+              continue;
+            } else if (xs > nx - 1) {
+              xs = nx - 1;
+            }
+            f[(size_t)i * N + c] = L.w[i] + h[(size_t)i * N + idx(xs, ys, zs)];
+          }
+        }
+  }
+
+  // -------------------------------------------------- 3. moments
+  void moments() {
+    mom.assign((size_t)10 * N, T(0.0));
+    u.assign((size_t)3 * N, T(0.0));
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+      T fc[Q], m[10];
+      for (int i = 0; i < Q; ++i) fc[i] = f[(size_t)i * N + c];
+      moments_of(fc, m);
+      for (int k = 0; k < 10; ++k) mom[(size_t)k * N + c] = m[k];
+      for (int a = 0; a < 3; ++a) u[(size_t)a * N + c] = m[1 + a] / m[0];
+    }
+  }
+
+  // trilinear interpolation of the fluid velocity at a point
+  void sample_u(const double X[3], T us[3]) const {
+    const int n3[3] = {nx, ny, nz};
+    int i0[3];
+    double fr[3];
+    for (int a = 0; a < 3; ++a) { double fl = std::floor(X[a]); i0[a] = (int)fl; fr[a] = X[a] - fl; }
+    for (int a = 0; a < 3; ++a) us[a] = T(0.0);
+    for (int corner = 0; corner < 8; ++corner) {
+      int q[3];
+      double wgt = 1.0;
+      for (int a = 0; a < 3; ++a) {
+        int bit = (corner >> a) & 1;
+        q[a] = i0[a] + bit;
+        wgt *= bit ? fr[a] : 1.0 - fr[a];
+      }
+      q[1] = wrap(q[1], n3[1]);
+      q[2] = wrap(q[2], n3[2]);
+      if (bc_x == 0) q[0] = wrap(q[0], n3[0]);
+      else q[0] = q[0] < 0 ? 0 : (q[0] > nx - 1 ? nx - 1 : q[0]);
+      const int64_t cc = idx(q[0], q[1], q[2]);
+      for (int a = 0; a < 3; ++a) us[a] = us[a] + wgt * u[(size_t)a * N + cc];
+    }
+  }
+
+  // -------------------------------------------------- 4. wall model
+  void wall_model() {
+    uwm.assign((size_t)3 * N, T(0.0));
+    Swm.assign((size_t)6 * N, T(0.0));
+    sigma.assign(N, 1.0);
+    const double nu = CS2 * (p.tau0 - 0.5);
+    std::vector<T> ut_new(N, T(0.0));
+    std::vector<uint8_t> act_new(N, 0);
+    int64_t iters = 0, calls = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(+ : iters, calls)
+    for (int64_t c = 0; c < N; ++c) {
+      if (!g_wall[c]) continue;
+      const int x = int(c % nx), y = int((c / nx) % ny), z = int(c / ((int64_t)nx * ny));
+      const Rotor& R = rotors[g_rot[c]];
+      const Frame& F = frames[g_rot[c]];
+      const double* nn = &g_n[3 * c];
+      const double y1 = -g_phi[c];
+      double xw[3], xs[3];
+      const double X[3] = {double(x), double(y), double(z)};
+      for (int a = 0; a < 3; ++a) { xw[a] = X[a] - y1 * nn[a]; xs[a] = xw[a] + p.y_s * nn[a]; }
+      double rel[3] = {xw[0] - R.center[0], xw[1] - R.center[1], xw[2] - R.center[2]};
+      double uw[3] = {R.omega * (F.e[1] * rel[2] - F.e[2] * rel[1]),
+                      R.omega * (F.e[2] * rel[0] - F.e[0] * rel[2]),
+                      R.omega * (F.e[0] * rel[1] - F.e[1] * rel[0])};
+      T us[3];
+      sample_u(xs, us);
+      WallOut<T> o = wall_model_cell(us, uw, nn, y1, utau[c], active[c] != 0, p, nu);
+      if (o.active) {
+        for (int a = 0; a < 3; ++a) uwm[(size_t)a * N + c] = o.uwm[a];
+        for (int k = 0; k < 6; ++k) Swm[(size_t)k * N + c] = o.S[k];
+        sigma[c] = 0.0;
+        ut_new[c] = o.utau;
+        act_new[c] = 1;
+        iters += o.iters_tau;
+        calls += 1;
+      }
+    }
+    wstats.newton_iters += iters;
+    wstats.calls += calls;
+    utau.swap(ut_new);
+    active.swap(act_new);
+  }
+
+  // -------------------------------------------------- 5. collision + 6. new state
+  void collide_and_record() {
+    const Lattice27& L = lat();
+    dP.assign((size_t)3 * N, T(0.0));
+    std::vector<T> rho(N);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+      T m[10], fs[Q], dp[3], uw3[3], S6[6];
+      for (int k = 0; k < 10; ++k) m[k] = mom[(size_t)k * N + c];
+      for (int a = 0; a < 3; ++a) uw3[a] = uwm[(size_t)a * N + c];
+      for (int k = 0; k < 6; ++k) S6[k] = Swm[(size_t)k * N + c];
+      collide_cell(m, d[c], &g_uB[3 * c], uw3, S6, sigma[c], p.tau0, p.cs_smag, fs, dp);
+      for (int i = 0; i < Q; ++i) h[(size_t)i * N + c] = fs[i] - L.w[i];
+      for (int a = 0; a < 3; ++a) dP[(size_t)a * N + c] = dp[a];
+      rho[c] = m[0];
+    }
+    // fixed (z, y, x) order FP64 sums
+    std::vector<double> rec(HIST, 0.0);
+    T Tax = T(0.0);
+    T mass = T(0.0);
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t c = idx(x, y, z);
+          mass = mass + rho[c];
+          const int t = g_tag[c];
+          if (t == 0) continue;
+          const T dp[3] = {dP[c], dP[(size_t)N + c], dP[(size_t)2 * N + c]};
+          const double r[3] = {x - tag_center[t][0], y - tag_center[t][1], z - tag_center[t][2]};
+          const T tq[3] = {r[1] * dp[2] - r[2] * dp[1], r[2] * dp[0] - r[0] * dp[2], r[0] * dp[1] - r[1] * dp[0]};
+          double* o = &rec[1 + 6 * (t - 1)];
+          for (int a = 0; a < 3; ++a) { o[a] += re(dp[a]); o[3 + a] += re(tq[a]); }
+          if (obj_on && (obj_tag == 0 || obj_tag == t))
+            Tax = Tax + tag_axis[t][0] * tq[0] + tag_axis[t][1] * tq[1] + tag_axis[t][2] * tq[2];
+        }
+    rec[0] = re(mass);
+    hist.insert(hist.end(), rec.begin(), rec.end());
+    if (obj_on && step >= obj_t0 && step < obj_t1) J = J + Tax / double(obj_t1 - obj_t0);
+  }
+
+  void do_step() {
+    geometry(step);
+    pull(step);
+    moments();
+    if (p.wall_model) wall_model();
+    else { uwm.assign((size_t)3 * N, T(0.0)); Swm.assign((size_t)6 * N, T(0.0)); sigma.assign(N, 1.0); }
+    collide_and_record();
+    ++step;
+  }
+
+  void init_equilibrium(const double* rho, const double* uu) {
+    const Lattice27& L = lat();
+    for (int64_t c = 0; c < N; ++c) {
+      T r = T(rho ? rho[c] : 1.0);
+      T u3[3];
+      for (int a = 0; a < 3; ++a) u3[a] = T(uu ? uu[(size_t)a * N + c] : 0.0);
+      T feq[Q];
+      equilibrium(r, u3, feq);
+      for (int i = 0; i < Q; ++i) h[(size_t)i * N + c] = feq[i] - L.w[i];
+    }
+    std::fill(utau.begin(), utau.end(), T(0.0));
+    std::fill(active.begin(), active.end(), 0);
+    step = 0;
+    hist.clear();
+  }
+};
+
+}  // namespace oracle

@@ -1,0 +1,340 @@
+"""ctypes binding of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only tests, the smoke check and the CPU-baseline leg of the benchmark use
+this module.  It mirrors the library's entry points with host numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class OrParams(C.Structure):
+    _fields_ = [("tau0", C.c_double), ("cs_smag", C.c_double), ("eps_h", C.c_double),
+                ("transition", C.c_int32), ("wall_model", C.c_int32),
+                ("E", C.c_double), ("kappa", C.c_double), ("y_s", C.c_double), ("tol", C.c_double),
+                ("maxit", C.c_int32), ("pad0", C.c_int32),
+                ("u_in", C.c_double * 3), ("turb_I", C.c_double), ("seed", C.c_uint64)]
+
+
+class OrRotor(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("axis", C.c_double * 3),
+                ("R", C.c_double), ("r_hub", C.c_double), ("chord", C.c_double), ("thick", C.c_double),
+                ("twist_root", C.c_double), ("twist_tip", C.c_double), ("omega", C.c_double),
+                ("phase0", C.c_double), ("n_blades", C.c_int32), ("tag", C.c_int32)]
+
+
+_D = C.POINTER(C.c_double)
+_U8 = C.POINTER(C.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = C.CDLL(path)
+        L.oracle_create.restype = C.c_void_p
+        L.oracle_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        L.oracle_destroy.argtypes = [C.c_void_p]
+        L.oracle_set_threads.argtypes = [C.c_void_p, C.c_int]
+        L.oracle_set_params.argtypes = [C.c_void_p, C.POINTER(OrParams)]
+        L.oracle_set_rotors.argtypes = [C.c_void_p, C.POINTER(OrRotor), C.c_int]
+        L.oracle_set_porosity_field.argtypes = [C.c_void_p, _D, _U8]
+        L.oracle_set_solid_velocity.argtypes = [C.c_void_p, _D]
+        L.oracle_set_control.argtypes = [C.c_void_p, _D]
+        L.oracle_set_tag_frame.argtypes = [C.c_void_p, C.c_int, _D, _D]
+        L.oracle_init_equilibrium.argtypes = [C.c_void_p, _D, _D]
+        L.oracle_step.argtypes = [C.c_void_p, C.c_int64]
+        L.oracle_get_step.restype = C.c_int64
+        L.oracle_get_step.argtypes = [C.c_void_p]
+        L.oracle_moments.argtypes = [C.c_void_p, _D, _D, _D]
+        L.oracle_get_populations.argtypes = [C.c_void_p, _D]
+        L.oracle_set_populations.argtypes = [C.c_void_p, _D]
+        L.oracle_get_wall_state.argtypes = [C.c_void_p, _D, _U8]
+        L.oracle_set_wall_state.argtypes = [C.c_void_p, _D, _U8, C.c_int64]
+        L.oracle_history.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _D]
+        L.oracle_history_len.restype = C.c_int64
+        L.oracle_history_len.argtypes = [C.c_void_p]
+        L.oracle_clear_history.argtypes = [C.c_void_p]
+        L.oracle_wall_newton_iters.restype = C.c_int64
+        L.oracle_wall_newton_iters.argtypes = [C.c_void_p]
+        L.oracle_wall_calls.restype = C.c_int64
+        L.oracle_wall_calls.argtypes = [C.c_void_p]
+        L.oracle_geometry.argtypes = [C.c_void_p, _D, _U8, _U8, _D, _D, _D]
+        L.oracle_lattice.argtypes = [C.POINTER(C.c_int32), _D]
+        L.oracle_equilibrium.argtypes = [C.c_double, _D, _D]
+        L.oracle_collide_cell.argtypes = [_D, C.c_double, _D, _D, _D, C.c_double, C.c_double, C.c_double, _D, _D]
+        L.oracle_moments_of.argtypes = [_D, _D]
+        L.oracle_spalding_yplus.restype = C.c_double
+        L.oracle_spalding_yplus.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_wall_cell.restype = C.c_int
+        L.oracle_wall_cell.argtypes = [_D, _D, _D, C.c_double, C.c_double, C.c_int, C.POINTER(OrParams), _D,
+                                       C.POINTER(C.c_int)]
+        L.oracle_rotor_phi.restype = C.c_double
+        L.oracle_rotor_phi.argtypes = [C.POINTER(OrRotor), _D, C.c_int64, _D]
+        L.oracle_transition.restype = C.c_double
+        L.oracle_transition.argtypes = [C.c_double, C.c_double, C.c_int]
+        L.oracle_gaussian.restype = C.c_double
+        L.oracle_gaussian.argtypes = [C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.oracle_splitmix64.restype = C.c_uint64
+        L.oracle_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        if hasattr(L, "oracle_adjoint_run"):
+            L.oracle_adjoint_run.restype = C.c_int
+            L.oracle_adjoint_run.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                             _D, _D]
+            L.oracle_complex_step_J.restype = C.c_int
+            L.oracle_complex_step_J.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                                                C.c_int64, C.c_double, _D, _D]
+        _lib = L
+    return _lib
+
+
+def _p(a, ctype=C.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_params(p) -> OrParams:
+    q = OrParams()
+    q.tau0, q.cs_smag, q.eps_h = p.tau0, p.cs_smag, p.eps_h
+    q.transition, q.wall_model = int(p.transition), int(p.wall_model)
+    q.E, q.kappa, q.y_s, q.tol, q.maxit = p.E, p.kappa, p.y_s, p.tol, int(p.maxit)
+    for a in range(3):
+        q.u_in[a] = p.u_in[a]
+    q.turb_I, q.seed = p.turb_I, int(p.seed)
+    return q
+
+
+def make_rotor(r) -> OrRotor:
+    o = OrRotor()
+    for a in range(3):
+        o.center[a] = r.center[a]
+        o.axis[a] = r.axis[a]
+    o.R, o.r_hub, o.chord, o.thick = r.R, r.r_hub, r.chord, r.thick
+    o.twist_root, o.twist_tip, o.omega, o.phase0 = r.twist_root, r.twist_tip, r.omega, r.phase0
+    o.n_blades, o.tag = int(r.n_blades), int(r.tag)
+    return o
+
+
+class OracleLattice:
+    """FP64 host lattice; state = post-collision populations minus weights."""
+
+    def __init__(self, nx, ny, nz, bc_x=0, threads=None):
+        self.L = lib()
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.N = nx * ny * nz
+        self.h = self.L.oracle_create(nx, ny, nz, bc_x)
+        if not self.h:
+            raise ValueError("oracle_create failed")
+        self.threads = threads or min(8, os.cpu_count() or 1)
+        self.L.oracle_set_threads(self.h, self.threads)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.oracle_destroy(self.h)
+            self.h = None
+
+    def set_params(self, p):
+        q = make_params(p)
+        if self.L.oracle_set_params(self.h, C.byref(q)):
+            raise ValueError("invalid params")
+
+    def set_rotors(self, rotors):
+        arr = (OrRotor * max(1, len(rotors)))(*[make_rotor(r) for r in rotors])
+        if self.L.oracle_set_rotors(self.h, arr, len(rotors)):
+            raise ValueError("invalid rotor")
+
+    def set_porosity_field(self, d, tag):
+        d = _f64(d)
+        tag = None if tag is None else np.ascontiguousarray(tag, dtype=np.uint8)
+        self.L.oracle_set_porosity_field(self.h, _p(d), _p(tag, C.c_uint8))
+
+    def set_solid_velocity(self, uB):
+        uB = _f64(uB)
+        self.L.oracle_set_solid_velocity(self.h, _p(uB))
+
+    def set_control(self, dd):
+        dd = _f64(dd)
+        self.L.oracle_set_control(self.h, _p(dd))
+
+    def set_tag_frame(self, tag, center, axis):
+        c = _f64(np.asarray(center))
+        a = _f64(np.asarray(axis))
+        if self.L.oracle_set_tag_frame(self.h, tag, _p(c), _p(a)):
+            raise ValueError("invalid tag frame")
+
+    def init_equilibrium(self, rho=None, u=None):
+        rho, u = _f64(rho), _f64(u)
+        self.L.oracle_init_equilibrium(self.h, _p(rho), _p(u))
+
+    def step(self, n=1):
+        self.L.oracle_step(self.h, n)
+
+    @property
+    def step_count(self):
+        return self.L.oracle_get_step(self.h)
+
+    def moments(self, uhat=False):
+        rho = np.empty(self.N)
+        u = np.empty((3, self.N))
+        uh = np.empty((3, self.N)) if uhat else None
+        self.L.oracle_moments(self.h, _p(rho), _p(u), _p(uh))
+        return (rho, u, uh) if uhat else (rho, u)
+
+    def get_populations(self):
+        out = np.empty((27, self.N))
+        self.L.oracle_get_populations(self.h, _p(out))
+        return out
+
+    def set_populations(self, h):
+        h = _f64(h)
+        self.L.oracle_set_populations(self.h, _p(h))
+
+    def wall_state(self):
+        ut = np.empty(self.N)
+        ac = np.empty(self.N, dtype=np.uint8)
+        self.L.oracle_get_wall_state(self.h, _p(ut), _p(ac, C.c_uint8))
+        return ut, ac
+
+    def set_wall_state(self, ut, ac, step):
+        ut = _f64(ut)
+        ac = np.ascontiguousarray(ac, dtype=np.uint8)
+        self.L.oracle_set_wall_state(self.h, _p(ut), _p(ac, C.c_uint8), int(step))
+
+    def history(self):
+        n = self.L.oracle_history_len(self.h)
+        out = np.empty((n, 91))
+        if n:
+            self.L.oracle_history(self.h, 0, n, _p(out))
+        return out
+
+    def clear_history(self):
+        self.L.oracle_clear_history(self.h)
+
+    def geometry(self):
+        N = self.N
+        d = np.empty(N)
+        tag = np.empty(N, dtype=np.uint8)
+        wall = np.empty(N, dtype=np.uint8)
+        phi = np.empty(N)
+        n = np.empty((3, N))
+        uB = np.empty((3, N))
+        self.L.oracle_geometry(self.h, _p(d), _p(tag, C.c_uint8), _p(wall, C.c_uint8), _p(phi), _p(n), _p(uB))
+        return dict(d=d, tag=tag, wall=wall, phi=phi, n=n, uB=uB)
+
+    def newton_stats(self):
+        return self.L.oracle_wall_newton_iters(self.h), self.L.oracle_wall_calls(self.h)
+
+    # ------------------------------------------------------------ adjoint
+    def adjoint_run(self, nsteps, t0, t1, obj_tag=0, ckpt_every=10):
+        J = np.zeros(1)
+        G = np.zeros(self.N)
+        rc = self.L.oracle_adjoint_run(self.h, nsteps, t0, t1, obj_tag, ckpt_every, _p(J), _p(G))
+        if rc:
+            raise RuntimeError("oracle_adjoint_run failed")
+        return float(J[0]), G
+
+    def complex_step_J(self, nsteps, t0, t1, cell, hstep=1e-30, obj_tag=0):
+        """(J, dJ/d(control at cell)) by the complex-step method on a copy."""
+        J = np.zeros(1)
+        dJ = np.zeros(1)
+        rc = self.L.oracle_complex_step_J(self.h, nsteps, t0, t1, obj_tag, int(cell), hstep, _p(J), _p(dJ))
+        if rc:
+            raise RuntimeError("oracle_complex_step_J failed")
+        return float(J[0]), float(dJ[0])
+
+
+def setup(w, threads=None) -> OracleLattice:
+    """Oracle lattice loaded with a workload's inputs at step 0."""
+    from paper_2510_13726_amd import workloads as W
+    o = OracleLattice(w.nx, w.ny, w.nz, w.bc_x, threads=threads)
+    o.set_params(w.params)
+    o.set_rotors(w.rotors)
+    d, tag = W.static_porosity(w)
+    if d is not None:
+        o.set_porosity_field(d, tag)
+        c = w.sphere[:3]
+        o.set_tag_frame(1, c, (1.0, 0.0, 0.0))
+    rho, u = W.initial_fields(w)
+    o.init_equilibrium(rho, u)
+    noise = W.population_noise(w)
+    if noise is not None:
+        o.set_populations(o.get_populations() + noise)
+    return o
+
+
+# --------------------------------------------------------------- cell API
+def lattice_tables():
+    c = np.zeros(81, dtype=np.int32)
+    w = np.zeros(27)
+    lib().oracle_lattice(c.ctypes.data_as(C.POINTER(C.c_int32)), _p(w))
+    return c.reshape(27, 3), w
+
+
+def equilibrium(rho, u):
+    u = _f64(np.asarray(u))
+    out = np.empty(27)
+    lib().oracle_equilibrium(float(rho), _p(u), _p(out))
+    return out
+
+
+def moments_of(f):
+    f = _f64(np.asarray(f))
+    m = np.empty(10)
+    lib().oracle_moments_of(_p(f), _p(m))
+    return m
+
+
+def collide_cell(m, d=0.0, uB=(0, 0, 0), uwm=(0, 0, 0), S=(0, 0, 0, 0, 0, 0), sigma=1.0, tau0=0.55, Cs=0.1):
+    m, uB, uwm, S = (_f64(np.asarray(v, dtype=np.float64)) for v in (m, uB, uwm, S))
+    fs = np.empty(27)
+    dP = np.empty(3)
+    lib().oracle_collide_cell(_p(m), float(d), _p(uB), _p(uwm), _p(S), float(sigma), float(tau0), float(Cs),
+                              _p(fs), _p(dP))
+    return fs, dP
+
+
+def spalding_yplus(uplus, E=9.8, kappa=0.41):
+    return lib().oracle_spalding_yplus(float(uplus), E, kappa)
+
+
+def wall_cell(us, uw, n, y1, params, utau_prev=0.0, prev_active=False):
+    q = make_params(params)
+    us, uw, n = (_f64(np.asarray(v, dtype=np.float64)) for v in (us, uw, n))
+    out = np.empty(11)
+    ip = C.c_int(0)
+    it = lib().oracle_wall_cell(_p(us), _p(uw), _p(n), float(y1), float(utau_prev), int(prev_active),
+                                C.byref(q), _p(out), C.byref(ip))
+    return dict(uwm=out[0:3].copy(), S=out[3:9].copy(), utau=out[9], active=bool(out[10]),
+                iters=it, iters_plus=ip.value)
+
+
+def rotor_phi(rotor, x, n=0):
+    r = make_rotor(rotor)
+    x = _f64(np.asarray(x, dtype=np.float64))
+    g = np.empty(3)
+    phi = lib().oracle_rotor_phi(C.byref(r), _p(x), int(n), _p(g))
+    return phi, g
+
+
+def transition(phi, eps=2.0, kind=0):
+    return lib().oracle_transition(float(phi), float(eps), int(kind))
+
+
+def gaussian(seed, n, y, z, comp, ny, nz):
+    return lib().oracle_gaussian(seed, n, y, z, comp, ny, nz)
+
+
+def splitmix64(seed, k):
+    return lib().oracle_splitmix64(seed, k)
