@@ -1,0 +1,203 @@
+/*
+ * hlbm.h -- C ABI of the MI355X fused HLBM stream-collide library (libhlbm.so).
+ *
+ * The library advances the homogenized hybrid recursive-regularized lattice
+ * Boltzmann method with Smagorinsky LES and a Spalding wall model on moving
+ * porous rotors ("Efficient Wall-Modelled Large Eddy Simulation of Rotors
+ * using Homogenized Lattice Boltzmann Methods", Sec. 2.2 eq. hlbm, Sec. 2.2.1,
+ * Sec. 2.2.2, Sec. 3) on a D3Q27 lattice, on one gfx950 GPU.
+ *
+ * Conventions used by every entry point:
+ *  - Cells (x, y, z), x fastest; linear cell index c = (z*ny + y)*nx + x.
+ *    Fields are stored component-major: a 3-vector field is [3][nz][ny][nx].
+ *  - Velocities c_i in {-1,0,1}^3, canonical order i = 9(cx+1)+3(cy+1)+(cz+1),
+ *    opposite of i is 26-i, rest population 13; weights 8/27, 2/27, 1/54,
+ *    1/216 by |c_i|^2 = 0, 1, 2, 3; lattice units dx = dt = 1, cs^2 = 1/3.
+ *  - State between steps: the post-collision populations f*_i(x) of the
+ *    previous step.  Step n pulls f_i(x, n) = f*_i(x - c_i) (the streaming of
+ *    eq. hlbm), applies the outer boundaries, collides and stores f*(x).
+ *    Canonical population arrays exchanged through this ABI hold
+ *    h_i(x) = f*_i(x) - w_i in FP64, layout [27][nz][ny][nx].
+ *  - Porosity convention of eq. convexVelocity: d = 1 solid, d = 0 fluid.
+ *  - "device" pointers are HIP device memory on the lattice's device; "host"
+ *    pointers are ordinary host memory.  The library never frees memory it
+ *    did not allocate; all device memory is owned by the caller.
+ *  - Every call returns HLBM_OK (0) or an error code; the message of the last
+ *    error is available from hlbm_last_error().  Nothing throws across the
+ *    ABI.  One handle may be used by one host thread at a time.
+ *  - All work is enqueued on the stream given at creation; calls that return
+ *    data to host memory synchronize that stream.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HLBM_Q 27
+#define HLBM_MAX_ROTORS 8
+#define HLBM_MAX_BLADES 8
+#define HLBM_NUM_TAGS 16          /* tags 1..15 name solid elements; 0 = none */
+#define HLBM_HIST_STRIDE 91       /* per step: mass, then (F[3], T[3]) for tags 1..15 */
+
+enum hlbm_status {
+  HLBM_OK = 0,
+  HLBM_ERR_INVALID = 1,     /* bad argument or size; nothing was changed */
+  HLBM_ERR_HIP = 2,         /* a HIP runtime call failed */
+  HLBM_ERR_NONFINITE = 3,   /* a non-finite density was detected by the step */
+  HLBM_ERR_STATE = 4        /* call not valid in the handle's current state */
+};
+
+enum hlbm_dtype { HLBM_F64 = 0, HLBM_F32 = 1, HLBM_F16 = 2, HLBM_BF16 = 3 };
+enum hlbm_bc { HLBM_BC_PERIODIC = 0, HLBM_BC_INFLOW_OUTFLOW = 1 };
+enum hlbm_transition { HLBM_TRANSITION_TANH = 0, HLBM_TRANSITION_LINEAR = 1 };
+
+/* Optional workspace sections requested at creation. */
+#define HLBM_WITH_SOLID_VELOCITY 1   /* reserve a static solid-velocity field */
+#define HLBM_WITH_CONTROL 2          /* reserve a porosity control field (adjoint) */
+
+typedef struct hlbm_lattice* hlbm_handle;
+
+/* Lattice description.  storage: type of the stored populations (FP16/BF16
+ * only with compute = HLBM_F32); compute: arithmetic type of the sweep
+ * (HLBM_F64 or HLBM_F32).  bc_x: x faces periodic, or equilibrium inflow at
+ * x = 0 and zero-gradient outflow at x = nx-1 (y and z are periodic).
+ * bbox_cells: total cells of the rotors' bounding boxes the workspace must
+ * hold (from hlbm_rotor_bbox_cells); history: steps kept in the force ring. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t storage;
+  int32_t compute;
+  int32_t bc_x;
+  int32_t flags;
+  int32_t pad0;
+  int64_t bbox_cells;
+  int64_t history;
+  void* stream;              /* hipStream_t; NULL = the null stream */
+} hlbm_desc;
+
+/* Model parameters (Sec. 2.2, 2.2.1, 2.2.2).  tau0 > 1/2 molecular relaxation
+ * time; cs_smag Smagorinsky constant; eps_h transition width of the lattice
+ * porosity; transition HLBM_TRANSITION_*; wall model E, kappa, sampling
+ * distance y_s, Newton tolerance tol on |f(u^{j+1}) - f(u^j)| and iteration
+ * cap maxit; u_in inflow velocity, turb_I inflow turbulence intensity and its
+ * seed; diag_every: every k-th step also reduces the total mass and checks
+ * for non-finite densities (0 = never); check_nonfinite: hlbm_step
+ * synchronizes at its end and reports HLBM_ERR_NONFINITE. */
+typedef struct {
+  double tau0, cs_smag, eps_h;
+  int32_t transition, wall_model;
+  double E, kappa, y_s, tol;
+  int32_t maxit, diag_every;
+  double u_in[3];
+  double turb_I;
+  uint64_t seed;
+  int32_t check_nonfinite, pad0;
+} hlbm_params;
+
+/* Rotor of n_blades flat-plate blades (chord x thick, from r_hub to R,
+ * pitch twisted linearly from twist_root to twist_tip, radians) and a hub
+ * sphere of radius r_hub, turning about axis through center at omega
+ * rad/step from phase0; its cells carry tag (1..15). */
+typedef struct {
+  double center[3], axis[3];
+  double R, r_hub, chord, thick, twist_root, twist_tip, omega, phase0;
+  int32_t n_blades, tag;
+} hlbm_rotor;
+
+/* Bytes of one population buffer (27 arrays, each padded). */
+int64_t hlbm_population_bytes(const hlbm_desc* desc);
+/* Bytes of the workspace for this description. */
+int64_t hlbm_workspace_bytes(const hlbm_desc* desc);
+/* Cells of the fixed bounding boxes of these rotors (value for desc->bbox_cells). */
+int64_t hlbm_rotor_bbox_cells(const hlbm_desc* desc, const hlbm_rotor* rotors, int32_t n);
+
+/* Create a lattice on the current HIP device.  pop_a, pop_b: device buffers of
+ * hlbm_population_bytes each; workspace: device buffer of
+ * hlbm_workspace_bytes.  The handle borrows them until destroy.  The
+ * lattice starts at rest (f* = w), step 0, no solids. */
+int hlbm_lattice_create(const hlbm_desc* desc, void* pop_a, void* pop_b, void* workspace,
+                        hlbm_handle* out);
+/* Destroy a handle; never frees caller memory.  NULL is a no-op. */
+void hlbm_lattice_destroy(hlbm_handle h);
+
+/* Parameters (validated: tau0 > 1/2, cs_smag >= 0, eps_h > 0, maxit >= 1). */
+int hlbm_set_params(hlbm_handle h, const hlbm_params* p);
+
+/* Rotors rasterized on the GPU every step (Sec. 3.1); n <= HLBM_MAX_ROTORS,
+ * tags distinct, n_blades <= HLBM_MAX_BLADES, bounding boxes inside the
+ * domain and within desc->bbox_cells.  n = 0 removes all rotors. */
+int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* rotors, int32_t n);
+
+/* Static porosity field d (device, compute type, N values, 0 <= d <= 1) and
+ * tags (device, uint8, N values, 0..15); both are copied.  NULL d clears the
+ * field (d = 0 everywhere), NULL tag sets tag 0. */
+int hlbm_set_porosity_field(hlbm_handle h, const void* d, const uint8_t* tag);
+
+/* Static solid velocity u^B (device, compute type, [3][N]) used where the
+ * cell is not covered by a rotor; copied.  Needs HLBM_WITH_SOLID_VELOCITY.
+ * NULL resets to zero. */
+int hlbm_set_solid_velocity(hlbm_handle h, const void* uB);
+
+/* Porosity control delta_d (device, compute type, N values) added to the
+ * porosity of every cell (d = max(d_static, d_rotor) + delta_d); copied.
+ * Needs HLBM_WITH_CONTROL.  NULL resets to zero. */
+int hlbm_set_control(hlbm_handle h, const void* dd);
+
+/* Reference frame (torque centre, axis) of a tag set through the static
+ * field; rotor tags use the rotor's centre and axis. */
+int hlbm_set_tag_frame(hlbm_handle h, int32_t tag, const double center[3], const double axis[3]);
+
+/* f* = f^eq(rho, u) (the third-order equilibrium of Sec. 2.2) in every
+ * cell; rho (N) and u ([3][N]) device, compute type; NULL rho = 1, NULL u =
+ * 0.  Resets the step counter, the wall-model state and the history. */
+int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u);
+
+/* Advance n >= 0 steps (asynchronous unless check_nonfinite is set). */
+int hlbm_step(hlbm_handle h, int64_t n);
+
+/* Current step counter. */
+int64_t hlbm_get_step(hlbm_handle h);
+
+/* Density and velocity of the pre-collision populations f(x, n) of the next
+ * step (rho N, u [3][N]) and the homogenized velocity u_hat it collides to
+ * ([3][N], eq. convexVelocity; nullable); device, compute type.  The lattice
+ * state is not changed. */
+int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat);
+
+/* Canonical state h = f* - w, FP64, device, [27][N]. */
+int hlbm_get_populations(hlbm_handle h, double* dst);
+int hlbm_set_populations(hlbm_handle h, const double* src);
+/* Canonical state at selected cells: dst[k*27 + i] for cell cells[k] (both device). */
+int hlbm_get_populations_at(hlbm_handle h, const int64_t* cells, int64_t count, double* dst);
+
+/* Complete restartable state (populations in storage format, wall-model
+ * state, step counter) as an opaque blob of hlbm_state_bytes bytes (device). */
+int64_t hlbm_state_bytes(hlbm_handle h);
+int hlbm_get_state(hlbm_handle h, void* dst);
+int hlbm_set_state(hlbm_handle h, const void* src);
+
+/* Force F and torque T (about the tag's centre) handed to the solid with
+ * this tag by the last step, FP64 host (syncs). */
+int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]);
+/* Records of steps [from, to) (absolute step numbers still in the ring),
+ * HLBM_HIST_STRIDE doubles each, host (syncs).  Mass is NaN on steps
+ * without diagnostics. */
+int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
+
+/* Wall-model counters since creation: Newton iterations for u_tau and wall
+ * cells processed (host, syncs). */
+int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
+
+/* Message of the last error of this handle (or of the last failed create
+ * when h is NULL).  Valid until the next call on the handle. */
+const char* hlbm_last_error(hlbm_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLBM_H */

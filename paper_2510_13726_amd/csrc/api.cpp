@@ -1,0 +1,634 @@
+// C ABI of libhlbm: validation, workspace layout, the host step loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hlbm.h"
+#include "hlbm_internal.h"
+#include "launch.h"
+
+using namespace hlbm;
+
+namespace {
+
+std::string g_create_error;
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int elem_size(int t) { return t == HLBM_F64 ? 8 : t == HLBM_F32 ? 4 : 2; }
+
+bool desc_ok(const hlbm_desc* d, std::string* why) {
+  if (!d) { *why = "desc is NULL"; return false; }
+  if (d->nx < 2 || d->ny < 1 || d->nz < 1) { *why = "lattice needs nx >= 2, ny >= 1, nz >= 1"; return false; }
+  const int64_t N = int64_t(d->nx) * d->ny * d->nz;
+  if (N >= (int64_t(1) << 31)) { *why = "lattice above 2^31 cells"; return false; }
+  if (d->compute != HLBM_F64 && d->compute != HLBM_F32) { *why = "compute must be F64 or F32"; return false; }
+  if (d->storage < HLBM_F64 || d->storage > HLBM_BF16) { *why = "unknown storage type"; return false; }
+  if (d->compute == HLBM_F64 && d->storage != HLBM_F64) { *why = "F64 compute needs F64 storage"; return false; }
+  if (d->compute == HLBM_F32 && d->storage == HLBM_F64) { *why = "F64 storage needs F64 compute"; return false; }
+  if (d->bc_x != HLBM_BC_PERIODIC && d->bc_x != HLBM_BC_INFLOW_OUTFLOW) { *why = "unknown bc_x"; return false; }
+  if (d->bbox_cells < 0 || d->history < 0) { *why = "negative bbox_cells or history"; return false; }
+  return true;
+}
+
+int64_t cells_of(const hlbm_desc* d) { return int64_t(d->nx) * d->ny * d->nz; }
+
+// Elements between the 27 population arrays: the array size rounded up to a
+// page plus a 512-byte skew, so the arrays do not all start on the same
+// DRAM channel.
+int64_t pop_stride(const hlbm_desc* d) {
+  const int es = elem_size(d->storage);
+  int64_t pad = 512;
+  if (const char* e = std::getenv("HLBM_POP_SKEW")) pad = std::atoll(e);
+  const int64_t bytes = align_up(cells_of(d) * es, 4096) + pad;
+  return bytes / es;
+}
+
+struct Layout {
+  int64_t d_eff, d_static, tag, tag_static, uB, dd, blk, partial, mass, massl1, flag, stats, rot, geo, ut0, ut1,
+      act0, act1, wall, hist, ghost, ghost64, total;
+};
+
+Layout layout(const hlbm_desc* d) {
+  Layout L{};
+  const int64_t N = cells_of(d);
+  const int cs = elem_size(d->compute);
+  const int64_t nb = (N + kBlock - 1) / kBlock;
+  const int64_t B = d->bbox_cells;
+  const int64_t H = d->history > 0 ? d->history : 1024;
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) { int64_t at = o; o = align_up(o + bytes, kAlign); return at; };
+  L.d_eff = take(N * cs);
+  L.d_static = take(N * cs);
+  L.tag = take(N);
+  L.tag_static = take(N);
+  L.uB = take((d->flags & HLBM_WITH_SOLID_VELOCITY) ? 3 * N * cs : 0);
+  L.dd = take((d->flags & HLBM_WITH_CONTROL) ? N * cs : 0);
+  L.blk = take(nb * 4);
+  L.partial = take(nb * kPartial * 8);
+  L.mass = take(nb * 8);
+  L.massl1 = take(kMassL1 * 8);
+  L.flag = take(64);
+  L.stats = take(64);
+  L.rot = take(sizeof(RotorTable));
+  L.geo = take(4 * B * 8);
+  L.ut0 = take(B * 8);
+  L.ut1 = take(B * 8);
+  L.act0 = take(B);
+  L.act1 = take(B);
+  L.wall = take(kWallOut * B * cs);
+  L.hist = take(H * kHist * 8);
+  const int64_t plane = int64_t(d->ny) * d->nz;
+  L.ghost = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * cs : 0);
+  L.ghost64 = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
+  L.total = o;
+  return L;
+}
+
+struct RotorBox { int32_t b0[3], bn[3]; };
+
+bool rotor_box(const hlbm_desc* d, const hlbm_rotor& r, double eps_h, RotorBox* box, std::string* why) {
+  const double an = std::sqrt(r.axis[0] * r.axis[0] + r.axis[1] * r.axis[1] + r.axis[2] * r.axis[2]);
+  if (!(an > 0)) { *why = "rotor axis is zero"; return false; }
+  const double hc = std::sqrt(0.25 * r.chord * r.chord + 0.25 * r.thick * r.thick);
+  const double rc = std::max(std::sqrt(r.R * r.R + hc * hc), r.r_hub);
+  const double ha = std::max(hc, r.r_hub);
+  const double m = 0.5 * eps_h + 1.0;
+  const int n3[3] = {d->nx, d->ny, d->nz};
+  for (int k = 0; k < 3; ++k) {
+    const double e = r.axis[k] / an;
+    const double ext = ha * std::fabs(e) + rc * std::sqrt(std::max(0.0, 1.0 - e * e));
+    const int lo = int(std::floor(r.center[k] - ext - m));
+    const int hi = int(std::ceil(r.center[k] + ext + m));
+    if (lo < 0 || hi > n3[k] - 1) { *why = "rotor bounding box leaves the domain"; return false; }
+    box->b0[k] = lo;
+    box->bn[k] = hi - lo + 1;
+  }
+  return true;
+}
+
+}  // namespace
+
+struct hlbm_lattice {
+  hlbm_desc desc{};
+  hipStream_t stream = nullptr;
+  Layout lay{};
+  Launch L{};
+  void* pop[2] = {nullptr, nullptr};
+  int cur = 0;                 // pop[cur] holds the state
+  double* ut[2] = {nullptr, nullptr};
+  uint8_t* act[2] = {nullptr, nullptr};
+  int wcur = 0;
+  RotorTable rot{};
+  std::vector<hlbm_rotor> rotors;
+  hlbm_params params{};
+  bool have_params = false;
+  int32_t nslots = 0;
+  int64_t step = 0;
+  int64_t hist_start = 0;      // first step recorded since init
+  int64_t hist_cap = 0;
+  std::string err;
+};
+
+namespace {
+
+int fail(hlbm_handle h, int code, const std::string& msg) {
+  if (h) h->err = msg; else g_create_error = msg;
+  return code;
+}
+int hip_fail(hlbm_handle h, hipError_t e, const char* where) {
+  return fail(h, HLBM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+void set_model(hlbm_handle h) {
+  const hlbm_params& p = h->params;
+  Model& m = h->L.m;
+  m.tau0 = p.tau0;
+  m.smag = 18.0 * std::sqrt(2.0) * p.cs_smag * p.cs_smag;
+  m.eps_h = p.eps_h;
+  m.transition = p.transition;
+  m.wall_model = p.wall_model;
+  m.E = p.E; m.kappa = p.kappa; m.y_s = p.y_s; m.tol = p.tol;
+  m.nu = (p.tau0 - 0.5) / 3.0;
+  m.maxit = p.maxit;
+  for (int a = 0; a < 3; ++a) m.u_in[a] = p.u_in[a];
+  const double mag = std::sqrt(p.u_in[0] * p.u_in[0] + p.u_in[1] * p.u_in[1] + p.u_in[2] * p.u_in[2]);
+  m.turb_amp = p.turb_I * mag;
+  m.seed = p.seed;
+}
+
+// Mark FSI workgroups and number them (host round trip; set-up time only).
+int rebuild_slots(hlbm_handle h) {
+  hipError_t e = launch_mark_blocks(h->L);
+  if (e != hipSuccess) return hip_fail(h, e, "mark blocks");
+  std::vector<int32_t> flags(h->L.nblocks);
+  e = hipMemcpyAsync(flags.data(), h->L.blk_slot, sizeof(int32_t) * flags.size(), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "read block flags");
+  int32_t n = 0;
+  for (auto& f : flags) f = f ? n++ : -1;
+  h->nslots = n;
+  e = hipMemcpyAsync(h->L.blk_slot, flags.data(), sizeof(int32_t) * flags.size(), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "write block slots");
+  return HLBM_OK;
+}
+
+int upload_rotors(hlbm_handle h) {
+  hipError_t e = hipMemcpyAsync(h->L.rot, &h->rot, sizeof(RotorTable), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "upload rotor table");
+  return HLBM_OK;
+}
+
+// Build the rotor table (frames, boxes, pools); validates capacity.
+int build_rotor_table(hlbm_handle h, const hlbm_rotor* r, int32_t n, RotorTable* out, int64_t* total) {
+  RotorTable t = h->rot;  // keeps tag frames of static tags
+  t.n = n;
+  for (int k = 0; k < kTags; ++k) t.tag2rot[k] = -1;
+  int64_t off = 0;
+  for (int k = 0; k < n; ++k) {
+    const hlbm_rotor& q = r[k];
+    if (q.tag < 1 || q.tag > 15) return fail(h, HLBM_ERR_INVALID, "rotor tag must be 1..15");
+    if (t.tag2rot[q.tag] >= 0) return fail(h, HLBM_ERR_INVALID, "rotor tags must be distinct");
+    if (q.n_blades < 0 || q.n_blades > HLBM_MAX_BLADES) return fail(h, HLBM_ERR_INVALID, "n_blades out of range");
+    if (!(q.R > q.r_hub) || !(q.r_hub >= 0) || !(q.chord > 0) || !(q.thick > 0))
+      return fail(h, HLBM_ERR_INVALID, "rotor needs R > r_hub >= 0, chord > 0, thick > 0");
+    RotorBox box;
+    std::string why;
+    if (!rotor_box(&h->desc, q, h->params.eps_h, &box, &why)) return fail(h, HLBM_ERR_INVALID, why);
+    RotorDev& d = t.r[k];
+    const double an = std::sqrt(q.axis[0] * q.axis[0] + q.axis[1] * q.axis[1] + q.axis[2] * q.axis[2]);
+    for (int a = 0; a < 3; ++a) { d.c[a] = q.center[a]; d.e[a] = q.axis[a] / an; }
+    double a0[3] = {1, 0, 0};
+    if (std::fabs(d.e[0]) >= 0.9) { a0[0] = 0; a0[1] = 1; }
+    const double ae = a0[0] * d.e[0] + a0[1] * d.e[1] + a0[2] * d.e[2];
+    double e1[3];
+    for (int a = 0; a < 3; ++a) e1[a] = a0[a] - ae * d.e[a];
+    const double n1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int a = 0; a < 3; ++a) d.e1[a] = e1[a] / n1;
+    d.e2[0] = d.e[1] * d.e1[2] - d.e[2] * d.e1[1];
+    d.e2[1] = d.e[2] * d.e1[0] - d.e[0] * d.e1[2];
+    d.e2[2] = d.e[0] * d.e1[1] - d.e[1] * d.e1[0];
+    d.R = q.R; d.r_hub = q.r_hub; d.chord = q.chord; d.thick = q.thick;
+    d.tw_root = q.twist_root; d.tw_tip = q.twist_tip; d.omega = q.omega; d.phase0 = q.phase0;
+    d.nb = q.n_blades; d.tag = q.tag;
+    for (int a = 0; a < 3; ++a) { d.b0[a] = box.b0[a]; d.bn[a] = box.bn[a]; }
+    d.cells = int64_t(box.bn[0]) * box.bn[1] * box.bn[2];
+    d.off = off;
+    off += d.cells;
+    t.tag2rot[q.tag] = k;
+    for (int a = 0; a < 3; ++a) { t.frame[q.tag][a] = d.c[a]; t.frame[q.tag][3 + a] = d.e[a]; }
+  }
+  if (off > h->desc.bbox_cells)
+    return fail(h, HLBM_ERR_INVALID, "rotor boxes need " + std::to_string(off) + " cells, workspace holds " +
+                                         std::to_string(h->desc.bbox_cells));
+  *out = t;
+  *total = off;
+  return HLBM_OK;
+}
+
+bool params_ok(const hlbm_params* p, std::string* why) {
+  if (!p) { *why = "params is NULL"; return false; }
+  if (!(p->tau0 > 0.5)) { *why = "tau0 must exceed 1/2"; return false; }
+  if (!(p->cs_smag >= 0)) { *why = "cs_smag must be >= 0"; return false; }
+  if (!(p->eps_h > 0)) { *why = "eps_h must be > 0"; return false; }
+  if (p->transition != HLBM_TRANSITION_TANH && p->transition != HLBM_TRANSITION_LINEAR) { *why = "bad transition"; return false; }
+  if (p->maxit < 1 || p->maxit > 100) { *why = "maxit must be 1..100"; return false; }
+  if (p->wall_model && (!(p->E > 0) || !(p->kappa > 0) || !(p->y_s > 0.5 * p->eps_h) || !(p->tol > 0))) {
+    *why = "wall model needs E > 0, kappa > 0, tol > 0, y_s > eps_h/2";
+    return false;
+  }
+  if (!(p->turb_I >= 0) || p->diag_every < 0) { *why = "turb_I and diag_every must be >= 0"; return false; }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->u_in[a])) { *why = "u_in not finite"; return false; }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t hlbm_population_bytes(const hlbm_desc* d) {
+  std::string why;
+  if (!desc_ok(d, &why)) return -1;
+  return 27 * pop_stride(d) * elem_size(d->storage);
+}
+
+int64_t hlbm_workspace_bytes(const hlbm_desc* d) {
+  std::string why;
+  if (!desc_ok(d, &why)) return -1;
+  return layout(d).total;
+}
+
+int64_t hlbm_rotor_bbox_cells(const hlbm_desc* d, const hlbm_rotor* r, int32_t n) {
+  std::string why;
+  if (!desc_ok(d, &why) || n < 0 || (n > 0 && !r)) return -1;
+  int64_t total = 0;
+  for (int k = 0; k < n; ++k) {
+    RotorBox b;
+    // the widest band the workspace must allow for: eps_h up to 4 cells
+    if (!rotor_box(d, r[k], 4.0, &b, &why)) return -1;
+    total += int64_t(b.bn[0]) * b.bn[1] * b.bn[2];
+  }
+  return total;
+}
+
+int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, hlbm_handle* out) {
+  std::string why;
+  if (!out) return fail(nullptr, HLBM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!desc_ok(d, &why)) return fail(nullptr, HLBM_ERR_INVALID, why);
+  if (!pop_a || !pop_b || !ws) return fail(nullptr, HLBM_ERR_INVALID, "population or workspace pointer is NULL");
+  if (pop_a == pop_b) return fail(nullptr, HLBM_ERR_INVALID, "the two population buffers must differ");
+  hlbm_handle h = new hlbm_lattice();
+  h->desc = *d;
+  h->stream = static_cast<hipStream_t>(d->stream);
+  h->lay = layout(d);
+  h->pop[0] = pop_a;
+  h->pop[1] = pop_b;
+  h->hist_cap = d->history > 0 ? d->history : 1024;
+  char* base = static_cast<char*>(ws);
+  Launch& L = h->L;
+  L.stream = h->stream;
+  L.storage = d->storage;
+  L.compute = d->compute;
+  L.g.nx = d->nx; L.g.ny = d->ny; L.g.nz = d->nz; L.g.bc_x = d->bc_x;
+  L.g.N = cells_of(d);
+  L.g.stride = pop_stride(d);
+  L.nblocks = (L.g.N + kBlock - 1) / kBlock;
+  L.xcd_remap = 1;
+  if (const char* e = std::getenv("HLBM_XCD_REMAP")) L.xcd_remap = std::atoi(e);
+  const Layout& Y = h->lay;
+  L.d_eff = base + Y.d_eff;
+  L.d_static = base + Y.d_static;
+  L.tag = reinterpret_cast<uint8_t*>(base + Y.tag);
+  L.tag_static = reinterpret_cast<uint8_t*>(base + Y.tag_static);
+  L.uB_static = nullptr;
+  L.dd = nullptr;
+  L.blk_slot = reinterpret_cast<int32_t*>(base + Y.blk);
+  L.partial = reinterpret_cast<double*>(base + Y.partial);
+  L.mass_part = reinterpret_cast<double*>(base + Y.mass);
+  L.mass_l1 = reinterpret_cast<double*>(base + Y.massl1);
+  L.flag = reinterpret_cast<int32_t*>(base + Y.flag);
+  L.stats = reinterpret_cast<unsigned long long*>(base + Y.stats);
+  L.rot = reinterpret_cast<RotorTable*>(base + Y.rot);
+  L.nrot = 0;
+  L.bbox_total = 0;
+  L.geo = reinterpret_cast<double*>(base + Y.geo);
+  h->ut[0] = reinterpret_cast<double*>(base + Y.ut0);
+  h->ut[1] = reinterpret_cast<double*>(base + Y.ut1);
+  h->act[0] = reinterpret_cast<uint8_t*>(base + Y.act0);
+  h->act[1] = reinterpret_cast<uint8_t*>(base + Y.act1);
+  L.wall_out = base + Y.wall;
+  L.hist = reinterpret_cast<double*>(base + Y.hist);
+  L.hist_cap = h->hist_cap;
+  L.ghost = base + Y.ghost;
+  L.ghost64 = reinterpret_cast<double*>(base + Y.ghost64);
+  if (L.compute == HLBM_F64) L.ghost64 = reinterpret_cast<double*>(L.ghost);
+  // defaults: Smagorinsky-free BGK-like relaxation at tau0 = 1 until set_params
+  hlbm_params p{};
+  p.tau0 = 1.0; p.cs_smag = 0.0; p.eps_h = 2.0; p.transition = HLBM_TRANSITION_TANH; p.wall_model = 0;
+  p.E = 9.8; p.kappa = 0.41; p.y_s = 3.0; p.tol = 1e-4; p.maxit = 10; p.diag_every = 1;
+  h->params = p;
+  set_model(h);
+  for (int k = 0; k < kTags; ++k) {
+    h->rot.tag2rot[k] = -1;
+    h->rot.frame[k][0] = 0.5 * (d->nx - 1); h->rot.frame[k][1] = 0.5 * (d->ny - 1); h->rot.frame[k][2] = 0.5 * (d->nz - 1);
+    h->rot.frame[k][3] = 1; h->rot.frame[k][4] = 0; h->rot.frame[k][5] = 0;
+  }
+  h->rot.n = 0;
+  hipError_t e = hipMemsetAsync(ws, 0, Y.total, h->stream);
+  if (e == hipSuccess) e = launch_fill_rest(L, h->pop[0]);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    hip_fail(nullptr, e, "create");
+    delete h;
+    return HLBM_ERR_HIP;
+  }
+  int rc = upload_rotors(h);
+  if (rc == HLBM_OK) rc = rebuild_slots(h);
+  if (rc != HLBM_OK) {
+    g_create_error = h->err;
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return HLBM_OK;
+}
+
+void hlbm_lattice_destroy(hlbm_handle h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+int hlbm_set_params(hlbm_handle h, const hlbm_params* p) {
+  if (!h) return HLBM_ERR_INVALID;
+  std::string why;
+  if (!params_ok(p, &why)) return fail(h, HLBM_ERR_INVALID, why);
+  const hlbm_params old = h->params;
+  h->params = *p;
+  if (!h->rotors.empty()) {
+    RotorTable t;
+    int64_t total;
+    int rc = build_rotor_table(h, h->rotors.data(), int32_t(h->rotors.size()), &t, &total);
+    if (rc != HLBM_OK) { h->params = old; return rc; }
+    h->rot = t;
+    h->L.bbox_total = total;
+    if ((rc = upload_rotors(h)) != HLBM_OK) return rc;
+    if ((rc = rebuild_slots(h)) != HLBM_OK) return rc;
+  }
+  set_model(h);
+  h->have_params = true;
+  return HLBM_OK;
+}
+
+int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* r, int32_t n) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (n < 0 || n > HLBM_MAX_ROTORS || (n > 0 && !r)) return fail(h, HLBM_ERR_INVALID, "0 <= n <= 8 rotors");
+  RotorTable t;
+  int64_t total;
+  int rc = build_rotor_table(h, r, n, &t, &total);
+  if (rc != HLBM_OK) return rc;
+  h->rot = t;
+  h->rotors.assign(r, r + n);
+  h->L.nrot = n;
+  h->L.bbox_total = total;
+  // reset cells of the old boxes to the static field, then re-mark
+  hipError_t e = launch_refill_porosity(h->L);
+  if (e != hipSuccess) return hip_fail(h, e, "refill porosity");
+  e = hipMemsetAsync(h->act[0], 0, std::max<int64_t>(total, 1), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->act[1], 0, std::max<int64_t>(total, 1), h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset wall state");
+  if ((rc = upload_rotors(h)) != HLBM_OK) return rc;
+  return rebuild_slots(h);
+}
+
+int hlbm_set_porosity_field(hlbm_handle h, const void* d, const uint8_t* tag) {
+  if (!h) return HLBM_ERR_INVALID;
+  const int64_t N = h->L.g.N;
+  const int cs = elem_size(h->desc.compute);
+  hipError_t e = d ? hipMemcpyAsync(h->L.d_static, d, N * cs, hipMemcpyDeviceToDevice, h->stream)
+                   : hipMemsetAsync(h->L.d_static, 0, N * cs, h->stream);
+  if (e == hipSuccess)
+    e = tag ? hipMemcpyAsync(h->L.tag_static, tag, N, hipMemcpyDeviceToDevice, h->stream)
+            : hipMemsetAsync(h->L.tag_static, 0, N, h->stream);
+  if (e == hipSuccess) e = launch_refill_porosity(h->L);
+  if (e != hipSuccess) return hip_fail(h, e, "set porosity field");
+  return rebuild_slots(h);
+}
+
+int hlbm_set_solid_velocity(hlbm_handle h, const void* uB) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (!(h->desc.flags & HLBM_WITH_SOLID_VELOCITY)) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_SOLID_VELOCITY");
+  const int64_t bytes = 3 * h->L.g.N * elem_size(h->desc.compute);
+  void* dst = static_cast<char*>(h->L.d_eff) - h->lay.d_eff + h->lay.uB;
+  hipError_t e = uB ? hipMemcpyAsync(dst, uB, bytes, hipMemcpyDeviceToDevice, h->stream)
+                    : hipMemsetAsync(dst, 0, bytes, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "set solid velocity");
+  h->L.uB_static = uB ? dst : nullptr;
+  return HLBM_OK;
+}
+
+int hlbm_set_control(hlbm_handle h, const void* dd) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (!(h->desc.flags & HLBM_WITH_CONTROL)) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_CONTROL");
+  const int64_t bytes = h->L.g.N * elem_size(h->desc.compute);
+  void* dst = static_cast<char*>(h->L.d_eff) - h->lay.d_eff + h->lay.dd;
+  hipError_t e = dd ? hipMemcpyAsync(dst, dd, bytes, hipMemcpyDeviceToDevice, h->stream)
+                    : hipMemsetAsync(dst, 0, bytes, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "set control");
+  h->L.dd = dd ? dst : nullptr;
+  e = launch_refill_porosity(h->L);
+  if (e != hipSuccess) return hip_fail(h, e, "refill porosity");
+  return rebuild_slots(h);
+}
+
+int hlbm_set_tag_frame(hlbm_handle h, int32_t tag, const double center[3], const double axis[3]) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (tag < 1 || tag > 15 || !center || !axis) return fail(h, HLBM_ERR_INVALID, "tag must be 1..15");
+  if (h->rot.tag2rot[tag] >= 0) return fail(h, HLBM_ERR_INVALID, "tag belongs to a rotor");
+  const double n = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+  if (!(n > 0)) return fail(h, HLBM_ERR_INVALID, "axis is zero");
+  for (int a = 0; a < 3; ++a) { h->rot.frame[tag][a] = center[a]; h->rot.frame[tag][3 + a] = axis[a] / n; }
+  return upload_rotors(h);
+}
+
+int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u) {
+  if (!h) return HLBM_ERR_INVALID;
+  hipError_t e = launch_init_equilibrium(h->L, h->pop[h->cur], rho, u);
+  const int64_t B = std::max<int64_t>(h->L.bbox_total, 1);
+  if (e == hipSuccess) e = hipMemsetAsync(h->act[0], 0, B, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->act[1], 0, B, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "init equilibrium");
+  h->step = 0;
+  h->hist_start = 0;
+  return HLBM_OK;
+}
+
+int hlbm_step(hlbm_handle h, int64_t n) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (n < 0) return fail(h, HLBM_ERR_INVALID, "n must be >= 0");
+  const bool wall = h->params.wall_model && h->L.nrot > 0;
+  for (int64_t k = 0; k < n; ++k) {
+    hipError_t e = launch_rasterize(h->L, h->step);
+    if (e == hipSuccess) e = launch_inflow(h->L, h->step);
+    if (e == hipSuccess && wall)
+      e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur],
+                      h->act[1 - h->wcur], h->step);
+    const bool diag = h->params.diag_every > 0 && h->step % h->params.diag_every == 0;
+    if (e == hipSuccess) e = launch_sweep(h->L, h->pop[h->cur], h->pop[1 - h->cur], h->step, diag);
+    if (e == hipSuccess) e = launch_finalize(h->L, h->step, h->nslots, diag);
+    if (e != hipSuccess) return hip_fail(h, e, "step");
+    h->cur = 1 - h->cur;
+    if (wall) h->wcur = 1 - h->wcur;
+    ++h->step;
+  }
+  if (h->params.check_nonfinite) {
+    int32_t flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, h->L.flag, 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "read non-finite flag");
+    if (flag) {
+      (void)hipMemsetAsync(h->L.flag, 0, 4, h->stream);
+      return fail(h, HLBM_ERR_NONFINITE, "non-finite density before step " + std::to_string(h->step));
+    }
+  }
+  return HLBM_OK;
+}
+
+int64_t hlbm_get_step(hlbm_handle h) { return h ? h->step : -1; }
+
+int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (!rho || !u) return fail(h, HLBM_ERR_INVALID, "rho and u are required");
+  const bool wall = h->params.wall_model && h->L.nrot > 0;
+  hipError_t e = launch_rasterize(h->L, h->step);
+  if (e == hipSuccess) e = launch_inflow(h->L, h->step);
+  // the wall model writes the next state slot, which is not committed here
+  if (e == hipSuccess && wall)
+    e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur], h->act[1 - h->wcur],
+                    h->step);
+  if (e == hipSuccess) e = launch_moments(h->L, h->pop[h->cur], h->step, rho, u, uhat);
+  if (e != hipSuccess) return hip_fail(h, e, "moments");
+  return HLBM_OK;
+}
+
+int hlbm_get_populations(hlbm_handle h, double* dst) {
+  if (!h || !dst) return h ? fail(h, HLBM_ERR_INVALID, "dst is NULL") : HLBM_ERR_INVALID;
+  hipError_t e = launch_get_populations(h->L, h->pop[h->cur], dst);
+  if (e != hipSuccess) return hip_fail(h, e, "get populations");
+  return HLBM_OK;
+}
+
+int hlbm_set_populations(hlbm_handle h, const double* src) {
+  if (!h || !src) return h ? fail(h, HLBM_ERR_INVALID, "src is NULL") : HLBM_ERR_INVALID;
+  hipError_t e = launch_set_populations(h->L, h->pop[h->cur], src);
+  if (e != hipSuccess) return hip_fail(h, e, "set populations");
+  return HLBM_OK;
+}
+
+int hlbm_get_populations_at(hlbm_handle h, const int64_t* cells, int64_t count, double* dst) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (count < 0 || (count > 0 && (!cells || !dst))) return fail(h, HLBM_ERR_INVALID, "bad cell list");
+  hipError_t e = launch_get_populations_at(h->L, h->pop[h->cur], cells, count, dst);
+  if (e != hipSuccess) return hip_fail(h, e, "get populations at");
+  return HLBM_OK;
+}
+
+// state blob: [int64 step, int64 bbox_total, pad to 256][populations][u_tau][active]
+int64_t hlbm_state_bytes(hlbm_handle h) {
+  if (!h) return -1;
+  const int64_t B = h->L.bbox_total;
+  return 256 + 27 * h->L.g.stride * elem_size(h->desc.storage) + align_up(B * 8, 256) + align_up(B, 256);
+}
+
+int hlbm_get_state(hlbm_handle h, void* dst) {
+  if (!h || !dst) return h ? fail(h, HLBM_ERR_INVALID, "dst is NULL") : HLBM_ERR_INVALID;
+  char* p = static_cast<char*>(dst);
+  const int64_t B = h->L.bbox_total;
+  const int64_t pb = 27 * h->L.g.stride * elem_size(h->desc.storage);
+  int64_t head[32] = {0};
+  head[0] = h->step;
+  head[1] = B;
+  head[2] = 0x484c424d;  // "HLBM"
+  hipError_t e = hipMemcpyAsync(p, head, sizeof(head), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p + 256, h->pop[h->cur], pb, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && B)
+    e = hipMemcpyAsync(p + 256 + pb, h->ut[h->wcur], B * 8, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && B)
+    e = hipMemcpyAsync(p + 256 + pb + align_up(B * 8, 256), h->act[h->wcur], B, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "get state");
+  return HLBM_OK;
+}
+
+int hlbm_set_state(hlbm_handle h, const void* src) {
+  if (!h || !src) return h ? fail(h, HLBM_ERR_INVALID, "src is NULL") : HLBM_ERR_INVALID;
+  const char* p = static_cast<const char*>(src);
+  int64_t head[32];
+  hipError_t e = hipMemcpyAsync(head, p, sizeof(head), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "read state header");
+  const int64_t B = h->L.bbox_total;
+  if (head[2] != 0x484c424d || head[1] != B) return fail(h, HLBM_ERR_INVALID, "state blob does not match this lattice");
+  const int64_t pb = 27 * h->L.g.stride * elem_size(h->desc.storage);
+  e = hipMemcpyAsync(h->pop[h->cur], p + 256, pb, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && B) e = hipMemcpyAsync(h->ut[h->wcur], p + 256 + pb, B * 8, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && B)
+    e = hipMemcpyAsync(h->act[h->wcur], p + 256 + pb + align_up(B * 8, 256), B, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "set state");
+  h->step = head[0];
+  h->hist_start = head[0];
+  return HLBM_OK;
+}
+
+int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst) {
+  if (!h) return HLBM_ERR_INVALID;
+  const int64_t lo = std::max(h->hist_start, h->step - h->hist_cap);
+  if (from < lo || to > h->step || from > to || (to > from && !dst))
+    return fail(h, HLBM_ERR_INVALID, "steps [" + std::to_string(from) + ", " + std::to_string(to) +
+                                         ") not in the history ring [" + std::to_string(lo) + ", " +
+                                         std::to_string(h->step) + ")");
+  for (int64_t s = from; s < to; ++s) {
+    hipError_t e = hipMemcpyAsync(dst + (s - from) * kHist, h->L.hist + (s % h->hist_cap) * kHist, kHist * 8,
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "history");
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "history");
+  return HLBM_OK;
+}
+
+int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (tag < 1 || tag > 15 || !F || !T) return fail(h, HLBM_ERR_INVALID, "tag must be 1..15");
+  if (h->step <= h->hist_start) return fail(h, HLBM_ERR_STATE, "no step taken yet");
+  double rec[kHist];
+  int rc = hlbm_history(h, h->step - 1, h->step, rec);
+  if (rc != HLBM_OK) return rc;
+  for (int a = 0; a < 3; ++a) { F[a] = rec[1 + 6 * (tag - 1) + a]; T[a] = rec[4 + 6 * (tag - 1) + a]; }
+  return HLBM_OK;
+}
+
+int hlbm_wall_stats(hlbm_handle h, int64_t* iters, int64_t* cells) {
+  if (!h) return HLBM_ERR_INVALID;
+  unsigned long long s[2];
+  hipError_t e = hipMemcpyAsync(s, h->L.stats, sizeof(s), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "wall stats");
+  if (iters) *iters = int64_t(s[0]);
+  if (cells) *cells = int64_t(s[1]);
+  return HLBM_OK;
+}
+
+const char* hlbm_last_error(hlbm_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

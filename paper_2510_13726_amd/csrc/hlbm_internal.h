@@ -1,0 +1,57 @@
+// Internal device/host data structures of libhlbm (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hlbm {
+
+constexpr int kQ = 27;
+constexpr int kBlock = 256;          // cells per sweep workgroup (4 waves of 64)
+constexpr int kMaxRotors = 8;
+constexpr int kMaxBlades = 8;
+constexpr int kTags = 16;
+constexpr int kHist = 91;            // mass + 15 x (F, T)
+constexpr int kPartial = 96;         // per FSI block: [16 tags][F3, T3]
+constexpr int kMassL1 = 256;         // first-level mass reduction width
+constexpr int kWallOut = 10;         // u_wm[3], S[6], sigma per wall slot
+
+// Tag byte of a cell: bits 0-3 tag, bit 6 = covered by a rotor, bit 7 = wall cell.
+constexpr uint8_t kTagMask = 0x0f;
+constexpr uint8_t kRotorBit = 0x40;
+constexpr uint8_t kWallBit = 0x80;
+
+struct RotorDev {
+  double c[3], e[3], e1[3], e2[3];
+  double R, r_hub, chord, thick, tw_root, tw_tip, omega, phase0;
+  int32_t nb, tag;
+  int32_t b0[3], bn[3];   // bounding box origin and extent (cells)
+  int64_t off;            // first slot of this box in the box pools
+  int64_t cells;          // bn[0]*bn[1]*bn[2]
+};
+
+struct RotorTable {
+  int32_t n;
+  int32_t tag2rot[kTags];  // rotor index of a tag, -1 if none
+  RotorDev r[kMaxRotors];
+  double frame[kTags][6];  // per tag: torque centre, axis
+};
+
+struct Model {
+  double tau0;
+  double smag;         // 18 sqrt(2) C_S^2 (coefficient of the Smagorinsky root)
+  double eps_h;
+  int32_t transition, wall_model;
+  double E, kappa, y_s, tol, nu;
+  int32_t maxit, pad;
+  double u_in[3];
+  double turb_amp;     // turb_I * |u_in|
+  uint64_t seed;
+};
+
+struct Geometry {
+  int32_t nx, ny, nz, bc_x;
+  int64_t N;
+  int64_t stride;      // elements between population arrays
+};
+
+}  // namespace hlbm

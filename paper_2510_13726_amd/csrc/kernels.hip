@@ -1,0 +1,845 @@
+// HIP kernels of libhlbm for gfx950 (CDNA4, wave64).
+//
+//  k_rasterize  rotor porosity embedding on the rotors' fixed bounding boxes
+//  k_wall       wall model on the wall cells (probe interpolation, Newton)
+//  k_sweep      fused pull-stream + moments + HLBM collision + store, with
+//               per-tag force/torque partials on FSI workgroups
+//  k_finalize   deterministic reduction of the partials into the history
+// plus initialisation, conversion and bookkeeping kernels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "hlbm_internal.h"
+#include "launch.h"
+#include "lbm_cell.h"
+
+namespace hlbm {
+
+// ================================================================ helpers
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// XCD-aware workgroup order: the hardware deals consecutive workgroup ids
+// round-robin to the 8 XCDs; give each XCD a contiguous run of the domain so
+// that the cache lines shared by neighbouring workgroups stay in one L2.
+__device__ __forceinline__ int64_t remap_block(int64_t bid, int64_t nb, int32_t on) {
+  if (!on) return bid;
+  const int64_t q = nb >> 3;
+  if (bid >= (q << 3)) return bid;
+  return (bid & 7) * q + (bid >> 3);
+}
+
+// Pre-collision deviations h_i = f_i - w_i of cell (x, y, z):
+// f_i(x) = f*_i(x - c_i) with periodic y, z; in x periodic, or the
+// equilibrium inflow ghost plane at x = -1 (precomputed for the step in
+// `ghost`, [9][nz][ny] for the velocities with c_x = +1) and the
+// zero-gradient copy at x = nx.
+template <class ST, class CT, bool kPeriodicX>
+__device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geometry& g, int x, int y, int z,
+                                          const CT* __restrict__ ghost, CT h[27]) {
+  const uint32_t nx = g.nx, nxy = uint32_t(g.nx) * uint32_t(g.ny);
+  const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
+  const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
+  int xp, xm;
+  if (kPeriodicX) {
+    xp = x + 1 == g.nx ? 0 : x + 1;
+    xm = x == 0 ? g.nx - 1 : x - 1;
+  } else {
+    xp = x + 1 == g.nx ? x : x + 1;  // outflow: copy of the last plane
+    xm = x == 0 ? 0 : x - 1;         // inflow plane is replaced below
+  }
+  // source of velocity c is x - c: c = -1 -> +1 neighbour, c = +1 -> -1 neighbour
+  const uint32_t oz[3] = {uint32_t(zp) * nxy, uint32_t(z) * nxy, uint32_t(zm) * nxy};
+  const uint32_t oy[3] = {uint32_t(yp) * nx, uint32_t(y) * nx, uint32_t(ym) * nx};
+  const uint32_t ox[3] = {uint32_t(xp), uint32_t(x), uint32_t(xm)};
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const ST* p = src + int64_t(i) * g.stride;
+    const uint32_t o = oz[cz_of(i) + 1] + oy[cy_of(i) + 1] + ox[cx_of(i) + 1];
+    h[i] = CT(w_of(i)) * Store<ST>::template load<CT>(p + o);
+  }
+  if (!kPeriodicX && x == 0) {
+    const uint32_t pz[3] = {uint32_t(zp) * g.ny, uint32_t(z) * g.ny, uint32_t(zm) * g.ny};
+    const uint32_t py[3] = {uint32_t(yp), uint32_t(y), uint32_t(ym)};
+    const int64_t plane = int64_t(g.ny) * g.nz;
+#pragma unroll
+    for (int i = 18; i < 27; ++i) h[i] = ghost[(i - 18) * plane + pz[cz_of(i) + 1] + py[cy_of(i) + 1]];
+  }
+}
+
+// Inflow ghost plane of step n: h_i = f^eq_i(1, u_in(n, y, z)) - w_i for the
+// nine velocities with c_x = +1, u_in = U + I |U| xi with seeded normals xi.
+template <class CT>
+__global__ __launch_bounds__(256) void k_inflow(Geometry g, Model m, int64_t n, CT* __restrict__ ghost) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t plane = int64_t(g.ny) * g.nz;
+  if (k >= plane) return;
+  const int z = int(k / g.ny), y = int(k - int64_t(z) * g.ny);
+  double u[3] = {m.u_in[0], m.u_in[1], m.u_in[2]};
+  if (m.turb_amp != 0.0)
+    for (int a = 0; a < 3; ++a) u[a] += m.turb_amp * inflow_normal(m.seed, n, y, z, a, g.ny, g.nz);
+  CT ge[27];
+  equilibrium_dev_unit<CT>(CT(u[0]), CT(u[1]), CT(u[2]), ge);
+#pragma unroll
+  for (int i = 18; i < 27; ++i) ghost[(i - 18) * plane + k] = CT(w_of(i)) * ge[i];
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ================================================================ geometry
+struct RotorPhi {
+  double phi;
+  double grad[3];
+};
+
+// Signed distance (positive inside) of a rotor at step n: hub sphere united
+// with flat-plate blades (box in blade coordinates r, chord s, thickness h;
+// pitch beta(r) linear from root to tip), and its gradient.
+__device__ RotorPhi rotor_phi(const RotorDev& r, double x, double y, double z, int64_t n) {
+  RotorPhi o;
+  const double rel[3] = {x - r.c[0], y - r.c[1], z - r.c[2]};
+  const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
+  o.phi = r.r_hub - dist;
+  for (int a = 0; a < 3; ++a) o.grad[a] = dist > 0 ? -rel[a] / dist : 0.0;
+  const double ax = rel[0] * r.e[0] + rel[1] * r.e[1] + rel[2] * r.e[2];
+  const double span = r.R - r.r_hub;
+  for (int b = 0; b < r.nb; ++b) {
+    const double th = r.phase0 + r.omega * double(n) + 6.283185307179586476925286766559 * double(b) / double(r.nb);
+    double st, ct;
+    sincos(th, &st, &ct);
+    double er[3], ep[3];
+    for (int a = 0; a < 3; ++a) {
+      er[a] = ct * r.e1[a] + st * r.e2[a];
+      ep[a] = -st * r.e1[a] + ct * r.e2[a];
+    }
+    const double rr = rel[0] * er[0] + rel[1] * er[1] + rel[2] * er[2];
+    const double qq = rel[0] * ep[0] + rel[1] * ep[1] + rel[2] * ep[2];
+    double frac = (rr - r.r_hub) / span, dbeta = 0.0;
+    if (frac <= 0.0) frac = 0.0;
+    else if (frac >= 1.0) frac = 1.0;
+    else dbeta = (r.tw_tip - r.tw_root) / span;
+    const double beta = r.tw_root + (r.tw_tip - r.tw_root) * frac;
+    double sb, cb;
+    sincos(beta, &sb, &cb);
+    const double p[3] = {rr - 0.5 * (r.R + r.r_hub), -cb * qq + sb * ax, cb * ax + sb * qq};
+    const double half[3] = {0.5 * span, 0.5 * r.chord, 0.5 * r.thick};
+    double q[3], qp[3], qn2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      q[k] = fabs(p[k]) - half[k];
+      qp[k] = q[k] > 0 ? q[k] : 0.0;
+      qn2 += qp[k] * qp[k];
+    }
+    int km = 0;
+    if (q[1] > q[km]) km = 1;
+    if (q[2] > q[km]) km = 2;
+    const double phi = -(sqrt(qn2) + (q[km] < 0 ? q[km] : 0.0));
+    if (phi > o.phi) {
+      o.phi = phi;
+      double gp[3] = {0.0, 0.0, 0.0};
+      if (qn2 > 0) {
+        const double qn = sqrt(qn2);
+        for (int k = 0; k < 3; ++k) gp[k] = (p[k] >= 0 ? 1.0 : -1.0) * qp[k] / qn;
+      } else {
+        gp[km] = p[km] >= 0 ? 1.0 : -1.0;
+      }
+      const double gs = dbeta * (sb * qq + cb * ax);
+      const double gh = dbeta * (-sb * ax + cb * qq);
+      for (int a = 0; a < 3; ++a) {
+        const double ds = -cb * ep[a] + sb * r.e[a] + gs * er[a];
+        const double dh = cb * r.e[a] + sb * ep[a] + gh * er[a];
+        o.grad[a] = -(gp[0] * er[a] + gp[1] * ds + gp[2] * dh);
+      }
+    }
+  }
+  return o;
+}
+
+// Lattice porosity of a signed distance (Def. Lattice Porosity).
+__device__ __forceinline__ double transition(double phi, double eps, int kind) {
+  if (phi <= -0.5 * eps) return 0.0;
+  if (phi >= 0.5 * eps) return 1.0;
+  if (kind == 1) return phi / eps + 0.5;
+  return 0.5 * (1.0 + tanh(4.0 * phi / eps) / tanh(2.0));
+}
+
+__device__ __forceinline__ int rotor_of_slot(const RotorTable& rt, int64_t s) {
+  int k = 0;
+  for (int j = 1; j < rt.n; ++j)
+    if (s >= rt.r[j].off) k = j;
+  return k;
+}
+
+__device__ __forceinline__ void slot_cell(const RotorDev& r, int64_t s, int& x, int& y, int& z) {
+  const int64_t l = s - r.off;
+  const int64_t pl = int64_t(r.bn[0]) * r.bn[1];
+  z = r.b0[2] + int(l / pl);
+  const int64_t rem = l - int64_t(z - r.b0[2]) * pl;
+  y = r.b0[1] + int(rem / r.bn[0]);
+  x = r.b0[0] + int(rem - int64_t(y - r.b0[1]) * r.bn[0]);
+}
+
+__device__ __forceinline__ bool in_box(const RotorDev& r, int x, int y, int z) {
+  return x >= r.b0[0] && x < r.b0[0] + r.bn[0] && y >= r.b0[1] && y < r.b0[1] + r.bn[1] && z >= r.b0[2] &&
+         z < r.b0[2] + r.bn[2];
+}
+
+// ---------------------------------------------------------------- rasterize
+template <class CT>
+__global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict__ rtp, Geometry g, Model m, int64_t n,
+                                                   int64_t total, const CT* __restrict__ d_static,
+                                                   const uint8_t* __restrict__ tag_static, const CT* __restrict__ dd,
+                                                   CT* __restrict__ d_eff, uint8_t* __restrict__ tag,
+                                                   double* __restrict__ geo) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= total) return;
+  const RotorTable& rt = *rtp;
+  const int k = rotor_of_slot(rt, s);
+  int x, y, z;
+  slot_cell(rt.r[k], s, x, y, z);
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+  double best = -1e300, gr[3] = {0, 0, 0};
+  int br = -1;
+  for (int j = 0; j < rt.n; ++j) {
+    if (!in_box(rt.r[j], x, y, z)) continue;
+    RotorPhi p = rotor_phi(rt.r[j], double(x), double(y), double(z), n);
+    if (p.phi > best) {
+      best = p.phi;
+      br = j;
+      gr[0] = p.grad[0]; gr[1] = p.grad[1]; gr[2] = p.grad[2];
+    }
+  }
+  const double drot = br >= 0 ? transition(best, m.eps_h, m.transition) : 0.0;
+  const double ds = double(d_static[c]);
+  const double base = ds > drot ? ds : drot;
+  d_eff[c] = CT(base) + (dd ? dd[c] : CT(0));
+  const double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+  uint8_t tb;
+  if (drot > 0.0) {
+    tb = uint8_t(rt.r[br].tag) | kRotorBit;
+    if (m.wall_model && best > -0.5 * m.eps_h && best < 0.0 && gn > 0) tb |= kWallBit;
+  } else {
+    tb = tag_static[c];
+  }
+  tag[c] = tb;
+  geo[s] = best;
+  const double inv = gn > 0 ? 1.0 / gn : 0.0;
+  geo[total + s] = -gr[0] * inv;
+  geo[2 * total + s] = -gr[1] * inv;
+  geo[3 * total + s] = -gr[2] * inv;
+}
+
+// ---------------------------------------------------------------- wall model
+__device__ __forceinline__ double spalding_bracket(double k) {
+  const double ek = k > 80.0 ? exp(80.0) : exp(k);
+  return ek - 1.0 - k - k * k * 0.5 - k * k * k / 6.0;
+}
+__device__ __forceinline__ double spalding_dbracket(double k) {
+  const double ek = k > 80.0 ? 0.0 : exp(k);
+  return ek - 1.0 - k - k * k * 0.5;
+}
+
+// Newton iteration of Sec. 2.2.1 (stop when |f(u^{j+1}) - f(u^j)| < tol or
+// after maxit steps, halving a non-positive iterate).
+template <class F>
+__device__ __forceinline__ double newton(double u, F&& fdf, double tol, int maxit, int& iters) {
+  double fu, du;
+  fdf(u, fu, du);
+  int it = 0;
+  for (; it < maxit; ++it) {
+    double un = u - fu / du;
+    if (un <= 0.0) un = 0.5 * u;
+    double fn, dn;
+    fdf(un, fn, dn);
+    const bool done = fabs(fn - fu) < tol;
+    u = un;
+    fu = fn;
+    du = dn;
+    if (done) {
+      ++it;
+      break;
+    }
+  }
+  iters = it;
+  return u;
+}
+
+template <class ST, class CT, bool kPeriodicX>
+__global__ __launch_bounds__(128) void k_wall(const RotorTable* __restrict__ rtp, Geometry g, Model m, int64_t n,
+                                              int64_t total, const ST* __restrict__ src,
+                                              const uint8_t* __restrict__ tag, const double* __restrict__ geo,
+                                              const double* __restrict__ ut_prev, const uint8_t* __restrict__ act_prev,
+                                              double* __restrict__ ut_new, uint8_t* __restrict__ act_new,
+                                              CT* __restrict__ wall_out, unsigned long long* __restrict__ stats,
+                                              const double* __restrict__ ghost) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= total) return;
+  const RotorTable& rt = *rtp;
+  const int k = rotor_of_slot(rt, s);
+  const RotorDev& R = rt.r[k];
+  int x, y, z;
+  slot_cell(R, s, x, y, z);
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+  const uint8_t tb = tag[c];
+  if (!(tb & kWallBit) || (tb & kTagMask) != R.tag) {
+    act_new[s] = 0;
+    return;
+  }
+  const double y1 = -geo[s];
+  const double nn[3] = {geo[total + s], geo[2 * total + s], geo[3 * total + s]};
+  const double X[3] = {double(x), double(y), double(z)};
+  double xw[3], xs[3];
+  for (int a = 0; a < 3; ++a) {
+    xw[a] = X[a] - y1 * nn[a];
+    xs[a] = xw[a] + m.y_s * nn[a];
+  }
+  const double rw[3] = {xw[0] - R.c[0], xw[1] - R.c[1], xw[2] - R.c[2]};
+  const double uw[3] = {R.omega * (R.e[1] * rw[2] - R.e[2] * rw[1]), R.omega * (R.e[2] * rw[0] - R.e[0] * rw[2]),
+                        R.omega * (R.e[0] * rw[1] - R.e[1] * rw[0])};
+  // trilinear sample of the pre-collision fluid velocity at the probe
+  int i0[3];
+  double fr[3];
+  for (int a = 0; a < 3; ++a) {
+    const double fl = floor(xs[a]);
+    i0[a] = int(fl);
+    fr[a] = xs[a] - fl;
+  }
+  double us[3] = {0.0, 0.0, 0.0};
+  for (int corner = 0; corner < 8; ++corner) {
+    int q[3];
+    double wgt = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      const int bit = (corner >> a) & 1;
+      q[a] = i0[a] + bit;
+      wgt *= bit ? fr[a] : 1.0 - fr[a];
+    }
+    q[1] = ((q[1] % g.ny) + g.ny) % g.ny;
+    q[2] = ((q[2] % g.nz) + g.nz) % g.nz;
+    if (kPeriodicX) q[0] = ((q[0] % g.nx) + g.nx) % g.nx;
+    else q[0] = q[0] < 0 ? 0 : (q[0] > g.nx - 1 ? g.nx - 1 : q[0]);
+    double h[27];
+    pull_cell<ST, double, kPeriodicX>(src, g, q[0], q[1], q[2], ghost, h);
+    const Moments<double> mo = moments_of<double>(h);
+    const double rho = 1.0 + mo.drho;
+    us[0] += wgt * (mo.jx / rho);
+    us[1] += wgt * (mo.jy / rho);
+    us[2] += wgt * (mo.jz / rho);
+  }
+  double v[3] = {us[0] - uw[0], us[1] - uw[1], us[2] - uw[2]};
+  const double vn = v[0] * nn[0] + v[1] * nn[1] + v[2] * nn[2];
+  double vt[3] = {v[0] - vn * nn[0], v[1] - vn * nn[1], v[2] - vn * nn[2]};
+  const double U = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
+  const int64_t T = total;
+  if (!(U >= 1e-10)) {
+    for (int q = 0; q < 9; ++q) wall_out[q * T + s] = CT(0);
+    wall_out[9 * T + s] = CT(1);
+    act_new[s] = 0;
+    return;
+  }
+  const double t[3] = {vt[0] / U, vt[1] / U, vt[2] / U};
+  const double nu = m.nu, ys = m.y_s, E = m.E, kap = m.kappa;
+  const double guess = act_prev[s] ? ut_prev[s] : sqrt(nu * U / ys);
+  int it1 = 0, it2 = 0;
+  const double ut = newton(
+      guess,
+      [&](double u, double& f, double& df) {
+        const double p = U / u;
+        f = p + spalding_bracket(kap * p) / E - ys * u / nu;
+        df = -(p / u) * (1.0 + kap * spalding_dbracket(kap * p) / E) - ys / nu;
+      },
+      m.tol, m.maxit, it1);
+  const double yp = y1 * ut / nu;
+  const double ulog = log(E * (yp > 1.0 ? yp : 1.0)) / kap;
+  const double up = newton(
+      ulog < yp ? ulog : yp,
+      [&](double u, double& f, double& df) {
+        f = u + spalding_bracket(kap * u) / E - yp;
+        df = 1.0 + kap * spalding_dbracket(kap * u) / E;
+      },
+      m.tol, m.maxit, it2);
+  const double qv = ut * up;
+  const double dudn = (U - qv) / (ys - y1);
+  wall_out[0 * T + s] = CT(qv * t[0]);
+  wall_out[1 * T + s] = CT(qv * t[1]);
+  wall_out[2 * T + s] = CT(qv * t[2]);
+  wall_out[3 * T + s] = CT(0.5 * dudn * (t[0] * nn[0] + nn[0] * t[0]));
+  wall_out[4 * T + s] = CT(0.5 * dudn * (t[1] * nn[1] + nn[1] * t[1]));
+  wall_out[5 * T + s] = CT(0.5 * dudn * (t[2] * nn[2] + nn[2] * t[2]));
+  wall_out[6 * T + s] = CT(0.5 * dudn * (t[0] * nn[1] + nn[0] * t[1]));
+  wall_out[7 * T + s] = CT(0.5 * dudn * (t[0] * nn[2] + nn[0] * t[2]));
+  wall_out[8 * T + s] = CT(0.5 * dudn * (t[1] * nn[2] + nn[1] * t[2]));
+  wall_out[9 * T + s] = CT(0);
+  ut_new[s] = ut;
+  act_new[s] = 1;
+  atomicAdd(&stats[0], (unsigned long long)it1);
+  atomicAdd(&stats[1], 1ull);
+}
+
+// ================================================================ fused sweep
+template <class CT>
+struct SweepArgs {
+  const void* src;
+  void* dst;
+  Geometry g;
+  Model m;
+  const int32_t* blk_slot;
+  const CT* d_eff;
+  const uint8_t* tag;
+  const CT* wall_out;
+  int64_t bbox_total;
+  const RotorTable* rot;
+  const CT* uB_static;
+  double* partial;
+  double* mass_part;
+  int32_t* flag;
+  const CT* ghost;
+  int64_t step;
+  int64_t nblocks;
+  int32_t remap;
+  CT* out_rho;
+  CT* out_u;
+  CT* out_uhat;
+};
+
+// One workgroup = kBlock consecutive cells.  Every cell pulls its 27
+// populations, forms the moments, collides and writes its 27 post-collision
+// values (kMoments: writes rho, u, u_hat instead).  Workgroups that touch a
+// porous region (blk_slot >= 0) read porosity and tags, apply the
+// homogenized velocity and the wall model outputs and reduce the momentum
+// handed to each tag; the others run the plain bulk collision.
+template <class ST, class CT, bool kPeriodicX, bool kMoments>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
+  const Geometry& g = a.g;
+  const int64_t blk = remap_block(blockIdx.x, a.nblocks, a.remap);
+  const int64_t c = blk * kBlock + threadIdx.x;
+  const bool valid = c < g.N;
+  const uint32_t cc = valid ? uint32_t(c) : 0u;
+  const uint32_t nxy = uint32_t(g.nx) * uint32_t(g.ny);
+  const int z = int(cc / nxy);
+  const uint32_t r = cc - uint32_t(z) * nxy;
+  const int y = int(r / uint32_t(g.nx));
+  const int x = int(r - uint32_t(y) * uint32_t(g.nx));
+
+  CT h[27];
+  pull_cell<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+  const Moments<CT> mo = moments_of<CT>(h);
+  const CT rho = CT(1) + mo.drho;
+  const CT irho = CT(1) / rho;
+  const CT ux = mo.jx * irho, uy = mo.jy * irho, uz = mo.jz * irho;
+  const CT tau0 = CT(a.m.tau0), smag = CT(a.m.smag);
+
+  const int32_t slot = a.blk_slot[blk];
+  CT g2[27];
+  __shared__ double lds[4][kPartial];
+  if (slot < 0) {
+    if (kMoments) {
+      if (valid) {
+        a.out_rho[c] = rho;
+        a.out_u[c] = ux; a.out_u[g.N + c] = uy; a.out_u[2 * g.N + c] = uz;
+        if (a.out_uhat) { a.out_uhat[c] = ux; a.out_uhat[g.N + c] = uy; a.out_uhat[2 * g.N + c] = uz; }
+      }
+      return;
+    }
+    const CT S0[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)};
+    collide<CT, false>(mo, rho, ux, uy, uz, CT(1), S0, tau0, smag, g2);
+  } else {
+    CT d = CT(0);
+    uint8_t tb = 0;
+    if (valid) {
+      d = a.d_eff[c];
+      tb = a.tag[c];
+    }
+    const int t = tb & kTagMask;
+    CT bx = CT(0), by = CT(0), bz = CT(0);
+    const RotorTable& rt = *a.rot;
+    int rk = -1;
+    if (tb & kRotorBit) {
+      rk = rt.tag2rot[t];
+      const RotorDev& R = rt.r[rk];
+      const double rx = x - R.c[0], ry = y - R.c[1], rz = z - R.c[2];
+      bx = CT(R.omega * (R.e[1] * rz - R.e[2] * ry));
+      by = CT(R.omega * (R.e[2] * rx - R.e[0] * rz));
+      bz = CT(R.omega * (R.e[0] * ry - R.e[1] * rx));
+    } else if (a.uB_static && valid) {
+      bx = a.uB_static[c]; by = a.uB_static[g.N + c]; bz = a.uB_static[2 * g.N + c];
+    }
+    CT S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)};
+    CT sigma = CT(1);
+    if (tb & kWallBit) {
+      const RotorDev& R = rt.r[rk];
+      const int64_t ws = R.off + (int64_t(z - R.b0[2]) * R.bn[1] + (y - R.b0[1])) * R.bn[0] + (x - R.b0[0]);
+      const int64_t T = a.bbox_total;
+      bx += a.wall_out[ws];
+      by += a.wall_out[T + ws];
+      bz += a.wall_out[2 * T + ws];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) S[q] = a.wall_out[(3 + q) * T + ws];
+      sigma = a.wall_out[9 * T + ws];
+    }
+    const CT hx = ux + d * (bx - ux), hy = uy + d * (by - uy), hz = uz + d * (bz - uz);
+    if (kMoments) {
+      if (valid) {
+        a.out_rho[c] = rho;
+        a.out_u[c] = ux; a.out_u[g.N + c] = uy; a.out_u[2 * g.N + c] = uz;
+        if (a.out_uhat) { a.out_uhat[c] = hx; a.out_uhat[g.N + c] = hy; a.out_uhat[2 * g.N + c] = hz; }
+      }
+      return;
+    }
+    collide<CT, true>(mo, rho, hx, hy, hz, sigma, S, tau0, smag, g2);
+    // momentum handed to the solid and its torque, per tag (FP64)
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (t != 0 && valid) {
+      const double px = double(mo.jx - rho * hx), py = double(mo.jy - rho * hy), pz = double(mo.jz - rho * hz);
+      const double* fr = rt.frame[t];
+      const double rx = x - fr[0], ry = y - fr[1], rz = z - fr[2];
+      v[0] = px; v[1] = py; v[2] = pz;
+      v[3] = ry * pz - rz * py;
+      v[4] = rz * px - rx * pz;
+      v[5] = rx * py - ry * px;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = threadIdx.x; q < 4 * kPartial; q += kBlock) (&lds[0][0])[q] = 0.0;
+    __syncthreads();
+    const int tt = (t != 0 && valid) ? t : 0;
+    uint64_t pending = __ballot(tt != 0);
+    while (pending) {
+      const int l0 = __ffsll((long long)pending) - 1;
+      const int cur = __shfl(tt, l0, 64);
+      const bool mine = tt == cur;
+      double s6[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) s6[q] = wave_sum(mine ? v[q] : 0.0);
+      if (lane == 0)
+        for (int q = 0; q < 6; ++q) lds[wv][cur * 6 + q] = s6[q];
+      pending &= ~__ballot(mine);
+    }
+    __syncthreads();
+    if (threadIdx.x < kPartial) {
+      const int q = threadIdx.x;
+      a.partial[int64_t(slot) * kPartial + q] = (lds[0][q] + lds[1][q]) + (lds[2][q] + lds[3][q]);
+    }
+  }
+  if (!kMoments) {
+    if (valid) {
+      ST* dst = static_cast<ST*>(a.dst);
+#pragma unroll
+      for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(dst + int64_t(i) * g.stride + c, g2[i]);
+    }
+    if (a.mass_part) {
+      const double mrho = valid ? double(rho) : 0.0;
+      if (valid && !(mrho == mrho && fabs(mrho) < 1e300)) atomicOr(a.flag, 1);
+      const double ws = wave_sum(mrho);
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) lds[0][threadIdx.x >> 6] = ws;
+      __syncthreads();
+      if (threadIdx.x == 0) a.mass_part[blk] = (lds[0][0] + lds[0][1]) + (lds[0][2] + lds[0][3]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+__global__ __launch_bounds__(256) void k_mass_l1(const double* __restrict__ part, int64_t nb,
+                                                 double* __restrict__ out) {
+  __shared__ double s[256];
+  const int64_t per = (nb + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = int64_t(blockIdx.x) * per, hi = lo + per < nb ? lo + per : nb;
+  double acc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += part[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(128) void k_finalize(const double* __restrict__ partial, int32_t nslots,
+                                                  const double* __restrict__ mass_l1, int diag,
+                                                  double* __restrict__ rec) {
+  const int q = threadIdx.x;
+  if (q < 90) {
+    const int k = 6 + q;  // tags 1..15
+    double acc = 0.0;
+    for (int32_t sl = 0; sl < nslots; ++sl) acc += partial[int64_t(sl) * kPartial + k];
+    rec[1 + q] = acc;
+  } else if (q == 127) {
+    if (diag) {
+      double acc = 0.0;
+      for (int i = 0; i < kMassL1; ++i) acc += mass_l1[i];
+      rec[0] = acc;
+    } else {
+      rec[0] = __builtin_nan("");
+    }
+  }
+}
+
+// ---------------------------------------------------------------- state I/O
+template <class ST, class CT>
+__global__ __launch_bounds__(256) void k_init_eq(ST* __restrict__ dst, Geometry g, const CT* __restrict__ rho,
+                                                 const CT* __restrict__ u) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const CT r = rho ? rho[c] : CT(1);
+  const CT ux = u ? u[c] : CT(0), uy = u ? u[g.N + c] : CT(0), uz = u ? u[2 * g.N + c] : CT(0);
+  CT ge[27];
+  equilibrium_dev<CT>(r, ux, uy, uz, ge);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(dst + int64_t(i) * g.stride + c, ge[i]);
+}
+
+template <class ST>
+__global__ __launch_bounds__(256) void k_get_pop(const ST* __restrict__ src, Geometry g, double* __restrict__ dst) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+#pragma unroll
+  for (int i = 0; i < 27; ++i)
+    dst[int64_t(i) * g.N + c] = w_of(i) * Store<ST>::template load<double>(src + int64_t(i) * g.stride + c);
+}
+
+template <class ST>
+__global__ __launch_bounds__(256) void k_set_pop(ST* __restrict__ dst, Geometry g, const double* __restrict__ src) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+#pragma unroll
+  for (int i = 0; i < 27; ++i)
+    Store<ST>::template store<double>(dst + int64_t(i) * g.stride + c, src[int64_t(i) * g.N + c] / w_of(i));
+}
+
+template <class ST>
+__global__ __launch_bounds__(256) void k_get_pop_at(const ST* __restrict__ src, Geometry g,
+                                                    const int64_t* __restrict__ cells, int64_t count,
+                                                    double* __restrict__ dst) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const int64_t c = cells[k];
+  if (c < 0 || c >= g.N) {
+    for (int i = 0; i < 27; ++i) dst[k * 27 + i] = __builtin_nan("");
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 27; ++i) dst[k * 27 + i] = w_of(i) * Store<ST>::template load<double>(src + int64_t(i) * g.stride + c);
+}
+
+template <class ST>
+__global__ __launch_bounds__(256) void k_fill_rest(ST* __restrict__ dst, Geometry g) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) Store<ST>::template store<double>(dst + int64_t(i) * g.stride + c, 0.0);
+}
+
+// FSI workgroups: any cell in a rotor box, or with static porosity, tag or control.
+template <class CT>
+__global__ __launch_bounds__(256) void k_mark(const RotorTable* __restrict__ rtp, Geometry g,
+                                              const CT* __restrict__ d_static, const uint8_t* __restrict__ tag_static,
+                                              const CT* __restrict__ dd, int32_t* __restrict__ blk) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int64_t nxy = int64_t(g.nx) * g.ny;
+  const int z = int(c / nxy);
+  const int64_t r = c - int64_t(z) * nxy;
+  const int y = int(r / g.nx), x = int(r - int64_t(y) * g.nx);
+  bool fsi = d_static[c] != CT(0) || tag_static[c] != 0 || (dd && dd[c] != CT(0));
+  const RotorTable& rt = *rtp;
+  for (int j = 0; j < rt.n && !fsi; ++j) fsi = in_box(rt.r[j], x, y, z);
+  if (fsi) blk[c / kBlock] = 1;
+}
+
+// d_eff = d_static + control everywhere (rotor boxes are overwritten each step),
+// tag = static tag.
+template <class CT>
+__global__ __launch_bounds__(256) void k_refill(Geometry g, const CT* __restrict__ d_static,
+                                                const uint8_t* __restrict__ tag_static, const CT* __restrict__ dd,
+                                                CT* __restrict__ d_eff, uint8_t* __restrict__ tag) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  d_eff[c] = d_static[c] + (dd ? dd[c] : CT(0));
+  tag[c] = tag_static[c];
+}
+
+// ================================================================ launchers
+static inline dim3 grid1(int64_t n, int b) { return dim3(unsigned((n + b - 1) / b)); }
+
+template <class F>
+static hipError_t by_types(int storage, int compute, F&& f) {
+  if (compute == 0 && storage == 0) return f((double*)nullptr, (double*)nullptr);
+  if (compute == 1 && storage == 1) return f((float*)nullptr, (float*)nullptr);
+  if (compute == 1 && storage == 2) return f((_Float16*)nullptr, (float*)nullptr);
+  if (compute == 1 && storage == 3) return f((bf16_t*)nullptr, (float*)nullptr);
+  return hipErrorInvalidValue;
+}
+
+template <class F>
+static hipError_t by_compute(int compute, F&& f) {
+  if (compute == 0) return f((double*)nullptr);
+  if (compute == 1) return f((float*)nullptr);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rasterize(const Launch& L, int64_t step) {
+  if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
+  return by_compute(L.compute, [&](auto* ct) {
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    hipLaunchKernelGGL(k_rasterize<CT>, grid1(L.bbox_total, 256), dim3(256), 0, L.stream, L.rot, L.g, L.m, step,
+                       L.bbox_total, (const CT*)L.d_static, L.tag_static, (const CT*)L.dd, (CT*)L.d_eff, L.tag,
+                       L.geo);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
+                       double* ut_new, uint8_t* act_new, int64_t step) {
+  if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    if (L.g.bc_x == 0)
+      hipLaunchKernelGGL((k_wall<ST, CT, true>), grid1(L.bbox_total, 128), dim3(128), 0, L.stream, L.rot, L.g, L.m,
+                         step, L.bbox_total, (const ST*)src, L.tag, L.geo, ut_prev, act_prev, ut_new, act_new,
+                         (CT*)L.wall_out, L.stats, L.ghost64);
+    else
+      hipLaunchKernelGGL((k_wall<ST, CT, false>), grid1(L.bbox_total, 128), dim3(128), 0, L.stream, L.rot, L.g, L.m,
+                         step, L.bbox_total, (const ST*)src, L.tag, L.geo, ut_prev, act_prev, ut_new, act_new,
+                         (CT*)L.wall_out, L.stats, L.ghost64);
+    return hipGetLastError();
+  });
+}
+
+template <class CT>
+static SweepArgs<CT> sweep_args(const Launch& L, const void* src, void* dst, int64_t step) {
+  SweepArgs<CT> a{};
+  a.src = src; a.dst = dst; a.g = L.g; a.m = L.m;
+  a.blk_slot = L.blk_slot; a.d_eff = (const CT*)L.d_eff; a.tag = L.tag;
+  a.wall_out = (const CT*)L.wall_out; a.bbox_total = L.bbox_total; a.rot = L.rot;
+  a.uB_static = (const CT*)L.uB_static; a.partial = L.partial; a.mass_part = nullptr; a.flag = L.flag;
+  a.step = step; a.nblocks = L.nblocks; a.remap = L.xcd_remap;
+  a.ghost = (const CT*)L.ghost;
+  return a;
+}
+
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag) {
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    SweepArgs<CT> a = sweep_args<CT>(L, src, dst, step);
+    if (diag) a.mass_part = L.mass_part;
+    if (L.g.bc_x == 0)
+      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+    else
+      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* rho, void* u, void* uhat) {
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    SweepArgs<CT> a = sweep_args<CT>(L, src, nullptr, step);
+    a.remap = 0;
+    a.out_rho = (CT*)rho; a.out_u = (CT*)u; a.out_uhat = (CT*)uhat;
+    if (L.g.bc_x == 0)
+      hipLaunchKernelGGL((k_sweep<ST, CT, true, true>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+    else
+      hipLaunchKernelGGL((k_sweep<ST, CT, false, true>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_inflow(const Launch& L, int64_t step) {
+  if (L.g.bc_x == 0) return hipSuccess;
+  const int64_t plane = int64_t(L.g.ny) * L.g.nz;
+  hipError_t e = by_compute(L.compute, [&](auto* ct) {
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    hipLaunchKernelGGL(k_inflow<CT>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, L.m, step, (CT*)L.ghost);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess || L.compute == 0 || L.nrot == 0) return e;
+  // the wall model samples in FP64
+  hipLaunchKernelGGL(k_inflow<double>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, L.m, step, L.ghost64);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag) {
+  if (diag) {
+    hipLaunchKernelGGL(k_mass_l1, dim3(kMassL1), dim3(256), 0, L.stream, L.mass_part, L.nblocks, L.mass_l1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  double* rec = L.hist + (step % L.hist_cap) * kHist;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(128), 0, L.stream, L.partial, nslots, L.mass_l1, diag ? 1 : 0, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, const void* u) {
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    hipLaunchKernelGGL((k_init_eq<ST, CT>), grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g,
+                       (const CT*)rho, (const CT*)u);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_get_populations(const Launch& L, const void* src, double* dst) {
+  return by_types(L.storage, L.compute, [&](auto* st, auto*) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    hipLaunchKernelGGL(k_get_pop<ST>, grid1(L.g.N, 256), dim3(256), 0, L.stream, (const ST*)src, L.g, dst);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_set_populations(const Launch& L, void* dst, const double* src) {
+  return by_types(L.storage, L.compute, [&](auto* st, auto*) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    hipLaunchKernelGGL(k_set_pop<ST>, grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g, src);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_get_populations_at(const Launch& L, const void* src, const int64_t* cells, int64_t count,
+                                     double* dst) {
+  if (count == 0) return hipSuccess;
+  return by_types(L.storage, L.compute, [&](auto* st, auto*) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    hipLaunchKernelGGL(k_get_pop_at<ST>, grid1(count, 256), dim3(256), 0, L.stream, (const ST*)src, L.g, cells,
+                       count, dst);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fill_rest(const Launch& L, void* dst) {
+  return by_types(L.storage, L.compute, [&](auto* st, auto*) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    hipLaunchKernelGGL(k_fill_rest<ST>, grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_mark_blocks(const Launch& L) {
+  hipError_t e = hipMemsetAsync(L.blk_slot, 0, sizeof(int32_t) * L.nblocks, L.stream);
+  if (e != hipSuccess) return e;
+  return by_compute(L.compute, [&](auto* ct) {
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    hipLaunchKernelGGL(k_mark<CT>, grid1(L.g.N, 256), dim3(256), 0, L.stream, L.rot, L.g, (const CT*)L.d_static,
+                       L.tag_static, (const CT*)L.dd, L.blk_slot);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_refill_porosity(const Launch& L) {
+  return by_compute(L.compute, [&](auto* ct) {
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    hipLaunchKernelGGL(k_refill<CT>, grid1(L.g.N, 256), dim3(256), 0, L.stream, L.g, (const CT*)L.d_static,
+                       L.tag_static, (const CT*)L.dd, (CT*)L.d_eff, L.tag);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace hlbm

@@ -1,0 +1,59 @@
+// Host-side launchers of the libhlbm kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hlbm_internal.h"
+
+namespace hlbm {
+
+// Everything a launch needs, with raw device pointers carved from the
+// caller's workspace.  Types of the typed fields follow storage / compute.
+struct Launch {
+  hipStream_t stream;
+  int storage, compute;      // hlbm_dtype values
+  Geometry g;
+  Model m;
+  int64_t nblocks;           // sweep workgroups = ceil(N / kBlock)
+  int32_t xcd_remap;
+  // fields
+  void* d_eff;
+  void* d_static;
+  uint8_t* tag;
+  uint8_t* tag_static;
+  void* uB_static;           // nullable
+  void* dd;                  // nullable
+  int32_t* blk_slot;
+  double* partial;
+  double* mass_part;
+  double* mass_l1;
+  int32_t* flag;
+  unsigned long long* stats; // [0] Newton iterations, [1] wall cells
+  RotorTable* rot;           // device copy
+  int32_t nrot;
+  int64_t bbox_total;
+  double* geo;               // [4][bbox_total]: phi, n
+  void* wall_out;            // [10][bbox_total] compute type
+  double* hist;
+  int64_t hist_cap;
+  void* ghost;               // inflow ghost plane [9][nz][ny], compute type
+  double* ghost64;           // same in FP64 for the wall model
+};
+
+hipError_t launch_rasterize(const Launch& L, int64_t step);
+hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
+                       double* ut_new, uint8_t* act_new, int64_t step);
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
+hipError_t launch_inflow(const Launch& L, int64_t step);
+hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag);
+hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* rho, void* u, void* uhat);
+hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, const void* u);
+hipError_t launch_get_populations(const Launch& L, const void* src, double* dst);
+hipError_t launch_set_populations(const Launch& L, void* dst, const double* src);
+hipError_t launch_get_populations_at(const Launch& L, const void* src, const int64_t* cells, int64_t count,
+                                     double* dst);
+hipError_t launch_mark_blocks(const Launch& L);
+hipError_t launch_refill_porosity(const Launch& L);
+hipError_t launch_fill_rest(const Launch& L, void* dst);
+
+}  // namespace hlbm

@@ -1,0 +1,320 @@
+"""Thin ctypes binding of libhlbm.so (argument marshalling only).
+
+Every step of the method runs in the library's HIP kernels; PyTorch only
+provides device memory and the stream.  The names follow the C ABI in
+include/hlbm.h.  Missing library -> ImportError/OSError, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhlbm.so")
+
+HLBM_OK, HLBM_ERR_INVALID, HLBM_ERR_HIP, HLBM_ERR_NONFINITE, HLBM_ERR_STATE = range(5)
+F64, F32, F16, BF16 = 0, 1, 2, 3
+BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
+WITH_SOLID_VELOCITY, WITH_CONTROL = 1, 2
+HIST_STRIDE = 91
+DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+
+
+class HlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hlbm error {code}: {msg}")
+        self.code = code
+
+
+class Desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("storage", C.c_int32),
+                ("compute", C.c_int32), ("bc_x", C.c_int32), ("flags", C.c_int32), ("pad0", C.c_int32),
+                ("bbox_cells", C.c_int64), ("history", C.c_int64), ("stream", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("tau0", C.c_double), ("cs_smag", C.c_double), ("eps_h", C.c_double),
+                ("transition", C.c_int32), ("wall_model", C.c_int32),
+                ("E", C.c_double), ("kappa", C.c_double), ("y_s", C.c_double), ("tol", C.c_double),
+                ("maxit", C.c_int32), ("diag_every", C.c_int32),
+                ("u_in", C.c_double * 3), ("turb_I", C.c_double), ("seed", C.c_uint64),
+                ("check_nonfinite", C.c_int32), ("pad0", C.c_int32)]
+
+
+class Rotor(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("axis", C.c_double * 3),
+                ("R", C.c_double), ("r_hub", C.c_double), ("chord", C.c_double), ("thick", C.c_double),
+                ("twist_root", C.c_double), ("twist_tip", C.c_double), ("omega", C.c_double),
+                ("phase0", C.c_double), ("n_blades", C.c_int32), ("tag", C.c_int32)]
+
+
+_lib = None
+_V = C.c_void_p
+_H = C.c_void_p
+
+# (name, restype, argtypes) of every entry point declared in include/hlbm.h
+SIGNATURES = [
+    ("hlbm_population_bytes", C.c_int64, [C.POINTER(Desc)]),
+    ("hlbm_workspace_bytes", C.c_int64, [C.POINTER(Desc)]),
+    ("hlbm_rotor_bbox_cells", C.c_int64, [C.POINTER(Desc), C.POINTER(Rotor), C.c_int32]),
+    ("hlbm_lattice_create", C.c_int, [C.POINTER(Desc), _V, _V, _V, C.POINTER(_H)]),
+    ("hlbm_lattice_destroy", None, [_H]),
+    ("hlbm_set_params", C.c_int, [_H, C.POINTER(Params)]),
+    ("hlbm_set_rotors", C.c_int, [_H, C.POINTER(Rotor), C.c_int32]),
+    ("hlbm_set_porosity_field", C.c_int, [_H, _V, _V]),
+    ("hlbm_set_solid_velocity", C.c_int, [_H, _V]),
+    ("hlbm_set_control", C.c_int, [_H, _V]),
+    ("hlbm_set_tag_frame", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("hlbm_init_equilibrium", C.c_int, [_H, _V, _V]),
+    ("hlbm_step", C.c_int, [_H, C.c_int64]),
+    ("hlbm_get_step", C.c_int64, [_H]),
+    ("hlbm_moments", C.c_int, [_H, _V, _V, _V]),
+    ("hlbm_get_populations", C.c_int, [_H, _V]),
+    ("hlbm_set_populations", C.c_int, [_H, _V]),
+    ("hlbm_get_populations_at", C.c_int, [_H, _V, C.c_int64, _V]),
+    ("hlbm_state_bytes", C.c_int64, [_H]),
+    ("hlbm_get_state", C.c_int, [_H, _V]),
+    ("hlbm_set_state", C.c_int, [_H, _V]),
+    ("hlbm_force_torque", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("hlbm_history", C.c_int, [_H, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
+    ("hlbm_wall_stats", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hlbm_last_error", C.c_char_p, [_H]),
+]
+
+
+def lib():
+    """Load libhlbm.so (built in-tree by __graft_entry__.build / build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_13726_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def make_params(p, diag_every=1, check_nonfinite=0) -> Params:
+    q = Params()
+    q.tau0, q.cs_smag, q.eps_h = p.tau0, p.cs_smag, p.eps_h
+    q.transition, q.wall_model = int(p.transition), int(p.wall_model)
+    q.E, q.kappa, q.y_s, q.tol, q.maxit = p.E, p.kappa, p.y_s, p.tol, int(p.maxit)
+    for a in range(3):
+        q.u_in[a] = p.u_in[a]
+    q.turb_I, q.seed = p.turb_I, int(p.seed)
+    q.diag_every, q.check_nonfinite = int(diag_every), int(check_nonfinite)
+    return q
+
+
+def make_rotor(r) -> Rotor:
+    o = Rotor()
+    for a in range(3):
+        o.center[a] = r.center[a]
+        o.axis[a] = r.axis[a]
+    o.R, o.r_hub, o.chord, o.thick = r.R, r.r_hub, r.chord, r.thick
+    o.twist_root, o.twist_tip, o.omega, o.phase0 = r.twist_root, r.twist_tip, r.omega, r.phase0
+    o.n_blades, o.tag = int(r.n_blades), int(r.tag)
+    return o
+
+
+def _rotor_array(rotors):
+    return (Rotor * max(1, len(rotors)))(*[make_rotor(r) for r in rotors])
+
+
+def make_desc(nx, ny, nz, storage=F32, compute=None, bc_x=BC_PERIODIC, flags=0, bbox_cells=0, history=1024,
+              stream=None) -> Desc:
+    d = Desc()
+    d.nx, d.ny, d.nz = nx, ny, nz
+    d.storage = storage
+    d.compute = compute if compute is not None else (F64 if storage == F64 else F32)
+    d.bc_x, d.flags = bc_x, flags
+    d.bbox_cells, d.history = int(bbox_cells), int(history)
+    d.stream = stream
+    return d
+
+
+class Lattice:
+    """A D3Q27 HLBM lattice on the current GPU.  Device memory (two population
+    buffers and the workspace) is held in torch uint8 tensors."""
+
+    def __init__(self, nx, ny, nz, storage="f32", bc_x=BC_PERIODIC, rotors: Sequence = (), flags=0,
+                 history=1024, device=None):
+        import torch
+        self.torch = torch
+        self.L = lib()
+        self.device = torch.device(device or "cuda")
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.N = nx * ny * nz
+        st = DTYPES[storage] if isinstance(storage, str) else storage
+        self.storage = st
+        self.compute = F64 if st == F64 else F32
+        self.ct = torch.float64 if self.compute == F64 else torch.float32
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream()
+        d = make_desc(nx, ny, nz, st, self.compute, bc_x, flags, 0, history, C.c_void_p(self.stream.cuda_stream))
+        if rotors:
+            arr = _rotor_array(rotors)
+            bb = self.L.hlbm_rotor_bbox_cells(C.byref(d), arr, len(rotors))
+            if bb < 0:
+                raise HlbmError(HLBM_ERR_INVALID, "rotor bounding boxes leave the domain")
+            d.bbox_cells = bb
+        self.desc = d
+        pb = self.L.hlbm_population_bytes(C.byref(d))
+        wb = self.L.hlbm_workspace_bytes(C.byref(d))
+        if pb < 0 or wb < 0:
+            raise HlbmError(HLBM_ERR_INVALID, "invalid lattice description")
+        self.pop_a = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self.pop_b = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        rc = self.L.hlbm_lattice_create(C.byref(d), C.c_void_p(self.pop_a.data_ptr()),
+                                        C.c_void_p(self.pop_b.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
+                                        C.byref(h))
+        if rc:
+            raise HlbmError(rc, self.L.hlbm_last_error(None).decode())
+        self.h = h
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, rc):
+        if rc:
+            raise HlbmError(rc, self.L.hlbm_last_error(self.h).decode())
+
+    def _dev(self, t, dtype=None, shape=None):
+        if t is None:
+            return None, None
+        torch = self.torch
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(np.asarray(t))
+        t = t.to(device=self.device, dtype=dtype or self.ct).contiguous()
+        if shape is not None:
+            t = t.reshape(shape)
+        return t, C.c_void_p(t.data_ptr())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.hlbm_lattice_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ set-up
+    def set_params(self, p, diag_every=1, check_nonfinite=0):
+        q = make_params(p, diag_every, check_nonfinite)
+        self._check(self.L.hlbm_set_params(self.h, C.byref(q)))
+
+    def set_rotors(self, rotors):
+        self._check(self.L.hlbm_set_rotors(self.h, _rotor_array(rotors), len(rotors)))
+
+    def set_porosity_field(self, d, tag=None):
+        dt, dp = self._dev(d, shape=(self.N,))
+        tt, tp = self._dev(tag, dtype=self.torch.uint8, shape=(self.N,))
+        self._check(self.L.hlbm_set_porosity_field(self.h, dp, tp))
+
+    def set_solid_velocity(self, uB):
+        t, p = self._dev(uB, shape=(3, self.N))
+        self._check(self.L.hlbm_set_solid_velocity(self.h, p))
+
+    def set_control(self, dd):
+        t, p = self._dev(dd, shape=(self.N,))
+        self._check(self.L.hlbm_set_control(self.h, p))
+
+    def set_tag_frame(self, tag, center, axis):
+        c = (C.c_double * 3)(*center)
+        a = (C.c_double * 3)(*axis)
+        self._check(self.L.hlbm_set_tag_frame(self.h, tag, c, a))
+
+    def init_equilibrium(self, rho=None, u=None):
+        rt, rp = self._dev(rho, shape=(self.N,))
+        ut, up = self._dev(u, shape=(3, self.N))
+        self._check(self.L.hlbm_init_equilibrium(self.h, rp, up))
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n=1):
+        self._check(self.L.hlbm_step(self.h, int(n)))
+
+    @property
+    def step_count(self):
+        return self.L.hlbm_get_step(self.h)
+
+    def moments(self, uhat=False):
+        torch = self.torch
+        rho = torch.empty(self.N, dtype=self.ct, device=self.device)
+        u = torch.empty(3, self.N, dtype=self.ct, device=self.device)
+        uh = torch.empty(3, self.N, dtype=self.ct, device=self.device) if uhat else None
+        self._check(self.L.hlbm_moments(self.h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()),
+                                        C.c_void_p(uh.data_ptr()) if uhat else None))
+        return (rho, u, uh) if uhat else (rho, u)
+
+    def get_populations(self):
+        out = self.torch.empty(27, self.N, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.hlbm_get_populations(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_populations(self, h):
+        t, p = self._dev(h, dtype=self.torch.float64, shape=(27, self.N))
+        self._check(self.L.hlbm_set_populations(self.h, p))
+        self.stream.synchronize()
+
+    def get_populations_at(self, cells):
+        ct, cp = self._dev(cells, dtype=self.torch.int64)
+        out = self.torch.empty(ct.numel(), 27, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.hlbm_get_populations_at(self.h, cp, ct.numel(), C.c_void_p(out.data_ptr())))
+        return out
+
+    def get_state(self):
+        nb = self.L.hlbm_state_bytes(self.h)
+        out = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        self._check(self.L.hlbm_get_state(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_state(self, blob):
+        self._check(self.L.hlbm_set_state(self.h, C.c_void_p(blob.data_ptr())))
+
+    def force_torque(self, tag):
+        F = (C.c_double * 3)()
+        T = (C.c_double * 3)()
+        self._check(self.L.hlbm_force_torque(self.h, tag, F, T))
+        return np.array(F[:]), np.array(T[:])
+
+    def history(self, start=None, stop=None):
+        stop = self.step_count if stop is None else stop
+        start = 0 if start is None else start
+        out = np.empty((max(0, stop - start), HIST_STRIDE))
+        self._check(self.L.hlbm_history(self.h, start, stop, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def wall_stats(self):
+        it = C.c_int64()
+        n = C.c_int64()
+        self._check(self.L.hlbm_wall_stats(self.h, C.byref(it), C.byref(n)))
+        return it.value, n.value
+
+
+def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None) -> Lattice:
+    """Lattice loaded with a workload's inputs at step 0 (same recipe as the oracle)."""
+    from . import workloads as W
+    lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device)
+    lat.set_params(w.params, diag_every=diag_every, check_nonfinite=check_nonfinite)
+    lat.set_rotors(w.rotors)
+    d, tag = W.static_porosity(w)
+    if d is not None:
+        lat.set_porosity_field(d, tag)
+        lat.set_tag_frame(1, w.sphere[:3], (1.0, 0.0, 0.0))
+    rho, u = W.initial_fields(w)
+    lat.init_equilibrium(rho, u)
+    noise = W.population_noise(w)
+    if noise is not None:
+        h = lat.get_populations()
+        lat.set_populations(h + lat.torch.as_tensor(noise, device=lat.device))
+    return lat

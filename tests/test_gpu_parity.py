@@ -1,0 +1,150 @@
+"""HIP path vs the FP64 oracle on the same seeded inputs, element by element.
+
+Tolerances (relative to the largest magnitude of the compared field):
+FP64 compute 1e-12, FP32 compute 2e-5.  Populations are compared as the
+deviations h = f* - w; forces and torques against the largest value of the
+history.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_13726_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def _hl():
+    from paper_2510_13726_amd import hlbm
+    return hlbm
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def run_both(w, storage, steps, check_every=None):
+    hl = _hl()
+    print(f"[parity] {w.name} storage={storage} steps={steps}", flush=True)
+    lat = hl.setup(w, storage=storage, check_nonfinite=1)
+    o = O.setup(w)
+    errs = []
+    done = 0
+    for k in ([check_every] * (steps // check_every) if check_every else [steps]):
+        lat.step(k)
+        o.step(k)
+        done += k
+        errs.append(rel(lat.get_populations().cpu().numpy(), o.get_populations()))
+    return lat, o, errs
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_tgv_sphere_parity(storage):
+    """Periodic 32^3 Taylor-Green vortex with a static porous sphere (tag 1),
+    seeded non-equilibrium noise, 100 steps."""
+    w = W.config1(noise=True)
+    lat, o, errs = run_both(w, storage, 100, check_every=25)
+    assert max(errs) < TOL[storage], errs
+    hg, ho = lat.history(), o.history()
+    assert hg.shape == ho.shape == (100, 91)
+    assert rel(hg[:, 1:7], ho[:, 1:7]) < 10 * TOL[storage]
+    assert rel(hg[:, 0], ho[:, 0]) < TOL[storage] * 1e-2 + 1e-15
+    rho_g, u_g, uh_g = (t.cpu().numpy() for t in lat.moments(uhat=True))
+    rho_o, u_o, uh_o = o.moments(uhat=True)
+    assert rel(rho_g - 1, rho_o - 1) < TOL[storage]
+    assert rel(u_g, u_o) < TOL[storage]
+    assert rel(uh_g, uh_o) < TOL[storage]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_rotor_wall_model_parity(storage):
+    """Rotor channel with inflow turbulence, outflow, rotating flat-plate rotor
+    and the wall model, 24 steps (several tiles, ragged x extent)."""
+    w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    lat, o, errs = run_both(w, storage, 24, check_every=8)
+    assert max(errs) < TOL[storage], errs
+    hg, ho = lat.history(), o.history()
+    assert rel(hg[:, 1:7], ho[:, 1:7]) < 10 * TOL[storage]
+    it_g, n_g = lat.wall_stats()
+    it_o, n_o = o.newton_stats()
+    assert n_g == n_o and n_g > 100
+    if storage == "f64":
+        assert it_g == it_o
+    rho_g, u_g, uh_g = (t.cpu().numpy() for t in lat.moments(uhat=True))
+    rho_o, u_o, uh_o = o.moments(uhat=True)
+    assert rel(u_g, u_o) < TOL[storage]
+    assert rel(uh_g, uh_o) < TOL[storage]
+
+
+def test_periodic_rotor_parity_fp64():
+    """Periodic box, two rotors with different axes and tags, no wall model."""
+    w = W.small_rotor(nx=48, ny=48, nz=48, R=9.0, chord=3.0, hub=2.0, tau0=0.52, wall=0)
+    w.bc_x = W.BC_PERIODIC
+    r2 = W.Rotor(center=(30.3, 24.1, 23.7), axis=(0.2, 1.0, 0.3), R=8.0, r_hub=1.5, chord=3.0, thick=2.0,
+                 omega=0.02, phase0=0.3, n_blades=2, tag=5)
+    w.rotors[0].center = (14.2, 24.4, 24.9)
+    w.rotors.append(r2)
+    w.init = "uniform"
+    w.u0 = 0.03
+    lat, o, errs = run_both(w, "f64", 16)
+    assert max(errs) < 1e-12, errs
+    hg, ho = lat.history(), o.history()
+    for t in (1, 5):
+        sl = slice(1 + 6 * (t - 1), 7 + 6 * (t - 1))
+        assert rel(hg[:, sl], ho[:, sl]) < 1e-10
+        assert np.abs(ho[:, sl]).max() > 0
+
+
+def test_restart_is_bitwise_and_deterministic():
+    """get_state / set_state continue the trajectory bit for bit; two runs of
+    the same input agree bit for bit."""
+    hl = _hl()
+    w = W.small_rotor(nx=64, ny=40, nz=40, R=10.0, chord=3.0, hub=2.0, turb=0.05)
+    lat = hl.setup(w, storage="f32")
+    lat.step(7)
+    blob = lat.get_state().clone()
+    lat.step(9)
+    ref = lat.get_populations().cpu().numpy()
+    ref_hist = lat.history(7, 16)
+    lat.set_state(blob)
+    assert lat.step_count == 7
+    lat.step(9)
+    assert np.array_equal(lat.get_populations().cpu().numpy(), ref)
+    assert np.array_equal(lat.history(7, 16), ref_hist)
+    lat2 = hl.setup(w, storage="f32")
+    lat2.step(16)
+    assert np.array_equal(lat2.get_populations().cpu().numpy(), ref)
+
+
+def test_populations_roundtrip_and_sampling():
+    hl = _hl()
+    w = W.config1(noise=True)
+    for storage in ("f64", "f32"):
+        lat = hl.setup(w, storage=storage)
+        h = lat.get_populations()
+        lat.set_populations(h)
+        assert rel(lat.get_populations().cpu().numpy(), h.cpu().numpy()) < (1e-16 if storage == "f64" else 1e-7)
+        cells = np.array([0, 5, 1000, w.cells - 1], dtype=np.int64)
+        at = lat.get_populations_at(cells).cpu().numpy()
+        assert np.array_equal(at, h.cpu().numpy()[:, cells].T)
+
+
+def test_error_paths():
+    hl = _hl()
+    w = W.config1()
+    lat = hl.setup(w, storage="f32")
+    bad = W.Params(tau0=0.4)
+    with pytest.raises(hl.HlbmError) as e:
+        lat.set_params(bad)
+    assert e.value.code == hl.HLBM_ERR_INVALID
+    with pytest.raises(hl.HlbmError):
+        lat.set_control(np.zeros(w.cells))  # created without the control section
+    h = lat.get_populations()
+    h[3, 17] = float("nan")
+    lat.set_populations(h)
+    lat.set_params(w.params, diag_every=1, check_nonfinite=1)
+    with pytest.raises(hl.HlbmError) as e:
+        lat.step(1)
+    assert e.value.code == hl.HLBM_ERR_NONFINITE
