@@ -1,0 +1,164 @@
+#!/usr/bin/env python
+"""Benchmark of the fused HLBM step on one MI355X.
+
+One step = the whole hot path for one time step of the rotor channel
+(256 x 128 x 128 D3Q27 cells, rotating 3-blade rotor with the wall model,
+inflow / outflow): rotor rasterization, inflow ghost plane, wall model, the
+fused pull-stream / moments / collision sweep and the per-tag force/torque
+reduction.  Populations are resident in HBM before the timed region.
+
+Prints one JSON line: MLUPS of the FP32-storage path (value), the roofline
+of the dominant kernel (the sweep) from HIP events around its launches, the
+FP16 / BF16 storage variants, and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM roofline (fwd FP32 vs FP16-storage); adjoint/forward cost ratio"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {"f64": 2 * 27 * 8, "f32": 2 * 27 * 4, "f16": 2 * 27 * 2, "bf16": 2 * 27 * 2}
+KERNEL_SOURCES = ["paper_2510_13726_amd/csrc/kernels.hip", "paper_2510_13726_amd/csrc/lbm_cell.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_storage(w, storage, steps, warmup):
+    """(MLUPS, ms/step, sweep launches, sweep avg ms) of `steps` timed steps."""
+    import torch
+    from paper_2510_13726_amd import hlbm
+    lat = hlbm.setup(w, storage=storage, diag_every=0)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    # second pass with HIP events around each sweep launch (same stream)
+    hlbm.profile_enable(lat, True)
+    lat.step(steps)
+    n, ms = hlbm.profile_read(lat, hlbm.KERNEL_SWEEP)
+    hlbm.profile_enable(lat, False)
+    it, cells = lat.wall_stats()
+    ok = bool(torch.isfinite(lat.moments()[0]).all().item())
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return dict(mlups=w.cells * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, sweep_launches=n,
+                sweep_avg_ms=ms / max(n, 1), finite=ok, wall_cells=cells, newton_iters=it)
+
+
+def roofline(w, storage, sweep_avg_ms):
+    algo = BYTES_PER_CELL[storage] * w.cells
+    achieved = algo / (sweep_avg_ms * 1e-3) / 1e9
+    traffic = None
+    f = os.path.join(ROOT, "profiles", f"sweep_traffic_{w.name}_{storage}.json")
+    if os.path.exists(f):
+        with open(f) as fh:
+            t = json.load(fh)
+        if t.get("kernel_hash") == kernel_hash():
+            traffic = t.get("bytes_per_launch")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_sweep", "algorithmic_bytes_per_launch": algo,
+            "avg_launch_ms": round(sweep_avg_ms, 5)}
+
+
+def cpu_baseline(w, steps):
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    o = O.setup(w, threads=threads)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(w.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} steps of {w.name} ({w.cells * steps} cell updates), FP64 oracle, "
+                      f"OpenMP over z-planes, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
+    ap.add_argument("--config", default="2", help="workload: 1..5 (3 and 5 are full size)")
+    ap.add_argument("--variants", default="f16,bf16", help="extra storage types timed on the same workload")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0 = skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_13726_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = W.ALL[args.config]()
+    log(f"workload {w.name}: {w.cells} cells, storage {args.storage}, {args.steps} steps after {args.warmup}")
+    main_run = time_storage(w, args.storage, args.steps, args.warmup)
+    log(f"main: {main_run}")
+    variants = {}
+    for st in [s for s in args.variants.split(",") if s and s != args.storage]:
+        r = time_storage(w, st, args.steps, args.warmup)
+        log(f"{st}: {r}")
+        variants[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+                        "roofline": roofline(w, st, r["sweep_avg_ms"]), "finite": r["finite"]}
+    cpu = None
+    if args.cpu_steps > 0:
+        log(f"cpu baseline: {args.cpu_steps} oracle steps")
+        cpu = cpu_baseline(w, args.cpu_steps)
+        log(f"cpu: {cpu}")
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage if args.storage != "f16" else "f16-storage/f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.cells, "storage": args.storage,
+                   "compute": "f64" if args.storage == "f64" else "f32", "rotors": len(w.rotors),
+                   "wall_model": bool(w.params.wall_model), "tau0": w.params.tau0, "cs_smag": w.params.cs_smag},
+        "roofline": roofline(w, args.storage, main_run["sweep_avg_ms"]),
+        "cpu_baseline": cpu,
+        "storage_variants": variants,
+        "finite": main_run["finite"],
+        "wall_cells_processed": main_run["wall_cells"],
+        "kernel_hash": kernel_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

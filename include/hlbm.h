@@ -192,6 +192,15 @@ int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
  * cells processed (host, syncs). */
 int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
 
+/* Opt-in kernel timing with HIP events recorded on the lattice's stream
+ * around every launch of the given kernel class during hlbm_step
+ * (HLBM_KERNEL_*).  hlbm_profile_enable(h, 1) starts a fresh count;
+ * hlbm_profile_read synchronizes and returns the number of timed launches
+ * and their summed duration in milliseconds.  For benchmarks and tests. */
+enum hlbm_kernel { HLBM_KERNEL_SWEEP = 0, HLBM_KERNEL_WALL = 1, HLBM_KERNEL_RASTERIZE = 2, HLBM_KERNEL_OTHER = 3 };
+int hlbm_profile_enable(hlbm_handle h, int32_t enable);
+int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* total_ms);
+
 /* Message of the last error of this handle (or of the last failed create
  * when h is NULL).  Valid until the next call on the handle. */
 const char* hlbm_last_error(hlbm_handle h);

@@ -51,7 +51,7 @@ int64_t pop_stride(const hlbm_desc* d) {
 }
 
 struct Layout {
-  int64_t d_eff, d_static, tag, tag_static, uB, dd, blk, partial, mass, massl1, flag, stats, rot, geo, ut0, ut1,
+  int64_t d_eff, d_static, tag, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wcount, flag, stats, rot, geo, ut0, ut1,
       act0, act1, wall, hist, ghost, ghost64, total;
 };
 
@@ -59,7 +59,7 @@ Layout layout(const hlbm_desc* d) {
   Layout L{};
   const int64_t N = cells_of(d);
   const int cs = elem_size(d->compute);
-  const int64_t nb = (N + kBlock - 1) / kBlock;
+  const int64_t nb = int64_t((d->nx + kTileX - 1) / kTileX) * ((d->ny + kTileY - 1) / kTileY) * d->nz;
   const int64_t B = d->bbox_cells;
   const int64_t H = d->history > 0 ? d->history : 1024;
   int64_t o = 0;
@@ -72,8 +72,11 @@ Layout layout(const hlbm_desc* d) {
   L.dd = take((d->flags & HLBM_WITH_CONTROL) ? N * cs : 0);
   L.blk = take(nb * 4);
   L.partial = take(nb * kPartial * 8);
+  L.partl1 = take(int64_t(kPartL1) * kPartial * 8);
   L.mass = take(nb * 8);
-  L.massl1 = take(kMassL1 * 8);
+  L.massl1 = take(kPartL1 * 8);
+  L.wlist = take(B * 4);
+  L.wcount = take(64);
   L.flag = take(64);
   L.stats = take(64);
   L.rot = take(sizeof(RotorTable));
@@ -134,6 +137,9 @@ struct hlbm_lattice {
   int64_t hist_start = 0;      // first step recorded since init
   int64_t hist_cap = 0;
   std::string err;
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[4];
+  std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -302,7 +308,9 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.g.nx = d->nx; L.g.ny = d->ny; L.g.nz = d->nz; L.g.bc_x = d->bc_x;
   L.g.N = cells_of(d);
   L.g.stride = pop_stride(d);
-  L.nblocks = (L.g.N + kBlock - 1) / kBlock;
+  L.g.ntx = (d->nx + kTileX - 1) / kTileX;
+  L.g.nty = (d->ny + kTileY - 1) / kTileY;
+  L.nblocks = int64_t(L.g.ntx) * L.g.nty * d->nz;
   L.xcd_remap = 1;
   if (const char* e = std::getenv("HLBM_XCD_REMAP")) L.xcd_remap = std::atoi(e);
   const Layout& Y = h->lay;
@@ -314,8 +322,11 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.dd = nullptr;
   L.blk_slot = reinterpret_cast<int32_t*>(base + Y.blk);
   L.partial = reinterpret_cast<double*>(base + Y.partial);
+  L.part_l1 = reinterpret_cast<double*>(base + Y.partl1);
   L.mass_part = reinterpret_cast<double*>(base + Y.mass);
   L.mass_l1 = reinterpret_cast<double*>(base + Y.massl1);
+  L.wlist = reinterpret_cast<int32_t*>(base + Y.wlist);
+  L.wcount = reinterpret_cast<int32_t*>(base + Y.wcount);
   L.flag = reinterpret_cast<int32_t*>(base + Y.flag);
   L.stats = reinterpret_cast<unsigned long long*>(base + Y.stats);
   L.rot = reinterpret_cast<RotorTable*>(base + Y.rot);
@@ -366,6 +377,9 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
 void hlbm_lattice_destroy(hlbm_handle h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  for (auto& v : h->prof)
+    for (auto& p : v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto e : h->pool) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -473,19 +487,71 @@ int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u) {
   return HLBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// cos / sin of every blade angle phase0 + omega n + 2 pi b / n_blades at step n
+BladeTrig blade_trig(hlbm_handle h, int64_t n) {
+  BladeTrig t{};
+  for (int k = 0; k < h->rot.n; ++k) {
+    const RotorDev& r = h->rot.r[k];
+    for (int b = 0; b < r.nb; ++b) {
+      const double th = r.phase0 + r.omega * double(n) + 6.283185307179586476925286766559 * double(b) / double(r.nb);
+      t.c[k][b] = std::cos(th);
+      t.s[k][b] = std::sin(th);
+    }
+  }
+  return t;
+}
+
+hipEvent_t take_event(hlbm_handle h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run one launch, bracketed by events when profiling is on.
+template <class F>
+hipError_t timed(hlbm_handle h, int kind, F&& f) {
+  if (!h->profiling) return f();
+  hipEvent_t a = take_event(h), b = take_event(h);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, h->stream);
+  if (e == hipSuccess) e = f();
+  if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+  h->prof[kind].push_back({a, b});
+  return e;
+}
+}  // namespace
+
+extern "C" {
+
 int hlbm_step(hlbm_handle h, int64_t n) {
   if (!h) return HLBM_ERR_INVALID;
   if (n < 0) return fail(h, HLBM_ERR_INVALID, "n must be >= 0");
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   for (int64_t k = 0; k < n; ++k) {
-    hipError_t e = launch_rasterize(h->L, h->step);
-    if (e == hipSuccess) e = launch_inflow(h->L, h->step);
+    const BladeTrig trig = blade_trig(h, h->step);
+    hipError_t e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_prologue(h->L, h->step); });
+    if (e == hipSuccess)
+      e = timed(h, HLBM_KERNEL_RASTERIZE,
+                [&] { return launch_rasterize(h->L, h->step, trig, h->act[1 - h->wcur]); });
     if (e == hipSuccess && wall)
-      e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur],
-                      h->act[1 - h->wcur], h->step);
+      e = timed(h, HLBM_KERNEL_WALL, [&] {
+        return launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur],
+                           h->act[1 - h->wcur], h->step);
+      });
     const bool diag = h->params.diag_every > 0 && h->step % h->params.diag_every == 0;
-    if (e == hipSuccess) e = launch_sweep(h->L, h->pop[h->cur], h->pop[1 - h->cur], h->step, diag);
-    if (e == hipSuccess) e = launch_finalize(h->L, h->step, h->nslots, diag);
+    if (e == hipSuccess)
+      e = timed(h, HLBM_KERNEL_SWEEP,
+                [&] { return launch_sweep(h->L, h->pop[h->cur], h->pop[1 - h->cur], h->step, diag); });
+    if (e == hipSuccess)
+      e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, h->step, h->nslots, diag); });
     if (e != hipSuccess) return hip_fail(h, e, "step");
     h->cur = 1 - h->cur;
     if (wall) h->wcur = 1 - h->wcur;
@@ -510,8 +576,8 @@ int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat) {
   if (!h) return HLBM_ERR_INVALID;
   if (!rho || !u) return fail(h, HLBM_ERR_INVALID, "rho and u are required");
   const bool wall = h->params.wall_model && h->L.nrot > 0;
-  hipError_t e = launch_rasterize(h->L, h->step);
-  if (e == hipSuccess) e = launch_inflow(h->L, h->step);
+  hipError_t e = launch_prologue(h->L, h->step);
+  if (e == hipSuccess) e = launch_rasterize(h->L, h->step, blade_trig(h, h->step), h->act[1 - h->wcur]);
   // the wall model writes the next state slot, which is not committed here
   if (e == hipSuccess && wall)
     e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur], h->act[1 - h->wcur],
@@ -626,6 +692,35 @@ int hlbm_wall_stats(hlbm_handle h, int64_t* iters, int64_t* cells) {
   if (e != hipSuccess) return hip_fail(h, e, "wall stats");
   if (iters) *iters = int64_t(s[0]);
   if (cells) *cells = int64_t(s[1]);
+  return HLBM_OK;
+}
+
+int hlbm_profile_enable(hlbm_handle h, int32_t enable) {
+  if (!h) return HLBM_ERR_INVALID;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "profile enable");
+  for (auto& v : h->prof) {
+    for (auto& p : v) { h->pool.push_back(p.first); h->pool.push_back(p.second); }
+    v.clear();
+  }
+  h->profiling = enable != 0;
+  return HLBM_OK;
+}
+
+int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* total_ms) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (kernel < 0 || kernel > 3) return fail(h, HLBM_ERR_INVALID, "unknown kernel class");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "profile read");
+  double sum = 0.0;
+  for (auto& p : h->prof[kernel]) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p.first, p.second);
+    if (e != hipSuccess) return hip_fail(h, e, "event elapsed time");
+    sum += ms;
+  }
+  if (launches) *launches = int64_t(h->prof[kernel].size());
+  if (total_ms) *total_ms = sum;
   return HLBM_OK;
 }
 

@@ -6,13 +6,16 @@
 namespace hlbm {
 
 constexpr int kQ = 27;
-constexpr int kBlock = 256;          // cells per sweep workgroup (4 waves of 64)
+constexpr int kTileX = 64;           // sweep workgroup: 64 x-cells (one wave) ...
+constexpr int kTileY = 4;            // ... by 4 y-rows (4 waves)
+constexpr int kBlock = kTileX * kTileY;
 constexpr int kMaxRotors = 8;
 constexpr int kMaxBlades = 8;
 constexpr int kTags = 16;
 constexpr int kHist = 91;            // mass + 15 x (F, T)
 constexpr int kPartial = 96;         // per FSI block: [16 tags][F3, T3]
 constexpr int kMassL1 = 256;         // first-level mass reduction width
+constexpr int kPartL1 = 64;          // first-level force reduction width
 constexpr int kWallOut = 10;         // u_wm[3], S[6], sigma per wall slot
 
 // Tag byte of a cell: bits 0-3 tag, bit 6 = covered by a rotor, bit 7 = wall cell.
@@ -52,6 +55,13 @@ struct Geometry {
   int32_t nx, ny, nz, bc_x;
   int64_t N;
   int64_t stride;      // elements between population arrays
+  int32_t ntx, nty;    // sweep tiles along x and y
+};
+
+// cos and sin of every blade angle of every rotor at the current step
+struct BladeTrig {
+  double c[kMaxRotors][kMaxBlades];
+  double s[kMaxRotors][kMaxBlades];
 };
 
 }  // namespace hlbm

@@ -56,8 +56,8 @@ __device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geom
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const ST* p = src + int64_t(i) * g.stride;
-    const uint32_t o = oz[cz_of(i) + 1] + oy[cy_of(i) + 1] + ox[cx_of(i) + 1];
-    h[i] = CT(w_of(i)) * Store<ST>::template load<CT>(p + o);
+    const uint32_t o = (oz[cz_of(i) + 1] + oy[cy_of(i) + 1] + ox[cx_of(i) + 1]) * uint32_t(sizeof(ST));
+    h[i] = CT(w_of(i)) * Store<ST>::template load<CT>(at_bytes(p, o));
   }
   if (!kPeriodicX && x == 0) {
     const uint32_t pz[3] = {uint32_t(zp) * g.ny, uint32_t(z) * g.ny, uint32_t(zm) * g.ny};
@@ -71,10 +71,12 @@ __device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geom
 // Inflow ghost plane of step n: h_i = f^eq_i(1, u_in(n, y, z)) - w_i for the
 // nine velocities with c_x = +1, u_in = U + I |U| xi with seeded normals xi.
 template <class CT>
-__global__ __launch_bounds__(256) void k_inflow(Geometry g, Model m, int64_t n, CT* __restrict__ ghost) {
+__global__ __launch_bounds__(256) void k_prologue(Geometry g, Model m, int64_t n, CT* __restrict__ ghost,
+                                                  double* __restrict__ ghost64, int32_t* __restrict__ wcount) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k == 0) *wcount = 0;
   const int64_t plane = int64_t(g.ny) * g.nz;
-  if (k >= plane) return;
+  if (g.bc_x == 0 || k >= plane) return;
   const int z = int(k / g.ny), y = int(k - int64_t(z) * g.ny);
   double u[3] = {m.u_in[0], m.u_in[1], m.u_in[2]};
   if (m.turb_amp != 0.0)
@@ -83,6 +85,12 @@ __global__ __launch_bounds__(256) void k_inflow(Geometry g, Model m, int64_t n, 
   equilibrium_dev_unit<CT>(CT(u[0]), CT(u[1]), CT(u[2]), ge);
 #pragma unroll
   for (int i = 18; i < 27; ++i) ghost[(i - 18) * plane + k] = CT(w_of(i)) * ge[i];
+  if (ghost64) {
+    double gd[27];
+    equilibrium_dev_unit<double>(u[0], u[1], u[2], gd);
+#pragma unroll
+    for (int i = 18; i < 27; ++i) ghost64[(i - 18) * plane + k] = w_of(i) * gd[i];
+  }
 }
 
 // ---------------------------------------------------------------- reductions
@@ -101,7 +109,8 @@ struct RotorPhi {
 // Signed distance (positive inside) of a rotor at step n: hub sphere united
 // with flat-plate blades (box in blade coordinates r, chord s, thickness h;
 // pitch beta(r) linear from root to tip), and its gradient.
-__device__ RotorPhi rotor_phi(const RotorDev& r, double x, double y, double z, int64_t n) {
+__device__ RotorPhi rotor_phi(const RotorDev& r, const double* ctab, const double* stab, double x, double y,
+                              double z, double cut) {
   RotorPhi o;
   const double rel[3] = {x - r.c[0], y - r.c[1], z - r.c[2]};
   const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
@@ -110,9 +119,7 @@ __device__ RotorPhi rotor_phi(const RotorDev& r, double x, double y, double z, i
   const double ax = rel[0] * r.e[0] + rel[1] * r.e[1] + rel[2] * r.e[2];
   const double span = r.R - r.r_hub;
   for (int b = 0; b < r.nb; ++b) {
-    const double th = r.phase0 + r.omega * double(n) + 6.283185307179586476925286766559 * double(b) / double(r.nb);
-    double st, ct;
-    sincos(th, &st, &ct);
+    const double ct = ctab[b], st = stab[b];
     double er[3], ep[3];
     for (int a = 0; a < 3; ++a) {
       er[a] = ct * r.e1[a] + st * r.e2[a];
@@ -120,6 +127,10 @@ __device__ RotorPhi rotor_phi(const RotorDev& r, double x, double y, double z, i
     }
     const double rr = rel[0] * er[0] + rel[1] * er[1] + rel[2] * er[2];
     const double qq = rel[0] * ep[0] + rel[1] * ep[1] + rel[2] * ep[2];
+    // the blade lies within r_hub <= r <= R and q^2 + a^2 <= (c/2)^2 + (t/2)^2:
+    // a point farther than `cut` from that slab cannot reach phi > -cut
+    const double hc = 0.5 * sqrt(r.chord * r.chord + r.thick * r.thick) + cut;
+    if (rr < r.r_hub - cut || rr > r.R + cut || qq * qq + ax * ax > hc * hc) continue;
     double frac = (rr - r.r_hub) / span, dbeta = 0.0;
     if (frac <= 0.0) frac = 0.0;
     else if (frac >= 1.0) frac = 1.0;
@@ -176,12 +187,13 @@ __device__ __forceinline__ int rotor_of_slot(const RotorTable& rt, int64_t s) {
 }
 
 __device__ __forceinline__ void slot_cell(const RotorDev& r, int64_t s, int& x, int& y, int& z) {
-  const int64_t l = s - r.off;
-  const int64_t pl = int64_t(r.bn[0]) * r.bn[1];
-  z = r.b0[2] + int(l / pl);
-  const int64_t rem = l - int64_t(z - r.b0[2]) * pl;
-  y = r.b0[1] + int(rem / r.bn[0]);
-  x = r.b0[0] + int(rem - int64_t(y - r.b0[1]) * r.bn[0]);
+  const uint32_t l = uint32_t(s - r.off);  // box slots fit in 32 bits
+  const uint32_t pl = uint32_t(r.bn[0]) * uint32_t(r.bn[1]);
+  const uint32_t lz = l / pl, rem = l - lz * pl;
+  const uint32_t ly = rem / uint32_t(r.bn[0]);
+  z = r.b0[2] + int(lz);
+  y = r.b0[1] + int(ly);
+  x = r.b0[0] + int(rem - ly * uint32_t(r.bn[0]));
 }
 
 __device__ __forceinline__ bool in_box(const RotorDev& r, int x, int y, int z) {
@@ -191,13 +203,14 @@ __device__ __forceinline__ bool in_box(const RotorDev& r, int x, int y, int z) {
 
 // ---------------------------------------------------------------- rasterize
 template <class CT>
-__global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict__ rtp, Geometry g, Model m, int64_t n,
-                                                   int64_t total, const CT* __restrict__ d_static,
+__global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict__ rtp, Geometry g, Model m,
+                                                   BladeTrig trig, int64_t total, const CT* __restrict__ d_static,
                                                    const uint8_t* __restrict__ tag_static, const CT* __restrict__ dd,
                                                    CT* __restrict__ d_eff, uint8_t* __restrict__ tag,
-                                                   double* __restrict__ geo) {
+                                                   double* __restrict__ geo, uint8_t* __restrict__ act_new,
+                                                   int32_t* __restrict__ wlist, int32_t* __restrict__ wcount) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= total) return;
+  if (s >= total) return;  // inactive lanes add nothing to the ballot below
   const RotorTable& rt = *rtp;
   const int k = rotor_of_slot(rt, s);
   int x, y, z;
@@ -207,7 +220,7 @@ __global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict_
   int br = -1;
   for (int j = 0; j < rt.n; ++j) {
     if (!in_box(rt.r[j], x, y, z)) continue;
-    RotorPhi p = rotor_phi(rt.r[j], double(x), double(y), double(z), n);
+    RotorPhi p = rotor_phi(rt.r[j], trig.c[j], trig.s[j], double(x), double(y), double(z), 0.5 * m.eps_h + 1.0);
     if (p.phi > best) {
       best = p.phi;
       br = j;
@@ -227,6 +240,19 @@ __global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict_
     tb = tag_static[c];
   }
   tag[c] = tb;
+  act_new[s] = 0;
+  // wall cells of this box's own rotor go to the wall model's work list
+  // (one atomic per wave: base from the first lane, rank from the ballot)
+  const bool mine = (tb & kWallBit) && br == k;
+  const uint64_t ball = __ballot(mine);
+  if (ball) {
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((long long)ball) - 1;
+    int base = 0;
+    if (lane == first) base = atomicAdd(wcount, __popcll(ball));
+    base = __shfl(base, first, 64);
+    if (mine) wlist[base + __popcll(ball & ((1ull << lane) - 1ull))] = int32_t(s);
+  }
   geo[s] = best;
   const double inv = gn > 0 ? 1.0 / gn : 0.0;
   geo[total + s] = -gr[0] * inv;
@@ -269,54 +295,50 @@ __device__ __forceinline__ double newton(double u, F&& fdf, double tol, int maxi
   return u;
 }
 
+// Wall model (Sec. 2.2.1, Sec. 3.2) on the listed wall cells, eight lanes per
+// cell: lane j pulls the populations of probe corner j and forms its
+// velocity; the trilinear sum is reduced over the eight lanes; lane 0 runs
+// the two Newton solves and writes u_wm, S_wm, sigma and the u_tau state.
 template <class ST, class CT, bool kPeriodicX>
-__global__ __launch_bounds__(128) void k_wall(const RotorTable* __restrict__ rtp, Geometry g, Model m, int64_t n,
-                                              int64_t total, const ST* __restrict__ src,
-                                              const uint8_t* __restrict__ tag, const double* __restrict__ geo,
+__global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp, Geometry g, Model m, int64_t total,
+                                              const ST* __restrict__ src, const double* __restrict__ geo,
+                                              const int32_t* __restrict__ wlist, const int32_t* __restrict__ wcount,
                                               const double* __restrict__ ut_prev, const uint8_t* __restrict__ act_prev,
                                               double* __restrict__ ut_new, uint8_t* __restrict__ act_new,
                                               CT* __restrict__ wall_out, unsigned long long* __restrict__ stats,
                                               const double* __restrict__ ghost) {
-  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= total) return;
   const RotorTable& rt = *rtp;
-  const int k = rotor_of_slot(rt, s);
-  const RotorDev& R = rt.r[k];
-  int x, y, z;
-  slot_cell(R, s, x, y, z);
-  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
-  const uint8_t tb = tag[c];
-  if (!(tb & kWallBit) || (tb & kTagMask) != R.tag) {
-    act_new[s] = 0;
-    return;
-  }
-  const double y1 = -geo[s];
-  const double nn[3] = {geo[total + s], geo[2 * total + s], geo[3 * total + s]};
-  const double X[3] = {double(x), double(y), double(z)};
-  double xw[3], xs[3];
-  for (int a = 0; a < 3; ++a) {
-    xw[a] = X[a] - y1 * nn[a];
-    xs[a] = xw[a] + m.y_s * nn[a];
-  }
-  const double rw[3] = {xw[0] - R.c[0], xw[1] - R.c[1], xw[2] - R.c[2]};
-  const double uw[3] = {R.omega * (R.e[1] * rw[2] - R.e[2] * rw[1]), R.omega * (R.e[2] * rw[0] - R.e[0] * rw[2]),
-                        R.omega * (R.e[0] * rw[1] - R.e[1] * rw[0])};
-  // trilinear sample of the pre-collision fluid velocity at the probe
-  int i0[3];
-  double fr[3];
-  for (int a = 0; a < 3; ++a) {
-    const double fl = floor(xs[a]);
-    i0[a] = int(fl);
-    fr[a] = xs[a] - fl;
-  }
-  double us[3] = {0.0, 0.0, 0.0};
-  for (int corner = 0; corner < 8; ++corner) {
+  const int corner = threadIdx.x & 7;
+  const int count = *wcount;
+  // each wave takes 8 consecutive list entries per iteration; the trip count
+  // is uniform over the wave so that every lane takes part in the shuffles
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t wb = wave * 8; wb < count; wb += nwaves * 8) {
+    const int64_t w = wb + ((threadIdx.x & 63) >> 3);
+    const bool live = w < count;
+    const int64_t s = wlist[live ? w : wb];
+    const int k = rotor_of_slot(rt, s);
+    const RotorDev& R = rt.r[k];
+    int x, y, z;
+    slot_cell(R, s, x, y, z);
+    const double y1 = -geo[s];
+    const double nn[3] = {geo[total + s], geo[2 * total + s], geo[3 * total + s]};
+    const double X[3] = {double(x), double(y), double(z)};
+    double xw[3], xs[3];
+    for (int a = 0; a < 3; ++a) {
+      xw[a] = X[a] - y1 * nn[a];
+      xs[a] = xw[a] + m.y_s * nn[a];
+    }
+    // this lane's probe corner and trilinear weight
     int q[3];
     double wgt = 1.0;
     for (int a = 0; a < 3; ++a) {
+      const double fl = floor(xs[a]);
       const int bit = (corner >> a) & 1;
-      q[a] = i0[a] + bit;
-      wgt *= bit ? fr[a] : 1.0 - fr[a];
+      const double fr = xs[a] - fl;
+      q[a] = int(fl) + bit;
+      wgt *= bit ? fr : 1.0 - fr;
     }
     q[1] = ((q[1] % g.ny) + g.ny) % g.ny;
     q[2] = ((q[2] % g.nz) + g.nz) % g.nz;
@@ -326,58 +348,80 @@ __global__ __launch_bounds__(128) void k_wall(const RotorTable* __restrict__ rtp
     pull_cell<ST, double, kPeriodicX>(src, g, q[0], q[1], q[2], ghost, h);
     const Moments<double> mo = moments_of<double>(h);
     const double rho = 1.0 + mo.drho;
-    us[0] += wgt * (mo.jx / rho);
-    us[1] += wgt * (mo.jy / rho);
-    us[2] += wgt * (mo.jz / rho);
+    // lanes 0..7 of the group are adjacent: butterfly within the group, fixed order
+    double us[3] = {wgt * (mo.jx / rho), wgt * (mo.jy / rho), wgt * (mo.jz / rho)};
+    double ord[3][8];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int base = int(threadIdx.x & 63) & ~7;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ord[a][j] = __shfl(us[a], base + j, 64);
+      us[a] = ((ord[a][0] + ord[a][1]) + (ord[a][2] + ord[a][3])) + ((ord[a][4] + ord[a][5]) + (ord[a][6] + ord[a][7]));
+    }
+    int it1 = 0, it2 = 0, done = 0;
+    if (corner == 0 && live) {
+    const double rw[3] = {xw[0] - R.c[0], xw[1] - R.c[1], xw[2] - R.c[2]};
+    const double uw[3] = {R.omega * (R.e[1] * rw[2] - R.e[2] * rw[1]), R.omega * (R.e[2] * rw[0] - R.e[0] * rw[2]),
+                          R.omega * (R.e[0] * rw[1] - R.e[1] * rw[0])};
+    double v[3] = {us[0] - uw[0], us[1] - uw[1], us[2] - uw[2]};
+    const double vn = v[0] * nn[0] + v[1] * nn[1] + v[2] * nn[2];
+    double vt[3] = {v[0] - vn * nn[0], v[1] - vn * nn[1], v[2] - vn * nn[2]};
+    const double U = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
+    const int64_t T = total;
+    if (!(U >= 1e-10)) {
+      for (int qq = 0; qq < 9; ++qq) wall_out[qq * T + s] = CT(0);
+      wall_out[9 * T + s] = CT(1);
+      act_new[s] = 0;
+    } else {
+    const double t[3] = {vt[0] / U, vt[1] / U, vt[2] / U};
+    const double nu = m.nu, ys = m.y_s, E = m.E, kap = m.kappa;
+    const double guess = act_prev[s] ? ut_prev[s] : sqrt(nu * U / ys);
+    const double ut = newton(
+        guess,
+        [&](double u, double& f, double& df) {
+          const double p = U / u;
+          f = p + spalding_bracket(kap * p) / E - ys * u / nu;
+          df = -(p / u) * (1.0 + kap * spalding_dbracket(kap * p) / E) - ys / nu;
+        },
+        m.tol, m.maxit, it1);
+    const double yp = y1 * ut / nu;
+    const double ulog = log(E * (yp > 1.0 ? yp : 1.0)) / kap;
+    const double up = newton(
+        ulog < yp ? ulog : yp,
+        [&](double u, double& f, double& df) {
+          f = u + spalding_bracket(kap * u) / E - yp;
+          df = 1.0 + kap * spalding_dbracket(kap * u) / E;
+        },
+        m.tol, m.maxit, it2);
+    const double qv = ut * up;
+    const double dudn = (U - qv) / (ys - y1);
+    wall_out[0 * T + s] = CT(qv * t[0]);
+    wall_out[1 * T + s] = CT(qv * t[1]);
+    wall_out[2 * T + s] = CT(qv * t[2]);
+    wall_out[3 * T + s] = CT(0.5 * dudn * (t[0] * nn[0] + nn[0] * t[0]));
+    wall_out[4 * T + s] = CT(0.5 * dudn * (t[1] * nn[1] + nn[1] * t[1]));
+    wall_out[5 * T + s] = CT(0.5 * dudn * (t[2] * nn[2] + nn[2] * t[2]));
+    wall_out[6 * T + s] = CT(0.5 * dudn * (t[0] * nn[1] + nn[0] * t[1]));
+    wall_out[7 * T + s] = CT(0.5 * dudn * (t[0] * nn[2] + nn[0] * t[2]));
+    wall_out[8 * T + s] = CT(0.5 * dudn * (t[1] * nn[2] + nn[1] * t[2]));
+    wall_out[9 * T + s] = CT(0);
+    ut_new[s] = ut;
+    act_new[s] = 1;
+    done = 1;
+    }
+    }
+    // Newton statistics: one atomic per wave
+    int a1 = it1, a2 = done;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a1 += __shfl_xor(a1, o, 64);
+      a2 += __shfl_xor(a2, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && a2) {
+      atomicAdd(&stats[0], (unsigned long long)a1);
+      atomicAdd(&stats[1], (unsigned long long)a2);
+    }
   }
-  double v[3] = {us[0] - uw[0], us[1] - uw[1], us[2] - uw[2]};
-  const double vn = v[0] * nn[0] + v[1] * nn[1] + v[2] * nn[2];
-  double vt[3] = {v[0] - vn * nn[0], v[1] - vn * nn[1], v[2] - vn * nn[2]};
-  const double U = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
-  const int64_t T = total;
-  if (!(U >= 1e-10)) {
-    for (int q = 0; q < 9; ++q) wall_out[q * T + s] = CT(0);
-    wall_out[9 * T + s] = CT(1);
-    act_new[s] = 0;
-    return;
-  }
-  const double t[3] = {vt[0] / U, vt[1] / U, vt[2] / U};
-  const double nu = m.nu, ys = m.y_s, E = m.E, kap = m.kappa;
-  const double guess = act_prev[s] ? ut_prev[s] : sqrt(nu * U / ys);
-  int it1 = 0, it2 = 0;
-  const double ut = newton(
-      guess,
-      [&](double u, double& f, double& df) {
-        const double p = U / u;
-        f = p + spalding_bracket(kap * p) / E - ys * u / nu;
-        df = -(p / u) * (1.0 + kap * spalding_dbracket(kap * p) / E) - ys / nu;
-      },
-      m.tol, m.maxit, it1);
-  const double yp = y1 * ut / nu;
-  const double ulog = log(E * (yp > 1.0 ? yp : 1.0)) / kap;
-  const double up = newton(
-      ulog < yp ? ulog : yp,
-      [&](double u, double& f, double& df) {
-        f = u + spalding_bracket(kap * u) / E - yp;
-        df = 1.0 + kap * spalding_dbracket(kap * u) / E;
-      },
-      m.tol, m.maxit, it2);
-  const double qv = ut * up;
-  const double dudn = (U - qv) / (ys - y1);
-  wall_out[0 * T + s] = CT(qv * t[0]);
-  wall_out[1 * T + s] = CT(qv * t[1]);
-  wall_out[2 * T + s] = CT(qv * t[2]);
-  wall_out[3 * T + s] = CT(0.5 * dudn * (t[0] * nn[0] + nn[0] * t[0]));
-  wall_out[4 * T + s] = CT(0.5 * dudn * (t[1] * nn[1] + nn[1] * t[1]));
-  wall_out[5 * T + s] = CT(0.5 * dudn * (t[2] * nn[2] + nn[2] * t[2]));
-  wall_out[6 * T + s] = CT(0.5 * dudn * (t[0] * nn[1] + nn[0] * t[1]));
-  wall_out[7 * T + s] = CT(0.5 * dudn * (t[0] * nn[2] + nn[0] * t[2]));
-  wall_out[8 * T + s] = CT(0.5 * dudn * (t[1] * nn[2] + nn[1] * t[2]));
-  wall_out[9 * T + s] = CT(0);
-  ut_new[s] = ut;
-  act_new[s] = 1;
-  atomicAdd(&stats[0], (unsigned long long)it1);
-  atomicAdd(&stats[1], 1ull);
 }
 
 // ================================================================ fused sweep
@@ -416,14 +460,16 @@ template <class ST, class CT, bool kPeriodicX, bool kMoments>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   const Geometry& g = a.g;
   const int64_t blk = remap_block(blockIdx.x, a.nblocks, a.remap);
-  const int64_t c = blk * kBlock + threadIdx.x;
-  const bool valid = c < g.N;
-  const uint32_t cc = valid ? uint32_t(c) : 0u;
-  const uint32_t nxy = uint32_t(g.nx) * uint32_t(g.ny);
-  const int z = int(cc / nxy);
-  const uint32_t r = cc - uint32_t(z) * nxy;
-  const int y = int(r / uint32_t(g.nx));
-  const int x = int(r - uint32_t(y) * uint32_t(g.nx));
+  // tile (tx, ty, z): 64 consecutive x-cells per wave, 4 y-rows per workgroup
+  const int tpz = g.ntx * g.nty;
+  const int z = int(blk / tpz);
+  const int trem = int(blk - int64_t(z) * tpz);
+  const int ty = trem / g.ntx, tx = trem - ty * g.ntx;
+  const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
+  const int yr = ty * kTileY + int(threadIdx.x >> 6);
+  const bool valid = xr < g.nx && yr < g.ny;
+  const int x = valid ? xr : 0, y = valid ? yr : 0;
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
 
   CT h[27];
   pull_cell<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
@@ -527,8 +573,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   if (!kMoments) {
     if (valid) {
       ST* dst = static_cast<ST*>(a.dst);
+      const uint32_t o = uint32_t(c) * uint32_t(sizeof(ST));
 #pragma unroll
-      for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(dst + int64_t(i) * g.stride + c, g2[i]);
+      for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(at_bytes(dst + int64_t(i) * g.stride, o), g2[i]);
     }
     if (a.mass_part) {
       const double mrho = valid ? double(rho) : 0.0;
@@ -542,36 +589,54 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   }
 }
 
-// ---------------------------------------------------------------- reductions
-__global__ __launch_bounds__(256) void k_mass_l1(const double* __restrict__ part, int64_t nb,
-                                                 double* __restrict__ out) {
-  __shared__ double s[256];
-  const int64_t per = (nb + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = int64_t(blockIdx.x) * per, hi = lo + per < nb ? lo + per : nb;
-  double acc = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += part[i];
-  s[threadIdx.x] = acc;
+// Force / torque / mass reduction of one step, level 1: workgroup b sums FSI
+// partials b, b + G, ... and the mass partials of its chunk in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce_l1(const double* __restrict__ partial, int32_t nslots,
+                                                   const double* __restrict__ mass_part, int64_t nmass, int diag,
+                                                   double* __restrict__ l1, double* __restrict__ ml1) {
+  __shared__ double s[2][kPartial];
+  __shared__ double sm[256];
+  const int G = gridDim.x, b = blockIdx.x;
+  const int k = threadIdx.x % kPartial, r = threadIdx.x / kPartial;  // r in {0, 1, 2}; row 2 idle
+  if (r < 2) {
+    double acc = 0.0;
+#pragma unroll 4
+    for (int32_t sl = b + r * G; sl < nslots; sl += 2 * G) acc += partial[int64_t(sl) * kPartial + k];
+    s[r][k] = acc;
+  }
+  double macc = 0.0;
+  if (diag) {
+    const int64_t per = (nmass + G - 1) / G;
+    const int64_t lo = int64_t(b) * per, hi = lo + per < nmass ? lo + per : nmass;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) macc += mass_part[i];
+  }
+  sm[threadIdx.x] = macc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+  if (threadIdx.x < kPartial) l1[int64_t(b) * kPartial + threadIdx.x] = s[0][threadIdx.x] + s[1][threadIdx.x];
+  if (threadIdx.x == 0) ml1[b] = sm[0];
 }
 
-__global__ __launch_bounds__(128) void k_finalize(const double* __restrict__ partial, int32_t nslots,
-                                                  const double* __restrict__ mass_l1, int diag,
-                                                  double* __restrict__ rec) {
-  const int q = threadIdx.x;
-  if (q < 90) {
-    const int k = 6 + q;  // tags 1..15
+// Level 2: one workgroup adds the G level-1 results in order into the record.
+__global__ __launch_bounds__(256) void k_reduce_l2(const double* __restrict__ l1, const double* __restrict__ ml1,
+                                                   int G, int diag, double* __restrict__ rec) {
+  __shared__ double s[2][kPartial];
+  const int k = threadIdx.x % kPartial, r = threadIdx.x / kPartial;
+  if (r < 2) {
     double acc = 0.0;
-    for (int32_t sl = 0; sl < nslots; ++sl) acc += partial[int64_t(sl) * kPartial + k];
-    rec[1 + q] = acc;
-  } else if (q == 127) {
+#pragma unroll 4
+    for (int j = r; j < G; j += 2) acc += l1[int64_t(j) * kPartial + k];
+    s[r][k] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 6 && threadIdx.x < kPartial) rec[1 + threadIdx.x - 6] = s[0][threadIdx.x] + s[1][threadIdx.x];
+  if (threadIdx.x == 255) {
     if (diag) {
       double acc = 0.0;
-      for (int i = 0; i < kMassL1; ++i) acc += mass_l1[i];
+      for (int j = 0; j < G; ++j) acc += ml1[j];
       rec[0] = acc;
     } else {
       rec[0] = __builtin_nan("");
@@ -648,7 +713,7 @@ __global__ __launch_bounds__(256) void k_mark(const RotorTable* __restrict__ rtp
   bool fsi = d_static[c] != CT(0) || tag_static[c] != 0 || (dd && dd[c] != CT(0));
   const RotorTable& rt = *rtp;
   for (int j = 0; j < rt.n && !fsi; ++j) fsi = in_box(rt.r[j], x, y, z);
-  if (fsi) blk[c / kBlock] = 1;
+  if (fsi) blk[(int64_t(z) * g.nty + y / kTileY) * g.ntx + x / kTileX] = 1;
 }
 
 // d_eff = d_static + control everywhere (rotor boxes are overwritten each step),
@@ -682,30 +747,35 @@ static hipError_t by_compute(int compute, F&& f) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_rasterize(const Launch& L, int64_t step) {
+hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig, uint8_t* act_new) {
+  (void)step;
   if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
   return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
-    hipLaunchKernelGGL(k_rasterize<CT>, grid1(L.bbox_total, 256), dim3(256), 0, L.stream, L.rot, L.g, L.m, step,
+    hipLaunchKernelGGL(k_rasterize<CT>, grid1(L.bbox_total, 256), dim3(256), 0, L.stream, L.rot, L.g, L.m, trig,
                        L.bbox_total, (const CT*)L.d_static, L.tag_static, (const CT*)L.dd, (CT*)L.d_eff, L.tag,
-                       L.geo);
+                       L.geo, act_new, L.wlist, L.wcount);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
                        double* ut_new, uint8_t* act_new, int64_t step) {
+  (void)step;
   if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
+  // persistent grid over the (device-side) wall-cell count, 32 cells per workgroup
+  int64_t blocks = (L.bbox_total + 31) / 32;
+  if (blocks > 1024) blocks = 1024;
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
     if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_wall<ST, CT, true>), grid1(L.bbox_total, 128), dim3(128), 0, L.stream, L.rot, L.g, L.m,
-                         step, L.bbox_total, (const ST*)src, L.tag, L.geo, ut_prev, act_prev, ut_new, act_new,
+      hipLaunchKernelGGL((k_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
+                         L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
                          (CT*)L.wall_out, L.stats, L.ghost64);
     else
-      hipLaunchKernelGGL((k_wall<ST, CT, false>), grid1(L.bbox_total, 128), dim3(128), 0, L.stream, L.rot, L.g, L.m,
-                         step, L.bbox_total, (const ST*)src, L.tag, L.geo, ut_prev, act_prev, ut_new, act_new,
+      hipLaunchKernelGGL((k_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
+                         L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
                          (CT*)L.wall_out, L.stats, L.ghost64);
     return hipGetLastError();
   });
@@ -752,28 +822,28 @@ hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* 
   });
 }
 
-hipError_t launch_inflow(const Launch& L, int64_t step) {
-  if (L.g.bc_x == 0) return hipSuccess;
+hipError_t launch_prologue(const Launch& L, int64_t step) {
   const int64_t plane = int64_t(L.g.ny) * L.g.nz;
-  hipError_t e = by_compute(L.compute, [&](auto* ct) {
+  if (L.g.bc_x == 0 && L.nrot == 0) return hipSuccess;
+  const int64_t threads = L.g.bc_x == 0 ? 1 : plane;
+  // the wall model samples in FP64: also fill the FP64 plane when it differs
+  double* g64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
+  return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
-    hipLaunchKernelGGL(k_inflow<CT>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, L.m, step, (CT*)L.ghost);
+    hipLaunchKernelGGL(k_prologue<CT>, grid1(threads, 256), dim3(256), 0, L.stream, L.g, L.m, step, (CT*)L.ghost,
+                       g64, L.wcount);
     return hipGetLastError();
   });
-  if (e != hipSuccess || L.compute == 0 || L.nrot == 0) return e;
-  // the wall model samples in FP64
-  hipLaunchKernelGGL(k_inflow<double>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, L.m, step, L.ghost64);
-  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag) {
-  if (diag) {
-    hipLaunchKernelGGL(k_mass_l1, dim3(kMassL1), dim3(256), 0, L.stream, L.mass_part, L.nblocks, L.mass_l1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+  const int G = kPartL1;
   double* rec = L.hist + (step % L.hist_cap) * kHist;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(128), 0, L.stream, L.partial, nslots, L.mass_l1, diag ? 1 : 0, rec);
+  hipLaunchKernelGGL(k_reduce_l1, dim3(G), dim3(256), 0, L.stream, L.partial, nslots, L.mass_part, L.nblocks,
+                     diag ? 1 : 0, L.part_l1, L.mass_l1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_l2, dim3(1), dim3(256), 0, L.stream, L.part_l1, L.mass_l1, G, diag ? 1 : 0, rec);
   return hipGetLastError();
 }
 

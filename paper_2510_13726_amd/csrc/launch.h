@@ -14,7 +14,7 @@ struct Launch {
   int storage, compute;      // hlbm_dtype values
   Geometry g;
   Model m;
-  int64_t nblocks;           // sweep workgroups = ceil(N / kBlock)
+  int64_t nblocks;           // sweep workgroups = ntx * nty * nz
   int32_t xcd_remap;
   // fields
   void* d_eff;
@@ -25,8 +25,11 @@ struct Launch {
   void* dd;                  // nullable
   int32_t* blk_slot;
   double* partial;
+  double* part_l1;           // [kPartL1][kPartial]
   double* mass_part;
-  double* mass_l1;
+  double* mass_l1;           // [kPartL1]
+  int32_t* wlist;            // wall cells of the step (box slots)
+  int32_t* wcount;
   int32_t* flag;
   unsigned long long* stats; // [0] Newton iterations, [1] wall cells
   RotorTable* rot;           // device copy
@@ -40,11 +43,11 @@ struct Launch {
   double* ghost64;           // same in FP64 for the wall model
 };
 
-hipError_t launch_rasterize(const Launch& L, int64_t step);
+hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig, uint8_t* act_new);
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
                        double* ut_new, uint8_t* act_new, int64_t step);
 hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
-hipError_t launch_inflow(const Launch& L, int64_t step);
+hipError_t launch_prologue(const Launch& L, int64_t step);
 hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag);
 hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* rho, void* u, void* uhat);
 hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, const void* u);

@@ -73,6 +73,17 @@ template <> struct Store<bf16_t> {
   }
 };
 
+// Element at a uniform (scalar) base plus a 32-bit per-lane byte offset, so
+// the compiler can use the scalar-base + 32-bit-offset global addressing.
+template <class T>
+__device__ __forceinline__ const T* at_bytes(const T* base, uint32_t byte_off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ T* at_bytes(T* base, uint32_t byte_off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
 // ---------------------------------------------------------------- moments
 // Deviation moments of h_i = f_i - w_i: drho = sum h, j = sum c h,
 // p = sum c c h (so P = cs^2 I + p).

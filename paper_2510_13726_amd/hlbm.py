@@ -82,6 +82,8 @@ SIGNATURES = [
     ("hlbm_force_torque", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("hlbm_history", C.c_int, [_H, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
     ("hlbm_wall_stats", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hlbm_profile_enable", C.c_int, [_H, C.c_int32]),
+    ("hlbm_profile_read", C.c_int, [_H, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     ("hlbm_last_error", C.c_char_p, [_H]),
 ]
 
@@ -299,6 +301,20 @@ class Lattice:
         n = C.c_int64()
         self._check(self.L.hlbm_wall_stats(self.h, C.byref(it), C.byref(n)))
         return it.value, n.value
+
+
+KERNEL_SWEEP, KERNEL_WALL, KERNEL_RASTERIZE, KERNEL_OTHER = range(4)
+
+
+def profile_enable(lat, on=True):
+    lat._check(lat.L.hlbm_profile_enable(lat.h, 1 if on else 0))
+
+
+def profile_read(lat, kernel):
+    n = C.c_int64()
+    ms = C.c_double()
+    lat._check(lat.L.hlbm_profile_read(lat.h, kernel, C.byref(n), C.byref(ms)))
+    return n.value, ms.value
 
 
 def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None) -> Lattice:

@@ -50,10 +50,15 @@ def test_tgv_sphere_parity(storage):
     hg, ho = lat.history(), o.history()
     assert hg.shape == ho.shape == (100, 91)
     assert rel(hg[:, 1:7], ho[:, 1:7]) < 10 * TOL[storage]
-    assert rel(hg[:, 0], ho[:, 0]) < TOL[storage] * 1e-2 + 1e-15
-    rho_g, u_g, uh_g = (t.cpu().numpy() for t in lat.moments(uhat=True))
+    # total mass: sums of 32768 densities in different orders (and FP32 densities)
+    assert rel(hg[:, 0], ho[:, 0]) < (1e-13 if storage == "f64" else 1e-6)
+    rho_g, u_g, uh_g = (t.cpu().numpy().astype(np.float64) for t in lat.moments(uhat=True))
     rho_o, u_o, uh_o = o.moments(uhat=True)
-    assert rel(rho_g - 1, rho_o - 1) < TOL[storage]
+    e_rho = np.abs(rho_g - rho_o).max()
+    print(f"[parity] errors h {max(errs):.3e} F,T {rel(hg[:, 1:7], ho[:, 1:7]):.3e} rho(abs) {e_rho:.3e} "
+          f"u {rel(u_g, u_o):.3e} uhat {rel(uh_g, uh_o):.3e}", flush=True)
+    # rho ~ 1: the oracle forms it as sum f with f = O(1), so compare on the scale of 1
+    assert e_rho < (1e-14 if storage == "f64" else 1.2e-7)
     assert rel(u_g, u_o) < TOL[storage]
     assert rel(uh_g, uh_o) < TOL[storage]
 
@@ -72,8 +77,11 @@ def test_rotor_wall_model_parity(storage):
     assert n_g == n_o and n_g > 100
     if storage == "f64":
         assert it_g == it_o
-    rho_g, u_g, uh_g = (t.cpu().numpy() for t in lat.moments(uhat=True))
+    rho_g, u_g, uh_g = (t.cpu().numpy().astype(np.float64) for t in lat.moments(uhat=True))
     rho_o, u_o, uh_o = o.moments(uhat=True)
+    print(f"[parity] errors h {max(errs):.3e} F,T {rel(hg[:, 1:7], ho[:, 1:7]):.3e} rho(abs) "
+          f"{np.abs(rho_g - rho_o).max():.3e} u {rel(u_g, u_o):.3e} uhat {rel(uh_g, uh_o):.3e} "
+          f"newton {it_g}/{it_o} wall cells {n_g}", flush=True)
     assert rel(u_g, u_o) < TOL[storage]
     assert rel(uh_g, uh_o) < TOL[storage]
 
