@@ -58,6 +58,7 @@ enum hlbm_transition { HLBM_TRANSITION_TANH = 0, HLBM_TRANSITION_LINEAR = 1 };
 /* Optional workspace sections requested at creation. */
 #define HLBM_WITH_SOLID_VELOCITY 1   /* reserve a static solid-velocity field */
 #define HLBM_WITH_CONTROL 2          /* reserve a porosity control field (adjoint) */
+#define HLBM_WITH_ADJOINT 4          /* reserve the discrete-adjoint work arrays */
 
 typedef struct hlbm_lattice* hlbm_handle;
 
@@ -187,6 +188,24 @@ int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]);
  * HLBM_HIST_STRIDE doubles each, host (syncs).  Mass is NaN on steps
  * without diagnostics. */
 int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
+
+/* Discrete adjoint of the time stepping (gradient of the time-averaged
+ * rotor torque with respect to the porosity control delta_d).
+ * Objective: J = 1/(t1-t0) sum over steps k in [t0, t1) of the record of
+ * the axial torque e_tag . T_tag (obj_tag 0 = all tags), with T from the
+ * momentum handed to the solid (Sec. 2.2.2).  Needs HLBM_WITH_ADJOINT.
+ * hlbm_forward_record advances nsteps from the current state, storing a
+ * restartable state every ckpt_every steps into ckpt (device, at least
+ * hlbm_checkpoint_bytes), and returns J (host double).  hlbm_adjoint then
+ * writes G = gJ dJ/d(delta_d) (device FP64, N values): it recomputes each
+ * segment of ckpt_every steps into stack (device, hlbm_adjoint_stack_bytes)
+ * and runs the reverse steps; Newton iterations of the wall model are
+ * differentiated as executed.  The lattice state is left unchanged. */
+int64_t hlbm_checkpoint_bytes(hlbm_handle h, int64_t nsteps, int32_t ckpt_every);
+int64_t hlbm_adjoint_stack_bytes(hlbm_handle h, int32_t ckpt_every);
+int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, int32_t obj_tag, int32_t ckpt_every,
+                        void* ckpt, int64_t ckpt_bytes, double* J);
+int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack_bytes);
 
 /* Wall-model counters since creation: Newton iterations for u_tau and wall
  * cells processed (host, syncs). */

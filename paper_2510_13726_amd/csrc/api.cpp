@@ -40,19 +40,25 @@ bool desc_ok(const hlbm_desc* d, std::string* why) {
 int64_t cells_of(const hlbm_desc* d) { return int64_t(d->nx) * d->ny * d->nz; }
 
 // Elements between the 27 population arrays: the array size rounded up to a
-// page plus a 512-byte skew, so the arrays do not all start on the same
-// DRAM channel.
+// page plus a skew of 8448 bytes (33 x 256), so the arrays do not all start
+// on the same DRAM channel (the fastest of the skews measured on MI355X).
 int64_t pop_stride(const hlbm_desc* d) {
   const int es = elem_size(d->storage);
-  int64_t pad = 512;
+  int64_t pad = 8448;
   if (const char* e = std::getenv("HLBM_POP_SKEW")) pad = std::atoll(e);
   const int64_t bytes = align_up(cells_of(d) * es, 4096) + pad;
   return bytes / es;
 }
 
+// Elements between the 27 arrays of the state adjoint (compute type).
+int64_t pop_stride_c(const hlbm_desc* d) {
+  const int es = elem_size(d->compute);
+  return (align_up(cells_of(d) * es, 4096) + 8448) / es;
+}
+
 struct Layout {
   int64_t d_eff, d_static, tag, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wcount, flag, stats, rot, geo, ut0, ut1,
-      act0, act1, wall, hist, ghost, ghost64, total;
+      act0, act1, wall, hist, ghost, ghost64, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut, scr_act, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -63,7 +69,8 @@ Layout layout(const hlbm_desc* d) {
   const int64_t B = d->bbox_cells;
   const int64_t H = d->history > 0 ? d->history : 1024;
   int64_t o = 0;
-  auto take = [&](int64_t bytes) { int64_t at = o; o = align_up(o + bytes, kAlign); return at; };
+  // every section gets at least one aligned block, so sections never alias
+  auto take = [&](int64_t bytes) { int64_t at = o; o = align_up(o + std::max<int64_t>(bytes, 1), kAlign); return at; };
   L.d_eff = take(N * cs);
   L.d_static = take(N * cs);
   L.tag = take(N);
@@ -90,25 +97,45 @@ Layout layout(const hlbm_desc* d) {
   const int64_t plane = int64_t(d->ny) * d->nz;
   L.ghost = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * cs : 0);
   L.ghost64 = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
+  const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
+  const int64_t lam_bytes = adj ? 27 * pop_stride_c(d) * cs : 0;
+  L.lam0 = take(lam_bytes);
+  L.lam1 = take(lam_bytes);
+  L.utb0 = take(adj ? B * 8 : 0);
+  L.utb1 = take(adj ? B * 8 : 0);
+  L.ubar = take(adj ? 3 * N * 8 : 0);
+  L.side = take(adj ? 9 * plane * cs : 0);
+  L.jac = take(adj ? B * 40 * 8 : 0);
+  L.scr_ut = take(adj ? B * 8 : 0);
+  L.scr_act = take(adj ? B : 0);
   L.total = o;
   return L;
 }
 
 struct RotorBox { int32_t b0[3], bn[3]; };
 
-bool rotor_box(const hlbm_desc* d, const hlbm_rotor& r, double eps_h, RotorBox* box, std::string* why) {
+// Fixed box around the rotor's swept cylinder plus a margin (the transition
+// band eps_h/2 and one cell for the rasterized box).
+bool rotor_box(const hlbm_desc* d, const hlbm_rotor& r, double margin, RotorBox* box, std::string* why,
+               bool clip = false) {
   const double an = std::sqrt(r.axis[0] * r.axis[0] + r.axis[1] * r.axis[1] + r.axis[2] * r.axis[2]);
   if (!(an > 0)) { *why = "rotor axis is zero"; return false; }
   const double hc = std::sqrt(0.25 * r.chord * r.chord + 0.25 * r.thick * r.thick);
   const double rc = std::max(std::sqrt(r.R * r.R + hc * hc), r.r_hub);
   const double ha = std::max(hc, r.r_hub);
-  const double m = 0.5 * eps_h + 1.0;
+  const double m = margin;
   const int n3[3] = {d->nx, d->ny, d->nz};
   for (int k = 0; k < 3; ++k) {
     const double e = r.axis[k] / an;
     const double ext = ha * std::fabs(e) + rc * std::sqrt(std::max(0.0, 1.0 - e * e));
-    const int lo = int(std::floor(r.center[k] - ext - m));
-    const int hi = int(std::ceil(r.center[k] + ext + m));
+    int lo = int(std::floor(r.center[k] - ext - m));
+    int hi = int(std::ceil(r.center[k] + ext + m));
+    if (clip) {
+      // capacity bound: the solid itself must fit, the margin is clipped
+      if (r.center[k] - ext < 0 || r.center[k] + ext > n3[k] - 1) { *why = "rotor leaves the domain"; return false; }
+      lo = lo < 0 ? 0 : lo;
+      hi = hi > n3[k] - 1 ? n3[k] - 1 : hi;
+    }
     if (lo < 0 || hi > n3[k] - 1) { *why = "rotor bounding box leaves the domain"; return false; }
     box->b0[k] = lo;
     box->bn[k] = hi - lo + 1;
@@ -137,6 +164,14 @@ struct hlbm_lattice {
   int64_t hist_start = 0;      // first step recorded since init
   int64_t hist_cap = 0;
   std::string err;
+  // forward record of the discrete adjoint
+  struct Record {
+    bool valid = false;
+    int64_t n0 = 0, nsteps = 0, t0 = 0, t1 = 0;
+    int32_t obj_tag = 0, ckpt_every = 1;
+    char* ckpt = nullptr;
+    double J = 0.0;
+  } rec;
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[4];
   std::vector<hipEvent_t> pool;
@@ -208,7 +243,7 @@ int build_rotor_table(hlbm_handle h, const hlbm_rotor* r, int32_t n, RotorTable*
       return fail(h, HLBM_ERR_INVALID, "rotor needs R > r_hub >= 0, chord > 0, thick > 0");
     RotorBox box;
     std::string why;
-    if (!rotor_box(&h->desc, q, h->params.eps_h, &box, &why)) return fail(h, HLBM_ERR_INVALID, why);
+    if (!rotor_box(&h->desc, q, 0.5 * h->params.eps_h + 1.0, &box, &why)) return fail(h, HLBM_ERR_INVALID, why);
     RotorDev& d = t.r[k];
     const double an = std::sqrt(q.axis[0] * q.axis[0] + q.axis[1] * q.axis[1] + q.axis[2] * q.axis[2]);
     for (int a = 0; a < 3; ++a) { d.c[a] = q.center[a]; d.e[a] = q.axis[a] / an; }
@@ -226,6 +261,11 @@ int build_rotor_table(hlbm_handle h, const hlbm_rotor* r, int32_t n, RotorTable*
     d.tw_root = q.twist_root; d.tw_tip = q.twist_tip; d.omega = q.omega; d.phase0 = q.phase0;
     d.nb = q.n_blades; d.tag = q.tag;
     for (int a = 0; a < 3; ++a) { d.b0[a] = box.b0[a]; d.bn[a] = box.bn[a]; }
+    // FSI workgroups also cover the wall model's probe corners (reach y_s + 1
+    // beyond the box; periodic in y and z), where the adjoint gathers the
+    // probe-velocity adjoints
+    const int reach = h->params.wall_model ? int(std::ceil(h->params.y_s)) + 1 : 0;
+    for (int a = 0; a < 3; ++a) { d.mb0[a] = box.b0[a] - reach; d.mbn[a] = box.bn[a] + 2 * reach; }
     d.cells = int64_t(box.bn[0]) * box.bn[1] * box.bn[2];
     d.off = off;
     off += d.cells;
@@ -279,8 +319,8 @@ int64_t hlbm_rotor_bbox_cells(const hlbm_desc* d, const hlbm_rotor* r, int32_t n
   int64_t total = 0;
   for (int k = 0; k < n; ++k) {
     RotorBox b;
-    // the widest band the workspace must allow for: eps_h up to 4 cells
-    if (!rotor_box(d, r[k], 4.0, &b, &why)) return -1;
+    // the widest band the workspace allows for: eps_h <= 4 cells
+    if (!rotor_box(d, r[k], 0.5 * 4.0 + 1.0, &b, &why, true)) return -1;
     total += int64_t(b.bn[0]) * b.bn[1] * b.bn[2];
   }
   return total;
@@ -531,42 +571,220 @@ hipError_t timed(hlbm_handle h, int kind, F&& f) {
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+// One forward step n from state `src` to `dst` with the wall-model state
+// (ut_prev, act_prev) -> (ut_new, act_new); `jac` (optional) receives the
+// wall Jacobians of the listed wall cells.
+hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, const double* ut_prev,
+                       const uint8_t* act_prev, double* ut_new, uint8_t* act_new) {
+  const bool wall = h->params.wall_model && h->L.nrot > 0;
+  const BladeTrig trig = blade_trig(h, n);
+  hipError_t e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_prologue(h->L, n); });
+  if (e == hipSuccess)
+    e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_rasterize(h->L, n, trig, act_new); });
+  if (e == hipSuccess && wall)
+    e = timed(h, HLBM_KERNEL_WALL, [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n); });
+  const bool diag = h->params.diag_every > 0 && n % h->params.diag_every == 0;
+  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, diag); });
+  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, n, h->nslots, diag); });
+  return e;
+}
+
+int check_flag(hlbm_handle h) {
+  int32_t flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, h->L.flag, 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "read non-finite flag");
+  if (flag) {
+    (void)hipMemsetAsync(h->L.flag, 0, 4, h->stream);
+    return fail(h, HLBM_ERR_NONFINITE, "non-finite density before step " + std::to_string(h->step));
+  }
+  return HLBM_OK;
+}
+
+// Restartable state in the checkpoint / stack layout: populations, u_tau, active.
+struct StateLayout {
+  int64_t pops, ut, act, bytes;
+};
+StateLayout state_layout(hlbm_handle h) {
+  StateLayout s;
+  const int64_t B = h->L.bbox_total;
+  s.pops = 27 * h->L.g.stride * elem_size(h->desc.storage);
+  s.ut = align_up(s.pops, 256);
+  s.act = s.ut + align_up(B * 8, 256);
+  s.bytes = s.act + align_up(std::max<int64_t>(B, 1), 256);
+  return s;
+}
+
+hipError_t copy_state_out(hlbm_handle h, char* dst) {
+  const StateLayout s = state_layout(h);
+  const int64_t B = h->L.bbox_total;
+  hipError_t e = hipMemcpyAsync(dst, h->pop[h->cur], s.pops, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && B) e = hipMemcpyAsync(dst + s.ut, h->ut[h->wcur], B * 8, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && B) e = hipMemcpyAsync(dst + s.act, h->act[h->wcur], B, hipMemcpyDeviceToDevice, h->stream);
+  return e;
+}
+
+// Axial torque of the selected tags in a history record.
+double axial_torque(hlbm_handle h, const double* rec, int32_t obj_tag) {
+  double J = 0.0;
+  for (int t = 1; t < kTags; ++t) {
+    if (obj_tag != 0 && obj_tag != t) continue;
+    const double* T = rec + 4 + 6 * (t - 1);
+    J += h->rot.frame[t][3] * T[0] + h->rot.frame[t][4] * T[1] + h->rot.frame[t][5] * T[2];
+  }
+  return J;
+}
+}  // namespace
+
+extern "C" {
+
 int hlbm_step(hlbm_handle h, int64_t n) {
   if (!h) return HLBM_ERR_INVALID;
   if (n < 0) return fail(h, HLBM_ERR_INVALID, "n must be >= 0");
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   for (int64_t k = 0; k < n; ++k) {
-    const BladeTrig trig = blade_trig(h, h->step);
-    hipError_t e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_prologue(h->L, h->step); });
-    if (e == hipSuccess)
-      e = timed(h, HLBM_KERNEL_RASTERIZE,
-                [&] { return launch_rasterize(h->L, h->step, trig, h->act[1 - h->wcur]); });
-    if (e == hipSuccess && wall)
-      e = timed(h, HLBM_KERNEL_WALL, [&] {
-        return launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur],
-                           h->act[1 - h->wcur], h->step);
-      });
-    const bool diag = h->params.diag_every > 0 && h->step % h->params.diag_every == 0;
-    if (e == hipSuccess)
-      e = timed(h, HLBM_KERNEL_SWEEP,
-                [&] { return launch_sweep(h->L, h->pop[h->cur], h->pop[1 - h->cur], h->step, diag); });
-    if (e == hipSuccess)
-      e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, h->step, h->nslots, diag); });
+    hipError_t e = forward_one(h, h->step, h->pop[h->cur], h->pop[1 - h->cur], h->ut[h->wcur], h->act[h->wcur],
+                               h->ut[1 - h->wcur], h->act[1 - h->wcur]);
     if (e != hipSuccess) return hip_fail(h, e, "step");
     h->cur = 1 - h->cur;
     if (wall) h->wcur = 1 - h->wcur;
     ++h->step;
   }
-  if (h->params.check_nonfinite) {
-    int32_t flag = 0;
-    hipError_t e = hipMemcpyAsync(&flag, h->L.flag, 4, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "read non-finite flag");
-    if (flag) {
-      (void)hipMemsetAsync(h->L.flag, 0, 4, h->stream);
-      return fail(h, HLBM_ERR_NONFINITE, "non-finite density before step " + std::to_string(h->step));
+  h->rec.valid = false;
+  if (h->params.check_nonfinite) return check_flag(h);
+  return HLBM_OK;
+}
+
+int64_t hlbm_checkpoint_bytes(hlbm_handle h, int64_t nsteps, int32_t ckpt_every) {
+  if (!h || nsteps < 1 || ckpt_every < 1) return -1;
+  return ((nsteps + ckpt_every - 1) / ckpt_every) * state_layout(h).bytes;
+}
+
+int64_t hlbm_adjoint_stack_bytes(hlbm_handle h, int32_t ckpt_every) {
+  if (!h || ckpt_every < 1) return -1;
+  return int64_t(ckpt_every) * state_layout(h).bytes;
+}
+
+int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, int32_t obj_tag, int32_t ckpt_every,
+                        void* ckpt, int64_t ckpt_bytes, double* J) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (!(h->desc.flags & HLBM_WITH_ADJOINT)) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_ADJOINT");
+  if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1 || obj_tag < 0 || obj_tag > 15 || !ckpt || !J)
+    return fail(h, HLBM_ERR_INVALID, "need 0 <= t0 < t1 <= nsteps, ckpt_every >= 1, 0 <= obj_tag <= 15");
+  if (ckpt_bytes < hlbm_checkpoint_bytes(h, nsteps, ckpt_every))
+    return fail(h, HLBM_ERR_INVALID, "checkpoint buffer too small");
+  const StateLayout sl = state_layout(h);
+  const int64_t n0 = h->step;
+  const int64_t chunk = std::max<int64_t>(1, h->hist_cap / 2);
+  std::vector<double> rec(kHist);
+  double acc = 0.0;
+  int64_t done = 0;
+  while (done < nsteps) {
+    const int64_t m = std::min(chunk, nsteps - done);
+    for (int64_t k = done; k < done + m; ++k) {
+      if (k % ckpt_every == 0) {
+        hipError_t e = copy_state_out(h, static_cast<char*>(ckpt) + (k / ckpt_every) * sl.bytes);
+        if (e != hipSuccess) return hip_fail(h, e, "checkpoint");
+      }
+      int rc = hlbm_step(h, 1);
+      if (rc != HLBM_OK) return rc;
+    }
+    // objective from the FP64 history of the chunk
+    for (int64_t k = std::max(done, t0); k < std::min(done + m, t1); ++k) {
+      int rc = hlbm_history(h, n0 + k, n0 + k + 1, rec.data());
+      if (rc != HLBM_OK) return rc;
+      acc += axial_torque(h, rec.data(), obj_tag);
+    }
+    done += m;
+  }
+  h->rec.valid = true;
+  h->rec.n0 = n0;
+  h->rec.nsteps = nsteps;
+  h->rec.t0 = t0;
+  h->rec.t1 = t1;
+  h->rec.obj_tag = obj_tag;
+  h->rec.ckpt_every = ckpt_every;
+  h->rec.ckpt = static_cast<char*>(ckpt);
+  h->rec.J = acc / double(t1 - t0);
+  *J = h->rec.J;
+  return HLBM_OK;
+}
+
+int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack_bytes) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (!h->rec.valid || h->step != h->rec.n0 + h->rec.nsteps)
+    return fail(h, HLBM_ERR_STATE, "hlbm_adjoint needs a preceding hlbm_forward_record and no steps since");
+  const int32_t ce = h->rec.ckpt_every;
+  if (!G || !stack || stack_bytes < hlbm_adjoint_stack_bytes(h, ce))
+    return fail(h, HLBM_ERR_INVALID, "G or stack missing, or stack too small");
+  const StateLayout sl = state_layout(h);
+  const Layout& Y = h->lay;
+  char* ws = static_cast<char*>(h->L.d_eff) - Y.d_eff;
+  void* lam[2] = {ws + Y.lam0, ws + Y.lam1};
+  double* utb[2] = {reinterpret_cast<double*>(ws + Y.utb0), reinterpret_cast<double*>(ws + Y.utb1)};
+  double* ubar = reinterpret_cast<double*>(ws + Y.ubar);
+  double* jac = reinterpret_cast<double*>(ws + Y.jac);
+  double* scr_ut = reinterpret_cast<double*>(ws + Y.scr_ut);
+  uint8_t* scr_act = reinterpret_cast<uint8_t*>(ws + Y.scr_act);
+  const int64_t N = h->L.g.N, B = std::max<int64_t>(h->L.bbox_total, 1);
+  const bool wall = h->params.wall_model && h->L.nrot > 0;
+  const int cs = elem_size(h->desc.compute);
+  const int64_t lam_bytes = 27 * pop_stride_c(&h->desc) * cs;
+  hipError_t e = hipMemsetAsync(lam[0], 0, lam_bytes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(utb[0], 0, B * 8, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ubar, 0, 3 * N * 8, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(G, 0, N * 8, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint init");
+  const int64_t nseg = (h->rec.nsteps + ce - 1) / ce;
+  int cur = 0;
+  const double w = gJ / double(h->rec.t1 - h->rec.t0);
+  char* st = static_cast<char*>(stack);
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t a = seg * ce, b = std::min<int64_t>(h->rec.nsteps, a + ce);
+    // recompute the states of the segment into the stack
+    e = hipMemcpyAsync(st, h->rec.ckpt + seg * sl.bytes, sl.bytes, hipMemcpyDeviceToDevice, h->stream);
+    for (int64_t k = a; e == hipSuccess && k + 1 < b; ++k) {
+      char* s0 = st + (k - a) * sl.bytes;
+      char* s1 = s0 + sl.bytes;
+      e = forward_one(h, h->rec.n0 + k, s0, s1, reinterpret_cast<double*>(s0 + sl.ut),
+                      reinterpret_cast<uint8_t*>(s0 + sl.act), reinterpret_cast<double*>(s1 + sl.ut),
+                      reinterpret_cast<uint8_t*>(s1 + sl.act));
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint recompute");
+    for (int64_t k = b - 1; k >= a; --k) {
+      const int64_t n = h->rec.n0 + k;
+      char* s0 = st + (k - a) * sl.bytes;
+      const double* ut0 = reinterpret_cast<const double*>(s0 + sl.ut);
+      const uint8_t* ac0 = reinterpret_cast<const uint8_t*>(s0 + sl.act);
+      // geometry, inflow and wall model of step n (with Jacobians)
+      e = launch_prologue(h->L, n);
+      if (e == hipSuccess) e = launch_rasterize(h->L, n, blade_trig(h, n), scr_act);
+      if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, jac);
+      if (e == hipSuccess) e = hipMemsetAsync(utb[1 - cur], 0, B * 8, h->stream);
+      AdjLaunch A{};
+      A.src = s0;
+      A.lam_in = lam[cur];
+      A.lam_out = lam[1 - cur];
+      A.side = ws + Y.side;
+      A.ubar = ubar;
+      A.G = G;
+      A.jac = jac;
+      A.ut_bar_in = utb[cur];
+      A.ut_bar_out = utb[1 - cur];
+      A.obj_w = (k >= h->rec.t0 && k < h->rec.t1) ? w : 0.0;
+      A.obj_tag = h->rec.obj_tag;
+      A.lstride = pop_stride_c(&h->desc);
+      if (e == hipSuccess && wall) e = launch_adjoint_wall(h->L, A);
+      if (e == hipSuccess) e = launch_adjoint_sweep(h->L, A);
+      if (e != hipSuccess) return hip_fail(h, e, "adjoint step");
+      cur = 1 - cur;
     }
   }
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint");
   return HLBM_OK;
 }
 

@@ -28,6 +28,7 @@ struct RotorDev {
   double R, r_hub, chord, thick, tw_root, tw_tip, omega, phase0;
   int32_t nb, tag;
   int32_t b0[3], bn[3];   // bounding box origin and extent (cells)
+  int32_t mb0[3], mbn[3]; // FSI marking box (box + probe reach, may wrap in y, z)
   int64_t off;            // first slot of this box in the box pools
   int64_t cells;          // bn[0]*bn[1]*bn[2]
 };

@@ -261,28 +261,69 @@ __global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict_
 }
 
 // ---------------------------------------------------------------- wall model
-__device__ __forceinline__ double spalding_bracket(double k) {
-  const double ek = k > 80.0 ? exp(80.0) : exp(k);
+// Forward-mode dual number with four directions (probe velocity, previous
+// friction velocity): differentiates the wall model exactly as executed.
+namespace dual {
+struct D4 {
+  double v, g[4];
+};
+__device__ __forceinline__ D4 mk(double v) { D4 r; r.v = v; r.g[0] = r.g[1] = r.g[2] = r.g[3] = 0.0; return r; }
+__device__ __forceinline__ D4 operator+(D4 a, D4 b) { D4 r; r.v = a.v + b.v; for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] + b.g[q]; return r; }
+__device__ __forceinline__ D4 operator-(D4 a, D4 b) { D4 r; r.v = a.v - b.v; for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] - b.g[q]; return r; }
+__device__ __forceinline__ D4 operator*(D4 a, D4 b) { D4 r; r.v = a.v * b.v; for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] * b.v + a.v * b.g[q]; return r; }
+__device__ __forceinline__ D4 operator/(D4 a, D4 b) {
+  D4 r; r.v = a.v / b.v;
+  const double ib = 1.0 / (b.v * b.v);
+  for (int q = 0; q < 4; ++q) r.g[q] = (a.g[q] * b.v - a.v * b.g[q]) * ib;
+  return r;
+}
+__device__ __forceinline__ D4 operator+(D4 a, double b) { return a + mk(b); }
+__device__ __forceinline__ D4 operator-(D4 a, double b) { return a - mk(b); }
+__device__ __forceinline__ D4 operator-(double a, D4 b) { return mk(a) - b; }
+__device__ __forceinline__ D4 operator*(double a, D4 b) { return mk(a) * b; }
+__device__ __forceinline__ D4 operator*(D4 a, double b) { return a * mk(b); }
+__device__ __forceinline__ D4 operator/(D4 a, double b) { return a / mk(b); }
+__device__ __forceinline__ D4 operator/(double a, D4 b) { return mk(a) / b; }
+__device__ __forceinline__ D4 operator+(double a, D4 b) { return mk(a) + b; }
+__device__ __forceinline__ D4 sqrt(D4 a) { D4 r; r.v = ::sqrt(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] / (2.0 * r.v); return r; }
+__device__ __forceinline__ D4 exp(D4 a) { D4 r; r.v = ::exp(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] * r.v; return r; }
+__device__ __forceinline__ D4 log(D4 a) { D4 r; r.v = ::log(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] / a.v; return r; }
+__device__ __forceinline__ double val(D4 a) { return a.v; }
+}  // namespace dual
+using dual::D4;
+using dual::mk;
+__device__ __forceinline__ double val(double a) { return a; }
+using dual::val;
+template <class R> __device__ __forceinline__ R cst(double v);
+template <> __device__ __forceinline__ double cst<double>(double v) { return v; }
+template <> __device__ __forceinline__ D4 cst<D4>(double v) { return mk(v); }
+
+// Truncated Spalding bracket e^k - 1 - k - k^2/2 - k^3/6 (eq. spalding) with
+// the exponential capped at e^80, and its derivative.
+template <class R>
+__device__ __forceinline__ R spalding_bracket(R k) {
+  const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
   return ek - 1.0 - k - k * k * 0.5 - k * k * k / 6.0;
 }
-__device__ __forceinline__ double spalding_dbracket(double k) {
-  const double ek = k > 80.0 ? 0.0 : exp(k);
+template <class R>
+__device__ __forceinline__ R spalding_dbracket(R k) {
+  const R ek = val(k) > 80.0 ? cst<R>(0.0) : exp(k);
   return ek - 1.0 - k - k * k * 0.5;
 }
 
 // Newton iteration of Sec. 2.2.1 (stop when |f(u^{j+1}) - f(u^j)| < tol or
 // after maxit steps, halving a non-positive iterate).
-template <class F>
-__device__ __forceinline__ double newton(double u, F&& fdf, double tol, int maxit, int& iters) {
-  double fu, du;
+template <class R, class F>
+__device__ __forceinline__ R newton(R u, F&& fdf, double tol, int maxit, int& iters) {
+  R fu, du;
   fdf(u, fu, du);
   int it = 0;
   for (; it < maxit; ++it) {
-    double un = u - fu / du;
-    if (un <= 0.0) un = 0.5 * u;
-    double fn, dn;
+    R un = u - fu / du;
+    if (val(un) <= 0.0) un = 0.5 * u;
+    R fn, dn;
     fdf(un, fn, dn);
-    const bool done = fabs(fn - fu) < tol;
+    const bool done = fabs(val(fn) - val(fu)) < tol;
     u = un;
     fu = fn;
     du = dn;
@@ -293,6 +334,109 @@ __device__ __forceinline__ double newton(double u, F&& fdf, double tol, int maxi
   }
   iters = it;
   return u;
+}
+
+// Wall model of one cell given its probe velocity us, wall velocity uw,
+// outward normal nn, wall distance y1 and the previous friction velocity:
+// out = (u_wm[3], S[6] as xx yy zz xy xz yz, u_tau).  Returns false when the
+// tangential slip is below 1e-10 (cell treated as a plain cell).
+template <class R>
+__device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], const double nn[3], double y1,
+                                           R utp, bool prev_active, const Model& m, R out[10], int& it1) {
+  R v[3] = {us[0] - uw[0], us[1] - uw[1], us[2] - uw[2]};
+  const R vn = v[0] * nn[0] + v[1] * nn[1] + v[2] * nn[2];
+  R vt[3] = {v[0] - vn * nn[0], v[1] - vn * nn[1], v[2] - vn * nn[2]};
+  const R U2 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
+  it1 = 0;
+  if (!(::sqrt(val(U2)) >= 1e-10)) return false;
+  const R U = sqrt(U2);
+  const R t[3] = {vt[0] / U, vt[1] / U, vt[2] / U};
+  const double nu = m.nu, ys = m.y_s, E = m.E, kap = m.kappa;
+  const R guess = prev_active ? utp : sqrt(nu * U / ys);
+  const R ut = newton(
+      guess,
+      [&](R u, R& f, R& df) {
+        const R p = U / u;
+        f = p + spalding_bracket(kap * p) / E - ys * u / nu;
+        df = 0.0 - (p / u) * (1.0 + kap * spalding_dbracket(kap * p) / E) - ys / nu;
+      },
+      m.tol, m.maxit, it1);
+  const R yp = y1 * ut / nu;
+  const R ylog = val(yp) > 1.0 ? yp : cst<R>(1.0);
+  const R ulog = log(E * ylog) / kap;
+  int it2 = 0;
+  const R up = newton(
+      val(ulog) < val(yp) ? ulog : yp,
+      [&](R u, R& f, R& df) {
+        f = u + spalding_bracket(kap * u) / E - yp;
+        df = 1.0 + kap * spalding_dbracket(kap * u) / E;
+      },
+      m.tol, m.maxit, it2);
+  const R qv = ut * up;
+  const R hd = 0.5 * ((U - qv) / (ys - y1));
+  out[0] = qv * t[0];
+  out[1] = qv * t[1];
+  out[2] = qv * t[2];
+  out[3] = hd * (t[0] * nn[0] + nn[0] * t[0]);
+  out[4] = hd * (t[1] * nn[1] + nn[1] * t[1]);
+  out[5] = hd * (t[2] * nn[2] + nn[2] * t[2]);
+  out[6] = hd * (t[0] * nn[1] + nn[0] * t[1]);
+  out[7] = hd * (t[0] * nn[2] + nn[0] * t[2]);
+  out[8] = hd * (t[1] * nn[2] + nn[1] * t[2]);
+  out[9] = ut;
+  return true;
+}
+
+// Probe corner `corner` (0..7) of wall slot s: its cell and trilinear weight,
+// the cell position and the foot-point wall velocity.
+struct Probe {
+  int x, y, z;        // wall cell
+  int q[3];           // this lane's corner cell
+  double wgt;
+  double y1, nn[3], uw[3];
+};
+__device__ __forceinline__ Probe probe_of(const RotorDev& R, const Geometry& g, const Model& m,
+                                          const double* __restrict__ geo, int64_t total, int64_t s, int corner,
+                                          bool periodic_x) {
+  Probe p;
+  slot_cell(R, s, p.x, p.y, p.z);
+  p.y1 = -geo[s];
+  p.nn[0] = geo[total + s]; p.nn[1] = geo[2 * total + s]; p.nn[2] = geo[3 * total + s];
+  const double X[3] = {double(p.x), double(p.y), double(p.z)};
+  double xw[3], xs[3];
+  for (int a = 0; a < 3; ++a) {
+    xw[a] = X[a] - p.y1 * p.nn[a];
+    xs[a] = xw[a] + m.y_s * p.nn[a];
+  }
+  const double rw[3] = {xw[0] - R.c[0], xw[1] - R.c[1], xw[2] - R.c[2]};
+  p.uw[0] = R.omega * (R.e[1] * rw[2] - R.e[2] * rw[1]);
+  p.uw[1] = R.omega * (R.e[2] * rw[0] - R.e[0] * rw[2]);
+  p.uw[2] = R.omega * (R.e[0] * rw[1] - R.e[1] * rw[0]);
+  p.wgt = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    const double fl = floor(xs[a]);
+    const int bit = (corner >> a) & 1;
+    const double fr = xs[a] - fl;
+    p.q[a] = int(fl) + bit;
+    p.wgt *= bit ? fr : 1.0 - fr;
+  }
+  p.q[1] = ((p.q[1] % g.ny) + g.ny) % g.ny;
+  p.q[2] = ((p.q[2] % g.nz) + g.nz) % g.nz;
+  if (periodic_x) p.q[0] = ((p.q[0] % g.nx) + g.nx) % g.nx;
+  else p.q[0] = p.q[0] < 0 ? 0 : (p.q[0] > g.nx - 1 ? g.nx - 1 : p.q[0]);
+  return p;
+}
+
+// Trilinear probe velocity summed over the eight lanes of a group in a fixed order.
+__device__ __forceinline__ void group8_sum(double us[3]) {
+  const int base = int(threadIdx.x & 63) & ~7;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = __shfl(us[a], base + j, 64);
+    us[a] = ((o[0] + o[1]) + (o[2] + o[3])) + ((o[4] + o[5]) + (o[6] + o[7]));
+  }
 }
 
 // Wall model (Sec. 2.2.1, Sec. 3.2) on the listed wall cells, eight lanes per
@@ -306,7 +450,7 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
                                               const double* __restrict__ ut_prev, const uint8_t* __restrict__ act_prev,
                                               double* __restrict__ ut_new, uint8_t* __restrict__ act_new,
                                               CT* __restrict__ wall_out, unsigned long long* __restrict__ stats,
-                                              const double* __restrict__ ghost) {
+                                              const double* __restrict__ ghost, double* __restrict__ jac) {
   const RotorTable& rt = *rtp;
   const int corner = threadIdx.x & 7;
   const int count = *wcount;
@@ -318,97 +462,44 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
     const int64_t w = wb + ((threadIdx.x & 63) >> 3);
     const bool live = w < count;
     const int64_t s = wlist[live ? w : wb];
-    const int k = rotor_of_slot(rt, s);
-    const RotorDev& R = rt.r[k];
-    int x, y, z;
-    slot_cell(R, s, x, y, z);
-    const double y1 = -geo[s];
-    const double nn[3] = {geo[total + s], geo[2 * total + s], geo[3 * total + s]};
-    const double X[3] = {double(x), double(y), double(z)};
-    double xw[3], xs[3];
-    for (int a = 0; a < 3; ++a) {
-      xw[a] = X[a] - y1 * nn[a];
-      xs[a] = xw[a] + m.y_s * nn[a];
-    }
-    // this lane's probe corner and trilinear weight
-    int q[3];
-    double wgt = 1.0;
-    for (int a = 0; a < 3; ++a) {
-      const double fl = floor(xs[a]);
-      const int bit = (corner >> a) & 1;
-      const double fr = xs[a] - fl;
-      q[a] = int(fl) + bit;
-      wgt *= bit ? fr : 1.0 - fr;
-    }
-    q[1] = ((q[1] % g.ny) + g.ny) % g.ny;
-    q[2] = ((q[2] % g.nz) + g.nz) % g.nz;
-    if (kPeriodicX) q[0] = ((q[0] % g.nx) + g.nx) % g.nx;
-    else q[0] = q[0] < 0 ? 0 : (q[0] > g.nx - 1 ? g.nx - 1 : q[0]);
+    const RotorDev& R = rt.r[rotor_of_slot(rt, s)];
+    const Probe pr = probe_of(R, g, m, geo, total, s, corner, kPeriodicX);
     double h[27];
-    pull_cell<ST, double, kPeriodicX>(src, g, q[0], q[1], q[2], ghost, h);
+    pull_cell<ST, double, kPeriodicX>(src, g, pr.q[0], pr.q[1], pr.q[2], ghost, h);
     const Moments<double> mo = moments_of<double>(h);
     const double rho = 1.0 + mo.drho;
-    // lanes 0..7 of the group are adjacent: butterfly within the group, fixed order
-    double us[3] = {wgt * (mo.jx / rho), wgt * (mo.jy / rho), wgt * (mo.jz / rho)};
-    double ord[3][8];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int base = int(threadIdx.x & 63) & ~7;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) ord[a][j] = __shfl(us[a], base + j, 64);
-      us[a] = ((ord[a][0] + ord[a][1]) + (ord[a][2] + ord[a][3])) + ((ord[a][4] + ord[a][5]) + (ord[a][6] + ord[a][7]));
-    }
-    int it1 = 0, it2 = 0, done = 0;
+    double us[3] = {pr.wgt * (mo.jx / rho), pr.wgt * (mo.jy / rho), pr.wgt * (mo.jz / rho)};
+    group8_sum(us);
+    int it1 = 0, done = 0;
     if (corner == 0 && live) {
-    const double rw[3] = {xw[0] - R.c[0], xw[1] - R.c[1], xw[2] - R.c[2]};
-    const double uw[3] = {R.omega * (R.e[1] * rw[2] - R.e[2] * rw[1]), R.omega * (R.e[2] * rw[0] - R.e[0] * rw[2]),
-                          R.omega * (R.e[0] * rw[1] - R.e[1] * rw[0])};
-    double v[3] = {us[0] - uw[0], us[1] - uw[1], us[2] - uw[2]};
-    const double vn = v[0] * nn[0] + v[1] * nn[1] + v[2] * nn[2];
-    double vt[3] = {v[0] - vn * nn[0], v[1] - vn * nn[1], v[2] - vn * nn[2]};
-    const double U = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
-    const int64_t T = total;
-    if (!(U >= 1e-10)) {
-      for (int qq = 0; qq < 9; ++qq) wall_out[qq * T + s] = CT(0);
-      wall_out[9 * T + s] = CT(1);
-      act_new[s] = 0;
-    } else {
-    const double t[3] = {vt[0] / U, vt[1] / U, vt[2] / U};
-    const double nu = m.nu, ys = m.y_s, E = m.E, kap = m.kappa;
-    const double guess = act_prev[s] ? ut_prev[s] : sqrt(nu * U / ys);
-    const double ut = newton(
-        guess,
-        [&](double u, double& f, double& df) {
-          const double p = U / u;
-          f = p + spalding_bracket(kap * p) / E - ys * u / nu;
-          df = -(p / u) * (1.0 + kap * spalding_dbracket(kap * p) / E) - ys / nu;
-        },
-        m.tol, m.maxit, it1);
-    const double yp = y1 * ut / nu;
-    const double ulog = log(E * (yp > 1.0 ? yp : 1.0)) / kap;
-    const double up = newton(
-        ulog < yp ? ulog : yp,
-        [&](double u, double& f, double& df) {
-          f = u + spalding_bracket(kap * u) / E - yp;
-          df = 1.0 + kap * spalding_dbracket(kap * u) / E;
-        },
-        m.tol, m.maxit, it2);
-    const double qv = ut * up;
-    const double dudn = (U - qv) / (ys - y1);
-    wall_out[0 * T + s] = CT(qv * t[0]);
-    wall_out[1 * T + s] = CT(qv * t[1]);
-    wall_out[2 * T + s] = CT(qv * t[2]);
-    wall_out[3 * T + s] = CT(0.5 * dudn * (t[0] * nn[0] + nn[0] * t[0]));
-    wall_out[4 * T + s] = CT(0.5 * dudn * (t[1] * nn[1] + nn[1] * t[1]));
-    wall_out[5 * T + s] = CT(0.5 * dudn * (t[2] * nn[2] + nn[2] * t[2]));
-    wall_out[6 * T + s] = CT(0.5 * dudn * (t[0] * nn[1] + nn[0] * t[1]));
-    wall_out[7 * T + s] = CT(0.5 * dudn * (t[0] * nn[2] + nn[0] * t[2]));
-    wall_out[8 * T + s] = CT(0.5 * dudn * (t[1] * nn[2] + nn[1] * t[2]));
-    wall_out[9 * T + s] = CT(0);
-    ut_new[s] = ut;
-    act_new[s] = 1;
-    done = 1;
-    }
+      const int64_t T = total;
+      bool active;
+      double out[10];
+      if (jac) {
+        // values and the 10 x 4 Jacobian with respect to (us, u_tau^prev)
+        D4 ud[3], o4[10];
+        for (int a = 0; a < 3; ++a) { ud[a] = mk(us[a]); ud[a].g[a] = 1.0; }
+        D4 up = mk(ut_prev[s]);
+        up.g[3] = 1.0;
+        active = wall_solve<D4>(ud, pr.uw, pr.nn, pr.y1, up, act_prev[s] != 0, m, o4, it1);
+        for (int q = 0; q < 10; ++q) {
+          out[q] = o4[q].v;
+          for (int r = 0; r < 4; ++r) jac[w * 40 + q * 4 + r] = active ? o4[q].g[r] : 0.0;
+        }
+      } else {
+        active = wall_solve<double>(us, pr.uw, pr.nn, pr.y1, ut_prev[s], act_prev[s] != 0, m, out, it1);
+      }
+      if (!active) {
+        for (int q = 0; q < 9; ++q) wall_out[q * T + s] = CT(0);
+        wall_out[9 * T + s] = CT(1);
+        act_new[s] = 0;
+      } else {
+        for (int q = 0; q < 9; ++q) wall_out[q * T + s] = CT(out[q]);
+        wall_out[9 * T + s] = CT(0);
+        ut_new[s] = out[9];
+        act_new[s] = 1;
+        done = 1;
+      }
     }
     // Newton statistics: one atomic per wave
     int a1 = it1, a2 = done;
@@ -712,7 +803,14 @@ __global__ __launch_bounds__(256) void k_mark(const RotorTable* __restrict__ rtp
   const int y = int(r / g.nx), x = int(r - int64_t(y) * g.nx);
   bool fsi = d_static[c] != CT(0) || tag_static[c] != 0 || (dd && dd[c] != CT(0));
   const RotorTable& rt = *rtp;
-  for (int j = 0; j < rt.n && !fsi; ++j) fsi = in_box(rt.r[j], x, y, z);
+  for (int j = 0; j < rt.n && !fsi; ++j) {
+    const RotorDev& r = rt.r[j];
+    const int lx = x - r.mb0[0];
+    const int ly = ((y - r.mb0[1]) % g.ny + g.ny) % g.ny, lz = ((z - r.mb0[2]) % g.nz + g.nz) % g.nz;
+    const bool inx = g.bc_x == 0 ? (((lx % g.nx) + g.nx) % g.nx < r.mbn[0] || r.mbn[0] >= g.nx)
+                                 : (lx >= 0 && lx < r.mbn[0]);
+    fsi = inx && (ly < r.mbn[1] || r.mbn[1] >= g.ny) && (lz < r.mbn[2] || r.mbn[2] >= g.nz);
+  }
   if (fsi) blk[(int64_t(z) * g.nty + y / kTileY) * g.ntx + x / kTileX] = 1;
 }
 
@@ -726,6 +824,246 @@ __global__ __launch_bounds__(256) void k_refill(Geometry g, const CT* __restrict
   if (c >= g.N) return;
   d_eff[c] = d_static[c] + (dd ? dd[c] : CT(0));
   tag[c] = tag_static[c];
+}
+
+
+// ================================================================ adjoint
+// Reverse of step n (discrete adjoint).  The state adjoint lam is the
+// derivative of the objective with respect to the stored post-collision
+// populations f*_i (not the normalized deviations), in compute type.
+template <class CT>
+struct AdjArgs {
+  const void* src;          // state at step n (storage type)
+  const CT* lam_in;         // adjoint of the state after step n, [27][stride]
+  CT* lam_out;              // adjoint of the state at step n, [27][stride]
+  CT* side;                 // outflow side buffer [9][nz][ny]
+  int64_t lstride;          // elements between the 27 arrays of lam
+  Geometry g;
+  Model m;
+  const int32_t* blk_slot;
+  const CT* d_eff;
+  const uint8_t* tag;
+  const CT* wall_out;
+  int64_t bbox_total;
+  const RotorTable* rot;
+  const CT* uB_static;
+  const CT* ghost;
+  double* ubar;             // [3][N] probe-velocity adjoints scattered by the wall cells; zeroed here
+  double* G;                // dJ/d(delta_d), accumulated
+  double obj_w;             // weight of this step's torque in J (0 outside the window)
+  int32_t obj_tag;
+  int64_t nblocks;
+};
+
+template <class CT>
+__device__ __forceinline__ void objective_dp(const RotorTable& rt, int t, int obj_tag, double w, int x, int y, int z,
+                                             CT pb[3]) {
+  pb[0] = pb[1] = pb[2] = CT(0);
+  if (w == 0.0 || t == 0 || (obj_tag != 0 && obj_tag != t)) return;
+  const double* fr = rt.frame[t];
+  const double rx = x - fr[0], ry = y - fr[1], rz = z - fr[2];
+  // d(e . (r x dP)) / d dP = e x r
+  pb[0] = CT(w * (fr[4] * rz - fr[5] * ry));
+  pb[1] = CT(w * (fr[5] * rx - fr[3] * rz));
+  pb[2] = CT(w * (fr[3] * ry - fr[4] * rx));
+}
+
+// Homogenization inputs of an FSI cell: porosity, b = u^B + u_wm, S, sigma.
+template <class CT>
+__device__ __forceinline__ void fsi_inputs(const AdjArgs<CT>& a, const RotorTable& rt, int64_t c, int x, int y, int z,
+                                           uint8_t tb, CT& d, CT b[3], CT S[6], CT& sigma) {
+  d = a.d_eff[c];
+  b[0] = b[1] = b[2] = CT(0);
+  for (int q = 0; q < 6; ++q) S[q] = CT(0);
+  sigma = CT(1);
+  const int t = tb & kTagMask;
+  if (tb & kRotorBit) {
+    const RotorDev& R = rt.r[rt.tag2rot[t]];
+    const double rx = x - R.c[0], ry = y - R.c[1], rz = z - R.c[2];
+    b[0] = CT(R.omega * (R.e[1] * rz - R.e[2] * ry));
+    b[1] = CT(R.omega * (R.e[2] * rx - R.e[0] * rz));
+    b[2] = CT(R.omega * (R.e[0] * ry - R.e[1] * rx));
+    if (tb & kWallBit) {
+      const int64_t ws = R.off + (int64_t(z - R.b0[2]) * R.bn[1] + (y - R.b0[1])) * R.bn[0] + (x - R.b0[0]);
+      const int64_t T = a.bbox_total;
+      b[0] += a.wall_out[ws];
+      b[1] += a.wall_out[T + ws];
+      b[2] += a.wall_out[2 * T + ws];
+      for (int q = 0; q < 6; ++q) S[q] = a.wall_out[(3 + q) * T + ws];
+      sigma = a.wall_out[9 * T + ws];
+    }
+  } else if (a.uB_static) {
+    b[0] = a.uB_static[c]; b[1] = a.uB_static[a.g.N + c]; b[2] = a.uB_static[2 * a.g.N + c];
+  }
+}
+
+// Adjoint sweep over all cells: collision VJP from the local adjoint of the
+// next state, the probe-velocity adjoints gathered from the wall cells, and
+// the transpose of the pull (lam_out_i(x - c_i) = mu_i(x)).
+template <class ST, class CT, bool kPeriodicX>
+__global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
+  const Geometry& g = a.g;
+  const int64_t blk = blockIdx.x;
+  const int tpz = g.ntx * g.nty;
+  const int z = int(blk / tpz);
+  const int trem = int(blk - int64_t(z) * tpz);
+  const int ty = trem / g.ntx, tx = trem - ty * g.ntx;
+  const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
+  const int yr = ty * kTileY + int(threadIdx.x >> 6);
+  if (xr >= g.nx || yr >= g.ny) return;
+  const int x = xr, y = yr;
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+  CT h[27];
+  pull_cell<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+  const Moments<CT> mo = moments_of<CT>(h);
+  const uint32_t o4 = uint32_t(c) * uint32_t(sizeof(CT));
+  CT gb[27];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) gb[i] = CT(w_of(i)) * *at_bytes(a.lam_in + int64_t(i) * a.lstride, o4);
+  const RotorTable& rt = *a.rot;
+  CT d = CT(0), b[3] = {CT(0), CT(0), CT(0)}, S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)}, sigma = CT(1);
+  CT pb[3] = {CT(0), CT(0), CT(0)};
+  double ub[3] = {0.0, 0.0, 0.0};
+  const bool fsi = a.blk_slot[blk] >= 0;
+  if (fsi) {
+    const uint8_t tb = a.tag[c];
+    fsi_inputs(a, rt, c, x, y, z, tb, d, b, S, sigma);
+    objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
+    for (int q = 0; q < 3; ++q) {
+      ub[q] = a.ubar[q * g.N + c];
+      a.ubar[q * g.N + c] = 0.0;
+    }
+  } else if (a.uB_static) {
+    b[0] = a.uB_static[c]; b[1] = a.uB_static[g.N + c]; b[2] = a.uB_static[2 * g.N + c];
+  }
+  Moments<CT> mb;
+  CT db, bb[3], Sb[6];
+  collide_vjp<CT>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
+  if (fsi) {
+    // probe velocity u = j / rho at this cell, sampled by wall cells
+    const CT rho = CT(1) + mo.drho, irho = CT(1) / rho;
+    const CT ju = CT(ub[0]) * mo.jx + CT(ub[1]) * mo.jy + CT(ub[2]) * mo.jz;
+    mb.drho -= ju * irho * irho;
+    mb.jx += CT(ub[0]) * irho;
+    mb.jy += CT(ub[1]) * irho;
+    mb.jz += CT(ub[2]) * irho;
+  }
+  a.G[c] += double(db);
+  // transpose of the pull: the state read by f_i(x) is at x - c_i
+  const uint32_t nx = g.nx, nxy = uint32_t(g.nx) * uint32_t(g.ny);
+  const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
+  const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
+  int xp, xm;
+  if (kPeriodicX) {
+    xp = x + 1 == g.nx ? 0 : x + 1;
+    xm = x == 0 ? g.nx - 1 : x - 1;
+  } else {
+    xp = x + 1 == g.nx ? x : x + 1;
+    xm = x == 0 ? 0 : x - 1;
+  }
+  const uint32_t oz[3] = {uint32_t(zp) * nxy, uint32_t(z) * nxy, uint32_t(zm) * nxy};
+  const uint32_t oy[3] = {uint32_t(yp) * nx, uint32_t(y) * nx, uint32_t(ym) * nx};
+  const uint32_t ox[3] = {uint32_t(xp), uint32_t(x), uint32_t(xm)};
+  const int64_t plane = int64_t(g.ny) * g.nz;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+    const CT mu = mb.drho + CT(cx) * mb.jx + CT(cy) * mb.jy + CT(cz) * mb.jz + CT(cx * cx) * mb.pxx +
+                  CT(cy * cy) * mb.pyy + CT(cz * cz) * mb.pzz + CT(cx * cy) * mb.pxy + CT(cx * cz) * mb.pxz +
+                  CT(cy * cz) * mb.pyz;
+    CT* base = a.lam_out + int64_t(i) * a.lstride;
+    if (!kPeriodicX) {
+      if (cx == 1 && x == 0) {
+        continue;  // read the inflow ghost, not the state
+      }
+      if (cx == -1 && x == g.nx - 1) {
+        // clamped outflow read of (nx-1, y - cy, z - cz): also read by (nx-2, ...)
+        a.side[(i) * plane + int64_t(zp * (cz == -1) + z * (cz == 0) + zm * (cz == 1)) * g.ny +
+               (yp * (cy == -1) + y * (cy == 0) + ym * (cy == 1))] = mu;
+        continue;
+      }
+    }
+    const uint32_t o = (oz[cz + 1] + oy[cy + 1] + ox[cx + 1]) * uint32_t(sizeof(CT));
+    *at_bytes(base, o) = mu;
+  }
+  if (!kPeriodicX) {
+    // states nobody reads: (nx-1, *) for c_x = +1 and (0, *) for c_x = -1
+    if (x == g.nx - 1)
+      for (int i = 18; i < 27; ++i) a.lam_out[int64_t(i) * a.lstride + c] = CT(0);
+    if (x == 0)
+      for (int i = 0; i < 9; ++i) a.lam_out[int64_t(i) * a.lstride + c] = CT(0);
+  }
+}
+
+// Outflow: the state at (nx-1, y', z') for c_x = -1 feeds both (nx-2, .) and
+// the clamped read of (nx-1, .); add the second reader's share.
+template <class CT>
+__global__ __launch_bounds__(256) void k_adj_fixup(Geometry g, int64_t lstride, const CT* __restrict__ side,
+                                                   CT* __restrict__ lam) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t plane = int64_t(g.ny) * g.nz;
+  if (k >= plane) return;
+  const int z = int(k / g.ny), y = int(k - int64_t(z) * g.ny);
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + (g.nx - 1);
+  for (int i = 0; i < 9; ++i) lam[int64_t(i) * lstride + c] += side[i * plane + k];
+}
+
+// Wall cells: collision VJP for the adjoints of u_wm and S, then the
+// transposed wall-model Jacobian: probe-velocity adjoint scattered to the
+// eight corners (FP64 atomics) and the adjoint of the previous u_tau.
+template <class ST, class CT, bool kPeriodicX>
+__global__ __launch_bounds__(256) void k_adj_wall(AdjArgs<CT> a, const double* __restrict__ geo,
+                                                  const int32_t* __restrict__ wlist, const int32_t* __restrict__ wcount,
+                                                  const double* __restrict__ jac, const double* __restrict__ ut_bar_in,
+                                                  double* __restrict__ ut_bar_out) {
+  const Geometry& g = a.g;
+  const RotorTable& rt = *a.rot;
+  const int corner = threadIdx.x & 7;
+  const int count = *wcount;
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
+  const int64_t T = a.bbox_total;
+  for (int64_t wb = wave * 8; wb < count; wb += nwaves * 8) {
+    const int64_t w = wb + ((threadIdx.x & 63) >> 3);
+    const bool live = w < count;
+    const int64_t s = wlist[live ? w : wb];
+    const RotorDev& R = rt.r[rotor_of_slot(rt, s)];
+    const Probe pr = probe_of(R, g, a.m, geo, T, s, corner, kPeriodicX);
+    double us_b[3] = {0.0, 0.0, 0.0};
+    if (corner == 0 && live && a.wall_out[9 * T + s] == CT(0)) {
+      const int x = pr.x, y = pr.y, z = pr.z;
+      const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+      CT h[27];
+      pull_cell<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+      const Moments<CT> mo = moments_of<CT>(h);
+      CT gb[27];
+      for (int i = 0; i < 27; ++i) gb[i] = CT(w_of(i)) * a.lam_in[int64_t(i) * a.lstride + c];
+      const uint8_t tb = a.tag[c];
+      CT d, b[3], S[6], sigma, pb[3];
+      fsi_inputs(a, rt, c, x, y, z, tb, d, b, S, sigma);
+      objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
+      Moments<CT> mb;
+      CT db, bb[3], Sb[6];
+      collide_vjp<CT>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
+      double ob[10];
+      for (int q = 0; q < 3; ++q) ob[q] = double(bb[q]);
+      for (int q = 0; q < 6; ++q) ob[3 + q] = double(Sb[q]);
+      ob[9] = ut_bar_in[s];
+      double ib[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < 10; ++q)
+        for (int r = 0; r < 4; ++r) ib[r] += ob[q] * jac[w * 40 + q * 4 + r];
+      us_b[0] = ib[0]; us_b[1] = ib[1]; us_b[2] = ib[2];
+      ut_bar_out[s] = ib[3];
+    }
+    // broadcast the probe adjoint of the group's lane 0 and scatter per corner
+    const int lead = int(threadIdx.x & 63) & ~7;
+    double v[3];
+    for (int q = 0; q < 3; ++q) v[q] = __shfl(us_b[q], lead, 64);
+    if (live && (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0)) {
+      const int64_t cc = (int64_t(pr.q[2]) * g.ny + pr.q[1]) * g.nx + pr.q[0];
+      for (int q = 0; q < 3; ++q) atomicAdd(&a.ubar[q * g.N + cc], pr.wgt * v[q]);
+    }
+  }
 }
 
 // ================================================================ launchers
@@ -760,7 +1098,7 @@ hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig
 }
 
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step) {
+                       double* ut_new, uint8_t* act_new, int64_t step, double* jac) {
   (void)step;
   if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
   // persistent grid over the (device-side) wall-cell count, 32 cells per workgroup
@@ -772,11 +1110,11 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
                          L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
-                         (CT*)L.wall_out, L.stats, L.ghost64);
+                         (CT*)L.wall_out, L.stats, L.ghost64, jac);
     else
       hipLaunchKernelGGL((k_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
                          L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
-                         (CT*)L.wall_out, L.stats, L.ghost64);
+                         (CT*)L.wall_out, L.stats, L.ghost64, jac);
     return hipGetLastError();
   });
 }
@@ -845,6 +1183,55 @@ hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool d
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_l2, dim3(1), dim3(256), 0, L.stream, L.part_l1, L.mass_l1, G, diag ? 1 : 0, rec);
   return hipGetLastError();
+}
+
+template <class CT>
+static AdjArgs<CT> adj_args(const Launch& L, const AdjLaunch& A) {
+  AdjArgs<CT> a{};
+  a.src = A.src; a.lam_in = (const CT*)A.lam_in; a.lam_out = (CT*)A.lam_out; a.side = (CT*)A.side;
+  a.lstride = A.lstride;
+  a.g = L.g; a.m = L.m; a.blk_slot = L.blk_slot; a.d_eff = (const CT*)L.d_eff; a.tag = L.tag;
+  a.wall_out = (const CT*)L.wall_out; a.bbox_total = L.bbox_total; a.rot = L.rot;
+  a.uB_static = (const CT*)L.uB_static; a.ghost = (const CT*)L.ghost; a.ubar = A.ubar; a.G = A.G;
+  a.obj_w = A.obj_w; a.obj_tag = A.obj_tag; a.nblocks = L.nblocks;
+  return a;
+}
+
+hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A) {
+  if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
+  int64_t blocks = (L.bbox_total + 31) / 32;
+  if (blocks > 1024) blocks = 1024;
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    AdjArgs<CT> a = adj_args<CT>(L, A);
+    if (L.g.bc_x == 0)
+      hipLaunchKernelGGL((k_adj_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo, L.wlist,
+                         L.wcount, A.jac, A.ut_bar_in, A.ut_bar_out);
+    else
+      hipLaunchKernelGGL((k_adj_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo,
+                         L.wlist, L.wcount, A.jac, A.ut_bar_in, A.ut_bar_out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A) {
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    AdjArgs<CT> a = adj_args<CT>(L, A);
+    if (L.g.bc_x == 0) {
+      hipLaunchKernelGGL((k_adj_sweep<ST, CT, true>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_adj_sweep<ST, CT, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t plane = int64_t(L.g.ny) * L.g.nz;
+    hipLaunchKernelGGL(k_adj_fixup<CT>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, A.lstride,
+                       (const CT*)A.side, (CT*)A.lam_out);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, const void* u) {

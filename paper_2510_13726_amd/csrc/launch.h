@@ -45,7 +45,7 @@ struct Launch {
 
 hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig, uint8_t* act_new);
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step);
+                       double* ut_new, uint8_t* act_new, int64_t step, double* jac = nullptr);
 hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
 hipError_t launch_prologue(const Launch& L, int64_t step);
 hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag);
@@ -56,6 +56,24 @@ hipError_t launch_set_populations(const Launch& L, void* dst, const double* src)
 hipError_t launch_get_populations_at(const Launch& L, const void* src, const int64_t* cells, int64_t count,
                                      double* dst);
 hipError_t launch_mark_blocks(const Launch& L);
+
+// One reverse step of the discrete adjoint.
+struct AdjLaunch {
+  const void* src;          // state at the step (storage type)
+  const void* lam_in;       // adjoint of the next state (compute type)
+  void* lam_out;            // adjoint of this state
+  void* side;               // outflow side buffer [9][nz][ny]
+  int64_t lstride;          // elements between the 27 arrays of lam
+  double* ubar;             // [3][N] FP64, zero on entry of the sweep except wall scatter
+  double* G;                // [N] FP64 gradient accumulator
+  const double* jac;        // wall Jacobians of the listed wall cells [count][40]
+  const double* ut_bar_in;  // adjoint of the friction velocity written by the step
+  double* ut_bar_out;       // adjoint of the friction velocity read by the step
+  double obj_w;
+  int32_t obj_tag;
+};
+hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A);
+hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A);
 hipError_t launch_refill_porosity(const Launch& L);
 hipError_t launch_fill_rest(const Launch& L, void* dst);
 

@@ -297,3 +297,190 @@ __device__ __forceinline__ double inflow_normal(uint64_t seed, int64_t n, int y,
 }
 
 }  // namespace hlbm
+
+namespace hlbm {
+
+// ---------------------------------------------------------------- reverse mode
+// Sums of the adjoint gbar over the velocities against the coefficient
+// patterns of `reconstruct` (its transpose): E0 -> 1, B_aa -> c_a^2,
+// D_ab -> c_a c_b, V_b -> c_b, T_ab -> c_a^2 c_b, X -> c_x c_y c_z.
+template <class CT>
+__device__ __forceinline__ Coef<CT> reconstruct_transpose(const CT gb[27]) {
+  CT s[9], d[9], a[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const CT gm = gb[k], g0 = gb[9 + k], gp = gb[18 + k];
+    a[k] = gp + gm;
+    d[k] = gp - gm;
+    s[k] = a[k] + g0;
+  }
+  // column k = 3(cy+1) + (cz+1)
+  Coef<CT> c;
+  const CT sy_m = s[0] + s[1] + s[2], sy_0 = s[3] + s[4] + s[5], sy_p = s[6] + s[7] + s[8];
+  const CT sz_m = s[0] + s[3] + s[6], sz_p = s[2] + s[5] + s[8];
+  c.E0 = sy_m + sy_0 + sy_p;
+  c.Vy = sy_p - sy_m;
+  c.Byy = sy_p + sy_m;
+  c.Vz = sz_p - sz_m;
+  c.Bzz = sz_p + sz_m;
+  c.Dyz = (s[8] + s[0]) - (s[6] + s[2]);
+  const CT dy_m = d[0] + d[1] + d[2], dy_0 = d[3] + d[4] + d[5], dy_p = d[6] + d[7] + d[8];
+  const CT dz_m = d[0] + d[3] + d[6], dz_p = d[2] + d[5] + d[8];
+  c.Vx = dy_m + dy_0 + dy_p;
+  c.Dxy = dy_p - dy_m;
+  c.Dxz = dz_p - dz_m;
+  const CT ay_m = a[0] + a[1] + a[2], ay_0 = a[3] + a[4] + a[5], ay_p = a[6] + a[7] + a[8];
+  c.Bxx = ay_m + ay_0 + ay_p;
+  c.Txy = ay_p - ay_m;                               // sum cx^2 cy g
+  c.Txz = (a[2] + a[5] + a[8]) - (a[0] + a[3] + a[6]);  // sum cx^2 cz g
+  c.Tyx = dy_m + dy_p;                               // sum cy^2 cx g
+  c.Tzx = dz_m + dz_p;                               // sum cz^2 cx g
+  c.Tyz = (s[8] + s[2]) - (s[6] + s[0]);             // sum cy^2 cz g
+  c.Tzy = (s[8] + s[6]) - (s[2] + s[0]);             // sum cz^2 cy g
+  c.X = (d[8] + d[0]) - (d[6] + d[2]);               // sum cx cy cz g
+  return c;
+}
+
+// Vector-Jacobian product of `collide` (with the homogenized velocity
+// u_hat = u + d (b - u), b = u^B + u_wm) and of the momentum handed to the
+// solid dP = j - rho u_hat.  gb = adjoint of the normalized post-collision
+// deviations (w_i times the adjoint of f*_i), pb = adjoint of dP.  Returns
+// the adjoints of the deviation moments, of d and of b (= of u_wm) and S.
+template <class CT>
+__device__ __forceinline__ void collide_vjp(const Moments<CT>& m, CT d, CT bx, CT by, CT bz, CT sigma, const CT S[6],
+                                            CT tau0, CT smag, const CT gb[27], const CT pb[3], Moments<CT>& mb,
+                                            CT& db, CT bb[3], CT Sb[6]) {
+  const CT third = CT(1.0 / 3.0), c45 = CT(4.5);
+  // ---- forward intermediates
+  const CT rho = CT(1) + m.drho, irho = CT(1) / rho;
+  const CT u[3] = {m.jx * irho, m.jy * irho, m.jz * irho};
+  const CT e[3] = {bx - u[0], by - u[1], bz - u[2]};
+  const CT uh[3] = {u[0] + d * e[0], u[1] + d * e[1], u[2] + d * e[2]};
+  const CT ru[3] = {rho * uh[0], rho * uh[1], rho * uh[2]};
+  const CT dd = m.drho * third;
+  // Pi in the order xx, yy, zz, xy, xz, yz
+  const CT P[6] = {m.pxx - dd - ru[0] * uh[0], m.pyy - dd - ru[1] * uh[1], m.pzz - dd - ru[2] * uh[2],
+                   m.pxy - ru[0] * uh[1],      m.pxz - ru[0] * uh[2],      m.pyz - ru[1] * uh[2]};
+  const CT q2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + CT(2) * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
+  const CT Q = sqrt(q2);
+  const CT sarg = smag * Q / rho;
+  const CT rr = sqrt(tau0 * tau0 + sarg);
+  const CT tau = CT(0.5) * (tau0 + rr);
+  const CT om = CT(1) - CT(1) / tau;
+  const CT os = om * sigma;
+  const CT fd = om * CT(3) * (CT(1) - sigma) * rho * tau;
+  const CT pi = c45 * os, t = c45 * os;
+  // ---- coefficient adjoints
+  const Coef<CT> k = reconstruct_transpose(gb);
+  // E0 = drho - tr(B2)/3; B_aa = b2_aa; D_ab = 2 b2_ab; T_ab = 3 b3_aab;
+  // V_b = 3 rho uh_b - sum_{a != b} b3_aab; X = 6 b3_xyz
+  CT b2b[6] = {k.Bxx - k.E0 * third, k.Byy - k.E0 * third, k.Bzz - k.E0 * third,
+               CT(2) * k.Dxy, CT(2) * k.Dxz, CT(2) * k.Dyz};
+  // b3 adjoints, indexed (a twice, b once): xxy, xxz, yyx, yyz, zzx, zzy
+  const CT b3xxy = CT(3) * k.Txy - k.Vy, b3xxz = CT(3) * k.Txz - k.Vz;
+  const CT b3yyx = CT(3) * k.Tyx - k.Vx, b3yyz = CT(3) * k.Tyz - k.Vz;
+  const CT b3zzx = CT(3) * k.Tzx - k.Vx, b3zzy = CT(3) * k.Tzy - k.Vy;
+  const CT b3xyz = CT(6) * k.X;
+  CT drho_b = k.E0;
+  CT rho_b = CT(3) * (k.Vx * uh[0] + k.Vy * uh[1] + k.Vz * uh[2]);
+  CT uh_b[3] = {CT(3) * rho * k.Vx, CT(3) * rho * k.Vy, CT(3) * rho * k.Vz};
+  CT ru_b[3] = {CT(0), CT(0), CT(0)};
+  CT Pb[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)};
+  CT t_b = CT(0);
+  // ---- B3_aab = 4.5 ru_a uh_a uh_b + t (2 uh_a Pi_ab + uh_b Pi_aa)
+  // indices into P for Pi_ab: pair(a,b)
+  auto b3_back = [&](int a, int b, int pab, CT g) {
+    ru_b[a] += c45 * uh[a] * uh[b] * g;
+    uh_b[a] += c45 * ru[a] * uh[b] * g + t * CT(2) * P[pab] * g;
+    uh_b[b] += c45 * ru[a] * uh[a] * g + t * P[a] * g;
+    t_b += (CT(2) * uh[a] * P[pab] + uh[b] * P[a]) * g;
+    Pb[pab] += t * CT(2) * uh[a] * g;
+    Pb[a] += t * uh[b] * g;
+  };
+  b3_back(0, 1, 3, b3xxy);
+  b3_back(0, 2, 4, b3xxz);
+  b3_back(1, 0, 3, b3yyx);
+  b3_back(1, 2, 5, b3yyz);
+  b3_back(2, 0, 4, b3zzx);
+  b3_back(2, 1, 5, b3zzy);
+  // B3_xyz = 4.5 ru_x uh_y uh_z + t (uh_x Pi_yz + uh_y Pi_xz + uh_z Pi_xy)
+  ru_b[0] += c45 * uh[1] * uh[2] * b3xyz;
+  uh_b[1] += c45 * ru[0] * uh[2] * b3xyz + t * P[4] * b3xyz;
+  uh_b[2] += c45 * ru[0] * uh[1] * b3xyz + t * P[3] * b3xyz;
+  uh_b[0] += t * P[5] * b3xyz;
+  t_b += (uh[0] * P[5] + uh[1] * P[4] + uh[2] * P[3]) * b3xyz;
+  Pb[5] += t * uh[0] * b3xyz;
+  Pb[4] += t * uh[1] * b3xyz;
+  Pb[3] += t * uh[2] * b3xyz;
+  // ---- B2_ab = 4.5 ru_a uh_b + pi Pi_ab - fd S_ab
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  CT pi_b = CT(0), fd_b = CT(0);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const CT g = b2b[q];
+    ru_b[ia[q]] += c45 * uh[ib[q]] * g;
+    uh_b[ib[q]] += c45 * ru[ia[q]] * g;
+    pi_b += P[q] * g;
+    Pb[q] += pi * g;
+    fd_b -= S[q] * g;
+    Sb[q] = -fd * g;
+  }
+  // ---- relaxation: os = om sigma, pi = t = 4.5 os, fd = 3 om (1 - sigma) rho tau
+  const CT os_b = c45 * (pi_b + t_b);
+  CT om_b = sigma * os_b + CT(3) * (CT(1) - sigma) * rho * tau * fd_b;
+  rho_b += CT(3) * om * (CT(1) - sigma) * tau * fd_b;
+  CT tau_b = CT(3) * om * (CT(1) - sigma) * rho * fd_b;
+  tau_b += om_b / (tau * tau);
+  // tau = (tau0 + sqrt(tau0^2 + smag Q / rho)) / 2
+  const CT sarg_b = CT(0.5) * tau_b / (CT(2) * rr);
+  const CT Q_b = smag * sarg_b / rho;
+  rho_b -= smag * Q * sarg_b / (rho * rho);
+  if (Q > CT(0)) {
+    const CT q2_b = Q_b / (CT(2) * Q);
+    Pb[0] += CT(2) * P[0] * q2_b;
+    Pb[1] += CT(2) * P[1] * q2_b;
+    Pb[2] += CT(2) * P[2] * q2_b;
+    Pb[3] += CT(4) * P[3] * q2_b;
+    Pb[4] += CT(4) * P[4] * q2_b;
+    Pb[5] += CT(4) * P[5] * q2_b;
+  }
+  // ---- Pi_aa = p_aa - drho/3 - ru_a uh_a, Pi_ab = p_ab - ru_a uh_b
+  mb.pxx = Pb[0]; mb.pyy = Pb[1]; mb.pzz = Pb[2]; mb.pxy = Pb[3]; mb.pxz = Pb[4]; mb.pyz = Pb[5];
+  drho_b -= (Pb[0] + Pb[1] + Pb[2]) * third;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    ru_b[ia[q]] -= uh[ib[q]] * Pb[q];
+    uh_b[ib[q]] -= ru[ia[q]] * Pb[q];
+  }
+  // ---- dP = j - ru
+  CT j_b[3] = {pb[0], pb[1], pb[2]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ru_b[a] -= pb[a];
+  // ---- ru = rho uh
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    rho_b += uh[a] * ru_b[a];
+    uh_b[a] += rho * ru_b[a];
+  }
+  // ---- uh = u + d (b - u)
+  CT u_b[3];
+  db = CT(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u_b[a] = (CT(1) - d) * uh_b[a];
+    db += e[a] * uh_b[a];
+    bb[a] = d * uh_b[a];
+  }
+  // ---- u = j / rho
+  CT ju = CT(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    j_b[a] += irho * u_b[a];
+    ju += m.jx * (a == 0) * u_b[a] + m.jy * (a == 1) * u_b[a] + m.jz * (a == 2) * u_b[a];
+  }
+  rho_b -= irho * irho * ju;
+  mb.drho = drho_b + rho_b;
+  mb.jx = j_b[0]; mb.jy = j_b[1]; mb.jz = j_b[2];
+}
+
+}  // namespace hlbm

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libhlbm.so")
 HLBM_OK, HLBM_ERR_INVALID, HLBM_ERR_HIP, HLBM_ERR_NONFINITE, HLBM_ERR_STATE = range(5)
 F64, F32, F16, BF16 = 0, 1, 2, 3
 BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
-WITH_SOLID_VELOCITY, WITH_CONTROL = 1, 2
+WITH_SOLID_VELOCITY, WITH_CONTROL, WITH_ADJOINT = 1, 2, 4
 HIST_STRIDE = 91
 DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 
@@ -82,6 +82,11 @@ SIGNATURES = [
     ("hlbm_force_torque", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("hlbm_history", C.c_int, [_H, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
     ("hlbm_wall_stats", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hlbm_checkpoint_bytes", C.c_int64, [_H, C.c_int64, C.c_int32]),
+    ("hlbm_adjoint_stack_bytes", C.c_int64, [_H, C.c_int32]),
+    ("hlbm_forward_record", C.c_int, [_H, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _V, C.c_int64,
+                                      C.POINTER(C.c_double)]),
+    ("hlbm_adjoint", C.c_int, [_H, C.c_double, _V, _V, C.c_int64]),
     ("hlbm_profile_enable", C.c_int, [_H, C.c_int32]),
     ("hlbm_profile_read", C.c_int, [_H, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     ("hlbm_last_error", C.c_char_p, [_H]),
@@ -296,6 +301,31 @@ class Lattice:
         self._check(self.L.hlbm_history(self.h, start, stop, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
+    # ------------------------------------------------------------ adjoint
+    def forward_record(self, nsteps, t0, t1, obj_tag=0, ckpt_every=100):
+        """Advance nsteps recording checkpoints; returns J (mean axial torque
+        over steps [t0, t1) of the run)."""
+        nb = self.L.hlbm_checkpoint_bytes(self.h, nsteps, ckpt_every)
+        if nb < 0:
+            raise HlbmError(HLBM_ERR_INVALID, "bad checkpoint request")
+        if getattr(self, "_ckpt", None) is None or self._ckpt.numel() < nb:
+            self._ckpt = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        J = C.c_double()
+        self._check(self.L.hlbm_forward_record(self.h, nsteps, t0, t1, obj_tag, ckpt_every,
+                                               C.c_void_p(self._ckpt.data_ptr()), self._ckpt.numel(), C.byref(J)))
+        self._ckpt_every = ckpt_every
+        return J.value
+
+    def adjoint(self, gJ=1.0):
+        """G = gJ dJ/d(delta_d) of the last forward_record, FP64 (N,) on the device."""
+        nb = self.L.hlbm_adjoint_stack_bytes(self.h, self._ckpt_every)
+        if getattr(self, "_stack", None) is None or self._stack.numel() < nb:
+            self._stack = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        G = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.hlbm_adjoint(self.h, float(gJ), C.c_void_p(G.data_ptr()),
+                                        C.c_void_p(self._stack.data_ptr()), self._stack.numel()))
+        return G
+
     def wall_stats(self):
         it = C.c_int64()
         n = C.c_int64()
@@ -317,7 +347,7 @@ def profile_read(lat, kernel):
     return n.value, ms.value
 
 
-def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None) -> Lattice:
+def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None) -> "Lattice":
     """Lattice loaded with a workload's inputs at step 0 (same recipe as the oracle)."""
     from . import workloads as W
     lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device)
@@ -334,3 +364,27 @@ def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=Non
         h = lat.get_populations()
         lat.set_populations(h + lat.torch.as_tensor(noise, device=lat.device))
     return lat
+
+
+def torque_objective_function():
+    """torch.autograd.Function: J = mean axial rotor torque over a window of
+    the run, as a function of the porosity control delta_d; backward runs the
+    library's discrete adjoint (checkpointed) and returns dJ/d(delta_d)."""
+    import torch
+
+    class TorqueObjective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, delta_d, lat, state0, nsteps, t0, t1, obj_tag, ckpt_every):
+            lat.set_state(state0)
+            lat.set_control(delta_d.detach())
+            J = lat.forward_record(nsteps, t0, t1, obj_tag, ckpt_every)
+            ctx.lat = lat
+            ctx.dshape, ctx.ddtype = delta_d.shape, delta_d.dtype
+            return torch.tensor(J, dtype=torch.float64, device=delta_d.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            G = ctx.lat.adjoint(float(gJ.item()))
+            return G.to(ctx.ddtype).reshape(ctx.dshape), None, None, None, None, None, None, None
+
+    return TorqueObjective

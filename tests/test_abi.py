@@ -39,7 +39,7 @@ def test_host_size_helpers():
     d = hlbm.make_desc(256, 128, 128, hlbm.F32)
     pb = L.hlbm_population_bytes(C.byref(d))
     N = 256 * 128 * 128
-    assert 27 * N * 4 <= pb < 27 * (N * 4 + 8192)
+    assert 27 * N * 4 <= pb <= 27 * (N * 4 + 4096 + 8448)  # page rounding + channel skew
     d16 = hlbm.make_desc(256, 128, 128, hlbm.F16)
     assert L.hlbm_population_bytes(C.byref(d16)) < pb / 1.9
     assert L.hlbm_workspace_bytes(C.byref(d)) > 0
@@ -56,8 +56,9 @@ def test_rotor_bbox_cells():
     d = hlbm.make_desc(w.nx, w.ny, w.nz, hlbm.F32, bc_x=w.bc_x)
     arr = hlbm._rotor_array(w.rotors)
     n = L.hlbm_rotor_bbox_cells(C.byref(d), arr, 1)
-    # bounding box of a cylinder of radius ~40 and half-length ~4, plus the band
-    assert 85 ** 2 * 10 < n < 95 ** 2 * 16
+    # bounding box of a cylinder of radius ~40 and half-length ~4, plus the
+    # widest band the workspace allows for (3 cells)
+    assert 85 ** 2 * 10 < n < 95 ** 2 * 18
     w.rotors[0].center = (51.0, 10.0, 64.0)  # sticks out of the domain
     assert L.hlbm_rotor_bbox_cells(C.byref(d), hlbm._rotor_array(w.rotors), 1) == -1
 

@@ -1,0 +1,74 @@
+"""GPU discrete adjoint vs the oracle's adjoint (itself pinned by complex-step
+derivatives), the autograd wrapper, and finite differences through the
+porosity control."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_13726_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _hl():
+    from paper_2510_13726_amd import hlbm
+    return hlbm
+
+
+def _cases():
+    a = W.config1(noise=True, n=12)
+    a.params.cs_smag = 0.15
+    b = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52, turb=0.05)
+    return {"sphere": (a, 12, 4, 12), "rotor": (b, 10, 3, 10)}
+
+
+@pytest.mark.parametrize("case", ["sphere", "rotor"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_matches_oracle(case, storage):
+    hl = _hl()
+    w, n, t0, t1 = _cases()[case]
+    print(f"[adjoint] {case} {storage}", flush=True)
+    o = O.setup(w)
+    J_or, G_or = o.adjoint_run(n, t0, t1, obj_tag=0, ckpt_every=4)
+    lat = hl.setup(w, storage=storage, flags=hl.WITH_ADJOINT)
+    J = lat.forward_record(n, t0, t1, obj_tag=0, ckpt_every=4)
+    G = lat.adjoint(1.0).cpu().numpy()
+    # J sums torques of opposite sign: measure its error on the scale of the
+    # largest force times the domain size
+    hist = o.history()
+    scale = max(abs(J_or), np.abs(hist[:, 1:].reshape(len(hist), 15, 6)[:, :, :3]).max() * w.nx)
+    eJ = abs(J - J_or) / scale
+    eG = np.abs(G - G_or).max() / np.abs(G_or).max()
+    print(f"[adjoint] {case} {storage}: J {J:.6e} vs {J_or:.6e} (rel {eJ:.2e}); G rel err {eG:.2e}", flush=True)
+    tol = {"f64": (1e-12, 1e-11), "f32": (1e-4, 1e-3)}[storage]
+    assert eJ < tol[0]
+    assert eG < tol[1]
+    # the lattice is left in the forward final state
+    h = lat.get_populations().cpu().numpy()
+    assert np.abs(h - o.get_populations()).max() / np.abs(o.get_populations()).max() < 10 * tol[0] + 1e-5 * (storage == "f32")
+
+
+def test_autograd_function_and_finite_differences():
+    hl = _hl()
+    torch = pytest.importorskip("torch")
+    w, n, t0, t1 = _cases()["rotor"]
+    lat = hl.setup(w, storage="f64", flags=hl.WITH_ADJOINT | hl.WITH_CONTROL)
+    state0 = lat.get_state().clone()
+    TorqueObjective = hl.torque_objective_function()
+    dd = torch.zeros(w.cells, dtype=torch.float64, device=lat.device, requires_grad=True)
+    J = TorqueObjective.apply(dd, lat, state0, n, t0, t1, 0, 4)
+    J.backward()
+    g = dd.grad.cpu().numpy()
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
+    # central differences of the GPU forward at the largest-gradient cells
+    cells = np.argsort(-np.abs(g))[:3]
+    eps = 1e-6
+    for c in cells:
+        Js = []
+        for sgn in (1.0, -1.0):
+            pert = torch.zeros(w.cells, dtype=torch.float64, device=lat.device)
+            pert[int(c)] = sgn * eps
+            Js.append(float(TorqueObjective.apply(pert, lat, state0, n, t0, t1, 0, 4)))
+        fd = (Js[0] - Js[1]) / (2 * eps)
+        print(f"[adjoint] cell {c}: adjoint {g[c]:.8e} fd {fd:.8e}", flush=True)
+        assert abs(fd - g[c]) < 1e-5 * abs(g[c]) + 1e-9
