@@ -58,17 +58,21 @@ def time_storage(w, storage, steps, warmup):
     lat.step(steps)
     n, ms = hlbm.profile_read(lat, hlbm.KERNEL_SWEEP)
     hlbm.profile_enable(lat, False)
+    fsi_cells, bulk_cells = hlbm.sweep_partition(lat)
+    # with the internal second stream the timed sweep launch is the bulk part
+    sweep_cells = bulk_cells if os.environ.get("HLBM_STREAMS", "2") != "1" else w.cells
     it, cells = lat.wall_stats()
     ok = bool(torch.isfinite(lat.moments()[0]).all().item())
     lat.close()
     del lat
     torch.cuda.empty_cache()
     return dict(mlups=w.cells * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, sweep_launches=n,
-                sweep_avg_ms=ms / max(n, 1), finite=ok, wall_cells=cells, newton_iters=it)
+                sweep_avg_ms=ms / max(n, 1), sweep_cells=sweep_cells, fsi_cells=fsi_cells, finite=ok,
+                wall_cells=cells, newton_iters=it)
 
 
-def roofline(w, storage, sweep_avg_ms):
-    algo = BYTES_PER_CELL[storage] * w.cells
+def roofline(w, storage, sweep_avg_ms, sweep_cells):
+    algo = BYTES_PER_CELL[storage] * sweep_cells
     achieved = algo / (sweep_avg_ms * 1e-3) / 1e9
     traffic = None
     f = os.path.join(ROOT, "profiles", f"sweep_traffic_{w.name}_{storage}.json")
@@ -79,8 +83,66 @@ def roofline(w, storage, sweep_avg_ms):
             traffic = t.get("bytes_per_launch")
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_sweep", "algorithmic_bytes_per_launch": algo,
+            "kernel": "k_sweep (bulk workgroups)", "cells_per_launch": sweep_cells,
+            "algorithmic_bytes_per_launch": algo,
             "avg_launch_ms": round(sweep_avg_ms, 5)}
+
+
+def adjoint_ratio(storage, steps, window, ckpt_every):
+    """Adjoint cost of the rotor-torque gradient relative to the forward run
+    on the adjoint workload (128 x 64 x 64 channel, rotor R = 20)."""
+    import torch
+    from paper_2510_13726_amd import hlbm, workloads as W
+    w = W.config4()
+    lat = hlbm.setup(w, storage=storage, diag_every=0, flags=hlbm.WITH_ADJOINT)
+    state0 = lat.get_state().clone()
+    lat.step(10)
+    lat.set_state(state0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    lat.set_state(state0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = lat.forward_record(steps, steps - window, steps, 0, ckpt_every)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    G = lat.adjoint(1.0)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    finite = bool(torch.isfinite(G).all().item())
+    gmax = float(G.abs().max().item())
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "storage": storage, "steps": steps, "window": [steps - window, steps],
+            "ckpt_every": ckpt_every, "forward_s": round(t_fwd, 4), "forward_record_s": round(t_rec, 4),
+            "adjoint_s": round(t_adj, 4), "ratio": round(t_adj / t_fwd, 3), "J": J, "grad_max": gmax,
+            "grad_finite": finite}
+
+
+def copy_bandwidth(gib=2.0, reps=20):
+    """HBM bandwidth of a plain device-to-device copy (the reference kernel
+    for scaling FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * n * 4, "avg_ms": round(ms, 4), "GB_s": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
 def cpu_baseline(w, steps):
@@ -104,6 +166,8 @@ def main():
     ap.add_argument("--config", default="2", help="workload: 1..5 (3 and 5 are full size)")
     ap.add_argument("--variants", default="f16,bf16", help="extra storage types timed on the same workload")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0 = skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint ratio run (0 = skip)")
+    ap.add_argument("--copy-reference", type=int, default=1, help="time a plain copy kernel (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -128,7 +192,15 @@ def main():
         r = time_storage(w, st, args.steps, args.warmup)
         log(f"{st}: {r}")
         variants[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
-                        "roofline": roofline(w, st, r["sweep_avg_ms"]), "finite": r["finite"]}
+                        "roofline": roofline(w, st, r["sweep_avg_ms"], r["sweep_cells"]), "finite": r["finite"]}
+    adj = None
+    if args.adjoint_steps > 0:
+        adj = adjoint_ratio(args.storage if args.storage in ("f32", "f64") else "f32", args.adjoint_steps,
+                            args.adjoint_steps // 2, 100)
+        log(f"adjoint: {adj}")
+    copy_ref = copy_bandwidth() if args.copy_reference else None
+    if copy_ref:
+        log(f"copy reference: {copy_ref}")
     cpu = None
     if args.cpu_steps > 0:
         log(f"cpu baseline: {args.cpu_steps} oracle steps")
@@ -150,9 +222,12 @@ def main():
         "config": {"workload": w.name, "cells": w.cells, "storage": args.storage,
                    "compute": "f64" if args.storage == "f64" else "f32", "rotors": len(w.rotors),
                    "wall_model": bool(w.params.wall_model), "tau0": w.params.tau0, "cs_smag": w.params.cs_smag},
-        "roofline": roofline(w, args.storage, main_run["sweep_avg_ms"]),
+        "roofline": roofline(w, args.storage, main_run["sweep_avg_ms"], main_run["sweep_cells"]),
         "cpu_baseline": cpu,
         "storage_variants": variants,
+        "adjoint_forward_ratio": adj["ratio"] if adj else None,
+        "adjoint": adj,
+        "copy_reference": copy_ref,
         "finite": main_run["finite"],
         "wall_cells_processed": main_run["wall_cells"],
         "kernel_hash": kernel_hash(),

@@ -219,6 +219,11 @@ int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
 enum hlbm_kernel { HLBM_KERNEL_SWEEP = 0, HLBM_KERNEL_WALL = 1, HLBM_KERNEL_RASTERIZE = 2, HLBM_KERNEL_OTHER = 3 };
 int hlbm_profile_enable(hlbm_handle h, int32_t enable);
 int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* total_ms);
+/* Cells swept by the porous (FSI) workgroups, which run on the caller's
+ * stream after the rotor kernels, and by the bulk workgroups, which run on
+ * an internal stream concurrently with them (host, syncs).  With the two
+ * streams on, HLBM_KERNEL_SWEEP times the bulk launches. */
+int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells);
 
 /* Message of the last error of this handle (or of the last failed create
  * when h is NULL).  Valid until the next call on the handle. */

@@ -58,7 +58,7 @@ int64_t pop_stride_c(const hlbm_desc* d) {
 
 struct Layout {
   int64_t d_eff, d_static, tag, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wcount, flag, stats, rot, geo, ut0, ut1,
-      act0, act1, wall, hist, ghost, ghost64, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut, scr_act, total;
+      act0, act1, wall, hist, ghost, ghost64, ghostb, ghost64b, blist, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut, scr_act, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -97,6 +97,9 @@ Layout layout(const hlbm_desc* d) {
   const int64_t plane = int64_t(d->ny) * d->nz;
   L.ghost = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * cs : 0);
   L.ghost64 = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
+  L.ghostb = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * cs : 0);
+  L.ghost64b = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
+  L.blist = take(nb * 4);
   const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
   const int64_t lam_bytes = adj ? 27 * pop_stride_c(d) * cs : 0;
   L.lam0 = take(lam_bytes);
@@ -172,6 +175,14 @@ struct hlbm_lattice {
     char* ckpt = nullptr;
     double J = 0.0;
   } rec;
+  // second stream for the bulk sweep and the events tying it to the caller's stream
+  bool dual = false;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t evP = nullptr, evB[2] = {nullptr, nullptr};
+  bool b_pending = false;
+  int last_b = 0;
+  void* ghost[2] = {nullptr, nullptr};
+  double* ghost64[2] = {nullptr, nullptr};
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[4];
   std::vector<hipEvent_t> pool;
@@ -213,9 +224,16 @@ int rebuild_slots(hlbm_handle h) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "read block flags");
   int32_t n = 0;
+  std::vector<int32_t> fsi, bulk;
+  for (size_t b = 0; b < flags.size(); ++b) (flags[b] ? fsi : bulk).push_back(int32_t(b));
   for (auto& f : flags) f = f ? n++ : -1;
   h->nslots = n;
+  h->L.nfsi = int64_t(fsi.size());
+  h->L.nbulk = int64_t(bulk.size());
+  fsi.insert(fsi.end(), bulk.begin(), bulk.end());
   e = hipMemcpyAsync(h->L.blk_slot, flags.data(), sizeof(int32_t) * flags.size(), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->L.blist, fsi.data(), sizeof(int32_t) * fsi.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "write block slots");
   return HLBM_OK;
@@ -264,7 +282,7 @@ int build_rotor_table(hlbm_handle h, const hlbm_rotor* r, int32_t n, RotorTable*
     // FSI workgroups also cover the wall model's probe corners (reach y_s + 1
     // beyond the box; periodic in y and z), where the adjoint gathers the
     // probe-velocity adjoints
-    const int reach = h->params.wall_model ? int(std::ceil(h->params.y_s)) + 1 : 0;
+    const int reach = h->params.wall_model ? int(std::ceil(h->params.y_s)) + 2 : 0;
     for (int a = 0; a < 3; ++a) { d.mb0[a] = box.b0[a] - reach; d.mbn[a] = box.bn[a] + 2 * reach; }
     d.cells = int64_t(box.bn[0]) * box.bn[1] * box.bn[2];
     d.off = off;
@@ -380,9 +398,32 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.wall_out = base + Y.wall;
   L.hist = reinterpret_cast<double*>(base + Y.hist);
   L.hist_cap = h->hist_cap;
-  L.ghost = base + Y.ghost;
-  L.ghost64 = reinterpret_cast<double*>(base + Y.ghost64);
-  if (L.compute == HLBM_F64) L.ghost64 = reinterpret_cast<double*>(L.ghost);
+  h->ghost[0] = base + Y.ghost;
+  h->ghost[1] = base + Y.ghostb;
+  h->ghost64[0] = reinterpret_cast<double*>(base + Y.ghost64);
+  h->ghost64[1] = reinterpret_cast<double*>(base + Y.ghost64b);
+  if (L.compute == HLBM_F64) {
+    h->ghost64[0] = reinterpret_cast<double*>(h->ghost[0]);
+    h->ghost64[1] = reinterpret_cast<double*>(h->ghost[1]);
+  }
+  L.ghost = h->ghost[0];
+  L.ghost64 = h->ghost64[0];
+  L.blist = reinterpret_cast<int32_t*>(base + Y.blist);
+  L.stream2 = nullptr;
+  h->dual = true;
+  if (const char* e = std::getenv("HLBM_STREAMS")) h->dual = std::atoi(e) != 1;
+  if (h->dual) {
+    hipError_t es = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
+    if (es == hipSuccess) es = hipEventCreateWithFlags(&h->evP, hipEventDisableTiming);
+    if (es == hipSuccess) es = hipEventCreateWithFlags(&h->evB[0], hipEventDisableTiming);
+    if (es == hipSuccess) es = hipEventCreateWithFlags(&h->evB[1], hipEventDisableTiming);
+    if (es != hipSuccess) {
+      hip_fail(nullptr, es, "create internal stream");
+      delete h;
+      return HLBM_ERR_HIP;
+    }
+    L.stream2 = h->stream2;
+  }
   // defaults: Smagorinsky-free BGK-like relaxation at tau0 = 1 until set_params
   hlbm_params p{};
   p.tau0 = 1.0; p.cs_smag = 0.0; p.eps_h = 2.0; p.transition = HLBM_TRANSITION_TANH; p.wall_model = 0;
@@ -420,6 +461,13 @@ void hlbm_lattice_destroy(hlbm_handle h) {
   for (auto& v : h->prof)
     for (auto& p : v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->stream2) {
+    (void)hipStreamSynchronize(h->stream2);
+    (void)hipStreamDestroy(h->stream2);
+  }
+  if (h->evP) (void)hipEventDestroy(h->evP);
+  for (auto e : h->evB)
+    if (e) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -557,13 +605,14 @@ hipEvent_t take_event(hlbm_handle h) {
 
 // Run one launch, bracketed by events when profiling is on.
 template <class F>
-hipError_t timed(hlbm_handle h, int kind, F&& f) {
+hipError_t timed(hlbm_handle h, int kind, F&& f, hipStream_t s = nullptr) {
   if (!h->profiling) return f();
+  if (!s) s = h->stream;
   hipEvent_t a = take_event(h), b = take_event(h);
   if (!a || !b) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(a, h->stream);
+  hipError_t e = hipEventRecord(a, s);
   if (e == hipSuccess) e = f();
-  if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
   h->prof[kind].push_back({a, b});
   return e;
 }
@@ -581,15 +630,50 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
                        const uint8_t* act_prev, double* ut_new, uint8_t* act_new) {
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   const BladeTrig trig = blade_trig(h, n);
+  // inflow ghost planes alternate by step so that step n-1's readers may still run
+  h->L.ghost = h->ghost[n & 1];
+  h->L.ghost64 = h->ghost64[n & 1];
+  const bool diag = h->params.diag_every > 0 && n % h->params.diag_every == 0;
   hipError_t e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_prologue(h->L, n); });
+  if (!h->dual) {
+    if (e == hipSuccess)
+      e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_rasterize(h->L, n, trig, act_new); });
+    if (e == hipSuccess && wall)
+      e = timed(h, HLBM_KERNEL_WALL, [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n); });
+    if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, diag, 0); });
+    if (e == hipSuccess)
+      e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, n, h->nslots, diag); });
+    return e;
+  }
+  // bulk workgroups on the internal stream, after this step's inflow plane
+  // (and, through the caller's stream order, after the previous FSI sweep)
+  if (e == hipSuccess) e = hipEventRecord(h->evP, h->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->stream2, h->evP, 0);
+  if (e == hipSuccess)
+    e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, diag, 2); }, h->stream2);
+  if (e == hipSuccess) e = hipEventRecord(h->evB[n & 1], h->stream2);
+  // rotor chain on the caller's stream; the FSI sweep also reads cells the
+  // previous bulk sweep wrote
   if (e == hipSuccess)
     e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_rasterize(h->L, n, trig, act_new); });
   if (e == hipSuccess && wall)
     e = timed(h, HLBM_KERNEL_WALL, [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n); });
-  const bool diag = h->params.diag_every > 0 && n % h->params.diag_every == 0;
-  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, diag); });
-  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, n, h->nslots, diag); });
+  if (e == hipSuccess && h->b_pending) e = hipStreamWaitEvent(h->stream, h->evB[(n + 1) & 1], 0);
+  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_sweep(h->L, src, dst, n, diag, 1); });
+  // the mass of a diagnostics step needs this step's bulk partials too
+  if (e == hipSuccess && diag) e = hipStreamWaitEvent(h->stream, h->evB[n & 1], 0);
+  if (e == hipSuccess)
+    e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, n, h->nslots, diag); });
+  h->b_pending = true;
+  h->last_b = n & 1;
   return e;
+}
+
+// Order the caller's stream after the last bulk sweep.
+hipError_t join(hlbm_handle h) {
+  if (!h->dual || !h->b_pending) return hipSuccess;
+  h->b_pending = false;
+  return hipStreamWaitEvent(h->stream, h->evB[h->last_b], 0);
 }
 
 int check_flag(hlbm_handle h) {
@@ -653,6 +737,8 @@ int hlbm_step(hlbm_handle h, int64_t n) {
     if (wall) h->wcur = 1 - h->wcur;
     ++h->step;
   }
+  hipError_t ej = join(h);
+  if (ej != hipSuccess) return hip_fail(h, ej, "step");
   h->rec.valid = false;
   if (h->params.check_nonfinite) return check_flag(h);
   return HLBM_OK;
@@ -753,6 +839,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
                       reinterpret_cast<uint8_t*>(s0 + sl.act), reinterpret_cast<double*>(s1 + sl.ut),
                       reinterpret_cast<uint8_t*>(s1 + sl.act));
     }
+    if (e == hipSuccess) e = join(h);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint recompute");
     for (int64_t k = b - 1; k >= a; --k) {
       const int64_t n = h->rec.n0 + k;
@@ -760,6 +847,8 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       const double* ut0 = reinterpret_cast<const double*>(s0 + sl.ut);
       const uint8_t* ac0 = reinterpret_cast<const uint8_t*>(s0 + sl.act);
       // geometry, inflow and wall model of step n (with Jacobians)
+      h->L.ghost = h->ghost[n & 1];
+      h->L.ghost64 = h->ghost64[n & 1];
       e = launch_prologue(h->L, n);
       if (e == hipSuccess) e = launch_rasterize(h->L, n, blade_trig(h, n), scr_act);
       if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, jac);
@@ -794,6 +883,8 @@ int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat) {
   if (!h) return HLBM_ERR_INVALID;
   if (!rho || !u) return fail(h, HLBM_ERR_INVALID, "rho and u are required");
   const bool wall = h->params.wall_model && h->L.nrot > 0;
+  h->L.ghost = h->ghost[h->step & 1];
+  h->L.ghost64 = h->ghost64[h->step & 1];
   hipError_t e = launch_prologue(h->L, h->step);
   if (e == hipSuccess) e = launch_rasterize(h->L, h->step, blade_trig(h, h->step), h->act[1 - h->wcur]);
   // the wall model writes the next state slot, which is not committed here
@@ -939,6 +1030,29 @@ int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* 
   }
   if (launches) *launches = int64_t(h->prof[kernel].size());
   if (total_ms) *total_ms = sum;
+  return HLBM_OK;
+}
+
+int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells) {
+  if (!h) return HLBM_ERR_INVALID;
+  std::vector<int32_t> list(h->L.nblocks);
+  hipError_t e = hipMemcpyAsync(list.data(), h->L.blist, sizeof(int32_t) * list.size(), hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "partition");
+  const Geometry& g = h->L.g;
+  int64_t cnt[2] = {0, 0};
+  for (int64_t k = 0; k < h->L.nblocks; ++k) {
+    const int64_t b = list[k];
+    const int64_t tpz = int64_t(g.ntx) * g.nty;
+    const int64_t rem = b % tpz;
+    const int ty = int(rem / g.ntx), tx = int(rem % g.ntx);
+    const int64_t cx = std::min<int64_t>(kTileX, g.nx - int64_t(tx) * kTileX);
+    const int64_t cy = std::min<int64_t>(kTileY, g.ny - int64_t(ty) * kTileY);
+    cnt[k < h->L.nfsi ? 0 : 1] += cx * cy;
+  }
+  if (fsi_cells) *fsi_cells = cnt[0];
+  if (bulk_cells) *bulk_cells = cnt[1];
   return HLBM_OK;
 }
 

@@ -535,6 +535,8 @@ struct SweepArgs {
   const CT* ghost;
   int64_t step;
   int64_t nblocks;
+  const int32_t* blist;      // optional list of the workgroups to run (FSI or bulk part)
+  int64_t nlist;
   int32_t remap;
   CT* out_rho;
   CT* out_u;
@@ -550,7 +552,8 @@ struct SweepArgs {
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   const Geometry& g = a.g;
-  const int64_t blk = remap_block(blockIdx.x, a.nblocks, a.remap);
+  const int64_t blk = a.blist ? int64_t(a.blist[remap_block(blockIdx.x, a.nlist, a.remap)])
+                              : remap_block(blockIdx.x, a.nblocks, a.remap);
   // tile (tx, ty, z): 64 consecutive x-cells per wave, 4 y-rows per workgroup
   const int tpz = g.ntx * g.nty;
   const int z = int(blk / tpz);
@@ -1131,16 +1134,22 @@ static SweepArgs<CT> sweep_args(const Launch& L, const void* src, void* dst, int
   return a;
 }
 
-hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag) {
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag, int part) {
+  // part 0: all workgroups; 1: FSI workgroups; 2: bulk workgroups
+  const int64_t n = part == 0 ? L.nblocks : part == 1 ? L.nfsi : L.nbulk;
+  if (n == 0) return hipSuccess;
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
     SweepArgs<CT> a = sweep_args<CT>(L, src, dst, step);
     if (diag) a.mass_part = L.mass_part;
+    a.blist = part == 0 ? nullptr : part == 1 ? L.blist : L.blist + L.nfsi;
+    a.nlist = n;
+    hipStream_t s = part == 2 ? L.stream2 : L.stream;
     if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(n)), dim3(kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(n)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
   });
 }

@@ -10,11 +10,14 @@ namespace hlbm {
 // Everything a launch needs, with raw device pointers carved from the
 // caller's workspace.  Types of the typed fields follow storage / compute.
 struct Launch {
-  hipStream_t stream;
+  hipStream_t stream;        // the caller's stream: rotor chain and FSI sweep
+  hipStream_t stream2;       // internal stream: bulk sweep
   int storage, compute;      // hlbm_dtype values
   Geometry g;
   Model m;
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
+  int32_t* blist;            // FSI workgroups, then bulk workgroups
+  int64_t nfsi, nbulk;
   int32_t xcd_remap;
   // fields
   void* d_eff;
@@ -46,7 +49,7 @@ struct Launch {
 hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig, uint8_t* act_new);
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
                        double* ut_new, uint8_t* act_new, int64_t step, double* jac = nullptr);
-hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag, int part = 0);
 hipError_t launch_prologue(const Launch& L, int64_t step);
 hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag);
 hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* rho, void* u, void* uhat);

@@ -89,6 +89,7 @@ SIGNATURES = [
     ("hlbm_adjoint", C.c_int, [_H, C.c_double, _V, _V, C.c_int64]),
     ("hlbm_profile_enable", C.c_int, [_H, C.c_int32]),
     ("hlbm_profile_read", C.c_int, [_H, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    ("hlbm_sweep_partition", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("hlbm_last_error", C.c_char_p, [_H]),
 ]
 
@@ -345,6 +346,13 @@ def profile_read(lat, kernel):
     ms = C.c_double()
     lat._check(lat.L.hlbm_profile_read(lat.h, kernel, C.byref(n), C.byref(ms)))
     return n.value, ms.value
+
+
+def sweep_partition(lat):
+    f = C.c_int64()
+    b = C.c_int64()
+    lat._check(lat.L.hlbm_sweep_partition(lat.h, C.byref(f), C.byref(b)))
+    return f.value, b.value
 
 
 def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None) -> "Lattice":
