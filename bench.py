@@ -157,6 +157,60 @@ def cpu_baseline(w, steps):
                       f"OpenMP over z-planes, {dt:.1f} s"}
 
 
+CACHE_RESIDENT_BYTES = 256 << 20   # MI355X Infinity Cache
+
+
+def config_sweep(keys, storages, main_key, main_results, cpu_seconds):
+    """MLUPS and sweep roofline of every workload in `keys` for each storage
+    type, with the FP64 oracle timed on a bounded sample of each."""
+    from paper_2510_13726_amd import workloads as W
+    out = []
+    for k in keys:
+        w = W.ALL[k]()
+        steps = max(50, min(2000, int(4e9 // w.cells)))
+        row = {"config": k, "workload": w.name, "cells": w.cells, "steps": steps}
+        for st in storages:
+            if k == main_key and st in main_results:
+                r = main_results[st]
+            else:
+                r = time_storage(w, st, steps, 10)
+            rl = roofline(w, st, r["sweep_avg_ms"], r["sweep_cells"])
+            row[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+                       "sweep_frac": rl["frac"], "sweep_GB_s": rl["achieved"], "finite": r["finite"],
+                       "cache_resident": BYTES_PER_CELL[st] // 2 * w.cells <= CACHE_RESIDENT_BYTES}
+            log(f"config {k} {st}: {row[st]}")
+        if cpu_seconds > 0:
+            row["cpu_oracle"] = cpu_sample(w, cpu_seconds)
+            log(f"config {k} oracle: {row['cpu_oracle']}")
+        out.append(row)
+    return out
+
+
+def cpu_sample(w, seconds):
+    """The oracle on a bounded part of a workload: the whole lattice if a step
+    fits the budget, else an x-slab of 16 planes through the first rotor."""
+    from oracle import oracle as O
+    from paper_2510_13726_amd import workloads as W
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    s, what = w, "whole lattice"
+    if w.cells > 5_000_000:
+        x0 = max(0, int(w.rotors[0].center[0]) - 8) if w.rotors else 0
+        s = W.x_slab(w, x0, 16)
+        what = f"x-slab [{x0}, {x0 + 16}) through the first rotor ({s.cells} cells)"
+    o = O.setup(s, threads=threads)
+    o.step(1)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.step(1)
+        n += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(s.cells * n / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the {what}, FP64, {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +222,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint ratio run (0 = skip)")
     ap.add_argument("--copy-reference", type=int, default=1, help="time a plain copy kernel (0 = skip)")
+    ap.add_argument("--configs", default="1,2,3,4,5", help="workloads timed for the per-config table ('' = skip)")
+    ap.add_argument("--config-cpu-seconds", type=float, default=3.0, help="oracle seconds per config (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -188,11 +244,17 @@ def main():
     main_run = time_storage(w, args.storage, args.steps, args.warmup)
     log(f"main: {main_run}")
     variants = {}
+    raw = {args.storage: main_run}
     for st in [s for s in args.variants.split(",") if s and s != args.storage]:
         r = time_storage(w, st, args.steps, args.warmup)
+        raw[st] = r
         log(f"{st}: {r}")
         variants[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
                         "roofline": roofline(w, st, r["sweep_avg_ms"], r["sweep_cells"]), "finite": r["finite"]}
+    per_config = None
+    keys = [k for k in args.configs.split(",") if k]
+    if keys:
+        per_config = config_sweep(keys, ["f32", "f16"], args.config, raw, args.config_cpu_seconds)
     adj = None
     if args.adjoint_steps > 0:
         adj = adjoint_ratio(args.storage if args.storage in ("f32", "f64") else "f32", args.adjoint_steps,
@@ -225,6 +287,7 @@ def main():
         "roofline": roofline(w, args.storage, main_run["sweep_avg_ms"], main_run["sweep_cells"]),
         "cpu_baseline": cpu,
         "storage_variants": variants,
+        "per_config": per_config,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,
         "copy_reference": copy_ref,

@@ -223,10 +223,14 @@ int rebuild_slots(hlbm_handle h) {
   e = hipMemcpyAsync(flags.data(), h->L.blk_slot, sizeof(int32_t) * flags.size(), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "read block flags");
+  // slot >= 0: FSI path with a force partial; -2: plain path within the wall
+  // model's probe reach (the adjoint gathers probe adjoints there); -1: plain
   int32_t n = 0;
   std::vector<int32_t> fsi, bulk;
-  for (size_t b = 0; b < flags.size(); ++b) (flags[b] ? fsi : bulk).push_back(int32_t(b));
-  for (auto& f : flags) f = f ? n++ : -1;
+  const char* rm = std::getenv("HLBM_REACH_MAIN");
+  const int lead = (rm && rm[0] == '1') ? 3 : 1;
+  for (size_t b = 0; b < flags.size(); ++b) ((flags[b] & lead) ? fsi : bulk).push_back(int32_t(b));
+  for (auto& f : flags) f = (f & 1) ? n++ : (f & 2) ? -2 : -1;
   h->nslots = n;
   h->L.nfsi = int64_t(fsi.size());
   h->L.nbulk = int64_t(bulk.size());
@@ -410,6 +414,9 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.ghost64 = h->ghost64[0];
   L.blist = reinterpret_cast<int32_t*>(base + Y.blist);
   L.stream2 = nullptr;
+  // optional cap on the bulk launch's grid (0: one workgroup per tile, measured fastest)
+  L.bulk_grid = 0;
+  if (const char* e = std::getenv("HLBM_BULK_GRID")) L.bulk_grid = std::atoll(e);
   h->dual = true;
   if (const char* e = std::getenv("HLBM_STREAMS")) h->dual = std::atoi(e) != 1;
   if (h->dual) {
@@ -639,7 +646,8 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
     if (e == hipSuccess)
       e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_rasterize(h->L, n, trig, act_new); });
     if (e == hipSuccess && wall)
-      e = timed(h, HLBM_KERNEL_WALL, [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n); });
+      e = timed(h, HLBM_KERNEL_WALL,
+              [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n, nullptr, diag); });
     if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, diag, 0); });
     if (e == hipSuccess)
       e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, n, h->nslots, diag); });
@@ -657,7 +665,8 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
   if (e == hipSuccess)
     e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_rasterize(h->L, n, trig, act_new); });
   if (e == hipSuccess && wall)
-    e = timed(h, HLBM_KERNEL_WALL, [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n); });
+    e = timed(h, HLBM_KERNEL_WALL,
+              [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n, nullptr, diag); });
   if (e == hipSuccess && h->b_pending) e = hipStreamWaitEvent(h->stream, h->evB[(n + 1) & 1], 0);
   if (e == hipSuccess) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_sweep(h->L, src, dst, n, diag, 1); });
   // the mass of a diagnostics step needs this step's bulk partials too
@@ -851,7 +860,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       h->L.ghost64 = h->ghost64[n & 1];
       e = launch_prologue(h->L, n);
       if (e == hipSuccess) e = launch_rasterize(h->L, n, blade_trig(h, n), scr_act);
-      if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, jac);
+      if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, jac, 0);
       if (e == hipSuccess) e = hipMemsetAsync(utb[1 - cur], 0, B * 8, h->stream);
       AdjLaunch A{};
       A.src = s0;
@@ -890,7 +899,7 @@ int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat) {
   // the wall model writes the next state slot, which is not committed here
   if (e == hipSuccess && wall)
     e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur], h->act[1 - h->wcur],
-                    h->step);
+                    h->step, nullptr, 0);
   if (e == hipSuccess) e = launch_moments(h->L, h->pop[h->cur], h->step, rho, u, uhat);
   if (e != hipSuccess) return hip_fail(h, e, "moments");
   return HLBM_OK;

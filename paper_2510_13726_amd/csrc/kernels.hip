@@ -209,8 +209,12 @@ __global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict_
                                                    CT* __restrict__ d_eff, uint8_t* __restrict__ tag,
                                                    double* __restrict__ geo, uint8_t* __restrict__ act_new,
                                                    int32_t* __restrict__ wlist, int32_t* __restrict__ wcount) {
-  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= total) return;  // inactive lanes add nothing to the ballot below
+  __shared__ int wl_count, wl_base;
+  if (threadIdx.x == 0) wl_count = 0;
+  __syncthreads();
+  const int64_t s0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool live = s0 < total;
+  const int64_t s = live ? s0 : total - 1;
   const RotorTable& rt = *rtp;
   const int k = rotor_of_slot(rt, s);
   int x, y, z;
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict_
   const double drot = br >= 0 ? transition(best, m.eps_h, m.transition) : 0.0;
   const double ds = double(d_static[c]);
   const double base = ds > drot ? ds : drot;
-  d_eff[c] = CT(base) + (dd ? dd[c] : CT(0));
+  if (live) d_eff[c] = CT(base) + (dd ? dd[c] : CT(0));
   const double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
   uint8_t tb;
   if (drot > 0.0) {
@@ -239,20 +243,20 @@ __global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict_
   } else {
     tb = tag_static[c];
   }
-  tag[c] = tb;
-  act_new[s] = 0;
-  // wall cells of this box's own rotor go to the wall model's work list
-  // (one atomic per wave: base from the first lane, rank from the ballot)
-  const bool mine = (tb & kWallBit) && br == k;
-  const uint64_t ball = __ballot(mine);
-  if (ball) {
-    const int lane = threadIdx.x & 63;
-    const int first = __ffsll((long long)ball) - 1;
-    int base = 0;
-    if (lane == first) base = atomicAdd(wcount, __popcll(ball));
-    base = __shfl(base, first, 64);
-    if (mine) wlist[base + __popcll(ball & ((1ull << lane) - 1ull))] = int32_t(s);
+  if (live) {
+    tag[c] = tb;
+    act_new[s] = 0;
   }
+  // wall cells of this box's own rotor go to the wall model's work list:
+  // ranks from an LDS counter, one global atomic per workgroup
+  const bool mine = live && (tb & kWallBit) && br == k;
+  int rank = 0;
+  if (mine) rank = atomicAdd(&wl_count, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) wl_base = wl_count ? atomicAdd(wcount, wl_count) : 0;
+  __syncthreads();
+  if (mine) wlist[wl_base + rank] = int32_t(s);
+  if (!live) return;
   geo[s] = best;
   const double inv = gn > 0 ? 1.0 / gn : 0.0;
   geo[total + s] = -gr[0] * inv;
@@ -356,9 +360,14 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   const R ut = newton(
       guess,
       [&](R u, R& f, R& df) {
-        const R p = U / u;
-        f = p + spalding_bracket(kap * p) / E - ys * u / nu;
-        df = 0.0 - (p / u) * (1.0 + kap * spalding_dbracket(kap * p) / E) - ys / nu;
+        const R iu = 1.0 / u;
+        const R p = U * iu;
+        const R k = kap * p;
+        const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
+        const R dek = val(k) > 80.0 ? cst<R>(0.0) : ek;
+        const R poly = 1.0 + k + k * k * 0.5;
+        f = p + (ek - poly - k * k * k / 6.0) / E - ys * u / nu;
+        df = 0.0 - (p * iu) * (1.0 + kap * (dek - poly) / E) - ys / nu;
       },
       m.tol, m.maxit, it1);
   const R yp = y1 * ut / nu;
@@ -368,8 +377,12 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   const R up = newton(
       val(ulog) < val(yp) ? ulog : yp,
       [&](R u, R& f, R& df) {
-        f = u + spalding_bracket(kap * u) / E - yp;
-        df = 1.0 + kap * spalding_dbracket(kap * u) / E;
+        const R k = kap * u;
+        const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
+        const R dek = val(k) > 80.0 ? cst<R>(0.0) : ek;
+        const R poly = 1.0 + k + k * k * 0.5;
+        f = u + (ek - poly - k * k * k / 6.0) / E - yp;
+        df = 1.0 + kap * (dek - poly) / E;
       },
       m.tol, m.maxit, it2);
   const R qv = ut * up;
@@ -450,7 +463,8 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
                                               const double* __restrict__ ut_prev, const uint8_t* __restrict__ act_prev,
                                               double* __restrict__ ut_new, uint8_t* __restrict__ act_new,
                                               CT* __restrict__ wall_out, unsigned long long* __restrict__ stats,
-                                              const double* __restrict__ ghost, double* __restrict__ jac) {
+                                              const double* __restrict__ ghost, double* __restrict__ jac,
+                                              int count_stats) {
   const RotorTable& rt = *rtp;
   const int corner = threadIdx.x & 7;
   const int count = *wcount;
@@ -501,16 +515,18 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
         done = 1;
       }
     }
-    // Newton statistics: one atomic per wave
-    int a1 = it1, a2 = done;
+    // Newton statistics (diagnostics steps): one atomic per wave
+    if (count_stats) {
+      int a1 = it1, a2 = done;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      a1 += __shfl_xor(a1, o, 64);
-      a2 += __shfl_xor(a2, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0 && a2) {
-      atomicAdd(&stats[0], (unsigned long long)a1);
-      atomicAdd(&stats[1], (unsigned long long)a2);
+      for (int o = 32; o > 0; o >>= 1) {
+        a1 += __shfl_xor(a1, o, 64);
+        a2 += __shfl_xor(a2, o, 64);
+      }
+      if ((threadIdx.x & 63) == 0 && a2) {
+        atomicAdd(&stats[0], (unsigned long long)a1);
+        atomicAdd(&stats[1], (unsigned long long)a2);
+      }
     }
   }
 }
@@ -550,10 +566,8 @@ struct SweepArgs {
 // homogenized velocity and the wall model outputs and reduce the momentum
 // handed to each tag; the others run the plain bulk collision.
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
+__device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, int64_t blk, double (&lds)[4][kPartial]) {
   const Geometry& g = a.g;
-  const int64_t blk = a.blist ? int64_t(a.blist[remap_block(blockIdx.x, a.nlist, a.remap)])
-                              : remap_block(blockIdx.x, a.nblocks, a.remap);
   // tile (tx, ty, z): 64 consecutive x-cells per wave, 4 y-rows per workgroup
   const int tpz = g.ntx * g.nty;
   const int z = int(blk / tpz);
@@ -575,7 +589,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
 
   const int32_t slot = a.blk_slot[blk];
   CT g2[27];
-  __shared__ double lds[4][kPartial];
   if (slot < 0) {
     if (kMoments) {
       if (valid) {
@@ -643,6 +656,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
       v[5] = rx * py - ry * px;
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (!__syncthreads_or(t != 0 && valid)) {
+      // no tagged cell in this tile: its partial is zero
+      if (threadIdx.x < kPartial) a.partial[int64_t(slot) * kPartial + threadIdx.x] = 0.0;
+    } else {
     for (int q = threadIdx.x; q < 4 * kPartial; q += kBlock) (&lds[0][0])[q] = 0.0;
     __syncthreads();
     const int tt = (t != 0 && valid) ? t : 0;
@@ -663,6 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
       const int q = threadIdx.x;
       a.partial[int64_t(slot) * kPartial + q] = (lds[0][q] + lds[1][q]) + (lds[2][q] + lds[3][q]);
     }
+    }
   }
   if (!kMoments) {
     if (valid) {
@@ -680,6 +698,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
       __syncthreads();
       if (threadIdx.x == 0) a.mass_part[blk] = (lds[0][0] + lds[0][1]) + (lds[0][2] + lds[0][3]);
     }
+  }
+}
+
+// Workgroups walk the tile list (all tiles, or the FSI / bulk part) with a
+// grid-stride loop; a grid smaller than the list keeps part of the GPU free
+// for the kernels that run concurrently on the other stream.
+template <class ST, class CT, bool kPeriodicX, bool kMoments>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
+  __shared__ double lds[4][kPartial];
+  const int64_t nwork = a.blist ? a.nlist : a.nblocks;
+  for (int64_t it = blockIdx.x; it < nwork; it += gridDim.x) {
+    const int64_t blk = a.blist ? int64_t(a.blist[remap_block(it, nwork, a.remap)]) : remap_block(it, nwork, a.remap);
+    sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
+    __syncthreads();
   }
 }
 
@@ -793,7 +825,10 @@ __global__ __launch_bounds__(256) void k_fill_rest(ST* __restrict__ dst, Geometr
   for (int i = 0; i < 27; ++i) Store<ST>::template store<double>(dst + int64_t(i) * g.stride + c, 0.0);
 }
 
-// FSI workgroups: any cell in a rotor box, or with static porosity, tag or control.
+// FSI workgroups (bit 0): any cell in a rotor box, or with static porosity,
+// tag or control.  Reach workgroups (bit 1): within the wall model's probe
+// stencil around a rotor box (periodic in y, z); they run the plain path but
+// are swept after the wall model, and the adjoint gathers probe adjoints there.
 template <class CT>
 __global__ __launch_bounds__(256) void k_mark(const RotorTable* __restrict__ rtp, Geometry g,
                                               const CT* __restrict__ d_static, const uint8_t* __restrict__ tag_static,
@@ -805,16 +840,19 @@ __global__ __launch_bounds__(256) void k_mark(const RotorTable* __restrict__ rtp
   const int64_t r = c - int64_t(z) * nxy;
   const int y = int(r / g.nx), x = int(r - int64_t(y) * g.nx);
   bool fsi = d_static[c] != CT(0) || tag_static[c] != 0 || (dd && dd[c] != CT(0));
+  bool reach = false;
   const RotorTable& rt = *rtp;
-  for (int j = 0; j < rt.n && !fsi; ++j) {
-    const RotorDev& r = rt.r[j];
-    const int lx = x - r.mb0[0];
-    const int ly = ((y - r.mb0[1]) % g.ny + g.ny) % g.ny, lz = ((z - r.mb0[2]) % g.nz + g.nz) % g.nz;
-    const bool inx = g.bc_x == 0 ? (((lx % g.nx) + g.nx) % g.nx < r.mbn[0] || r.mbn[0] >= g.nx)
-                                 : (lx >= 0 && lx < r.mbn[0]);
-    fsi = inx && (ly < r.mbn[1] || r.mbn[1] >= g.ny) && (lz < r.mbn[2] || r.mbn[2] >= g.nz);
+  for (int j = 0; j < rt.n; ++j) {
+    const RotorDev& rr = rt.r[j];
+    fsi = fsi || in_box(rr, x, y, z);
+    const int lx = x - rr.mb0[0];
+    const int ly = ((y - rr.mb0[1]) % g.ny + g.ny) % g.ny, lz = ((z - rr.mb0[2]) % g.nz + g.nz) % g.nz;
+    const bool inx = g.bc_x == 0 ? (((lx % g.nx) + g.nx) % g.nx < rr.mbn[0] || rr.mbn[0] >= g.nx)
+                                 : (lx >= 0 && lx < rr.mbn[0]);
+    reach = reach || (inx && (ly < rr.mbn[1] || rr.mbn[1] >= g.ny) && (lz < rr.mbn[2] || rr.mbn[2] >= g.nz));
   }
-  if (fsi) blk[(int64_t(z) * g.nty + y / kTileY) * g.ntx + x / kTileX] = 1;
+  const int bits = (fsi ? 1 : 0) | (reach ? 2 : 0);
+  if (bits) atomicOr(&blk[(int64_t(z) * g.nty + y / kTileY) * g.ntx + x / kTileX], bits);
 }
 
 // d_eff = d_static + control everywhere (rotor boxes are overwritten each step),
@@ -927,22 +965,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   CT d = CT(0), b[3] = {CT(0), CT(0), CT(0)}, S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)}, sigma = CT(1);
   CT pb[3] = {CT(0), CT(0), CT(0)};
   double ub[3] = {0.0, 0.0, 0.0};
-  const bool fsi = a.blk_slot[blk] >= 0;
-  if (fsi) {
-    const uint8_t tb = a.tag[c];
-    fsi_inputs(a, rt, c, x, y, z, tb, d, b, S, sigma);
-    objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
+  const int32_t slot = a.blk_slot[blk];
+  const bool fsi = slot >= 0, gather = slot != -1;
+  if (gather) {
     for (int q = 0; q < 3; ++q) {
       ub[q] = a.ubar[q * g.N + c];
       a.ubar[q * g.N + c] = 0.0;
     }
+  }
+  if (fsi) {
+    const uint8_t tb = a.tag[c];
+    fsi_inputs(a, rt, c, x, y, z, tb, d, b, S, sigma);
+    objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
   } else if (a.uB_static) {
     b[0] = a.uB_static[c]; b[1] = a.uB_static[g.N + c]; b[2] = a.uB_static[2 * g.N + c];
   }
   Moments<CT> mb;
   CT db, bb[3], Sb[6];
   collide_vjp<CT>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
-  if (fsi) {
+  if (gather) {
     // probe velocity u = j / rho at this cell, sampled by wall cells
     const CT rho = CT(1) + mo.drho, irho = CT(1) / rho;
     const CT ju = CT(ub[0]) * mo.jx + CT(ub[1]) * mo.jy + CT(ub[2]) * mo.jz;
@@ -1101,7 +1142,7 @@ hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig
 }
 
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step, double* jac) {
+                       double* ut_new, uint8_t* act_new, int64_t step, double* jac, int count_stats) {
   (void)step;
   if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
   // persistent grid over the (device-side) wall-cell count, 32 cells per workgroup
@@ -1113,11 +1154,11 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
                          L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
-                         (CT*)L.wall_out, L.stats, L.ghost64, jac);
+                         (CT*)L.wall_out, L.stats, L.ghost64, jac, count_stats);
     else
       hipLaunchKernelGGL((k_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
                          L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
-                         (CT*)L.wall_out, L.stats, L.ghost64, jac);
+                         (CT*)L.wall_out, L.stats, L.ghost64, jac, count_stats);
     return hipGetLastError();
   });
 }
@@ -1146,10 +1187,14 @@ hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t ste
     a.blist = part == 0 ? nullptr : part == 1 ? L.blist : L.blist + L.nfsi;
     a.nlist = n;
     hipStream_t s = part == 2 ? L.stream2 : L.stream;
+    // the bulk part runs beside the rotor chain: cap its grid (a multiple of
+    // the 8 XCDs) so that workgroup slots stay free for the other stream
+    int64_t grid = n;
+    if (part == 2 && L.bulk_grid > 0 && grid > L.bulk_grid) grid = L.bulk_grid;
     if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(n)), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(grid)), dim3(kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(n)), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(grid)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
   });
 }

@@ -18,6 +18,7 @@ struct Launch {
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
   int32_t* blist;            // FSI workgroups, then bulk workgroups
   int64_t nfsi, nbulk;
+  int64_t bulk_grid;         // workgroups of the persistent bulk launch (0 = one per tile)
   int32_t xcd_remap;
   // fields
   void* d_eff;
@@ -48,7 +49,8 @@ struct Launch {
 
 hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig, uint8_t* act_new);
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step, double* jac = nullptr);
+                       double* ut_new, uint8_t* act_new, int64_t step, double* jac = nullptr,
+                       int count_stats = 1);
 hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag, int part = 0);
 hipError_t launch_prologue(const Launch& L, int64_t step);
 hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag);

@@ -365,8 +365,16 @@ def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=Non
     if d is not None:
         lat.set_porosity_field(d, tag)
         lat.set_tag_frame(1, w.sphere[:3], (1.0, 0.0, 0.0))
-    rho, u = W.initial_fields(w)
-    lat.init_equilibrium(rho, u)
+    if w.init == "uniform":
+        # rho = 1, u = (u0, 0, 0) everywhere, built on the device
+        torch = lat.torch
+        u = torch.zeros(3, lat.N, dtype=lat.ct, device=lat.device)
+        u[0].fill_(w.u0)
+        lat.init_equilibrium(None, u)
+        del u
+    else:
+        rho, u = W.initial_fields(w)
+        lat.init_equilibrium(rho, u)
     noise = W.population_noise(w)
     if noise is not None:
         h = lat.get_populations()

@@ -218,3 +218,22 @@ def random_cells(w: Workload, count: int, seed: int, region: str = "rotor") -> n
         z = int(round(r.center[2] + rad * math.sin(th)))
         out.add((z * w.ny + y) * w.nx + x)
     return np.array(sorted(out), dtype=np.int64)
+
+
+def x_slab(w: Workload, x0: int, length: int) -> Workload:
+    """The cells x0 <= x < x0 + length of `w` (all of y and z) as a workload
+    of its own, for light-cone comparisons of a large run against a small
+    one: rotors are moved by -x0, and the slab is periodic in x unless it
+    starts at the inlet (then it keeps the inflow, and its last plane is an
+    outflow that the large run does not have).  After n steps the cells
+    farther than the per-step dependency reach times n from the slab's cut
+    faces hold the same values as in `w`."""
+    import copy
+    s = copy.deepcopy(w)
+    s.name = f"{w.name}_x{x0}+{length}"
+    s.nx = int(length)
+    if x0 != 0:
+        s.bc_x = BC_PERIODIC
+    for r in s.rotors:
+        r.center = (r.center[0] - x0, r.center[1], r.center[2])
+    return s

@@ -1,0 +1,128 @@
+"""HIP path vs the FP64 oracle at the full sizes of the rotor workloads, in
+the launch configuration the benchmark times (no per-step diagnostics).
+
+The 256x128x128 channel fits the oracle whole.  The 1024x512x384 wake and the
+1536x768x256 rotor array do not; there the oracle runs an x-slab of the
+domain (all of y and z) for a few steps.  One step moves information at most
+five cells (one by streaming, four by the wall-model probe stencil: probe at
+most y_s = 3 cells off the wall cell, plus the trilinear corner), so after n
+steps the slab's cells farther than 6n + 2 planes from its cut faces hold
+the same values as the full run; those cells are compared.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_13726_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _hl():
+    from paper_2510_13726_amd import hlbm
+    return hlbm
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _free(lat):
+    import torch
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage,diag", [("f64", 1), ("f32", 0)])
+def test_rotor_channel_full_domain(storage, diag):
+    """256x128x128 channel, rotor R = 40 with the wall model, 6 steps."""
+    hl = _hl()
+    w = W.config2()
+    n = 6
+    print(f"[fullsize] {w.name} {storage} diag={diag} {n} steps", flush=True)
+    lat = hl.setup(w, storage=storage, diag_every=diag)
+    lat.step(n)
+    hg = lat.get_populations().cpu().numpy()
+    it_g, nw_g = lat.wall_stats()
+    hist_g = lat.history() if diag else None
+    _free(lat)
+    o = O.setup(w, threads=THREADS)
+    o.step(n)
+    ho = o.get_populations()
+    e = rel(hg, ho)
+    print(f"[fullsize] {w.name} {storage}: h rel err {e:.3e}", flush=True)
+    assert e < TOL[storage]
+    if diag:
+        hist_o = o.history()
+        eF = rel(hist_g[:, 1:7], hist_o[:, 1:7])
+        print(f"[fullsize] F,T rel err {eF:.3e}; newton {it_g}/{o.newton_stats()[0]} wall cells {nw_g}", flush=True)
+        assert eF < 10 * TOL[storage]
+        assert (it_g, nw_g) == o.newton_stats()
+        assert nw_g > 1000
+
+
+def _slab_case(w, x0, length, n, storage, box):
+    """Run `w` on the GPU for n steps and the x-slab [x0, x0 + length) on the
+    oracle; compare the slab's interior cells inside the y-z window `box`."""
+    hl = _hl()
+    m = 6 * n + 2
+    lo = x0 + (m if x0 != 0 else 0)
+    hi = x0 + length - m
+    assert hi > lo
+    (y0, y1), (z0, z1) = box
+    zz, yy, xx = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(lo, hi), indexing="ij")
+    cells = ((zz * w.ny + yy) * w.nx + xx).reshape(-1).astype(np.int64)
+    print(f"[fullsize] {w.name} {storage}: {n} steps, slab x [{x0}, {x0 + length}), "
+          f"compare x [{lo}, {hi}) ({cells.size} cells)", flush=True)
+    lat = hl.setup(w, storage=storage, diag_every=0)
+    lat.step(n)
+    hg = lat.get_populations_at(cells).cpu().numpy()          # [cells][27]
+    _free(lat)
+    s = W.x_slab(w, x0, length)
+    o = O.setup(s, threads=THREADS)
+    o.step(n)
+    ho = o.get_populations()                                   # [27][slab cells]
+    lc = ((zz * s.ny + yy) * s.nx + (xx - x0)).reshape(-1)
+    ho = ho[:, lc].T
+    e = rel(hg, ho)
+    print(f"[fullsize] {w.name} {storage}: h rel err {e:.3e} (max |h| {np.abs(ho).max():.3e}); "
+          f"slab newton {o.newton_stats()}", flush=True)
+    return e, o
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_wake_rotor_slab(storage):
+    """1024x512x384 wake workload (rotor R = 120, inflow turbulence), slab
+    around the rotor plane."""
+    w = W.config3()
+    n = 4
+    xc = int(w.rotors[0].center[0])
+    e, o = _slab_case(w, xc - 16 - (6 * n + 2), 32 + 2 * (6 * n + 2), n, storage, ((128, 384), (64, 320)))
+    assert o.newton_stats()[1] > 1000
+    assert e < TOL[storage]
+
+
+def test_wake_inflow_slab():
+    """1024x512x384 wake workload: slab at the inlet (turbulent equilibrium
+    inflow drawn from the counter-based generator of every (step, y, z))."""
+    w = W.config3()
+    n = 4
+    e, _ = _slab_case(w, 0, 24 + 6 * n + 2, n, "f32", ((0, 512), (100, 160)))
+    assert e < TOL["f32"]
+
+
+def test_rotor_array_slab():
+    """1536x768x256 array of 8 rotors (R = 48): slab around the first column
+    of two rotors with different phases."""
+    w = W.config5()
+    n = 4
+    xc = int(w.rotors[0].center[0])
+    e, o = _slab_case(w, xc - 10 - (6 * n + 2), 20 + 2 * (6 * n + 2), n, "f32", ((250, 520), (70, 190)))
+    assert o.newton_stats()[1] > 1000
+    assert e < TOL["f32"]

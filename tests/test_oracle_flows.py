@@ -196,3 +196,30 @@ def test_inflow_turbulence_statistics():
     ux = u[0].reshape(w.nz, w.ny, w.nx)[:, :, 0]
     assert abs(ux.mean() - 0.05) < 0.05 * 0.05 * 0.5
     assert 0.2 * 0.05 * 0.05 < ux.std() < 0.05 * 0.05 * 1.5
+
+
+@pytest.mark.parametrize("x0", [0, 10])
+def test_light_cone_of_an_x_slab(x0):
+    """The dependency reach the full-size GPU comparisons rely on: after n
+    steps, an x-slab run on its own agrees with the full run on every cell
+    farther than 6n + 2 planes from the slab's cut faces (streaming moves one
+    cell per step, the wall-model probe stencil four more)."""
+    w = W.small_rotor(nx=100, ny=36, nz=36, R=9.0, chord=3.0, hub=2.0, tau0=0.51, turb=0.05)
+    w.rotors[0].center = (30.0, w.rotors[0].center[1], w.rotors[0].center[2])
+    n = 3
+    m = 6 * n + 2
+    length = 2 * m + 14 if x0 else m + 14
+    full = O.setup(w)
+    full.step(n)
+    s = W.x_slab(w, x0, length)
+    assert s.bc_x == (w.bc_x if x0 == 0 else W.BC_PERIODIC)
+    o = O.setup(s)
+    o.step(n)
+    assert o.newton_stats()[1] > 50 or x0 == 0
+    lo = m if x0 else 0
+    hf = full.get_populations().reshape(27, w.nz, w.ny, w.nx)[..., x0 + lo:x0 + length - m]
+    hs = o.get_populations().reshape(27, s.nz, s.ny, s.nx)[..., lo:length - m]
+    assert hf.shape == hs.shape and hf.shape[-1] == 14
+    assert np.abs(hf - hs).max() <= 1e-13 * np.abs(hf).max()
+    # the compared planes hold the rotor's disturbance, not only free stream
+    assert np.abs(hf - hf[:, :1, :1, :1]).max() > 1e-4 * np.abs(hf).max()
