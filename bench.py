@@ -59,8 +59,9 @@ def time_storage(w, storage, steps, warmup):
     n, ms = hlbm.profile_read(lat, hlbm.KERNEL_SWEEP)
     hlbm.profile_enable(lat, False)
     fsi_cells, bulk_cells = hlbm.sweep_partition(lat)
-    # with the internal second stream the timed sweep launch is the bulk part
-    sweep_cells = bulk_cells if os.environ.get("HLBM_STREAMS", "2") != "1" else w.cells
+    # one launch sweeps every cell (with the overlap option, the timed launch
+    # would be the part away from the rotors)
+    sweep_cells = w.cells
     it, cells = lat.wall_stats()
     ok = bool(torch.isfinite(lat.moments()[0]).all().item())
     lat.close()

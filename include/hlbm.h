@@ -55,10 +55,14 @@ enum hlbm_dtype { HLBM_F64 = 0, HLBM_F32 = 1, HLBM_F16 = 2, HLBM_BF16 = 3 };
 enum hlbm_bc { HLBM_BC_PERIODIC = 0, HLBM_BC_INFLOW_OUTFLOW = 1 };
 enum hlbm_transition { HLBM_TRANSITION_TANH = 0, HLBM_TRANSITION_LINEAR = 1 };
 
-/* Optional workspace sections requested at creation. */
+/* Options requested at creation: workspace sections, and the scheduling of
+ * the sweep. */
 #define HLBM_WITH_SOLID_VELOCITY 1   /* reserve a static solid-velocity field */
 #define HLBM_WITH_CONTROL 2          /* reserve a porosity control field (adjoint) */
 #define HLBM_WITH_ADJOINT 4          /* reserve the discrete-adjoint work arrays */
+#define HLBM_OVERLAP_STREAMS 8       /* sweep the workgroups away from the rotors on an
+                                        internal second stream, concurrently with the
+                                        rotor chain (same results, different timing) */
 
 typedef struct hlbm_lattice* hlbm_handle;
 

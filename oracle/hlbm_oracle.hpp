@@ -284,7 +284,11 @@ WallOut<T> wall_model_cell(const T us[3], const double uw[3], const double n[3],
   for (int a = 0; a < 3; ++a) vt[a] = v[a] - vn * n[a];
   T U2 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
   o.iters_tau = o.iters_plus = 0;
-  if (!(std::sqrt(re(U2)) >= 1e-10)) {
+  // below a tangential slip of 1e-6 lattice units (2e-5 of the free-stream
+  // speed of the rotor workloads) the wall law is not applied: the slip
+  // direction t is undefined as U -> 0 (on a rotor axis U vanishes by
+  // symmetry), and the bound lies above FP32 rounding noise in U
+  if (!(std::sqrt(re(U2)) >= 1e-6)) {
     o.active = false;
     for (int a = 0; a < 3; ++a) o.uwm[a] = T(0.0);
     for (int k = 0; k < 6; ++k) o.S[k] = T(0.0);

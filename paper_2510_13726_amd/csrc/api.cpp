@@ -28,6 +28,11 @@ bool desc_ok(const hlbm_desc* d, std::string* why) {
   if (d->nx < 2 || d->ny < 1 || d->nz < 1) { *why = "lattice needs nx >= 2, ny >= 1, nz >= 1"; return false; }
   const int64_t N = int64_t(d->nx) * d->ny * d->nz;
   if (N >= (int64_t(1) << 31)) { *why = "lattice above 2^31 cells"; return false; }
+  // kernels address inside one population array with 32-bit byte offsets
+  if (d->storage >= HLBM_F64 && d->storage <= HLBM_BF16 && N * elem_size(d->storage) > (int64_t(1) << 32) - 65536) {
+    *why = "one population array above 4 GiB (F64 storage above 536 million cells)";
+    return false;
+  }
   if (d->compute != HLBM_F64 && d->compute != HLBM_F32) { *why = "compute must be F64 or F32"; return false; }
   if (d->storage < HLBM_F64 || d->storage > HLBM_BF16) { *why = "unknown storage type"; return false; }
   if (d->compute == HLBM_F64 && d->storage != HLBM_F64) { *why = "F64 compute needs F64 storage"; return false; }
@@ -224,12 +229,13 @@ int rebuild_slots(hlbm_handle h) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "read block flags");
   // slot >= 0: FSI path with a force partial; -2: plain path within the wall
-  // model's probe reach (the adjoint gathers probe adjoints there); -1: plain
+  // model's probe reach; -1: plain path.  Both of the first two kinds are
+  // swept on the caller's stream: the wall model of the next step reads the
+  // probe cells (and their pull neighbours) that they write, with no wait on
+  // the internal stream; the adjoint gathers probe adjoints there.
   int32_t n = 0;
   std::vector<int32_t> fsi, bulk;
-  const char* rm = std::getenv("HLBM_REACH_MAIN");
-  const int lead = (rm && rm[0] == '1') ? 3 : 1;
-  for (size_t b = 0; b < flags.size(); ++b) ((flags[b] & lead) ? fsi : bulk).push_back(int32_t(b));
+  for (size_t b = 0; b < flags.size(); ++b) (flags[b] ? fsi : bulk).push_back(int32_t(b));
   for (auto& f : flags) f = (f & 1) ? n++ : (f & 2) ? -2 : -1;
   h->nslots = n;
   h->L.nfsi = int64_t(fsi.size());
@@ -414,11 +420,7 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.ghost64 = h->ghost64[0];
   L.blist = reinterpret_cast<int32_t*>(base + Y.blist);
   L.stream2 = nullptr;
-  // optional cap on the bulk launch's grid (0: one workgroup per tile, measured fastest)
-  L.bulk_grid = 0;
-  if (const char* e = std::getenv("HLBM_BULK_GRID")) L.bulk_grid = std::atoll(e);
-  h->dual = true;
-  if (const char* e = std::getenv("HLBM_STREAMS")) h->dual = std::atoi(e) != 1;
+  h->dual = (d->flags & HLBM_OVERLAP_STREAMS) != 0;
   if (h->dual) {
     hipError_t es = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
     if (es == hipSuccess) es = hipEventCreateWithFlags(&h->evP, hipEventDisableTiming);

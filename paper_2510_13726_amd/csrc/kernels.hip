@@ -23,9 +23,9 @@ __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >
 // XCD-aware workgroup order: the hardware deals consecutive workgroup ids
 // round-robin to the 8 XCDs; give each XCD a contiguous run of the domain so
 // that the cache lines shared by neighbouring workgroups stay in one L2.
-__device__ __forceinline__ int64_t remap_block(int64_t bid, int64_t nb, int32_t on) {
+__device__ __forceinline__ uint32_t remap_block(uint32_t bid, uint32_t nb, int32_t on) {
   if (!on) return bid;
-  const int64_t q = nb >> 3;
+  const uint32_t q = nb >> 3;
   if (bid >= (q << 3)) return bid;
   return (bid & 7) * q + (bid >> 3);
 }
@@ -63,6 +63,53 @@ __device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geom
     const uint32_t pz[3] = {uint32_t(zp) * g.ny, uint32_t(z) * g.ny, uint32_t(zm) * g.ny};
     const uint32_t py[3] = {uint32_t(yp), uint32_t(y), uint32_t(ym)};
     const int64_t plane = int64_t(g.ny) * g.nz;
+#pragma unroll
+    for (int i = 18; i < 27; ++i) h[i] = ghost[(i - 18) * plane + pz[cz_of(i) + 1] + py[cy_of(i) + 1]];
+  }
+}
+
+// Byte pointers into global memory (address space 1), so that a pointer
+// kept in scalar registers through an empty asm stays a global pointer.
+typedef __attribute__((address_space(1))) const char* gconst_bytes;
+typedef __attribute__((address_space(1))) char* gbytes;
+
+// pull_cell for a wave whose 64 lanes share y and z (uniform values): the
+// y/z part of every source address is a scalar, the per-lane part is one of
+// three x offsets, so each load is a scalar base plus a 32-bit lane offset.
+template <class ST, class CT, bool kPeriodicX>
+__device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geometry& g, int x, int y, int z,
+                                         const CT* __restrict__ ghost, CT h[27]) {
+  const int64_t nx = g.nx, nxy = int64_t(g.nx) * g.ny;
+  const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
+  const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
+  int xp, xm;
+  if (kPeriodicX) {
+    xp = x + 1 == g.nx ? 0 : x + 1;
+    xm = x == 0 ? g.nx - 1 : x - 1;
+  } else {
+    xp = x + 1 == g.nx ? x : x + 1;  // outflow: copy of the last plane
+    xm = x == 0 ? 0 : x - 1;         // inflow plane is replaced below
+  }
+  // byte offsets inside one population array fit 32 bits
+  constexpr uint32_t es = sizeof(ST);
+  const uint32_t oz[3] = {uint32_t(zp * nxy) * es, uint32_t(z * nxy) * es, uint32_t(zm * nxy) * es};
+  const uint32_t oy[3] = {uint32_t(yp * nx) * es, uint32_t(y * nx) * es, uint32_t(ym * nx) * es};
+  const uint32_t ox[3] = {uint32_t(xp) * es, uint32_t(x) * es, uint32_t(xm) * es};
+  const uint64_t step = uint64_t(g.stride) * es;
+  gconst_bytes p = (gconst_bytes)src;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    gconst_bytes q = p + (oz[cz_of(i) + 1] + oy[cy_of(i) + 1]);
+    h[i] = CT(w_of(i)) * Store<ST>::template load<CT>((const ST*)(q + ox[cx_of(i) + 1]));
+    // next array: a scalar pointer increment (kept from being folded into
+    // a multiply of the array index)
+    p += step;
+    asm("" : "+s"(p));
+  }
+  if (!kPeriodicX && x == 0) {
+    const int64_t plane = int64_t(g.ny) * g.nz;
+    const int64_t pz[3] = {int64_t(zp) * g.ny, int64_t(z) * g.ny, int64_t(zm) * g.ny};
+    const int py[3] = {yp, y, ym};
 #pragma unroll
     for (int i = 18; i < 27; ++i) h[i] = ghost[(i - 18) * plane + pz[cz_of(i) + 1] + py[cy_of(i) + 1]];
   }
@@ -343,7 +390,9 @@ __device__ __forceinline__ R newton(R u, F&& fdf, double tol, int maxit, int& it
 // Wall model of one cell given its probe velocity us, wall velocity uw,
 // outward normal nn, wall distance y1 and the previous friction velocity:
 // out = (u_wm[3], S[6] as xx yy zz xy xz yz, u_tau).  Returns false when the
-// tangential slip is below 1e-10 (cell treated as a plain cell).
+// tangential slip is below 1e-6 (cell treated as a plain cell): the slip
+// direction is undefined as the slip vanishes (by symmetry on a rotor axis),
+// and the bound sits above FP32 rounding noise in the probe velocity.
 template <class R>
 __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], const double nn[3], double y1,
                                            R utp, bool prev_active, const Model& m, R out[10], int& it1) {
@@ -352,7 +401,7 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   R vt[3] = {v[0] - vn * nn[0], v[1] - vn * nn[1], v[2] - vn * nn[2]};
   const R U2 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
   it1 = 0;
-  if (!(::sqrt(val(U2)) >= 1e-10)) return false;
+  if (!(::sqrt(val(U2)) >= 1e-6)) return false;
   const R U = sqrt(U2);
   const R t[3] = {vt[0] / U, vt[1] / U, vt[2] / U};
   const double nu = m.nu, ys = m.y_s, E = m.E, kap = m.kappa;
@@ -566,24 +615,28 @@ struct SweepArgs {
 // homogenized velocity and the wall model outputs and reduce the momentum
 // handed to each tag; the others run the plain bulk collision.
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
-__device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, int64_t blk, double (&lds)[4][kPartial]) {
+__device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk, double (&lds)[4][kPartial]) {
   const Geometry& g = a.g;
   // tile (tx, ty, z): 64 consecutive x-cells per wave, 4 y-rows per workgroup
-  const int tpz = g.ntx * g.nty;
-  const int z = int(blk / tpz);
-  const int trem = int(blk - int64_t(z) * tpz);
-  const int ty = trem / g.ntx, tx = trem - ty * g.ntx;
+  // tile ids and counts fit 32 bits (fewer than 2^31 cells, 256 per tile)
+  const uint32_t tpz = uint32_t(g.ntx) * uint32_t(g.nty);
+  const int z = int(uint32_t(blk) / tpz);
+  const uint32_t trem = uint32_t(blk) - uint32_t(z) * tpz;
+  const int ty = int(trem / uint32_t(g.ntx)), tx = int(trem - uint32_t(ty) * uint32_t(g.ntx));
   const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
-  const int yr = ty * kTileY + int(threadIdx.x >> 6);
-  const bool valid = xr < g.nx && yr < g.ny;
-  const int x = valid ? xr : 0, y = valid ? yr : 0;
-  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+  // one row per wave: y is uniform over the wave
+  const int yr = __builtin_amdgcn_readfirstlane(ty * kTileY + int(threadIdx.x >> 6));
+  const bool row_ok = yr < g.ny;
+  const bool valid = xr < g.nx && row_ok;
+  const int x = valid ? xr : 0, y = row_ok ? yr : 0;
+  const int64_t row = (int64_t(z) * g.ny + y) * g.nx;
+  const int64_t c = row + x;
 
   CT h[27];
-  pull_cell<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+  pull_row<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
   const Moments<CT> mo = moments_of<CT>(h);
   const CT rho = CT(1) + mo.drho;
-  const CT irho = CT(1) / rho;
+  const CT irho = rcp_ct(rho);
   const CT ux = mo.jx * irho, uy = mo.jy * irho, uz = mo.jz * irho;
   const CT tau0 = CT(a.m.tau0), smag = CT(a.m.smag);
 
@@ -684,10 +737,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, int64_t blk, 
   }
   if (!kMoments) {
     if (valid) {
-      ST* dst = static_cast<ST*>(a.dst);
-      const uint32_t o = uint32_t(c) * uint32_t(sizeof(ST));
+      gbytes p = (gbytes)(static_cast<ST*>(a.dst) + row);
+      const uint32_t o = uint32_t(x) * uint32_t(sizeof(ST));
+      const uint64_t step = uint64_t(g.stride) * sizeof(ST);
 #pragma unroll
-      for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(at_bytes(dst + int64_t(i) * g.stride, o), g2[i]);
+      for (int i = 0; i < 27; ++i) {
+        Store<ST>::template store<CT>((ST*)(p + o), g2[i]);
+        p += step;
+        asm("" : "+s"(p));
+      }
     }
     if (a.mass_part) {
       const double mrho = valid ? double(rho) : 0.0;
@@ -701,18 +759,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, int64_t blk, 
   }
 }
 
-// Workgroups walk the tile list (all tiles, or the FSI / bulk part) with a
-// grid-stride loop; a grid smaller than the list keeps part of the GPU free
-// for the kernels that run concurrently on the other stream.
+// One workgroup per entry of the tile list (all tiles, or the FSI / bulk
+// part), XCD-aware order.
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   __shared__ double lds[4][kPartial];
-  const int64_t nwork = a.blist ? a.nlist : a.nblocks;
-  for (int64_t it = blockIdx.x; it < nwork; it += gridDim.x) {
-    const int64_t blk = a.blist ? int64_t(a.blist[remap_block(it, nwork, a.remap)]) : remap_block(it, nwork, a.remap);
-    sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
-    __syncthreads();
-  }
+  const uint32_t nwork = uint32_t(a.blist ? a.nlist : a.nblocks);
+  const uint32_t it = blockIdx.x;
+  const uint32_t blk = a.blist ? uint32_t(a.blist[remap_block(it, nwork, a.remap)]) : remap_block(it, nwork, a.remap);
+  sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
 }
 
 // Force / torque / mass reduction of one step, level 1: workgroup b sums FSI
@@ -945,10 +1000,11 @@ template <class ST, class CT, bool kPeriodicX>
 __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const Geometry& g = a.g;
   const int64_t blk = blockIdx.x;
-  const int tpz = g.ntx * g.nty;
-  const int z = int(blk / tpz);
-  const int trem = int(blk - int64_t(z) * tpz);
-  const int ty = trem / g.ntx, tx = trem - ty * g.ntx;
+  // tile ids and counts fit 32 bits (fewer than 2^31 cells, 256 per tile)
+  const uint32_t tpz = uint32_t(g.ntx) * uint32_t(g.nty);
+  const int z = int(uint32_t(blk) / tpz);
+  const uint32_t trem = uint32_t(blk) - uint32_t(z) * tpz;
+  const int ty = int(trem / uint32_t(g.ntx)), tx = int(trem - uint32_t(ty) * uint32_t(g.ntx));
   const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
   const int yr = ty * kTileY + int(threadIdx.x >> 6);
   if (xr >= g.nx || yr >= g.ny) return;
@@ -985,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   collide_vjp<CT>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
   if (gather) {
     // probe velocity u = j / rho at this cell, sampled by wall cells
-    const CT rho = CT(1) + mo.drho, irho = CT(1) / rho;
+    const CT rho = CT(1) + mo.drho, irho = rcp_ct(rho);
     const CT ju = CT(ub[0]) * mo.jx + CT(ub[1]) * mo.jy + CT(ub[2]) * mo.jz;
     mb.drho -= ju * irho * irho;
     mb.jx += CT(ub[0]) * irho;
@@ -1187,10 +1243,7 @@ hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t ste
     a.blist = part == 0 ? nullptr : part == 1 ? L.blist : L.blist + L.nfsi;
     a.nlist = n;
     hipStream_t s = part == 2 ? L.stream2 : L.stream;
-    // the bulk part runs beside the rotor chain: cap its grid (a multiple of
-    // the 8 XCDs) so that workgroup slots stay free for the other stream
-    int64_t grid = n;
-    if (part == 2 && L.bulk_grid > 0 && grid > L.bulk_grid) grid = L.bulk_grid;
+    const int64_t grid = n;
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(grid)), dim3(kBlock), 0, s, a);
     else

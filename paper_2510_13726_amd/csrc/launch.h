@@ -18,7 +18,6 @@ struct Launch {
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
   int32_t* blist;            // FSI workgroups, then bulk workgroups
   int64_t nfsi, nbulk;
-  int64_t bulk_grid;         // workgroups of the persistent bulk launch (0 = one per tile)
   int32_t xcd_remap;
   // fields
   void* d_eff;

@@ -84,6 +84,16 @@ __device__ __forceinline__ T* at_bytes(T* base, uint32_t byte_off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
 }
 
+// ---------------------------------------------------------------- rcp / sqrt
+// Reciprocal and square root in the compute type: correctly rounded in FP64;
+// in FP32 the hardware approximations (v_rcp_f32, v_sqrt_f32, about 1 ulp),
+// far inside the FP32 tolerance and a fraction of the instructions of the
+// correctly rounded sequences.
+template <class T> __device__ __forceinline__ T rcp_ct(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float rcp_ct<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <class T> __device__ __forceinline__ T sqrt_ct(T x) { return sqrt(x); }
+template <> __device__ __forceinline__ float sqrt_ct<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---------------------------------------------------------------- moments
 // Deviation moments of h_i = f_i - w_i: drho = sum h, j = sum c h,
 // p = sum c c h (so P = cs^2 I + p).
@@ -240,9 +250,9 @@ __device__ __forceinline__ void collide(const Moments<CT>& m, CT rho, CT ux, CT 
   const CT Pxz = m.pxz - ru_x * uz;
   const CT Pyz = m.pyz - ru_y * uz;
   const CT q2 = Pxx * Pxx + Pyy * Pyy + Pzz * Pzz + CT(2) * (Pxy * Pxy + Pxz * Pxz + Pyz * Pyz);
-  const CT Q = sqrt(q2);
-  const CT tau = CT(0.5) * (tau0 + sqrt(tau0 * tau0 + smag * Q / rho));
-  const CT om = CT(1) - CT(1) / tau;
+  const CT Q = sqrt_ct(q2);
+  const CT tau = CT(0.5) * (tau0 + sqrt_ct(tau0 * tau0 + smag * Q * rcp_ct(rho)));
+  const CT om = CT(1) - rcp_ct(tau);
   const CT c45 = CT(4.5);
   CT b2xx, b2yy, b2zz, b2xy, b2xz, b2yz, os;
   if (kWall) {
@@ -352,7 +362,7 @@ __device__ __forceinline__ void collide_vjp(const Moments<CT>& m, CT d, CT bx, C
                                             CT& db, CT bb[3], CT Sb[6]) {
   const CT third = CT(1.0 / 3.0), c45 = CT(4.5);
   // ---- forward intermediates
-  const CT rho = CT(1) + m.drho, irho = CT(1) / rho;
+  const CT rho = CT(1) + m.drho, irho = rcp_ct(rho);
   const CT u[3] = {m.jx * irho, m.jy * irho, m.jz * irho};
   const CT e[3] = {bx - u[0], by - u[1], bz - u[2]};
   const CT uh[3] = {u[0] + d * e[0], u[1] + d * e[1], u[2] + d * e[2]};
@@ -362,11 +372,11 @@ __device__ __forceinline__ void collide_vjp(const Moments<CT>& m, CT d, CT bx, C
   const CT P[6] = {m.pxx - dd - ru[0] * uh[0], m.pyy - dd - ru[1] * uh[1], m.pzz - dd - ru[2] * uh[2],
                    m.pxy - ru[0] * uh[1],      m.pxz - ru[0] * uh[2],      m.pyz - ru[1] * uh[2]};
   const CT q2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + CT(2) * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
-  const CT Q = sqrt(q2);
-  const CT sarg = smag * Q / rho;
-  const CT rr = sqrt(tau0 * tau0 + sarg);
+  const CT Q = sqrt_ct(q2);
+  const CT sarg = smag * Q * irho;
+  const CT rr = sqrt_ct(tau0 * tau0 + sarg);
   const CT tau = CT(0.5) * (tau0 + rr);
-  const CT om = CT(1) - CT(1) / tau;
+  const CT om = CT(1) - rcp_ct(tau);
   const CT os = om * sigma;
   const CT fd = om * CT(3) * (CT(1) - sigma) * rho * tau;
   const CT pi = c45 * os, t = c45 * os;

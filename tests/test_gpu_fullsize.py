@@ -93,6 +93,17 @@ def _slab_case(w, x0, length, n, storage, box):
     e = rel(hg, ho)
     print(f"[fullsize] {w.name} {storage}: h rel err {e:.3e} (max |h| {np.abs(ho).max():.3e}); "
           f"slab newton {o.newton_stats()}", flush=True)
+    if e >= TOL[storage]:
+        err = np.abs(hg - ho).max(axis=1)
+        bad = np.argsort(-err)[:8]
+        for b in bad:
+            c = int(cells[b])
+            x, y, z = c % w.nx, (c // w.nx) % w.ny, c // (w.nx * w.ny)
+            near = min(((x - r.center[0]) ** 2 + (y - r.center[1]) ** 2 + (z - r.center[2]) ** 2) ** 0.5
+                       for r in w.rotors) if w.rotors else -1
+            print(f"[fullsize]   cell ({x},{y},{z}) err {err[b]:.3e} dist to nearest rotor centre {near:.1f}",
+                  flush=True)
+        print(f"[fullsize]   cells above tolerance: {(err > TOL[storage] * np.abs(ho).max()).sum()}", flush=True)
     return e, o
 
 

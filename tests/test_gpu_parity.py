@@ -25,10 +25,10 @@ def rel(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
 
 
-def run_both(w, storage, steps, check_every=None):
+def run_both(w, storage, steps, check_every=None, flags=0):
     hl = _hl()
-    print(f"[parity] {w.name} storage={storage} steps={steps}", flush=True)
-    lat = hl.setup(w, storage=storage, check_nonfinite=1)
+    print(f"[parity] {w.name} storage={storage} steps={steps} flags={flags}", flush=True)
+    lat = hl.setup(w, storage=storage, check_nonfinite=1, flags=flags)
     o = O.setup(w)
     errs = []
     done = 0
@@ -63,12 +63,13 @@ def test_tgv_sphere_parity(storage):
     assert rel(uh_g, uh_o) < TOL[storage]
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_rotor_wall_model_parity(storage):
+@pytest.mark.parametrize("storage,flags", [("f64", 0), ("f32", 0), ("f64", 8)])
+def test_rotor_wall_model_parity(storage, flags):
     """Rotor channel with inflow turbulence, outflow, rotating flat-plate rotor
-    and the wall model, 24 steps (several tiles, ragged x extent)."""
+    and the wall model, 24 steps (several tiles, ragged x extent); flags 8:
+    the sweep away from the rotor on the second stream."""
     w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
-    lat, o, errs = run_both(w, storage, 24, check_every=8)
+    lat, o, errs = run_both(w, storage, 24, check_every=8, flags=flags)
     assert max(errs) < TOL[storage], errs
     hg, ho = lat.history(), o.history()
     assert rel(hg[:, 1:7], ho[:, 1:7]) < 10 * TOL[storage]
@@ -84,6 +85,30 @@ def test_rotor_wall_model_parity(storage):
           f"newton {it_g}/{it_o} wall cells {n_g}", flush=True)
     assert rel(u_g, u_o) < TOL[storage]
     assert rel(uh_g, uh_o) < TOL[storage]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_two_rotor_wall_model_parity(storage):
+    """Two rotors side by side (tags 1 and 2, different phases) with the wall
+    model and inflow turbulence: per-rotor boxes, wall lists and states."""
+    w = W.small_rotor(nx=80, ny=72, nz=36, R=11.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    r0 = w.rotors[0]
+    r0.center = (24.3, 19.6, 18.2)
+    r0.phase0 = 0.3
+    r1 = W.Rotor(center=(24.8, 53.1, 17.7), R=11.0, r_hub=2.0, chord=4.0, thick=3.0, omega=r0.omega,
+                 phase0=1.7, tag=2)
+    w.rotors.append(r1)
+    lat, o, errs = run_both(w, storage, 16, check_every=8)
+    hg, ho = lat.history(), o.history()
+    it_g, n_g = lat.wall_stats()
+    it_o, n_o = o.newton_stats()
+    print(f"[parity] two rotors {storage}: h {max(errs):.3e} F,T {rel(hg[:, 1:13], ho[:, 1:13]):.3e} "
+          f"newton {it_g}/{it_o} wall cells {n_g}/{n_o}", flush=True)
+    assert max(errs) < TOL[storage], errs
+    assert rel(hg[:, 1:13], ho[:, 1:13]) < 10 * TOL[storage]
+    assert n_g == n_o and n_g > 200
+    if storage == "f64":
+        assert it_g == it_o
 
 
 def test_periodic_rotor_parity_fp64():

@@ -234,20 +234,27 @@ def test_wall_newton_root_and_log_law():
 
 
 def test_wall_laminar_guess_exact():
-    """In the viscous sublayer (y+ << 1) the laminar guess sqrt(nu U / y) already
-    solves the wall law up to the O(u+^4) bracket: Newton stops after one step."""
+    """In the viscous sublayer the laminar guess u0 = sqrt(nu U / y) makes the
+    linear part of the wall law vanish, leaving f(u0) = bracket(kappa p0)/E =
+    (kappa p0)^4 / (24 E) + ... with p0 = y u0 / nu; one Newton step (f' =
+    -2 y / nu there) moves u0 by the relative amount kappa^4 p0^3 / (48 E),
+    after which the stop rule ends the iteration."""
     p = _params()
     nu = CS2 * (p.tau0 - 0.5)
-    U = 1e-9
-    r = O.wall_cell((U, 0, 0), (0, 0, 0), (0, 0, 1.0), 0.5, p)
-    assert r["iters"] == 1
-    assert abs(r["utau"] - math.sqrt(nu * U / p.y_s)) / r["utau"] < 1e-9
+    for U in (1.5e-6, 6e-6):
+        r = O.wall_cell((U, 0, 0), (0, 0, 0), (0, 0, 1.0), 0.5, p)
+        assert r["active"] and r["iters"] == 1
+        u0 = math.sqrt(nu * U / p.y_s)
+        p0 = p.y_s * u0 / nu
+        dev = (r["utau"] - u0) / u0
+        expect = p.kappa ** 4 * p0 ** 3 / (48.0 * p.E)
+        assert 0 < dev and abs(dev / expect - 1.0) < 0.05
 
 
 def test_wall_stop_rule_and_guess():
     """Stop rule |f(u^{j+1}) - f(u^j)| < 1e-4 with at most 10 iterations; a
     previous friction velocity is used as the guess when the cell was active
-    (eq. guess); below U = 1e-10 the cell is inactive."""
+    (eq. guess); below a tangential slip U = 1e-6 the cell is inactive."""
     p = _params()
     r1 = O.wall_cell((0.05, 0, 0), (0, 0, 0), (0, 1.0, 0), 0.5, p)
     assert 1 <= r1["iters"] <= 10
@@ -255,6 +262,9 @@ def test_wall_stop_rule_and_guess():
     assert r2["iters"] == 1 and abs(r2["utau"] - r1["utau"]) / r1["utau"] < 1e-6
     r3 = O.wall_cell((1e-12, 0, 0), (1e-12, 0, 0), (0, 1.0, 0), 0.5, p)
     assert not r3["active"] and np.all(r3["uwm"] == 0)
+    # the bound is on the tangential part of the slip only
+    assert not O.wall_cell((0.06 + 9e-7, 0.02, 0), (0.06, 0.0, 0), (0, 1.0, 0), 0.5, p)["active"]
+    assert O.wall_cell((0.06 + 2e-6, 0.02, 0), (0.06, 0.0, 0), (0, 1.0, 0), 0.5, p)["active"]
     # a moving wall: only the velocity relative to the wall counts
     r4 = O.wall_cell((0.07, 0.01, 0), (0.02, 0.0, 0), (0, 1.0, 0), 0.5, p)
     r5 = O.wall_cell((0.05, 0.03, 0), (0.0, 0.0, 0), (0, 1.0, 0), 0.5, p)
