@@ -55,14 +55,10 @@ enum hlbm_dtype { HLBM_F64 = 0, HLBM_F32 = 1, HLBM_F16 = 2, HLBM_BF16 = 3 };
 enum hlbm_bc { HLBM_BC_PERIODIC = 0, HLBM_BC_INFLOW_OUTFLOW = 1 };
 enum hlbm_transition { HLBM_TRANSITION_TANH = 0, HLBM_TRANSITION_LINEAR = 1 };
 
-/* Options requested at creation: workspace sections, and the scheduling of
- * the sweep. */
+/* Optional workspace sections requested at creation. */
 #define HLBM_WITH_SOLID_VELOCITY 1   /* reserve a static solid-velocity field */
 #define HLBM_WITH_CONTROL 2          /* reserve a porosity control field (adjoint) */
 #define HLBM_WITH_ADJOINT 4          /* reserve the discrete-adjoint work arrays */
-#define HLBM_OVERLAP_STREAMS 8       /* sweep the workgroups away from the rotors on an
-                                        internal second stream, concurrently with the
-                                        rotor chain (same results, different timing) */
 
 typedef struct hlbm_lattice* hlbm_handle;
 
@@ -211,8 +207,9 @@ int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, i
                         void* ckpt, int64_t ckpt_bytes, double* J);
 int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack_bytes);
 
-/* Wall-model counters since creation: Newton iterations for u_tau and wall
- * cells processed (host, syncs). */
+/* Wall-model counters since creation, accumulated on diagnostics steps
+ * (every diag_every-th step): Newton iterations for u_tau and wall cells
+ * solved (host, syncs). */
 int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
 
 /* Opt-in kernel timing with HIP events recorded on the lattice's stream
@@ -220,13 +217,15 @@ int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
  * (HLBM_KERNEL_*).  hlbm_profile_enable(h, 1) starts a fresh count;
  * hlbm_profile_read synchronizes and returns the number of timed launches
  * and their summed duration in milliseconds.  For benchmarks and tests. */
+/* SWEEP: stream-collide sweep; WALL: wall model; RASTERIZE: rotor geometry
+ * (with the step's inflow plane); OTHER: batched force reductions and
+ * separately launched inflow planes. */
 enum hlbm_kernel { HLBM_KERNEL_SWEEP = 0, HLBM_KERNEL_WALL = 1, HLBM_KERNEL_RASTERIZE = 2, HLBM_KERNEL_OTHER = 3 };
 int hlbm_profile_enable(hlbm_handle h, int32_t enable);
 int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* total_ms);
-/* Cells swept by the porous (FSI) workgroups, which run on the caller's
- * stream after the rotor kernels, and by the bulk workgroups, which run on
- * an internal stream concurrently with them (host, syncs).  With the two
- * streams on, HLBM_KERNEL_SWEEP times the bulk launches. */
+/* Cells of the sweep's porous (FSI) workgroups, which apply porosity, solid
+ * and wall-model velocities and reduce the per-tag momentum, and of its
+ * plain workgroups (host, syncs). */
 int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells);
 
 /* Message of the last error of this handle (or of the last failed create

@@ -63,7 +63,8 @@ int64_t pop_stride_c(const hlbm_desc* d) {
 
 struct Layout {
   int64_t d_eff, d_static, tag, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wcount, flag, stats, rot, geo, ut0, ut1,
-      act0, act1, wall, hist, ghost, ghost64, ghostb, ghost64b, blist, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut, scr_act, total;
+      act0, act1, wall, hist, ghost, ghost64, ghostb, ghost64b, blist, trig, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut,
+      scr_act, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -84,9 +85,9 @@ Layout layout(const hlbm_desc* d) {
   L.dd = take((d->flags & HLBM_WITH_CONTROL) ? N * cs : 0);
   L.blk = take(nb * 4);
   L.partial = take(nb * kPartial * 8);
-  L.partl1 = take(int64_t(kPartL1) * kPartial * 8);
-  L.mass = take(nb * 8);
-  L.massl1 = take(kPartL1 * 8);
+  L.partl1 = take(int64_t(kMaxBatch) * kPartL1 * kPartial * 8);
+  L.mass = take(int64_t(kMaxBatch) * nb * 8);
+  L.massl1 = take(int64_t(kMaxBatch) * kPartL1 * 8);
   L.wlist = take(B * 4);
   L.wcount = take(64);
   L.flag = take(64);
@@ -105,6 +106,7 @@ Layout layout(const hlbm_desc* d) {
   L.ghostb = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * cs : 0);
   L.ghost64b = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
   L.blist = take(nb * 4);
+  L.trig = take(d->bbox_cells > 0 ? int64_t(kTrigSteps) * int64_t(sizeof(BladeTrig)) : 0);
   const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
   const int64_t lam_bytes = adj ? 27 * pop_stride_c(d) * cs : 0;
   L.lam0 = take(lam_bytes);
@@ -180,12 +182,15 @@ struct hlbm_lattice {
     char* ckpt = nullptr;
     double J = 0.0;
   } rec;
-  // second stream for the bulk sweep and the events tying it to the caller's stream
-  bool dual = false;
-  hipStream_t stream2 = nullptr;
-  hipEvent_t evP = nullptr, evB[2] = {nullptr, nullptr};
-  bool b_pending = false;
-  int last_b = 0;
+  int wc_epoch = 0;  // wall-list counter of the next geometry launch
+  // steps swept but not yet reduced: pending steps from pend_n0; their force
+  // partials are slices of `batch` steps in the partial buffer
+  int64_t pend_n0 = 0;
+  int32_t pending = 0, batch = 1;
+  // blade angles on the device for steps [trig_base, trig_base + kTrigSteps)
+  BladeTrig* trig_host = nullptr;  // pinned staging buffer
+  hipEvent_t trig_ev = nullptr;
+  int64_t trig_base = -1;
   void* ghost[2] = {nullptr, nullptr};
   double* ghost64[2] = {nullptr, nullptr};
   bool profiling = false;
@@ -228,22 +233,25 @@ int rebuild_slots(hlbm_handle h) {
   e = hipMemcpyAsync(flags.data(), h->L.blk_slot, sizeof(int32_t) * flags.size(), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "read block flags");
-  // slot >= 0: FSI path with a force partial; -2: plain path within the wall
-  // model's probe reach; -1: plain path.  Both of the first two kinds are
-  // swept on the caller's stream: the wall model of the next step reads the
-  // probe cells (and their pull neighbours) that they write, with no wait on
-  // the internal stream; the adjoint gathers probe adjoints there.
+  // slot >= 0: FSI path (porosity, tags, wall-model outputs, force partial);
+  // -2: plain path within the wall model's probe reach, where the adjoint
+  // gathers the probe-velocity adjoints; -1: plain path.
   int32_t n = 0;
-  std::vector<int32_t> fsi, bulk;
-  for (size_t b = 0; b < flags.size(); ++b) (flags[b] ? fsi : bulk).push_back(int32_t(b));
   for (auto& f : flags) f = (f & 1) ? n++ : (f & 2) ? -2 : -1;
   h->nslots = n;
-  h->L.nfsi = int64_t(fsi.size());
-  h->L.nbulk = int64_t(bulk.size());
-  fsi.insert(fsi.end(), bulk.begin(), bulk.end());
+  // the partial buffer holds nblocks slots: as many steps of slices as fit
+  h->batch = int32_t(std::max<int64_t>(1, std::min<int64_t>(kMaxBatch, h->L.nblocks / std::max<int32_t>(n, 1))));
+  // Launch order.  Workgroup i runs on XCD i mod 8, in the order of i: list
+  // entry 8j + k is the j-th tile of XCD k.  Each XCD sweeps one contiguous
+  // eighth of the tiles, so the lines shared by neighbouring tiles stay in
+  // its L2 (measured fastest, ahead of spreading the FSI tiles first).
+  const int64_t T = int64_t(flags.size());
+  const int64_t q = T / kXcds;
+  std::vector<int32_t> order(T);
+  for (int64_t i = 0; i < T; ++i) order[i] = int32_t(i >= q * kXcds ? i : (i % kXcds) * q + i / kXcds);
   e = hipMemcpyAsync(h->L.blk_slot, flags.data(), sizeof(int32_t) * flags.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h->L.blist, fsi.data(), sizeof(int32_t) * fsi.size(), hipMemcpyHostToDevice, h->stream);
+    e = hipMemcpyAsync(h->L.blist, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "write block slots");
   return HLBM_OK;
@@ -379,8 +387,6 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.g.ntx = (d->nx + kTileX - 1) / kTileX;
   L.g.nty = (d->ny + kTileY - 1) / kTileY;
   L.nblocks = int64_t(L.g.ntx) * L.g.nty * d->nz;
-  L.xcd_remap = 1;
-  if (const char* e = std::getenv("HLBM_XCD_REMAP")) L.xcd_remap = std::atoi(e);
   const Layout& Y = h->lay;
   L.d_eff = base + Y.d_eff;
   L.d_static = base + Y.d_static;
@@ -419,20 +425,7 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.ghost = h->ghost[0];
   L.ghost64 = h->ghost64[0];
   L.blist = reinterpret_cast<int32_t*>(base + Y.blist);
-  L.stream2 = nullptr;
-  h->dual = (d->flags & HLBM_OVERLAP_STREAMS) != 0;
-  if (h->dual) {
-    hipError_t es = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
-    if (es == hipSuccess) es = hipEventCreateWithFlags(&h->evP, hipEventDisableTiming);
-    if (es == hipSuccess) es = hipEventCreateWithFlags(&h->evB[0], hipEventDisableTiming);
-    if (es == hipSuccess) es = hipEventCreateWithFlags(&h->evB[1], hipEventDisableTiming);
-    if (es != hipSuccess) {
-      hip_fail(nullptr, es, "create internal stream");
-      delete h;
-      return HLBM_ERR_HIP;
-    }
-    L.stream2 = h->stream2;
-  }
+  L.trig_tab = d->bbox_cells > 0 ? reinterpret_cast<BladeTrig*>(base + Y.trig) : nullptr;
   // defaults: Smagorinsky-free BGK-like relaxation at tau0 = 1 until set_params
   hlbm_params p{};
   p.tau0 = 1.0; p.cs_smag = 0.0; p.eps_h = 2.0; p.transition = HLBM_TRANSITION_TANH; p.wall_model = 0;
@@ -470,13 +463,8 @@ void hlbm_lattice_destroy(hlbm_handle h) {
   for (auto& v : h->prof)
     for (auto& p : v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto e : h->pool) (void)hipEventDestroy(e);
-  if (h->stream2) {
-    (void)hipStreamSynchronize(h->stream2);
-    (void)hipStreamDestroy(h->stream2);
-  }
-  if (h->evP) (void)hipEventDestroy(h->evP);
-  for (auto e : h->evB)
-    if (e) (void)hipEventDestroy(e);
+  if (h->trig_ev) (void)hipEventDestroy(h->trig_ev);
+  if (h->trig_host) (void)hipHostFree(h->trig_host);
   delete h;
 }
 
@@ -509,6 +497,7 @@ int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* r, int32_t n) {
   int rc = build_rotor_table(h, r, n, &t, &total);
   if (rc != HLBM_OK) return rc;
   h->rot = t;
+  h->trig_base = -1;  // the blade angles change with the rotors
   h->rotors.assign(r, r + n);
   h->L.nrot = n;
   h->L.bbox_total = total;
@@ -601,6 +590,32 @@ BladeTrig blade_trig(hlbm_handle h, int64_t n) {
   return t;
 }
 
+// Blade angles of step n on the device: the table holds kTrigSteps steps
+// from trig_base; a step outside it reloads the table from step n (host
+// cos / sin, one asynchronous copy from a pinned buffer).
+hipError_t trig_of(hlbm_handle h, int64_t n, const BladeTrig** out) {
+  *out = nullptr;
+  if (h->rot.n == 0 || !h->L.trig_tab) return hipSuccess;
+  if (h->trig_base < 0 || n < h->trig_base || n >= h->trig_base + kTrigSteps) {
+    hipError_t e = hipSuccess;
+    if (!h->trig_host) {
+      e = hipHostMalloc(reinterpret_cast<void**>(&h->trig_host), sizeof(BladeTrig) * kTrigSteps, 0);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&h->trig_ev, hipEventDisableTiming);
+    } else {
+      e = hipEventSynchronize(h->trig_ev);  // the previous copy has read the buffer
+    }
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < kTrigSteps; ++k) h->trig_host[k] = blade_trig(h, n + k);
+    e = hipMemcpyAsync(h->L.trig_tab, h->trig_host, sizeof(BladeTrig) * kTrigSteps, hipMemcpyHostToDevice,
+                       h->stream);
+    if (e == hipSuccess) e = hipEventRecord(h->trig_ev, h->stream);
+    if (e != hipSuccess) return e;
+    h->trig_base = n;
+  }
+  *out = h->L.trig_tab + (n - h->trig_base);
+  return hipSuccess;
+}
+
 hipEvent_t take_event(hlbm_handle h) {
   if (!h->pool.empty()) {
     hipEvent_t e = h->pool.back();
@@ -614,9 +629,9 @@ hipEvent_t take_event(hlbm_handle h) {
 
 // Run one launch, bracketed by events when profiling is on.
 template <class F>
-hipError_t timed(hlbm_handle h, int kind, F&& f, hipStream_t s = nullptr) {
+hipError_t timed(hlbm_handle h, int kind, F&& f) {
   if (!h->profiling) return f();
-  if (!s) s = h->stream;
+  hipStream_t s = h->stream;
   hipEvent_t a = take_event(h), b = take_event(h);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, s);
@@ -625,66 +640,60 @@ hipError_t timed(hlbm_handle h, int kind, F&& f, hipStream_t s = nullptr) {
   h->prof[kind].push_back({a, b});
   return e;
 }
-}  // namespace
+// Force / torque / mass records of the pending steps (one reduction launch
+// pair for all of them).
+hipError_t flush(hlbm_handle h) {
+  if (h->pending == 0) return hipSuccess;
+  const int32_t cnt = h->pending;
+  h->pending = 0;
+  return timed(h, HLBM_KERNEL_OTHER, [&] {
+    return launch_finalize(h->L, h->pend_n0, cnt, h->nslots, h->params.diag_every);
+  });
+}
 
-extern "C" {
+// A wall-model probe (and the pull around it) can reach the inflow plane
+// when a rotor's marking box touches x = 0.
+bool probe_reaches_inlet(hlbm_handle h) {
+  if (h->L.g.bc_x == 0 || !h->params.wall_model) return false;
+  for (int k = 0; k < h->rot.n; ++k)
+    if (h->rot.r[k].mb0[0] <= 0) return true;
+  return false;
+}
 
-}  // extern "C"
-
-namespace {
 // One forward step n from state `src` to `dst` with the wall-model state
-// (ut_prev, act_prev) -> (ut_new, act_new); `jac` (optional) receives the
-// wall Jacobians of the listed wall cells.
+// (ut_prev, act_prev) -> (ut_new, act_new): inflow plane, the step sweep
+// (geometry and wall model inside its FSI workgroups), force reduction.
 hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, const double* ut_prev,
                        const uint8_t* act_prev, double* ut_new, uint8_t* act_new) {
-  const bool wall = h->params.wall_model && h->L.nrot > 0;
-  const BladeTrig trig = blade_trig(h, n);
-  // inflow ghost planes alternate by step so that step n-1's readers may still run
+  const BladeTrig* trig = nullptr;
+  hipError_t e = trig_of(h, n, &trig);
+  if (e != hipSuccess) return e;
+  // inflow ghost planes alternate by step
   h->L.ghost = h->ghost[n & 1];
   h->L.ghost64 = h->ghost64[n & 1];
   const bool diag = h->params.diag_every > 0 && n % h->params.diag_every == 0;
-  hipError_t e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_prologue(h->L, n); });
-  if (!h->dual) {
-    if (e == hipSuccess)
-      e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_rasterize(h->L, n, trig, act_new); });
-    if (e == hipSuccess && wall)
-      e = timed(h, HLBM_KERNEL_WALL,
-              [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n, nullptr, diag); });
-    if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, diag, 0); });
-    if (e == hipSuccess)
-      e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, n, h->nslots, diag); });
-    return e;
-  }
-  // bulk workgroups on the internal stream, after this step's inflow plane
-  // (and, through the caller's stream order, after the previous FSI sweep)
-  if (e == hipSuccess) e = hipEventRecord(h->evP, h->stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(h->stream2, h->evP, 0);
+  const bool wall = h->params.wall_model && h->L.nrot > 0;
+  // the inflow plane is written by the geometry launch, unless a wall-model
+  // probe can reach the inlet: then it must be complete before that launch
+  const bool inlet = probe_reaches_inlet(h);
+  if (inlet) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_prologue(h->L, n); });
+  const int epoch = h->wc_epoch++;
   if (e == hipSuccess)
-    e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, diag, 2); }, h->stream2);
-  if (e == hipSuccess) e = hipEventRecord(h->evB[n & 1], h->stream2);
-  // rotor chain on the caller's stream; the FSI sweep also reads cells the
-  // previous bulk sweep wrote
-  if (e == hipSuccess)
-    e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_rasterize(h->L, n, trig, act_new); });
+    e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_geometry(h->L, n, trig, epoch, act_new, !inlet); });
   if (e == hipSuccess && wall)
-    e = timed(h, HLBM_KERNEL_WALL,
-              [&] { return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n, nullptr, diag); });
-  if (e == hipSuccess && h->b_pending) e = hipStreamWaitEvent(h->stream, h->evB[(n + 1) & 1], 0);
-  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_sweep(h->L, src, dst, n, diag, 1); });
-  // the mass of a diagnostics step needs this step's bulk partials too
-  if (e == hipSuccess && diag) e = hipStreamWaitEvent(h->stream, h->evB[n & 1], 0);
-  if (e == hipSuccess)
-    e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_finalize(h->L, n, h->nslots, diag); });
-  h->b_pending = true;
-  h->last_b = n & 1;
+    e = timed(h, HLBM_KERNEL_WALL, [&] {
+      return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n, epoch, nullptr, diag ? 1 : 0);
+    });
+  // force partials (and mass partials of a diagnostics step) into this step's slice
+  if (e == hipSuccess && h->pending == h->batch) e = flush(h);
+  if (h->pending == 0) h->pend_n0 = n;
+  const int32_t j = h->pending;
+  Launch Ls = h->L;
+  Ls.partial = h->L.partial + int64_t(j) * std::max<int32_t>(h->nslots, 1) * kPartial;
+  Ls.mass_part = h->L.mass_part + int64_t(j) * h->L.nblocks;
+  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(Ls, src, dst, n, diag); });
+  if (e == hipSuccess) ++h->pending;
   return e;
-}
-
-// Order the caller's stream after the last bulk sweep.
-hipError_t join(hlbm_handle h) {
-  if (!h->dual || !h->b_pending) return hipSuccess;
-  h->b_pending = false;
-  return hipStreamWaitEvent(h->stream, h->evB[h->last_b], 0);
 }
 
 int check_flag(hlbm_handle h) {
@@ -748,8 +757,8 @@ int hlbm_step(hlbm_handle h, int64_t n) {
     if (wall) h->wcur = 1 - h->wcur;
     ++h->step;
   }
-  hipError_t ej = join(h);
-  if (ej != hipSuccess) return hip_fail(h, ej, "step");
+  hipError_t ef = flush(h);
+  if (ef != hipSuccess) return hip_fail(h, ef, "step");
   h->rec.valid = false;
   if (h->params.check_nonfinite) return check_flag(h);
   return HLBM_OK;
@@ -850,7 +859,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
                       reinterpret_cast<uint8_t*>(s0 + sl.act), reinterpret_cast<double*>(s1 + sl.ut),
                       reinterpret_cast<uint8_t*>(s1 + sl.act));
     }
-    if (e == hipSuccess) e = join(h);
+    if (e == hipSuccess) e = flush(h);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint recompute");
     for (int64_t k = b - 1; k >= a; --k) {
       const int64_t n = h->rec.n0 + k;
@@ -860,9 +869,13 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       // geometry, inflow and wall model of step n (with Jacobians)
       h->L.ghost = h->ghost[n & 1];
       h->L.ghost64 = h->ghost64[n & 1];
-      e = launch_prologue(h->L, n);
-      if (e == hipSuccess) e = launch_rasterize(h->L, n, blade_trig(h, n), scr_act);
-      if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, jac, 0);
+      const BladeTrig* trig = nullptr;
+      e = trig_of(h, n, &trig);
+      const bool inlet = probe_reaches_inlet(h);
+      if (e == hipSuccess && inlet) e = launch_prologue(h->L, n);
+      const int epoch = h->wc_epoch++;
+      if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act, !inlet);
+      if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, epoch, jac, 0);
       if (e == hipSuccess) e = hipMemsetAsync(utb[1 - cur], 0, B * 8, h->stream);
       AdjLaunch A{};
       A.src = s0;
@@ -877,6 +890,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       A.obj_w = (k >= h->rec.t0 && k < h->rec.t1) ? w : 0.0;
       A.obj_tag = h->rec.obj_tag;
       A.lstride = pop_stride_c(&h->desc);
+      A.epoch = epoch;
       if (e == hipSuccess && wall) e = launch_adjoint_wall(h->L, A);
       if (e == hipSuccess) e = launch_adjoint_sweep(h->L, A);
       if (e != hipSuccess) return hip_fail(h, e, "adjoint step");
@@ -896,12 +910,16 @@ int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat) {
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   h->L.ghost = h->ghost[h->step & 1];
   h->L.ghost64 = h->ghost64[h->step & 1];
-  hipError_t e = launch_prologue(h->L, h->step);
-  if (e == hipSuccess) e = launch_rasterize(h->L, h->step, blade_trig(h, h->step), h->act[1 - h->wcur]);
+  const BladeTrig* trig = nullptr;
+  hipError_t e = trig_of(h, h->step, &trig);
+  const bool inlet = probe_reaches_inlet(h);
+  if (e == hipSuccess && inlet) e = launch_prologue(h->L, h->step);
   // the wall model writes the next state slot, which is not committed here
+  const int epoch = h->wc_epoch++;
+  if (e == hipSuccess) e = launch_geometry(h->L, h->step, trig, epoch, h->act[1 - h->wcur], !inlet);
   if (e == hipSuccess && wall)
     e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur], h->act[1 - h->wcur],
-                    h->step, nullptr, 0);
+                    h->step, epoch, nullptr, 0);
   if (e == hipSuccess) e = launch_moments(h->L, h->pop[h->cur], h->step, rho, u, uhat);
   if (e != hipSuccess) return hip_fail(h, e, "moments");
   return HLBM_OK;
@@ -1046,21 +1064,20 @@ int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* 
 
 int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells) {
   if (!h) return HLBM_ERR_INVALID;
-  std::vector<int32_t> list(h->L.nblocks);
-  hipError_t e = hipMemcpyAsync(list.data(), h->L.blist, sizeof(int32_t) * list.size(), hipMemcpyDeviceToHost,
+  std::vector<int32_t> slot(h->L.nblocks);
+  hipError_t e = hipMemcpyAsync(slot.data(), h->L.blk_slot, sizeof(int32_t) * slot.size(), hipMemcpyDeviceToHost,
                                 h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "partition");
   const Geometry& g = h->L.g;
   int64_t cnt[2] = {0, 0};
-  for (int64_t k = 0; k < h->L.nblocks; ++k) {
-    const int64_t b = list[k];
+  for (int64_t b = 0; b < h->L.nblocks; ++b) {
     const int64_t tpz = int64_t(g.ntx) * g.nty;
     const int64_t rem = b % tpz;
     const int ty = int(rem / g.ntx), tx = int(rem % g.ntx);
     const int64_t cx = std::min<int64_t>(kTileX, g.nx - int64_t(tx) * kTileX);
     const int64_t cy = std::min<int64_t>(kTileY, g.ny - int64_t(ty) * kTileY);
-    cnt[k < h->L.nfsi ? 0 : 1] += cx * cy;
+    cnt[slot[b] >= 0 ? 0 : 1] += cx * cy;
   }
   if (fsi_cells) *fsi_cells = cnt[0];
   if (bulk_cells) *bulk_cells = cnt[1];

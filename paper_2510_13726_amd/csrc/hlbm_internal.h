@@ -16,6 +16,7 @@ constexpr int kHist = 91;            // mass + 15 x (F, T)
 constexpr int kPartial = 96;         // per FSI block: [16 tags][F3, T3]
 constexpr int kMassL1 = 256;         // first-level mass reduction width
 constexpr int kPartL1 = 64;          // first-level force reduction width
+constexpr int kMaxBatch = 8;         // steps whose reductions are launched together
 constexpr int kWallOut = 10;         // u_wm[3], S[6], sigma per wall slot
 
 // Tag byte of a cell: bits 0-3 tag, bit 6 = covered by a rotor, bit 7 = wall cell.
@@ -64,5 +65,10 @@ struct BladeTrig {
   double c[kMaxRotors][kMaxBlades];
   double s[kMaxRotors][kMaxBlades];
 };
+// Accelerator complex dies of MI355X: consecutive workgroups of a launch are
+// dispatched round-robin over them.
+constexpr int kXcds = 8;
+// Steps of blade angles held on the device at once (uploaded in chunks).
+constexpr int kTrigSteps = 2048;
 
 }  // namespace hlbm

@@ -20,16 +20,6 @@ namespace hlbm {
 // ================================================================ helpers
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// XCD-aware workgroup order: the hardware deals consecutive workgroup ids
-// round-robin to the 8 XCDs; give each XCD a contiguous run of the domain so
-// that the cache lines shared by neighbouring workgroups stay in one L2.
-__device__ __forceinline__ uint32_t remap_block(uint32_t bid, uint32_t nb, int32_t on) {
-  if (!on) return bid;
-  const uint32_t q = nb >> 3;
-  if (bid >= (q << 3)) return bid;
-  return (bid & 7) * q + (bid >> 3);
-}
-
 // Pre-collision deviations h_i = f_i - w_i of cell (x, y, z):
 // f_i(x) = f*_i(x - c_i) with periodic y, z; in x periodic, or the
 // equilibrium inflow ghost plane at x = -1 (precomputed for the step in
@@ -117,13 +107,11 @@ __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geome
 
 // Inflow ghost plane of step n: h_i = f^eq_i(1, u_in(n, y, z)) - w_i for the
 // nine velocities with c_x = +1, u_in = U + I |U| xi with seeded normals xi.
+// Cell k = z ny + y of the plane; ghost64 (nullable) gets the FP64 values.
 template <class CT>
-__global__ __launch_bounds__(256) void k_prologue(Geometry g, Model m, int64_t n, CT* __restrict__ ghost,
-                                                  double* __restrict__ ghost64, int32_t* __restrict__ wcount) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k == 0) *wcount = 0;
+__device__ __forceinline__ void inflow_plane_cell(const Geometry& g, const Model& m, int64_t n, int64_t k,
+                                                  CT* __restrict__ ghost, double* __restrict__ ghost64) {
   const int64_t plane = int64_t(g.ny) * g.nz;
-  if (g.bc_x == 0 || k >= plane) return;
   const int z = int(k / g.ny), y = int(k - int64_t(z) * g.ny);
   double u[3] = {m.u_in[0], m.u_in[1], m.u_in[2]};
   if (m.turb_amp != 0.0)
@@ -140,6 +128,14 @@ __global__ __launch_bounds__(256) void k_prologue(Geometry g, Model m, int64_t n
   }
 }
 
+template <class CT>
+__global__ __launch_bounds__(256) void k_prologue(Geometry g, Model m, int64_t n, CT* __restrict__ ghost,
+                                                  double* __restrict__ ghost64) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g.bc_x == 0 || k >= int64_t(g.ny) * g.nz) return;
+  inflow_plane_cell<CT>(g, m, n, k, ghost, ghost64);
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -148,74 +144,120 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ================================================================ geometry
-struct RotorPhi {
-  double phi;
-  double grad[3];
-};
-
 // Signed distance (positive inside) of a rotor at step n: hub sphere united
 // with flat-plate blades (box in blade coordinates r, chord s, thickness h;
-// pitch beta(r) linear from root to tip), and its gradient.
-__device__ RotorPhi rotor_phi(const RotorDev& r, const double* ctab, const double* stab, double x, double y,
-                              double z, double cut) {
+// pitch beta(r) linear from root to tip).  The value pass returns the
+// distance and the piece attaining it (-1 hub, b blade b); the gradient pass
+// differentiates that piece (the same arithmetic as the value pass).
+struct RotorPhi {
+  double phi;
+  int piece;
+};
+
+// Blade b in its own frame: radial r, tangential q, axial a of the point;
+// box coordinates p and the pitch derivative dbeta.
+struct BladeFrame {
+  double er[3], ep[3], rr, qq, ax, p[3], sb, cb, dbeta;
+};
+__device__ __forceinline__ void blade_frame(const RotorDev& r, double ct, double st, const double rel[3], double ax,
+                                            BladeFrame& f) {
+  for (int a = 0; a < 3; ++a) {
+    f.er[a] = ct * r.e1[a] + st * r.e2[a];
+    f.ep[a] = -st * r.e1[a] + ct * r.e2[a];
+  }
+  f.rr = rel[0] * f.er[0] + rel[1] * f.er[1] + rel[2] * f.er[2];
+  f.qq = rel[0] * f.ep[0] + rel[1] * f.ep[1] + rel[2] * f.ep[2];
+  f.ax = ax;
+}
+__device__ __forceinline__ void blade_box(const RotorDev& r, BladeFrame& f) {
+  const double span = r.R - r.r_hub;
+  double frac = (f.rr - r.r_hub) / span;
+  f.dbeta = 0.0;
+  if (frac <= 0.0) frac = 0.0;
+  else if (frac >= 1.0) frac = 1.0;
+  else f.dbeta = (r.tw_tip - r.tw_root) / span;
+  const double beta = r.tw_root + (r.tw_tip - r.tw_root) * frac;
+  sincos(beta, &f.sb, &f.cb);
+  f.p[0] = f.rr - 0.5 * (r.R + r.r_hub);
+  f.p[1] = -f.cb * f.qq + f.sb * f.ax;
+  f.p[2] = f.cb * f.ax + f.sb * f.qq;
+}
+
+__device__ __forceinline__ RotorPhi rotor_phi(const RotorDev& r, const double* ctab, const double* stab, double x,
+                                              double y, double z, double cut) {
   RotorPhi o;
   const double rel[3] = {x - r.c[0], y - r.c[1], z - r.c[2]};
   const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
   o.phi = r.r_hub - dist;
-  for (int a = 0; a < 3; ++a) o.grad[a] = dist > 0 ? -rel[a] / dist : 0.0;
+  o.piece = -1;
   const double ax = rel[0] * r.e[0] + rel[1] * r.e[1] + rel[2] * r.e[2];
   const double span = r.R - r.r_hub;
+  const double half[3] = {0.5 * span, 0.5 * r.chord, 0.5 * r.thick};
+  // the blade lies within r_hub <= r <= R and q^2 + a^2 <= (c/2)^2 + (t/2)^2:
+  // a point farther than `cut` from that slab cannot reach phi > -cut
+  const double hc = 0.5 * sqrt(r.chord * r.chord + r.thick * r.thick) + cut;
   for (int b = 0; b < r.nb; ++b) {
-    const double ct = ctab[b], st = stab[b];
-    double er[3], ep[3];
-    for (int a = 0; a < 3; ++a) {
-      er[a] = ct * r.e1[a] + st * r.e2[a];
-      ep[a] = -st * r.e1[a] + ct * r.e2[a];
-    }
-    const double rr = rel[0] * er[0] + rel[1] * er[1] + rel[2] * er[2];
-    const double qq = rel[0] * ep[0] + rel[1] * ep[1] + rel[2] * ep[2];
-    // the blade lies within r_hub <= r <= R and q^2 + a^2 <= (c/2)^2 + (t/2)^2:
-    // a point farther than `cut` from that slab cannot reach phi > -cut
-    const double hc = 0.5 * sqrt(r.chord * r.chord + r.thick * r.thick) + cut;
-    if (rr < r.r_hub - cut || rr > r.R + cut || qq * qq + ax * ax > hc * hc) continue;
-    double frac = (rr - r.r_hub) / span, dbeta = 0.0;
-    if (frac <= 0.0) frac = 0.0;
-    else if (frac >= 1.0) frac = 1.0;
-    else dbeta = (r.tw_tip - r.tw_root) / span;
-    const double beta = r.tw_root + (r.tw_tip - r.tw_root) * frac;
-    double sb, cb;
-    sincos(beta, &sb, &cb);
-    const double p[3] = {rr - 0.5 * (r.R + r.r_hub), -cb * qq + sb * ax, cb * ax + sb * qq};
-    const double half[3] = {0.5 * span, 0.5 * r.chord, 0.5 * r.thick};
-    double q[3], qp[3], qn2 = 0.0;
+    BladeFrame f;
+    blade_frame(r, ctab[b], stab[b], rel, ax, f);
+    if (f.rr < r.r_hub - cut || f.rr > r.R + cut || f.qq * f.qq + ax * ax > hc * hc) continue;
+    blade_box(r, f);
+    double q[3], qn2 = 0.0;
     for (int k = 0; k < 3; ++k) {
-      q[k] = fabs(p[k]) - half[k];
-      qp[k] = q[k] > 0 ? q[k] : 0.0;
-      qn2 += qp[k] * qp[k];
+      q[k] = fabs(f.p[k]) - half[k];
+      const double qp = q[k] > 0 ? q[k] : 0.0;
+      qn2 += qp * qp;
     }
-    int km = 0;
-    if (q[1] > q[km]) km = 1;
-    if (q[2] > q[km]) km = 2;
-    const double phi = -(sqrt(qn2) + (q[km] < 0 ? q[km] : 0.0));
+    // largest component (first on ties), selected without indexing
+    double qm = q[0];
+    if (q[1] > qm) qm = q[1];
+    if (q[2] > qm) qm = q[2];
+    const double phi = -(sqrt(qn2) + (qm < 0 ? qm : 0.0));
     if (phi > o.phi) {
       o.phi = phi;
-      double gp[3] = {0.0, 0.0, 0.0};
-      if (qn2 > 0) {
-        const double qn = sqrt(qn2);
-        for (int k = 0; k < 3; ++k) gp[k] = (p[k] >= 0 ? 1.0 : -1.0) * qp[k] / qn;
-      } else {
-        gp[km] = p[km] >= 0 ? 1.0 : -1.0;
-      }
-      const double gs = dbeta * (sb * qq + cb * ax);
-      const double gh = dbeta * (-sb * ax + cb * qq);
-      for (int a = 0; a < 3; ++a) {
-        const double ds = -cb * ep[a] + sb * r.e[a] + gs * er[a];
-        const double dh = cb * r.e[a] + sb * ep[a] + gh * er[a];
-        o.grad[a] = -(gp[0] * er[a] + gp[1] * ds + gp[2] * dh);
-      }
+      o.piece = b;
     }
   }
   return o;
+}
+
+// Gradient of the rotor distance at (x, y, z) for the piece found by rotor_phi.
+__device__ __forceinline__ void rotor_grad(const RotorDev& r, const double* ctab, const double* stab, double x,
+                                           double y, double z, int piece, double grad[3]) {
+  const double rel[3] = {x - r.c[0], y - r.c[1], z - r.c[2]};
+  const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
+  if (piece < 0) {
+    for (int a = 0; a < 3; ++a) grad[a] = dist > 0 ? -rel[a] / dist : 0.0;
+    return;
+  }
+  const double ax = rel[0] * r.e[0] + rel[1] * r.e[1] + rel[2] * r.e[2];
+  const double span = r.R - r.r_hub;
+  const double half[3] = {0.5 * span, 0.5 * r.chord, 0.5 * r.thick};
+  BladeFrame f;
+  blade_frame(r, ctab[piece], stab[piece], rel, ax, f);
+  blade_box(r, f);
+  double q[3], qp[3], qn2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    q[k] = fabs(f.p[k]) - half[k];
+    qp[k] = q[k] > 0 ? q[k] : 0.0;
+    qn2 += qp[k] * qp[k];
+  }
+  int km = 0;
+  if (q[1] > q[0]) km = 1;
+  if (q[2] > (km == 1 ? q[1] : q[0])) km = 2;
+  double gp[3] = {0.0, 0.0, 0.0};
+  if (qn2 > 0) {
+    const double qn = sqrt(qn2);
+    for (int k = 0; k < 3; ++k) gp[k] = (f.p[k] >= 0 ? 1.0 : -1.0) * qp[k] / qn;
+  } else {
+    for (int k = 0; k < 3; ++k) gp[k] = k == km ? (f.p[k] >= 0 ? 1.0 : -1.0) : 0.0;
+  }
+  const double gs = f.dbeta * (f.sb * f.qq + f.cb * ax);
+  const double gh = f.dbeta * (-f.sb * ax + f.cb * f.qq);
+  for (int a = 0; a < 3; ++a) {
+    const double ds = -f.cb * f.ep[a] + f.sb * r.e[a] + gs * f.er[a];
+    const double dh = f.cb * r.e[a] + f.sb * f.ep[a] + gh * f.er[a];
+    grad[a] = -(gp[0] * f.er[a] + gp[1] * ds + gp[2] * dh);
+  }
 }
 
 // Lattice porosity of a signed distance (Def. Lattice Porosity).
@@ -246,69 +288,6 @@ __device__ __forceinline__ void slot_cell(const RotorDev& r, int64_t s, int& x, 
 __device__ __forceinline__ bool in_box(const RotorDev& r, int x, int y, int z) {
   return x >= r.b0[0] && x < r.b0[0] + r.bn[0] && y >= r.b0[1] && y < r.b0[1] + r.bn[1] && z >= r.b0[2] &&
          z < r.b0[2] + r.bn[2];
-}
-
-// ---------------------------------------------------------------- rasterize
-template <class CT>
-__global__ __launch_bounds__(256) void k_rasterize(const RotorTable* __restrict__ rtp, Geometry g, Model m,
-                                                   BladeTrig trig, int64_t total, const CT* __restrict__ d_static,
-                                                   const uint8_t* __restrict__ tag_static, const CT* __restrict__ dd,
-                                                   CT* __restrict__ d_eff, uint8_t* __restrict__ tag,
-                                                   double* __restrict__ geo, uint8_t* __restrict__ act_new,
-                                                   int32_t* __restrict__ wlist, int32_t* __restrict__ wcount) {
-  __shared__ int wl_count, wl_base;
-  if (threadIdx.x == 0) wl_count = 0;
-  __syncthreads();
-  const int64_t s0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const bool live = s0 < total;
-  const int64_t s = live ? s0 : total - 1;
-  const RotorTable& rt = *rtp;
-  const int k = rotor_of_slot(rt, s);
-  int x, y, z;
-  slot_cell(rt.r[k], s, x, y, z);
-  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
-  double best = -1e300, gr[3] = {0, 0, 0};
-  int br = -1;
-  for (int j = 0; j < rt.n; ++j) {
-    if (!in_box(rt.r[j], x, y, z)) continue;
-    RotorPhi p = rotor_phi(rt.r[j], trig.c[j], trig.s[j], double(x), double(y), double(z), 0.5 * m.eps_h + 1.0);
-    if (p.phi > best) {
-      best = p.phi;
-      br = j;
-      gr[0] = p.grad[0]; gr[1] = p.grad[1]; gr[2] = p.grad[2];
-    }
-  }
-  const double drot = br >= 0 ? transition(best, m.eps_h, m.transition) : 0.0;
-  const double ds = double(d_static[c]);
-  const double base = ds > drot ? ds : drot;
-  if (live) d_eff[c] = CT(base) + (dd ? dd[c] : CT(0));
-  const double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
-  uint8_t tb;
-  if (drot > 0.0) {
-    tb = uint8_t(rt.r[br].tag) | kRotorBit;
-    if (m.wall_model && best > -0.5 * m.eps_h && best < 0.0 && gn > 0) tb |= kWallBit;
-  } else {
-    tb = tag_static[c];
-  }
-  if (live) {
-    tag[c] = tb;
-    act_new[s] = 0;
-  }
-  // wall cells of this box's own rotor go to the wall model's work list:
-  // ranks from an LDS counter, one global atomic per workgroup
-  const bool mine = live && (tb & kWallBit) && br == k;
-  int rank = 0;
-  if (mine) rank = atomicAdd(&wl_count, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) wl_base = wl_count ? atomicAdd(wcount, wl_count) : 0;
-  __syncthreads();
-  if (mine) wlist[wl_base + rank] = int32_t(s);
-  if (!live) return;
-  geo[s] = best;
-  const double inv = gn > 0 ? 1.0 / gn : 0.0;
-  geo[total + s] = -gr[0] * inv;
-  geo[2 * total + s] = -gr[1] * inv;
-  geo[3 * total + s] = -gr[2] * inv;
 }
 
 // ---------------------------------------------------------------- wall model
@@ -505,7 +484,7 @@ __device__ __forceinline__ void group8_sum(double us[3]) {
 // cell: lane j pulls the populations of probe corner j and forms its
 // velocity; the trilinear sum is reduced over the eight lanes; lane 0 runs
 // the two Newton solves and writes u_wm, S_wm, sigma and the u_tau state.
-template <class ST, class CT, bool kPeriodicX>
+template <class ST, class CT, bool kPeriodicX, bool kJac>
 __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp, Geometry g, Model m, int64_t total,
                                               const ST* __restrict__ src, const double* __restrict__ geo,
                                               const int32_t* __restrict__ wlist, const int32_t* __restrict__ wcount,
@@ -538,7 +517,7 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
       const int64_t T = total;
       bool active;
       double out[10];
-      if (jac) {
+      if constexpr (kJac) {
         // values and the 10 x 4 Jacobian with respect to (us, u_tau^prev)
         D4 ud[3], o4[10];
         for (int a = 0; a < 3; ++a) { ud[a] = mk(us[a]); ud[a].g[a] = 1.0; }
@@ -580,6 +559,102 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
   }
 }
 
+// ---------------------------------------------------------------- geometry
+// One launch per step over the rotor boxes' slots (one lane per slot): the
+// rotor geometry of the step (porosity, tag, wall flag, normal and wall
+// distance) and the wall-model work list; extra workgroups write the step's
+// inflow plane.
+template <class CT>
+struct GeoArgs {
+  const RotorTable* rot;
+  Geometry g;
+  Model m;
+  const BladeTrig* trig;     // blade angles of the step
+  int64_t total;             // box slots
+  const CT* d_static;
+  const uint8_t* tag_static;
+  const CT* dd;              // nullable
+  CT* d_eff;
+  uint8_t* tag;
+  double* geo;               // [4][total]: phi, n
+  uint8_t* act_new;          // wall-state slots, reset to inactive
+  int32_t* wlist;
+  int32_t* wcount;           // this launch's counter (zero on entry)
+  int32_t* wcount_next;      // the next launch's counter, zeroed here
+  int64_t step;              // inflow plane of the step (extra workgroups)
+  CT* ghost;
+  double* ghost64;
+};
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
+  const Geometry& g = a.g;
+  const Model& m = a.m;
+  const uint32_t nbw = uint32_t((a.total + 255) / 256);
+  if (blockIdx.x >= nbw) {
+    const int64_t k = int64_t(blockIdx.x - nbw) * 256 + threadIdx.x;
+    if (k < int64_t(g.ny) * g.nz) inflow_plane_cell<CT>(g, m, a.step, k, a.ghost, a.ghost64);
+    return;
+  }
+  __shared__ int wl_count, wl_base;
+  if (threadIdx.x == 0) {
+    wl_count = 0;
+    if (blockIdx.x == 0) *a.wcount_next = 0;
+  }
+  __syncthreads();
+  const int64_t s0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool live = s0 < a.total;
+  const int64_t s = live ? s0 : a.total - 1;
+  const RotorTable& rt = *a.rot;
+  const int k = rotor_of_slot(rt, s);
+  int x, y, z;
+  slot_cell(rt.r[k], s, x, y, z);
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+  double best = -1e300, gr[3] = {0, 0, 0};
+  int br = -1, piece = -1;
+  for (int j = 0; j < rt.n; ++j) {
+    if (!in_box(rt.r[j], x, y, z)) continue;
+    RotorPhi p = rotor_phi(rt.r[j], a.trig->c[j], a.trig->s[j], double(x), double(y), double(z), 0.5 * m.eps_h + 1.0);
+    if (p.phi > best) {
+      best = p.phi;
+      br = j;
+      piece = p.piece;
+    }
+  }
+  if (br >= 0) rotor_grad(rt.r[br], a.trig->c[br], a.trig->s[br], double(x), double(y), double(z), piece, gr);
+  const double drot = br >= 0 ? transition(best, m.eps_h, m.transition) : 0.0;
+  const double ds = double(a.d_static[c]);
+  const double base = ds > drot ? ds : drot;
+  if (live) a.d_eff[c] = CT(base) + (a.dd ? a.dd[c] : CT(0));
+  const double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+  uint8_t tb;
+  if (drot > 0.0) {
+    tb = uint8_t(rt.r[br].tag) | kRotorBit;
+    if (m.wall_model && best > -0.5 * m.eps_h && best < 0.0 && gn > 0) tb |= kWallBit;
+  } else {
+    tb = a.tag_static[c];
+  }
+  if (live) {
+    a.tag[c] = tb;
+    a.act_new[s] = 0;
+  }
+  // wall cells of this box's own rotor go to the work list: ranks from an
+  // LDS counter, one global atomic per workgroup
+  const bool mine = live && (tb & kWallBit) && br == k;
+  int rank = 0;
+  if (mine) rank = atomicAdd(&wl_count, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) wl_base = wl_count ? atomicAdd(a.wcount, wl_count) : 0;
+  __syncthreads();
+  if (mine) a.wlist[wl_base + rank] = int32_t(s);
+  if (!live) return;
+  const double inv = gn > 0 ? 1.0 / gn : 0.0;
+  a.geo[s] = best;
+  a.geo[a.total + s] = -gr[0] * inv;
+  a.geo[2 * a.total + s] = -gr[1] * inv;
+  a.geo[3 * a.total + s] = -gr[2] * inv;
+}
+
 // ================================================================ fused sweep
 template <class CT>
 struct SweepArgs {
@@ -602,7 +677,6 @@ struct SweepArgs {
   int64_t nblocks;
   const int32_t* blist;      // optional list of the workgroups to run (FSI or bulk part)
   int64_t nlist;
-  int32_t remap;
   CT* out_rho;
   CT* out_u;
   CT* out_uhat;
@@ -631,6 +705,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   const int x = valid ? xr : 0, y = row_ok ? yr : 0;
   const int64_t row = (int64_t(z) * g.ny + y) * g.nx;
   const int64_t c = row + x;
+  const int32_t slot = a.blk_slot[blk];
 
   CT h[27];
   pull_row<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
@@ -640,7 +715,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   const CT ux = mo.jx * irho, uy = mo.jy * irho, uz = mo.jz * irho;
   const CT tau0 = CT(a.m.tau0), smag = CT(a.m.smag);
 
-  const int32_t slot = a.blk_slot[blk];
   CT g2[27];
   if (slot < 0) {
     if (kMoments) {
@@ -764,32 +838,36 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   __shared__ double lds[4][kPartial];
-  const uint32_t nwork = uint32_t(a.blist ? a.nlist : a.nblocks);
-  const uint32_t it = blockIdx.x;
-  const uint32_t blk = a.blist ? uint32_t(a.blist[remap_block(it, nwork, a.remap)]) : remap_block(it, nwork, a.remap);
+  const uint32_t blk = a.blist ? uint32_t(a.blist[blockIdx.x]) : uint32_t(blockIdx.x);
   sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
 }
 
-// Force / torque / mass reduction of one step, level 1: workgroup b sums FSI
-// partials b, b + G, ... and the mass partials of its chunk in a fixed order.
+// Force / torque / mass reduction, level 1: workgroup (b, j) sums the force
+// partials b, b + G, ... of step slice j and the mass partials of its chunk,
+// in a fixed order.
 __global__ __launch_bounds__(256) void k_reduce_l1(const double* __restrict__ partial, int32_t nslots,
-                                                   const double* __restrict__ mass_part, int64_t nmass, int diag,
-                                                   double* __restrict__ l1, double* __restrict__ ml1) {
+                                                   const double* __restrict__ mass_part, int64_t nmass, int64_t n0,
+                                                   int32_t diag_every, double* __restrict__ l1,
+                                                   double* __restrict__ ml1) {
   __shared__ double s[2][kPartial];
   __shared__ double sm[256];
-  const int G = gridDim.x, b = blockIdx.x;
+  const int G = gridDim.x, b = blockIdx.x, j = blockIdx.y;
+  const int64_t n = n0 + j;
+  const bool diag = diag_every > 0 && n % diag_every == 0;
+  const double* P = partial + int64_t(j) * (nslots > 0 ? nslots : 1) * kPartial;
+  const double* M = mass_part + int64_t(j) * nmass;
   const int k = threadIdx.x % kPartial, r = threadIdx.x / kPartial;  // r in {0, 1, 2}; row 2 idle
   if (r < 2) {
     double acc = 0.0;
 #pragma unroll 4
-    for (int32_t sl = b + r * G; sl < nslots; sl += 2 * G) acc += partial[int64_t(sl) * kPartial + k];
+    for (int32_t sl = b + r * G; sl < nslots; sl += 2 * G) acc += P[int64_t(sl) * kPartial + k];
     s[r][k] = acc;
   }
   double macc = 0.0;
   if (diag) {
     const int64_t per = (nmass + G - 1) / G;
     const int64_t lo = int64_t(b) * per, hi = lo + per < nmass ? lo + per : nmass;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) macc += mass_part[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) macc += M[i];
   }
   sm[threadIdx.x] = macc;
   __syncthreads();
@@ -797,19 +875,28 @@ __global__ __launch_bounds__(256) void k_reduce_l1(const double* __restrict__ pa
     if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < kPartial) l1[int64_t(b) * kPartial + threadIdx.x] = s[0][threadIdx.x] + s[1][threadIdx.x];
-  if (threadIdx.x == 0) ml1[b] = sm[0];
+  double* L1 = l1 + (int64_t(j) * G + b) * kPartial;
+  if (threadIdx.x < kPartial) L1[threadIdx.x] = s[0][threadIdx.x] + s[1][threadIdx.x];
+  if (threadIdx.x == 0) ml1[int64_t(j) * G + b] = sm[0];
 }
 
-// Level 2: one workgroup adds the G level-1 results in order into the record.
+// Level 2: workgroup j adds the G level-1 results of slice j in order into
+// the record of step n0 + j.
 __global__ __launch_bounds__(256) void k_reduce_l2(const double* __restrict__ l1, const double* __restrict__ ml1,
-                                                   int G, int diag, double* __restrict__ rec) {
+                                                   int G, int64_t n0, int32_t diag_every, double* __restrict__ hist,
+                                                   int64_t hist_cap) {
   __shared__ double s[2][kPartial];
+  const int j = blockIdx.x;
+  const int64_t n = n0 + j;
+  const bool diag = diag_every > 0 && n % diag_every == 0;
+  const double* L1 = l1 + int64_t(j) * G * kPartial;
+  const double* M1 = ml1 + int64_t(j) * G;
+  double* rec = hist + (n % hist_cap) * kHist;
   const int k = threadIdx.x % kPartial, r = threadIdx.x / kPartial;
   if (r < 2) {
     double acc = 0.0;
 #pragma unroll 4
-    for (int j = r; j < G; j += 2) acc += l1[int64_t(j) * kPartial + k];
+    for (int q = r; q < G; q += 2) acc += L1[int64_t(q) * kPartial + k];
     s[r][k] = acc;
   }
   __syncthreads();
@@ -817,7 +904,7 @@ __global__ __launch_bounds__(256) void k_reduce_l2(const double* __restrict__ l1
   if (threadIdx.x == 255) {
     if (diag) {
       double acc = 0.0;
-      for (int j = 0; j < G; ++j) acc += ml1[j];
+      for (int q = 0; q < G; ++q) acc += M1[q];
       rec[0] = acc;
     } else {
       rec[0] = __builtin_nan("");
@@ -1185,21 +1272,31 @@ static hipError_t by_compute(int compute, F&& f) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig, uint8_t* act_new) {
-  (void)step;
-  if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
+hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
+                           bool with_ghost) {
+  const int64_t nbw = L.nrot > 0 ? (L.bbox_total + 255) / 256 : 0;
+  const int64_t plane = int64_t(L.g.ny) * L.g.nz;
+  const int64_t nghost = (with_ghost && L.g.bc_x != 0) ? (plane + 255) / 256 : 0;
+  if (nbw + nghost == 0) return hipSuccess;
   return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
-    hipLaunchKernelGGL(k_rasterize<CT>, grid1(L.bbox_total, 256), dim3(256), 0, L.stream, L.rot, L.g, L.m, trig,
-                       L.bbox_total, (const CT*)L.d_static, L.tag_static, (const CT*)L.dd, (CT*)L.d_eff, L.tag,
-                       L.geo, act_new, L.wlist, L.wcount);
+    GeoArgs<CT> a{};
+    a.rot = L.rot; a.g = L.g; a.m = L.m; a.trig = trig; a.total = nbw > 0 ? L.bbox_total : 0;
+    a.d_static = (const CT*)L.d_static; a.tag_static = L.tag_static; a.dd = (const CT*)L.dd;
+    a.d_eff = (CT*)L.d_eff; a.tag = L.tag; a.geo = L.geo; a.act_new = act_new; a.wlist = L.wlist;
+    a.wcount = L.wcount + (epoch & 1); a.wcount_next = L.wcount + ((epoch + 1) & 1);
+    a.step = step; a.ghost = (CT*)L.ghost;
+    // the wall model samples in FP64: also fill the FP64 plane when it differs
+    a.ghost64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
+    hipLaunchKernelGGL(k_geometry<CT>, dim3(unsigned(nbw + nghost)), dim3(256), 0, L.stream, a);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step, double* jac, int count_stats) {
+                       double* ut_new, uint8_t* act_new, int64_t step, int epoch, double* jac, int count_stats) {
   (void)step;
+  const int32_t* wcount = L.wcount + (epoch & 1);
   if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
   // persistent grid over the (device-side) wall-cell count, 32 cells per workgroup
   int64_t blocks = (L.bbox_total + 31) / 32;
@@ -1207,14 +1304,18 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
-    if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
-                         L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
-                         (CT*)L.wall_out, L.stats, L.ghost64, jac, count_stats);
-    else
-      hipLaunchKernelGGL((k_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m,
-                         L.bbox_total, (const ST*)src, L.geo, L.wlist, L.wcount, ut_prev, act_prev, ut_new, act_new,
-                         (CT*)L.wall_out, L.stats, L.ghost64, jac, count_stats);
+    auto go = [&](auto kernel) {
+      hipLaunchKernelGGL(kernel, dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m, L.bbox_total,
+                         (const ST*)src, L.geo, L.wlist, wcount, ut_prev, act_prev, ut_new, act_new, (CT*)L.wall_out,
+                         L.stats, L.ghost64, jac, count_stats);
+    };
+    if (L.g.bc_x == 0) {
+      if (jac) go(k_wall<ST, CT, true, true>);
+      else go(k_wall<ST, CT, true, false>);
+    } else {
+      if (jac) go(k_wall<ST, CT, false, true>);
+      else go(k_wall<ST, CT, false, false>);
+    }
     return hipGetLastError();
   });
 }
@@ -1226,28 +1327,25 @@ static SweepArgs<CT> sweep_args(const Launch& L, const void* src, void* dst, int
   a.blk_slot = L.blk_slot; a.d_eff = (const CT*)L.d_eff; a.tag = L.tag;
   a.wall_out = (const CT*)L.wall_out; a.bbox_total = L.bbox_total; a.rot = L.rot;
   a.uB_static = (const CT*)L.uB_static; a.partial = L.partial; a.mass_part = nullptr; a.flag = L.flag;
-  a.step = step; a.nblocks = L.nblocks; a.remap = L.xcd_remap;
+  a.step = step; a.nblocks = L.nblocks;
   a.ghost = (const CT*)L.ghost;
   return a;
 }
 
-hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag, int part) {
-  // part 0: all workgroups; 1: FSI workgroups; 2: bulk workgroups
-  const int64_t n = part == 0 ? L.nblocks : part == 1 ? L.nfsi : L.nbulk;
-  if (n == 0) return hipSuccess;
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag) {
+  if (L.nblocks == 0) return hipSuccess;
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
     SweepArgs<CT> a = sweep_args<CT>(L, src, dst, step);
     if (diag) a.mass_part = L.mass_part;
-    a.blist = part == 0 ? nullptr : part == 1 ? L.blist : L.blist + L.nfsi;
-    a.nlist = n;
-    hipStream_t s = part == 2 ? L.stream2 : L.stream;
-    const int64_t grid = n;
+    // the host's XCD-balanced order (FSI tiles first on every XCD)
+    a.blist = L.blist;
+    a.nlist = L.nblocks;
     if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(grid)), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
     else
-      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(grid)), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
     return hipGetLastError();
   });
 }
@@ -1257,7 +1355,6 @@ hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* 
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
     SweepArgs<CT> a = sweep_args<CT>(L, src, nullptr, step);
-    a.remap = 0;
     a.out_rho = (CT*)rho; a.out_u = (CT*)u; a.out_uhat = (CT*)uhat;
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_sweep<ST, CT, true, true>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
@@ -1269,26 +1366,24 @@ hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* 
 
 hipError_t launch_prologue(const Launch& L, int64_t step) {
   const int64_t plane = int64_t(L.g.ny) * L.g.nz;
-  if (L.g.bc_x == 0 && L.nrot == 0) return hipSuccess;
-  const int64_t threads = L.g.bc_x == 0 ? 1 : plane;
+  if (L.g.bc_x == 0) return hipSuccess;
   // the wall model samples in FP64: also fill the FP64 plane when it differs
   double* g64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
   return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
-    hipLaunchKernelGGL(k_prologue<CT>, grid1(threads, 256), dim3(256), 0, L.stream, L.g, L.m, step, (CT*)L.ghost,
-                       g64, L.wcount);
+    hipLaunchKernelGGL(k_prologue<CT>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, L.m, step, (CT*)L.ghost, g64);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag) {
+hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t nslots, int32_t diag_every) {
   const int G = kPartL1;
-  double* rec = L.hist + (step % L.hist_cap) * kHist;
-  hipLaunchKernelGGL(k_reduce_l1, dim3(G), dim3(256), 0, L.stream, L.partial, nslots, L.mass_part, L.nblocks,
-                     diag ? 1 : 0, L.part_l1, L.mass_l1);
+  hipLaunchKernelGGL(k_reduce_l1, dim3(G, unsigned(count)), dim3(256), 0, L.stream, L.partial, nslots, L.mass_part,
+                     L.nblocks, n0, diag_every, L.part_l1, L.mass_l1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_l2, dim3(1), dim3(256), 0, L.stream, L.part_l1, L.mass_l1, G, diag ? 1 : 0, rec);
+  hipLaunchKernelGGL(k_reduce_l2, dim3(unsigned(count)), dim3(256), 0, L.stream, L.part_l1, L.mass_l1, G, n0,
+                     diag_every, L.hist, L.hist_cap);
   return hipGetLastError();
 }
 
@@ -1314,10 +1409,10 @@ hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A) {
     AdjArgs<CT> a = adj_args<CT>(L, A);
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_adj_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo, L.wlist,
-                         L.wcount, A.jac, A.ut_bar_in, A.ut_bar_out);
+                         L.wcount + (A.epoch & 1), A.jac, A.ut_bar_in, A.ut_bar_out);
     else
       hipLaunchKernelGGL((k_adj_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo,
-                         L.wlist, L.wcount, A.jac, A.ut_bar_in, A.ut_bar_out);
+                         L.wlist, L.wcount + (A.epoch & 1), A.jac, A.ut_bar_in, A.ut_bar_out);
     return hipGetLastError();
   });
 }

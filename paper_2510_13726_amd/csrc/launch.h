@@ -10,15 +10,13 @@ namespace hlbm {
 // Everything a launch needs, with raw device pointers carved from the
 // caller's workspace.  Types of the typed fields follow storage / compute.
 struct Launch {
-  hipStream_t stream;        // the caller's stream: rotor chain and FSI sweep
-  hipStream_t stream2;       // internal stream: bulk sweep
+  hipStream_t stream;        // the caller's stream
   int storage, compute;      // hlbm_dtype values
   Geometry g;
   Model m;
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
-  int32_t* blist;            // FSI workgroups, then bulk workgroups
-  int64_t nfsi, nbulk;
-  int32_t xcd_remap;
+  int32_t* blist;            // launch order of the tiles
+  BladeTrig* trig_tab;       // blade angles of kTrigSteps consecutive steps
   // fields
   void* d_eff;
   void* d_static;
@@ -32,7 +30,7 @@ struct Launch {
   double* mass_part;
   double* mass_l1;           // [kPartL1]
   int32_t* wlist;            // wall cells of the step (box slots)
-  int32_t* wcount;
+  int32_t* wcount;           // [2] wall-list counters, alternating by launch
   int32_t* flag;
   unsigned long long* stats; // [0] Newton iterations, [1] wall cells
   RotorTable* rot;           // device copy
@@ -46,13 +44,24 @@ struct Launch {
   double* ghost64;           // same in FP64 for the wall model
 };
 
-hipError_t launch_rasterize(const Launch& L, int64_t step, const BladeTrig& trig, uint8_t* act_new);
+// Rotor geometry of the step on the box slots and the wall-cell list
+// (counter `epoch & 1`; the other counter is zeroed for the next launch);
+// with_ghost: also the step's inflow plane.
+hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
+                           bool with_ghost);
+// Wall model of the listed wall cells of `epoch` (jac: with Jacobians).
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step, double* jac = nullptr,
+                       double* ut_new, uint8_t* act_new, int64_t step, int epoch, double* jac = nullptr,
                        int count_stats = 1);
-hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag, int part = 0);
+// Step sweep of every cell: pull, moments, collision (porosity, solid and
+// wall-model velocities in the FSI tiles), store, per-tag momentum partials.
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
 hipError_t launch_prologue(const Launch& L, int64_t step);
-hipError_t launch_finalize(const Launch& L, int64_t step, int32_t nslots, bool diag);
+// Records of steps n0 .. n0 + count - 1 from their partial slices (slice j:
+// force partials at partial + j nslots kPartial, mass partials at
+// mass_part + j nblocks); the mass of the steps that are not diagnostics
+// steps is recorded as NaN.
+hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t nslots, int32_t diag_every);
 hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* rho, void* u, void* uhat);
 hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, const void* u);
 hipError_t launch_get_populations(const Launch& L, const void* src, double* dst);
@@ -75,6 +84,7 @@ struct AdjLaunch {
   double* ut_bar_out;       // adjoint of the friction velocity read by the step
   double obj_w;
   int32_t obj_tag;
+  int32_t epoch;            // wall-list counter of the step's geometry launch
 };
 hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A);
 hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A);

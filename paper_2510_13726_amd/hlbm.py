@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libhlbm.so")
 HLBM_OK, HLBM_ERR_INVALID, HLBM_ERR_HIP, HLBM_ERR_NONFINITE, HLBM_ERR_STATE = range(5)
 F64, F32, F16, BF16 = 0, 1, 2, 3
 BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
-WITH_SOLID_VELOCITY, WITH_CONTROL, WITH_ADJOINT, OVERLAP_STREAMS = 1, 2, 4, 8
+WITH_SOLID_VELOCITY, WITH_CONTROL, WITH_ADJOINT = 1, 2, 4
 HIST_STRIDE = 91
 DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 

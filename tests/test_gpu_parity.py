@@ -63,13 +63,12 @@ def test_tgv_sphere_parity(storage):
     assert rel(uh_g, uh_o) < TOL[storage]
 
 
-@pytest.mark.parametrize("storage,flags", [("f64", 0), ("f32", 0), ("f64", 8)])
-def test_rotor_wall_model_parity(storage, flags):
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_rotor_wall_model_parity(storage):
     """Rotor channel with inflow turbulence, outflow, rotating flat-plate rotor
-    and the wall model, 24 steps (several tiles, ragged x extent); flags 8:
-    the sweep away from the rotor on the second stream."""
+    and the wall model, 24 steps (several tiles, ragged x extent)."""
     w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
-    lat, o, errs = run_both(w, storage, 24, check_every=8, flags=flags)
+    lat, o, errs = run_both(w, storage, 24, check_every=8)
     assert max(errs) < TOL[storage], errs
     hg, ho = lat.history(), o.history()
     assert rel(hg[:, 1:7], ho[:, 1:7]) < 10 * TOL[storage]
