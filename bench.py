@@ -59,8 +59,7 @@ def time_storage(w, storage, steps, warmup):
     n, ms = hlbm.profile_read(lat, hlbm.KERNEL_SWEEP)
     hlbm.profile_enable(lat, False)
     fsi_cells, bulk_cells = hlbm.sweep_partition(lat)
-    # one launch sweeps every cell (with the overlap option, the timed launch
-    # would be the part away from the rotors)
+    # one launch sweeps every cell
     sweep_cells = w.cells
     it, cells = lat.wall_stats()
     ok = bool(torch.isfinite(lat.moments()[0]).all().item())
@@ -84,7 +83,7 @@ def roofline(w, storage, sweep_avg_ms, sweep_cells):
             traffic = t.get("bytes_per_launch")
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_sweep (bulk workgroups)", "cells_per_launch": sweep_cells,
+            "kernel": "k_sweep", "cells_per_launch": sweep_cells,
             "algorithmic_bytes_per_launch": algo,
             "avg_launch_ms": round(sweep_avg_ms, 5)}
 
