@@ -218,6 +218,12 @@ void set_model(hlbm_handle h) {
   m.wall_model = p.wall_model;
   m.E = p.E; m.kappa = p.kappa; m.y_s = p.y_s; m.tol = p.tol;
   m.nu = (p.tau0 - 0.5) / 3.0;
+  m.inv_E = 1.0 / p.E;
+  m.kappa_E = p.kappa / p.E;
+  m.inv_kappa = 1.0 / p.kappa;
+  m.inv_nu = 1.0 / m.nu;
+  m.ys_nu = p.y_s / m.nu;
+  m.nu_ys = m.nu / p.y_s;
   m.maxit = p.maxit;
   for (int a = 0; a < 3; ++a) m.u_in[a] = p.u_in[a];
   const double mag = std::sqrt(p.u_in[0] * p.u_in[0] + p.u_in[1] * p.u_in[1] + p.u_in[2] * p.u_in[2]);

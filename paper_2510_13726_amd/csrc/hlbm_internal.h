@@ -47,6 +47,8 @@ struct Model {
   double eps_h;
   int32_t transition, wall_model;
   double E, kappa, y_s, tol, nu;
+  // reciprocals and ratios for the wall law (one division each, on the host)
+  double inv_E, kappa_E, inv_kappa, inv_nu, ys_nu, nu_ys;
   int32_t maxit, pad;
   double u_in[3];
   double turb_amp;     // turb_I * |u_in|

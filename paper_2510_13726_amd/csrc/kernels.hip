@@ -382,9 +382,13 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   it1 = 0;
   if (!(::sqrt(val(U2)) >= 1e-6)) return false;
   const R U = sqrt(U2);
-  const R t[3] = {vt[0] / U, vt[1] / U, vt[2] / U};
-  const double nu = m.nu, ys = m.y_s, E = m.E, kap = m.kappa;
-  const R guess = prev_active ? utp : sqrt(nu * U / ys);
+  const R iU = 1.0 / U;
+  const R t[3] = {vt[0] * iU, vt[1] * iU, vt[2] * iU};
+  const double ys = m.y_s, E = m.E, kap = m.kappa;
+  // the Newton chains run on one lane per wall cell: every division is a
+  // long dependent sequence in FP64, so the constants enter as reciprocals
+  const double sixth = 1.0 / 6.0;
+  const R guess = prev_active ? utp : sqrt(m.nu_ys * U);
   const R ut = newton(
       guess,
       [&](R u, R& f, R& df) {
@@ -394,13 +398,13 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
         const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
         const R dek = val(k) > 80.0 ? cst<R>(0.0) : ek;
         const R poly = 1.0 + k + k * k * 0.5;
-        f = p + (ek - poly - k * k * k / 6.0) / E - ys * u / nu;
-        df = 0.0 - (p * iu) * (1.0 + kap * (dek - poly) / E) - ys / nu;
+        f = p + (ek - poly - k * k * k * sixth) * m.inv_E - m.ys_nu * u;
+        df = 0.0 - (p * iu) * (1.0 + m.kappa_E * (dek - poly)) - m.ys_nu;
       },
       m.tol, m.maxit, it1);
-  const R yp = y1 * ut / nu;
+  const R yp = y1 * ut * m.inv_nu;
   const R ylog = val(yp) > 1.0 ? yp : cst<R>(1.0);
-  const R ulog = log(E * ylog) / kap;
+  const R ulog = log(E * ylog) * m.inv_kappa;
   int it2 = 0;
   const R up = newton(
       val(ulog) < val(yp) ? ulog : yp,
@@ -409,8 +413,8 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
         const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
         const R dek = val(k) > 80.0 ? cst<R>(0.0) : ek;
         const R poly = 1.0 + k + k * k * 0.5;
-        f = u + (ek - poly - k * k * k / 6.0) / E - yp;
-        df = 1.0 + kap * (dek - poly) / E;
+        f = u + (ek - poly - k * k * k * sixth) * m.inv_E - yp;
+        df = 1.0 + m.kappa_E * (dek - poly);
       },
       m.tol, m.maxit, it2);
   const R qv = ut * up;
