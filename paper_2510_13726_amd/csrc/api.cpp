@@ -852,6 +852,9 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
   if (e != hipSuccess) return hip_fail(h, e, "adjoint init");
   const int64_t nseg = (h->rec.nsteps + ce - 1) / ce;
   int cur = 0;
+  // the outflow fix-up of each reverse step's lam and the zeroing of the
+  // next u_tau adjoint run inside the following geometry launch
+  bool fix_pending = false;
   const double w = gJ / double(h->rec.t1 - h->rec.t0);
   char* st = static_cast<char*>(stack);
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
@@ -880,9 +883,14 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       const bool inlet = probe_reaches_inlet(h);
       if (e == hipSuccess && inlet) e = launch_prologue(h->L, n);
       const int epoch = h->wc_epoch++;
-      if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act, !inlet);
+      AdjChores ch{};
+      ch.lam = fix_pending ? lam[cur] : nullptr;
+      ch.side = ws + Y.side;
+      ch.lstride = pop_stride_c(&h->desc);
+      ch.zero = utb[1 - cur];
+      ch.nzero = B;
+      if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act, !inlet, &ch);
       if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, epoch, jac, 0);
-      if (e == hipSuccess) e = hipMemsetAsync(utb[1 - cur], 0, B * 8, h->stream);
       AdjLaunch A{};
       A.src = s0;
       A.lam_in = lam[cur];
@@ -898,8 +906,9 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       A.lstride = pop_stride_c(&h->desc);
       A.epoch = epoch;
       if (e == hipSuccess && wall) e = launch_adjoint_wall(h->L, A);
-      if (e == hipSuccess) e = launch_adjoint_sweep(h->L, A);
+      if (e == hipSuccess) e = launch_adjoint_sweep(h->L, A, false);
       if (e != hipSuccess) return hip_fail(h, e, "adjoint step");
+      fix_pending = true;
       cur = 1 - cur;
     }
   }

@@ -588,6 +588,15 @@ struct GeoArgs {
   int64_t step;              // inflow plane of the step (extra workgroups)
   CT* ghost;
   double* ghost64;
+  int32_t ghost_blocks;
+  // adjoint bookkeeping done by further workgroups (nullable): the outflow
+  // fix-up of the previous reverse step's lam, and zeroing an FP64 buffer
+  CT* fix_lam;
+  const CT* fix_side;
+  int64_t fix_lstride;
+  int32_t fix_blocks;
+  double* zero;
+  int64_t nzero;
 };
 
 template <class CT>
@@ -596,8 +605,28 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
   const Model& m = a.m;
   const uint32_t nbw = uint32_t((a.total + 255) / 256);
   if (blockIdx.x >= nbw) {
-    const int64_t k = int64_t(blockIdx.x - nbw) * 256 + threadIdx.x;
-    if (k < int64_t(g.ny) * g.nz) inflow_plane_cell<CT>(g, m, a.step, k, a.ghost, a.ghost64);
+    const int64_t plane = int64_t(g.ny) * g.nz;
+    int64_t b = int64_t(blockIdx.x) - nbw;
+    if (b < a.ghost_blocks) {
+      const int64_t k = b * 256 + threadIdx.x;
+      if (k < plane) inflow_plane_cell<CT>(g, m, a.step, k, a.ghost, a.ghost64);
+      return;
+    }
+    b -= a.ghost_blocks;
+    if (b < a.fix_blocks) {
+      // outflow: the state at (nx-1, y', z') for c_x = -1 feeds both
+      // (nx-2, .) and the clamped read of (nx-1, .): add the second share
+      const int64_t k = b * 256 + threadIdx.x;
+      if (k < plane) {
+        const int z = int(k / g.ny), y = int(k - int64_t(z) * g.ny);
+        const int64_t c = (int64_t(z) * g.ny + y) * g.nx + (g.nx - 1);
+        for (int i = 0; i < 9; ++i) a.fix_lam[int64_t(i) * a.fix_lstride + c] += a.fix_side[i * plane + k];
+      }
+      return;
+    }
+    b -= a.fix_blocks;
+    const int64_t k = b * 256 + threadIdx.x;
+    if (k < a.nzero) a.zero[k] = 0.0;
     return;
   }
   __shared__ int wl_count, wl_base;
@@ -1277,11 +1306,13 @@ static hipError_t by_compute(int compute, F&& f) {
 }
 
 hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
-                           bool with_ghost) {
+                           bool with_ghost, const AdjChores* chores) {
   const int64_t nbw = L.nrot > 0 ? (L.bbox_total + 255) / 256 : 0;
   const int64_t plane = int64_t(L.g.ny) * L.g.nz;
   const int64_t nghost = (with_ghost && L.g.bc_x != 0) ? (plane + 255) / 256 : 0;
-  if (nbw + nghost == 0) return hipSuccess;
+  const int64_t nfix = (chores && chores->lam && L.g.bc_x != 0) ? (plane + 255) / 256 : 0;
+  const int64_t nzero = (chores && chores->zero) ? (chores->nzero + 255) / 256 : 0;
+  if (nbw + nghost + nfix + nzero == 0) return hipSuccess;
   return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
     GeoArgs<CT> a{};
@@ -1292,7 +1323,13 @@ hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig,
     a.step = step; a.ghost = (CT*)L.ghost;
     // the wall model samples in FP64: also fill the FP64 plane when it differs
     a.ghost64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
-    hipLaunchKernelGGL(k_geometry<CT>, dim3(unsigned(nbw + nghost)), dim3(256), 0, L.stream, a);
+    a.ghost_blocks = int32_t(nghost);
+    if (nfix) {
+      a.fix_lam = (CT*)chores->lam; a.fix_side = (const CT*)chores->side; a.fix_lstride = chores->lstride;
+    }
+    a.fix_blocks = int32_t(nfix);
+    if (nzero) { a.zero = chores->zero; a.nzero = chores->nzero; }
+    hipLaunchKernelGGL(k_geometry<CT>, dim3(unsigned(nbw + nghost + nfix + nzero)), dim3(256), 0, L.stream, a);
     return hipGetLastError();
   });
 }
@@ -1421,7 +1458,7 @@ hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A) {
   });
 }
 
-hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A) {
+hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A, bool fixup) {
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
@@ -1432,7 +1469,7 @@ hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A) {
     }
     hipLaunchKernelGGL((k_adj_sweep<ST, CT, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !fixup) return e;
     const int64_t plane = int64_t(L.g.ny) * L.g.nz;
     hipLaunchKernelGGL(k_adj_fixup<CT>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, A.lstride,
                        (const CT*)A.side, (CT*)A.lam_out);

@@ -44,11 +44,21 @@ struct Launch {
   double* ghost64;           // same in FP64 for the wall model
 };
 
+// Adjoint bookkeeping folded into the geometry launch of a reverse step:
+// the outflow fix-up of the previous reverse step's lam (lam += side on the
+// last x plane, skipped when lam is null) and zeroing nzero doubles.
+struct AdjChores {
+  void* lam;
+  const void* side;
+  int64_t lstride;
+  double* zero;
+  int64_t nzero;
+};
 // Rotor geometry of the step on the box slots and the wall-cell list
 // (counter `epoch & 1`; the other counter is zeroed for the next launch);
-// with_ghost: also the step's inflow plane.
+// with_ghost: also the step's inflow plane; chores (nullable): see above.
 hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
-                           bool with_ghost);
+                           bool with_ghost, const AdjChores* chores = nullptr);
 // Wall model of the listed wall cells of `epoch` (jac: with Jacobians).
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
                        double* ut_new, uint8_t* act_new, int64_t step, int epoch, double* jac = nullptr,
@@ -87,7 +97,8 @@ struct AdjLaunch {
   int32_t epoch;            // wall-list counter of the step's geometry launch
 };
 hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A);
-hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A);
+// fixup: apply the outflow fix-up now (else a later geometry launch does).
+hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A, bool fixup);
 hipError_t launch_refill_porosity(const Launch& L);
 hipError_t launch_fill_rest(const Launch& L, void* dst);
 
