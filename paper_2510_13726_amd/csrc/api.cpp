@@ -62,9 +62,9 @@ int64_t pop_stride_c(const hlbm_desc* d) {
 }
 
 struct Layout {
-  int64_t d_eff, d_static, tag, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wcount, flag, stats, rot, geo, ut0, ut1,
-      act0, act1, wall, hist, ghost, ghost64, ghostb, ghost64b, blist, trig, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut,
-      scr_act, total;
+  int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
+      wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b, blist,
+      trig, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut, scr_act, scr_actb, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -77,9 +77,12 @@ Layout layout(const hlbm_desc* d) {
   int64_t o = 0;
   // every section gets at least one aligned block, so sections never alias
   auto take = [&](int64_t bytes) { int64_t at = o; o = align_up(o + std::max<int64_t>(bytes, 1), kAlign); return at; };
+  // porosity, tags, box geometry and wall list in two sets, by step parity
   L.d_eff = take(N * cs);
+  L.d_effb = take(N * cs);
   L.d_static = take(N * cs);
   L.tag = take(N);
+  L.tagb = take(N);
   L.tag_static = take(N);
   L.uB = take((d->flags & HLBM_WITH_SOLID_VELOCITY) ? 3 * N * cs : 0);
   L.dd = take((d->flags & HLBM_WITH_CONTROL) ? N * cs : 0);
@@ -89,15 +92,18 @@ Layout layout(const hlbm_desc* d) {
   L.mass = take(int64_t(kMaxBatch) * nb * 8);
   L.massl1 = take(int64_t(kMaxBatch) * kPartL1 * 8);
   L.wlist = take(B * 4);
+  L.wlistb = take(B * 4);
   L.wcount = take(64);
   L.flag = take(64);
   L.stats = take(64);
   L.rot = take(sizeof(RotorTable));
   L.geo = take(4 * B * 8);
+  L.geob = take(4 * B * 8);
   L.ut0 = take(B * 8);
   L.ut1 = take(B * 8);
   L.act0 = take(B);
   L.act1 = take(B);
+  L.act2 = take(B);
   L.wall = take(kWallOut * B * cs);
   L.hist = take(H * kHist * 8);
   const int64_t plane = int64_t(d->ny) * d->nz;
@@ -118,6 +124,7 @@ Layout layout(const hlbm_desc* d) {
   L.jac = take(adj ? B * 40 * 8 : 0);
   L.scr_ut = take(adj ? B * 8 : 0);
   L.scr_act = take(adj ? B : 0);
+  L.scr_actb = take(adj ? B : 0);
   L.total = o;
   return L;
 }
@@ -162,9 +169,21 @@ struct hlbm_lattice {
   Launch L{};
   void* pop[2] = {nullptr, nullptr};
   int cur = 0;                 // pop[cur] holds the state
+  char* ws = nullptr;           // the caller's workspace
+  // geometry buffer sets (porosity, tags, box geometry, wall list) by step parity
+  struct GeoSet {
+    void* d_eff;
+    uint8_t* tag;
+    double* geo;
+    int32_t* wlist;
+  } set[2] = {};
   double* ut[2] = {nullptr, nullptr};
-  uint8_t* act[2] = {nullptr, nullptr};
-  int wcur = 0;
+  int wcur = 0;                // ut[wcur] holds the friction-velocity state
+  // wall-model activity of the state (act[acur]), of the next state, and of
+  // the one after it, which the geometry of the next step resets while the
+  // wall model of this step runs
+  uint8_t* act[3] = {nullptr, nullptr, nullptr};
+  int acur = 0;
   RotorTable rot{};
   std::vector<hlbm_rotor> rotors;
   hlbm_params params{};
@@ -182,7 +201,11 @@ struct hlbm_lattice {
     char* ckpt = nullptr;
     double J = 0.0;
   } rec;
-  int wc_epoch = 0;  // wall-list counter of the next geometry launch
+  int wc_epoch = 0;  // wall-list counter of the next geometry launch (0 .. kCounters - 1)
+  // the geometry of step ahead_step (counter ahead_epoch) is already in its
+  // buffer set, computed by the previous step's wall-model launch; -1: none
+  int64_t ahead_step = -1;
+  int ahead_epoch = 0;
   // steps swept but not yet reduced: pending steps from pend_n0; their force
   // partials are slices of `batch` steps in the partial buffer
   int64_t pend_n0 = 0;
@@ -229,6 +252,36 @@ void set_model(hlbm_handle h) {
   const double mag = std::sqrt(p.u_in[0] * p.u_in[0] + p.u_in[1] * p.u_in[1] + p.u_in[2] * p.u_in[2]);
   m.turb_amp = p.turb_I * mag;
   m.seed = p.seed;
+}
+
+// The launch state with the geometry buffer set and inflow plane of step n.
+Launch launch_of(hlbm_handle h, int64_t n) {
+  Launch L = h->L;
+  const auto& q = h->set[n & 1];
+  L.d_eff = q.d_eff;
+  L.tag = q.tag;
+  L.geo = q.geo;
+  L.wlist = q.wlist;
+  L.ghost = h->ghost[n & 1];
+  L.ghost64 = h->ghost64[n & 1];
+  return L;
+}
+void select_step(hlbm_handle h, int64_t n) { h->L = launch_of(h, n); }
+
+int next_epoch(hlbm_handle h) {
+  const int e = h->wc_epoch;
+  h->wc_epoch = (e + 1) % kCounters;
+  return e;
+}
+
+// Static porosity and tags (plus the control field) into both buffer sets.
+hipError_t refill_porosity(hlbm_handle h) {
+  h->ahead_step = -1;
+  for (int p = 0; p < 2; ++p) {
+    hipError_t e = launch_refill_porosity(launch_of(h, p));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Mark FSI workgroups and number them (host round trip; set-up time only).
@@ -394,9 +447,14 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.g.nty = (d->ny + kTileY - 1) / kTileY;
   L.nblocks = int64_t(L.g.ntx) * L.g.nty * d->nz;
   const Layout& Y = h->lay;
-  L.d_eff = base + Y.d_eff;
+  h->ws = base;
+  h->set[0] = {base + Y.d_eff, reinterpret_cast<uint8_t*>(base + Y.tag), reinterpret_cast<double*>(base + Y.geo),
+               reinterpret_cast<int32_t*>(base + Y.wlist)};
+  h->set[1] = {base + Y.d_effb, reinterpret_cast<uint8_t*>(base + Y.tagb), reinterpret_cast<double*>(base + Y.geob),
+               reinterpret_cast<int32_t*>(base + Y.wlistb)};
+  L.d_eff = h->set[0].d_eff;
   L.d_static = base + Y.d_static;
-  L.tag = reinterpret_cast<uint8_t*>(base + Y.tag);
+  L.tag = h->set[0].tag;
   L.tag_static = reinterpret_cast<uint8_t*>(base + Y.tag_static);
   L.uB_static = nullptr;
   L.dd = nullptr;
@@ -405,18 +463,19 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.part_l1 = reinterpret_cast<double*>(base + Y.partl1);
   L.mass_part = reinterpret_cast<double*>(base + Y.mass);
   L.mass_l1 = reinterpret_cast<double*>(base + Y.massl1);
-  L.wlist = reinterpret_cast<int32_t*>(base + Y.wlist);
+  L.wlist = h->set[0].wlist;
   L.wcount = reinterpret_cast<int32_t*>(base + Y.wcount);
   L.flag = reinterpret_cast<int32_t*>(base + Y.flag);
   L.stats = reinterpret_cast<unsigned long long*>(base + Y.stats);
   L.rot = reinterpret_cast<RotorTable*>(base + Y.rot);
   L.nrot = 0;
   L.bbox_total = 0;
-  L.geo = reinterpret_cast<double*>(base + Y.geo);
+  L.geo = h->set[0].geo;
   h->ut[0] = reinterpret_cast<double*>(base + Y.ut0);
   h->ut[1] = reinterpret_cast<double*>(base + Y.ut1);
   h->act[0] = reinterpret_cast<uint8_t*>(base + Y.act0);
   h->act[1] = reinterpret_cast<uint8_t*>(base + Y.act1);
+  h->act[2] = reinterpret_cast<uint8_t*>(base + Y.act2);
   L.wall_out = base + Y.wall;
   L.hist = reinterpret_cast<double*>(base + Y.hist);
   L.hist_cap = h->hist_cap;
@@ -492,6 +551,7 @@ int hlbm_set_params(hlbm_handle h, const hlbm_params* p) {
   }
   set_model(h);
   h->have_params = true;
+  h->ahead_step = -1;
   return HLBM_OK;
 }
 
@@ -508,10 +568,9 @@ int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* r, int32_t n) {
   h->L.nrot = n;
   h->L.bbox_total = total;
   // reset cells of the old boxes to the static field, then re-mark
-  hipError_t e = launch_refill_porosity(h->L);
+  hipError_t e = refill_porosity(h);
   if (e != hipSuccess) return hip_fail(h, e, "refill porosity");
-  e = hipMemsetAsync(h->act[0], 0, std::max<int64_t>(total, 1), h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->act[1], 0, std::max<int64_t>(total, 1), h->stream);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMemsetAsync(h->act[k], 0, std::max<int64_t>(total, 1), h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "reset wall state");
   if ((rc = upload_rotors(h)) != HLBM_OK) return rc;
   return rebuild_slots(h);
@@ -526,7 +585,7 @@ int hlbm_set_porosity_field(hlbm_handle h, const void* d, const uint8_t* tag) {
   if (e == hipSuccess)
     e = tag ? hipMemcpyAsync(h->L.tag_static, tag, N, hipMemcpyDeviceToDevice, h->stream)
             : hipMemsetAsync(h->L.tag_static, 0, N, h->stream);
-  if (e == hipSuccess) e = launch_refill_porosity(h->L);
+  if (e == hipSuccess) e = refill_porosity(h);
   if (e != hipSuccess) return hip_fail(h, e, "set porosity field");
   return rebuild_slots(h);
 }
@@ -535,7 +594,7 @@ int hlbm_set_solid_velocity(hlbm_handle h, const void* uB) {
   if (!h) return HLBM_ERR_INVALID;
   if (!(h->desc.flags & HLBM_WITH_SOLID_VELOCITY)) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_SOLID_VELOCITY");
   const int64_t bytes = 3 * h->L.g.N * elem_size(h->desc.compute);
-  void* dst = static_cast<char*>(h->L.d_eff) - h->lay.d_eff + h->lay.uB;
+  void* dst = h->ws + h->lay.uB;
   hipError_t e = uB ? hipMemcpyAsync(dst, uB, bytes, hipMemcpyDeviceToDevice, h->stream)
                     : hipMemsetAsync(dst, 0, bytes, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "set solid velocity");
@@ -547,12 +606,12 @@ int hlbm_set_control(hlbm_handle h, const void* dd) {
   if (!h) return HLBM_ERR_INVALID;
   if (!(h->desc.flags & HLBM_WITH_CONTROL)) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_CONTROL");
   const int64_t bytes = h->L.g.N * elem_size(h->desc.compute);
-  void* dst = static_cast<char*>(h->L.d_eff) - h->lay.d_eff + h->lay.dd;
+  void* dst = h->ws + h->lay.dd;
   hipError_t e = dd ? hipMemcpyAsync(dst, dd, bytes, hipMemcpyDeviceToDevice, h->stream)
                     : hipMemsetAsync(dst, 0, bytes, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "set control");
   h->L.dd = dd ? dst : nullptr;
-  e = launch_refill_porosity(h->L);
+  e = refill_porosity(h);
   if (e != hipSuccess) return hip_fail(h, e, "refill porosity");
   return rebuild_slots(h);
 }
@@ -571,9 +630,9 @@ int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u) {
   if (!h) return HLBM_ERR_INVALID;
   hipError_t e = launch_init_equilibrium(h->L, h->pop[h->cur], rho, u);
   const int64_t B = std::max<int64_t>(h->L.bbox_total, 1);
-  if (e == hipSuccess) e = hipMemsetAsync(h->act[0], 0, B, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->act[1], 0, B, h->stream);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMemsetAsync(h->act[k], 0, B, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "init equilibrium");
+  h->ahead_step = -1;
   h->step = 0;
   h->hist_start = 0;
   return HLBM_OK;
@@ -597,8 +656,9 @@ BladeTrig blade_trig(hlbm_handle h, int64_t n) {
 }
 
 // Blade angles of step n on the device: the table holds kTrigSteps steps
-// from trig_base; a step outside it reloads the table from step n (host
-// cos / sin, one asynchronous copy from a pinned buffer).
+// from trig_base; a step outside it reloads the table (host cos / sin, one
+// asynchronous copy from a pinned buffer) from step n, or up to step n when
+// n lies before the table, as in the reverse sweep of the adjoint.
 hipError_t trig_of(hlbm_handle h, int64_t n, const BladeTrig** out) {
   *out = nullptr;
   if (h->rot.n == 0 || !h->L.trig_tab) return hipSuccess;
@@ -611,12 +671,13 @@ hipError_t trig_of(hlbm_handle h, int64_t n, const BladeTrig** out) {
       e = hipEventSynchronize(h->trig_ev);  // the previous copy has read the buffer
     }
     if (e != hipSuccess) return e;
-    for (int k = 0; k < kTrigSteps; ++k) h->trig_host[k] = blade_trig(h, n + k);
+    const int64_t base = (h->trig_base >= 0 && n < h->trig_base) ? std::max<int64_t>(0, n - (kTrigSteps - 1)) : n;
+    for (int k = 0; k < kTrigSteps; ++k) h->trig_host[k] = blade_trig(h, base + k);
     e = hipMemcpyAsync(h->L.trig_tab, h->trig_host, sizeof(BladeTrig) * kTrigSteps, hipMemcpyHostToDevice,
                        h->stream);
     if (e == hipSuccess) e = hipEventRecord(h->trig_ev, h->stream);
     if (e != hipSuccess) return e;
-    h->trig_base = n;
+    h->trig_base = base;
   }
   *out = h->L.trig_tab + (n - h->trig_base);
   return hipSuccess;
@@ -667,29 +728,49 @@ bool probe_reaches_inlet(hlbm_handle h) {
 }
 
 // One forward step n from state `src` to `dst` with the wall-model state
-// (ut_prev, act_prev) -> (ut_new, act_new): inflow plane, the step sweep
-// (geometry and wall model inside its FSI workgroups), force reduction.
+// (ut_prev, act_prev) -> (ut_new, act_new): inflow plane, geometry (unless
+// the previous step's wall-model launch computed it), wall model, sweep.
+// act_ahead (nullable): the activity buffer of the state after the next
+// step; given, the wall-model launch also computes the geometry of step
+// n + 1, which resets it.
 hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, const double* ut_prev,
-                       const uint8_t* act_prev, double* ut_new, uint8_t* act_new) {
-  const BladeTrig* trig = nullptr;
-  hipError_t e = trig_of(h, n, &trig);
-  if (e != hipSuccess) return e;
-  // inflow ghost planes alternate by step
-  h->L.ghost = h->ghost[n & 1];
-  h->L.ghost64 = h->ghost64[n & 1];
+                       const uint8_t* act_prev, double* ut_new, uint8_t* act_new, uint8_t* act_ahead) {
+  select_step(h, n);
   const bool diag = h->params.diag_every > 0 && n % h->params.diag_every == 0;
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   // the inflow plane is written by the geometry launch, unless a wall-model
-  // probe can reach the inlet: then it must be complete before that launch
+  // probe can reach the inlet: then it must be complete before the wall launch
   const bool inlet = probe_reaches_inlet(h);
+  hipError_t e = hipSuccess;
   if (inlet) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_prologue(h->L, n); });
-  const int epoch = h->wc_epoch++;
-  if (e == hipSuccess)
-    e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_geometry(h->L, n, trig, epoch, act_new, !inlet); });
-  if (e == hipSuccess && wall)
-    e = timed(h, HLBM_KERNEL_WALL, [&] {
-      return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, n, epoch, nullptr, diag ? 1 : 0);
-    });
+  int epoch = h->ahead_epoch;
+  if (h->ahead_step != n) {
+    const BladeTrig* trig = nullptr;
+    if (e == hipSuccess) e = trig_of(h, n, &trig);
+    epoch = next_epoch(h);
+    if (e == hipSuccess)
+      e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_geometry(h->L, n, trig, epoch, act_new, !inlet); });
+  }
+  h->ahead_step = -1;
+  if (e == hipSuccess && wall) {
+    NextGeometry ng{};
+    Launch L1;
+    if (act_ahead) {
+      const BladeTrig* trig1 = nullptr;
+      e = trig_of(h, n + 1, &trig1);
+      L1 = launch_of(h, n + 1);
+      ng = NextGeometry{&L1, n + 1, trig1, next_epoch(h), act_ahead, !inlet, nullptr};
+    }
+    if (e == hipSuccess)
+      e = timed(h, HLBM_KERNEL_WALL, [&] {
+        return launch_wall(h->L, src, ut_prev, act_prev, ut_new, act_new, epoch, nullptr, diag ? 1 : 0,
+                           act_ahead ? &ng : nullptr);
+      });
+    if (e == hipSuccess && act_ahead) {
+      h->ahead_step = n + 1;
+      h->ahead_epoch = ng.epoch;
+    }
+  }
   // force partials (and mass partials of a diagnostics step) into this step's slice
   if (e == hipSuccess && h->pending == h->batch) e = flush(h);
   if (h->pending == 0) h->pend_n0 = n;
@@ -733,7 +814,7 @@ hipError_t copy_state_out(hlbm_handle h, char* dst) {
   const int64_t B = h->L.bbox_total;
   hipError_t e = hipMemcpyAsync(dst, h->pop[h->cur], s.pops, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && B) e = hipMemcpyAsync(dst + s.ut, h->ut[h->wcur], B * 8, hipMemcpyDeviceToDevice, h->stream);
-  if (e == hipSuccess && B) e = hipMemcpyAsync(dst + s.act, h->act[h->wcur], B, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess && B) e = hipMemcpyAsync(dst + s.act, h->act[h->acur], B, hipMemcpyDeviceToDevice, h->stream);
   return e;
 }
 
@@ -756,11 +837,15 @@ int hlbm_step(hlbm_handle h, int64_t n) {
   if (n < 0) return fail(h, HLBM_ERR_INVALID, "n must be >= 0");
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   for (int64_t k = 0; k < n; ++k) {
-    hipError_t e = forward_one(h, h->step, h->pop[h->cur], h->pop[1 - h->cur], h->ut[h->wcur], h->act[h->wcur],
-                               h->ut[1 - h->wcur], h->act[1 - h->wcur]);
+    const int a1 = (h->acur + 1) % 3, a2 = (h->acur + 2) % 3;
+    hipError_t e = forward_one(h, h->step, h->pop[h->cur], h->pop[1 - h->cur], h->ut[h->wcur], h->act[h->acur],
+                               h->ut[1 - h->wcur], h->act[a1], wall ? h->act[a2] : nullptr);
     if (e != hipSuccess) return hip_fail(h, e, "step");
     h->cur = 1 - h->cur;
-    if (wall) h->wcur = 1 - h->wcur;
+    if (wall) {
+      h->wcur = 1 - h->wcur;
+      h->acur = a1;
+    }
     ++h->step;
   }
   hipError_t ef = flush(h);
@@ -834,13 +919,14 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
     return fail(h, HLBM_ERR_INVALID, "G or stack missing, or stack too small");
   const StateLayout sl = state_layout(h);
   const Layout& Y = h->lay;
-  char* ws = static_cast<char*>(h->L.d_eff) - Y.d_eff;
+  char* ws = h->ws;
   void* lam[2] = {ws + Y.lam0, ws + Y.lam1};
   double* utb[2] = {reinterpret_cast<double*>(ws + Y.utb0), reinterpret_cast<double*>(ws + Y.utb1)};
   double* ubar = reinterpret_cast<double*>(ws + Y.ubar);
   double* jac = reinterpret_cast<double*>(ws + Y.jac);
   double* scr_ut = reinterpret_cast<double*>(ws + Y.scr_ut);
-  uint8_t* scr_act = reinterpret_cast<uint8_t*>(ws + Y.scr_act);
+  // activity written by the wall model of a reverse step, by step parity
+  uint8_t* scr_act[2] = {reinterpret_cast<uint8_t*>(ws + Y.scr_act), reinterpret_cast<uint8_t*>(ws + Y.scr_actb)};
   const int64_t N = h->L.g.N, B = std::max<int64_t>(h->L.bbox_total, 1);
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   const int cs = elem_size(h->desc.compute);
@@ -853,20 +939,24 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
   const int64_t nseg = (h->rec.nsteps + ce - 1) / ce;
   int cur = 0;
   // the outflow fix-up of each reverse step's lam and the zeroing of the
-  // next u_tau adjoint run inside the following geometry launch
+  // next u_tau adjoint run inside the following geometry or wall launch
   bool fix_pending = false;
   const double w = gJ / double(h->rec.t1 - h->rec.t0);
   char* st = static_cast<char*>(stack);
+  h->ahead_step = -1;
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t a = seg * ce, b = std::min<int64_t>(h->rec.nsteps, a + ce);
-    // recompute the states of the segment into the stack
+    // recompute the states of the segment into the stack; each wall-model
+    // launch also computes the next step's geometry, the last one that of the
+    // first reverse step
     e = hipMemcpyAsync(st, h->rec.ckpt + seg * sl.bytes, sl.bytes, hipMemcpyDeviceToDevice, h->stream);
     for (int64_t k = a; e == hipSuccess && k + 1 < b; ++k) {
       char* s0 = st + (k - a) * sl.bytes;
       char* s1 = s0 + sl.bytes;
+      uint8_t* ahead = k + 2 < b ? reinterpret_cast<uint8_t*>(s1 + sl.bytes + sl.act) : scr_act[(h->rec.n0 + k + 1) & 1];
       e = forward_one(h, h->rec.n0 + k, s0, s1, reinterpret_cast<double*>(s0 + sl.ut),
                       reinterpret_cast<uint8_t*>(s0 + sl.act), reinterpret_cast<double*>(s1 + sl.ut),
-                      reinterpret_cast<uint8_t*>(s1 + sl.act));
+                      reinterpret_cast<uint8_t*>(s1 + sl.act), wall ? ahead : nullptr);
     }
     if (e == hipSuccess) e = flush(h);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint recompute");
@@ -876,21 +966,50 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       const double* ut0 = reinterpret_cast<const double*>(s0 + sl.ut);
       const uint8_t* ac0 = reinterpret_cast<const uint8_t*>(s0 + sl.act);
       // geometry, inflow and wall model of step n (with Jacobians)
-      h->L.ghost = h->ghost[n & 1];
-      h->L.ghost64 = h->ghost64[n & 1];
-      const BladeTrig* trig = nullptr;
-      e = trig_of(h, n, &trig);
+      select_step(h, n);
       const bool inlet = probe_reaches_inlet(h);
-      if (e == hipSuccess && inlet) e = launch_prologue(h->L, n);
-      const int epoch = h->wc_epoch++;
+      if (inlet) e = launch_prologue(h->L, n);
       AdjChores ch{};
       ch.lam = fix_pending ? lam[cur] : nullptr;
       ch.side = ws + Y.side;
       ch.lstride = pop_stride_c(&h->desc);
       ch.zero = utb[1 - cur];
       ch.nzero = B;
-      if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act, !inlet, &ch);
-      if (e == hipSuccess && wall) e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act, n, epoch, jac, 0);
+      bool chores_done = false;
+      int epoch = h->ahead_epoch;
+      if (h->ahead_step != n) {
+        const BladeTrig* trig = nullptr;
+        if (e == hipSuccess) e = trig_of(h, n, &trig);
+        epoch = next_epoch(h);
+        if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act[n & 1], !inlet, &ch);
+        chores_done = true;
+      }
+      h->ahead_step = -1;
+      // the wall launch also runs the geometry of step n - 1 when it is in
+      // this segment, and the chores if the geometry of step n did not
+      NextGeometry ng{};
+      Launch L1;
+      bool with_next = false;
+      if (e == hipSuccess && wall && k > a) {
+        const BladeTrig* trig1 = nullptr;
+        e = trig_of(h, n - 1, &trig1);
+        L1 = launch_of(h, n - 1);
+        ng = NextGeometry{&L1, n - 1, trig1, next_epoch(h), scr_act[(n - 1) & 1], !inlet, chores_done ? nullptr : &ch};
+        with_next = true;
+      } else if (!chores_done) {
+        L1 = h->L;
+        L1.nrot = 0;  // chores only: no box slots, no inflow plane
+        ng = NextGeometry{&L1, n, nullptr, 0, nullptr, false, &ch};
+        with_next = true;
+      }
+      if (e == hipSuccess && wall)
+        e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act[n & 1], epoch, jac, 0, with_next ? &ng : nullptr);
+      else if (e == hipSuccess && with_next)
+        e = launch_geometry(L1, ng.step, ng.trig, ng.epoch, ng.act_new, ng.with_ghost, ng.chores);
+      if (e == hipSuccess && wall && k > a) {
+        h->ahead_step = n - 1;
+        h->ahead_epoch = ng.epoch;
+      }
       AdjLaunch A{};
       A.src = s0;
       A.lam_in = lam[cur];
@@ -912,6 +1031,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       cur = 1 - cur;
     }
   }
+  h->ahead_step = -1;
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint");
   return HLBM_OK;
@@ -923,18 +1043,20 @@ int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat) {
   if (!h) return HLBM_ERR_INVALID;
   if (!rho || !u) return fail(h, HLBM_ERR_INVALID, "rho and u are required");
   const bool wall = h->params.wall_model && h->L.nrot > 0;
-  h->L.ghost = h->ghost[h->step & 1];
-  h->L.ghost64 = h->ghost64[h->step & 1];
+  select_step(h, h->step);
   const BladeTrig* trig = nullptr;
   hipError_t e = trig_of(h, h->step, &trig);
   const bool inlet = probe_reaches_inlet(h);
   if (e == hipSuccess && inlet) e = launch_prologue(h->L, h->step);
-  // the wall model writes the next state slot, which is not committed here
-  const int epoch = h->wc_epoch++;
-  if (e == hipSuccess) e = launch_geometry(h->L, h->step, trig, epoch, h->act[1 - h->wcur], !inlet);
+  // the wall model writes the next state slot, which is not committed here;
+  // the geometry is computed afresh (and any computed ahead is dropped)
+  h->ahead_step = -1;
+  uint8_t* act_next = h->act[(h->acur + 1) % 3];
+  const int epoch = next_epoch(h);
+  if (e == hipSuccess) e = launch_geometry(h->L, h->step, trig, epoch, act_next, !inlet);
   if (e == hipSuccess && wall)
-    e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->wcur], h->ut[1 - h->wcur], h->act[1 - h->wcur],
-                    h->step, epoch, nullptr, 0);
+    e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->acur], h->ut[1 - h->wcur], act_next, epoch,
+                    nullptr, 0);
   if (e == hipSuccess) e = launch_moments(h->L, h->pop[h->cur], h->step, rho, u, uhat);
   if (e != hipSuccess) return hip_fail(h, e, "moments");
   return HLBM_OK;
@@ -983,7 +1105,7 @@ int hlbm_get_state(hlbm_handle h, void* dst) {
   if (e == hipSuccess && B)
     e = hipMemcpyAsync(p + 256 + pb, h->ut[h->wcur], B * 8, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && B)
-    e = hipMemcpyAsync(p + 256 + pb + align_up(B * 8, 256), h->act[h->wcur], B, hipMemcpyDeviceToDevice, h->stream);
+    e = hipMemcpyAsync(p + 256 + pb + align_up(B * 8, 256), h->act[h->acur], B, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "get state");
   return HLBM_OK;
@@ -1002,8 +1124,9 @@ int hlbm_set_state(hlbm_handle h, const void* src) {
   e = hipMemcpyAsync(h->pop[h->cur], p + 256, pb, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && B) e = hipMemcpyAsync(h->ut[h->wcur], p + 256 + pb, B * 8, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && B)
-    e = hipMemcpyAsync(h->act[h->wcur], p + 256 + pb + align_up(B * 8, 256), B, hipMemcpyDeviceToDevice, h->stream);
+    e = hipMemcpyAsync(h->act[h->acur], p + 256 + pb + align_up(B * 8, 256), B, hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "set state");
+  h->ahead_step = -1;
   h->step = head[0];
   h->hist_start = head[0];
   return HLBM_OK;

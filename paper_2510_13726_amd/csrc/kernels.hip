@@ -488,22 +488,50 @@ __device__ __forceinline__ void group8_sum(double us[3]) {
 // cell: lane j pulls the populations of probe corner j and forms its
 // velocity; the trilinear sum is reduced over the eight lanes; lane 0 runs
 // the two Newton solves and writes u_wm, S_wm, sigma and the u_tau state.
+template <class CT>
+struct WallArgs {
+  const RotorTable* rot;
+  Geometry g;
+  Model m;
+  int64_t total;             // box slots
+  const void* src;           // state of the step (storage type)
+  const double* geo;         // [4][total] of the step's geometry
+  const int32_t* wlist;
+  const int32_t* wcount;
+  const double* ut_prev;
+  const uint8_t* act_prev;
+  double* ut_new;
+  uint8_t* act_new;
+  CT* wall_out;              // [10][total]
+  unsigned long long* stats; // Newton statistics (count_stats != 0)
+  const double* ghost;       // FP64 inflow plane of the step
+  double* jac;               // [count][40] (the Jacobian instantiation)
+  int32_t count_stats;
+};
+
+// Workgroup `blk` of `nblk` doing the wall model: a persistent loop over the
+// device-side wall-cell count.
 template <class ST, class CT, bool kPeriodicX, bool kJac>
-__global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp, Geometry g, Model m, int64_t total,
-                                              const ST* __restrict__ src, const double* __restrict__ geo,
-                                              const int32_t* __restrict__ wlist, const int32_t* __restrict__ wcount,
-                                              const double* __restrict__ ut_prev, const uint8_t* __restrict__ act_prev,
-                                              double* __restrict__ ut_new, uint8_t* __restrict__ act_new,
-                                              CT* __restrict__ wall_out, unsigned long long* __restrict__ stats,
-                                              const double* __restrict__ ghost, double* __restrict__ jac,
-                                              int count_stats) {
-  const RotorTable& rt = *rtp;
+__device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, uint32_t nblk) {
+  const RotorTable& rt = *a.rot;
+  const Geometry& g = a.g;
+  const Model& m = a.m;
+  const int64_t total = a.total;
+  const ST* __restrict__ src = static_cast<const ST*>(a.src);
+  const double* __restrict__ geo = a.geo;
+  const int32_t* __restrict__ wlist = a.wlist;
+  const double* __restrict__ ut_prev = a.ut_prev;
+  const uint8_t* __restrict__ act_prev = a.act_prev;
+  double* __restrict__ ut_new = a.ut_new;
+  uint8_t* __restrict__ act_new = a.act_new;
+  CT* __restrict__ wall_out = a.wall_out;
+  double* __restrict__ jac = a.jac;
   const int corner = threadIdx.x & 7;
-  const int count = *wcount;
+  const int count = *a.wcount;
   // each wave takes 8 consecutive list entries per iteration; the trip count
   // is uniform over the wave so that every lane takes part in the shuffles
-  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
+  const int64_t wave = (int64_t(blk) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t(nblk) * blockDim.x) >> 6;
   for (int64_t wb = wave * 8; wb < count; wb += nwaves * 8) {
     const int64_t w = wb + ((threadIdx.x & 63) >> 3);
     const bool live = w < count;
@@ -511,7 +539,7 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
     const RotorDev& R = rt.r[rotor_of_slot(rt, s)];
     const Probe pr = probe_of(R, g, m, geo, total, s, corner, kPeriodicX);
     double h[27];
-    pull_cell<ST, double, kPeriodicX>(src, g, pr.q[0], pr.q[1], pr.q[2], ghost, h);
+    pull_cell<ST, double, kPeriodicX>(src, g, pr.q[0], pr.q[1], pr.q[2], a.ghost, h);
     const Moments<double> mo = moments_of<double>(h);
     const double rho = 1.0 + mo.drho;
     double us[3] = {pr.wgt * (mo.jx / rho), pr.wgt * (mo.jy / rho), pr.wgt * (mo.jz / rho)};
@@ -548,7 +576,7 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
       }
     }
     // Newton statistics (diagnostics steps): one atomic per wave
-    if (count_stats) {
+    if (a.count_stats) {
       int a1 = it1, a2 = done;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
@@ -556,11 +584,16 @@ __global__ __launch_bounds__(256) void k_wall(const RotorTable* __restrict__ rtp
         a2 += __shfl_xor(a2, o, 64);
       }
       if ((threadIdx.x & 63) == 0 && a2) {
-        atomicAdd(&stats[0], (unsigned long long)a1);
-        atomicAdd(&stats[1], (unsigned long long)a2);
+        atomicAdd(&a.stats[0], (unsigned long long)a1);
+        atomicAdd(&a.stats[1], (unsigned long long)a2);
       }
     }
   }
+}
+
+template <class ST, class CT, bool kPeriodicX, bool kJac>
+__global__ __launch_bounds__(256) void k_wall(WallArgs<CT> a) {
+  wall_cells<ST, CT, kPeriodicX, kJac>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- geometry
@@ -599,14 +632,16 @@ struct GeoArgs {
   int64_t nzero;
 };
 
+// Workgroup `bid` of the geometry work: box slots first, then the extra
+// workgroups (inflow plane, adjoint chores).
 template <class CT>
-__global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
+__device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bid) {
   const Geometry& g = a.g;
   const Model& m = a.m;
   const uint32_t nbw = uint32_t((a.total + 255) / 256);
-  if (blockIdx.x >= nbw) {
+  if (bid >= nbw) {
     const int64_t plane = int64_t(g.ny) * g.nz;
-    int64_t b = int64_t(blockIdx.x) - nbw;
+    int64_t b = int64_t(bid) - nbw;
     if (b < a.ghost_blocks) {
       const int64_t k = b * 256 + threadIdx.x;
       if (k < plane) inflow_plane_cell<CT>(g, m, a.step, k, a.ghost, a.ghost64);
@@ -632,10 +667,10 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
   __shared__ int wl_count, wl_base;
   if (threadIdx.x == 0) {
     wl_count = 0;
-    if (blockIdx.x == 0) *a.wcount_next = 0;
+    if (bid == 0) *a.wcount_next = 0;
   }
   __syncthreads();
-  const int64_t s0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t s0 = int64_t(bid) * blockDim.x + threadIdx.x;
   const bool live = s0 < a.total;
   const int64_t s = live ? s0 : a.total - 1;
   const RotorTable& rt = *a.rot;
@@ -686,6 +721,21 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
   a.geo[a.total + s] = -gr[0] * inv;
   a.geo[2 * a.total + s] = -gr[1] * inv;
   a.geo[3 * a.total + s] = -gr[2] * inv;
+}
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
+  geometry_block<CT>(a, blockIdx.x);
+}
+
+// The wall model of one step (workgroups [0, wall_blocks)) and the geometry
+// of the next step (the remaining workgroups) in one launch: the two are
+// independent when the geometry writes the other buffer set, and both are
+// latency-bound chains that overlap well.
+template <class ST, class CT, bool kPeriodicX, bool kJac>
+__global__ __launch_bounds__(256) void k_wall_geometry(WallArgs<CT> w, GeoArgs<CT> ga, uint32_t wall_blocks) {
+  if (blockIdx.x < wall_blocks) wall_cells<ST, CT, kPeriodicX, kJac>(w, blockIdx.x, wall_blocks);
+  else geometry_block<CT>(ga, blockIdx.x - wall_blocks);
 }
 
 // ================================================================ fused sweep
@@ -1305,57 +1355,82 @@ static hipError_t by_compute(int compute, F&& f) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
-                           bool with_ghost, const AdjChores* chores) {
+// Arguments of the geometry launch of `step` and its workgroup count.
+template <class CT>
+static GeoArgs<CT> geo_args(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
+                            bool with_ghost, const AdjChores* chores, int64_t* blocks) {
   const int64_t nbw = L.nrot > 0 ? (L.bbox_total + 255) / 256 : 0;
   const int64_t plane = int64_t(L.g.ny) * L.g.nz;
   const int64_t nghost = (with_ghost && L.g.bc_x != 0) ? (plane + 255) / 256 : 0;
   const int64_t nfix = (chores && chores->lam && L.g.bc_x != 0) ? (plane + 255) / 256 : 0;
   const int64_t nzero = (chores && chores->zero) ? (chores->nzero + 255) / 256 : 0;
-  if (nbw + nghost + nfix + nzero == 0) return hipSuccess;
+  GeoArgs<CT> a{};
+  a.rot = L.rot; a.g = L.g; a.m = L.m; a.trig = trig; a.total = nbw > 0 ? L.bbox_total : 0;
+  a.d_static = (const CT*)L.d_static; a.tag_static = L.tag_static; a.dd = (const CT*)L.dd;
+  a.d_eff = (CT*)L.d_eff; a.tag = L.tag; a.geo = L.geo; a.act_new = act_new; a.wlist = L.wlist;
+  a.wcount = L.wcount + epoch % kCounters; a.wcount_next = L.wcount + (epoch + 1) % kCounters;
+  a.step = step; a.ghost = (CT*)L.ghost;
+  // the wall model samples in FP64: also fill the FP64 plane when it differs
+  a.ghost64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
+  a.ghost_blocks = int32_t(nghost);
+  if (nfix) {
+    a.fix_lam = (CT*)chores->lam; a.fix_side = (const CT*)chores->side; a.fix_lstride = chores->lstride;
+  }
+  a.fix_blocks = int32_t(nfix);
+  if (nzero) { a.zero = chores->zero; a.nzero = chores->nzero; }
+  *blocks = nbw + nghost + nfix + nzero;
+  return a;
+}
+
+hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
+                           bool with_ghost, const AdjChores* chores) {
   return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
-    GeoArgs<CT> a{};
-    a.rot = L.rot; a.g = L.g; a.m = L.m; a.trig = trig; a.total = nbw > 0 ? L.bbox_total : 0;
-    a.d_static = (const CT*)L.d_static; a.tag_static = L.tag_static; a.dd = (const CT*)L.dd;
-    a.d_eff = (CT*)L.d_eff; a.tag = L.tag; a.geo = L.geo; a.act_new = act_new; a.wlist = L.wlist;
-    a.wcount = L.wcount + (epoch & 1); a.wcount_next = L.wcount + ((epoch + 1) & 1);
-    a.step = step; a.ghost = (CT*)L.ghost;
-    // the wall model samples in FP64: also fill the FP64 plane when it differs
-    a.ghost64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
-    a.ghost_blocks = int32_t(nghost);
-    if (nfix) {
-      a.fix_lam = (CT*)chores->lam; a.fix_side = (const CT*)chores->side; a.fix_lstride = chores->lstride;
-    }
-    a.fix_blocks = int32_t(nfix);
-    if (nzero) { a.zero = chores->zero; a.nzero = chores->nzero; }
-    hipLaunchKernelGGL(k_geometry<CT>, dim3(unsigned(nbw + nghost + nfix + nzero)), dim3(256), 0, L.stream, a);
+    int64_t blocks = 0;
+    const GeoArgs<CT> a = geo_args<CT>(L, step, trig, epoch, act_new, with_ghost, chores, &blocks);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_geometry<CT>, dim3(unsigned(blocks)), dim3(256), 0, L.stream, a);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step, int epoch, double* jac, int count_stats) {
-  (void)step;
-  const int32_t* wcount = L.wcount + (epoch & 1);
-  if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
+                       double* ut_new, uint8_t* act_new, int epoch, double* jac, int count_stats,
+                       const NextGeometry* next) {
+  if (L.nrot == 0 || L.bbox_total == 0) {
+    if (!next) return hipSuccess;
+    return launch_geometry(*next->L, next->step, next->trig, next->epoch, next->act_new, next->with_ghost,
+                           next->chores);
+  }
   // persistent grid over the (device-side) wall-cell count, 32 cells per workgroup
-  int64_t blocks = (L.bbox_total + 31) / 32;
-  if (blocks > 1024) blocks = 1024;
+  int64_t wall_blocks = (L.bbox_total + 31) / 32;
+  if (wall_blocks > 1024) wall_blocks = 1024;
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
-    auto go = [&](auto kernel) {
-      hipLaunchKernelGGL(kernel, dim3(unsigned(blocks)), dim3(256), 0, L.stream, L.rot, L.g, L.m, L.bbox_total,
-                         (const ST*)src, L.geo, L.wlist, wcount, ut_prev, act_prev, ut_new, act_new, (CT*)L.wall_out,
-                         L.stats, L.ghost64, jac, count_stats);
+    WallArgs<CT> w{};
+    w.rot = L.rot; w.g = L.g; w.m = L.m; w.total = L.bbox_total; w.src = src; w.geo = L.geo; w.wlist = L.wlist;
+    w.wcount = L.wcount + epoch % kCounters; w.ut_prev = ut_prev; w.act_prev = act_prev; w.ut_new = ut_new;
+    w.act_new = act_new; w.wall_out = (CT*)L.wall_out; w.stats = L.stats; w.ghost = L.ghost64; w.jac = jac;
+    w.count_stats = count_stats;
+    int64_t geo_blocks = 0;
+    GeoArgs<CT> ga{};
+    if (next)
+      ga = geo_args<CT>(*next->L, next->step, next->trig, next->epoch, next->act_new, next->with_ghost, next->chores,
+                        &geo_blocks);
+    auto go = [&](auto wall_kernel, auto fused_kernel) {
+      if (geo_blocks == 0)
+        hipLaunchKernelGGL(wall_kernel, dim3(unsigned(wall_blocks)), dim3(256), 0, L.stream, w);
+      else
+        hipLaunchKernelGGL(fused_kernel, dim3(unsigned(wall_blocks + geo_blocks)), dim3(256), 0, L.stream, w, ga,
+                           uint32_t(wall_blocks));
     };
     if (L.g.bc_x == 0) {
-      if (jac) go(k_wall<ST, CT, true, true>);
-      else go(k_wall<ST, CT, true, false>);
+      if (jac) go(k_wall<ST, CT, true, true>, k_wall_geometry<ST, CT, true, true>);
+      else go(k_wall<ST, CT, true, false>, k_wall_geometry<ST, CT, true, false>);
     } else {
-      if (jac) go(k_wall<ST, CT, false, true>);
-      else go(k_wall<ST, CT, false, false>);
+      if (jac) go(k_wall<ST, CT, false, true>, k_wall_geometry<ST, CT, false, true>);
+      else go(k_wall<ST, CT, false, false>, k_wall_geometry<ST, CT, false, false>);
     }
     return hipGetLastError();
   });
@@ -1450,10 +1525,10 @@ hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A) {
     AdjArgs<CT> a = adj_args<CT>(L, A);
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_adj_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo, L.wlist,
-                         L.wcount + (A.epoch & 1), A.jac, A.ut_bar_in, A.ut_bar_out);
+                         L.wcount + A.epoch % kCounters, A.jac, A.ut_bar_in, A.ut_bar_out);
     else
       hipLaunchKernelGGL((k_adj_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo,
-                         L.wlist, L.wcount + (A.epoch & 1), A.jac, A.ut_bar_in, A.ut_bar_out);
+                         L.wlist, L.wcount + A.epoch % kCounters, A.jac, A.ut_bar_in, A.ut_bar_out);
     return hipGetLastError();
   });
 }

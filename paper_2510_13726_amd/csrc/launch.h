@@ -29,8 +29,11 @@ struct Launch {
   double* part_l1;           // [kPartL1][kPartial]
   double* mass_part;
   double* mass_l1;           // [kPartL1]
+  // d_eff, tag, geo and wlist point into the buffer set of the step being
+  // launched: the sets alternate by step so that the geometry of step n + 1
+  // can be written while step n reads its own
   int32_t* wlist;            // wall cells of the step (box slots)
-  int32_t* wcount;           // [2] wall-list counters, alternating by launch
+  int32_t* wcount;           // [kCounters] wall-list counters, in turn by launch
   int32_t* flag;
   unsigned long long* stats; // [0] Newton iterations, [1] wall cells
   RotorTable* rot;           // device copy
@@ -54,15 +57,35 @@ struct AdjChores {
   double* zero;
   int64_t nzero;
 };
+// Wall-list counters: a geometry launch of epoch e (0 <= e < kCounters)
+// counts into counter e and zeroes counter e + 1 (mod kCounters) for the
+// next launch.  Three of them let the geometry of one step run beside the
+// wall model of the previous one, which still reads its own counter.
+constexpr int kCounters = 3;
+
 // Rotor geometry of the step on the box slots and the wall-cell list
-// (counter `epoch & 1`; the other counter is zeroed for the next launch);
-// with_ghost: also the step's inflow plane; chores (nullable): see above.
+// (counter `epoch`); with_ghost: also the step's inflow plane; chores
+// (nullable): see above.
 hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
                            bool with_ghost, const AdjChores* chores = nullptr);
-// Wall model of the listed wall cells of `epoch` (jac: with Jacobians).
+// A geometry launch folded into a wall-model launch: the arguments of
+// launch_geometry, with L giving the buffer set and inflow plane it writes
+// (which the wall model must not read).
+struct NextGeometry {
+  const Launch* L;
+  int64_t step;
+  const BladeTrig* trig;
+  int epoch;
+  uint8_t* act_new;
+  bool with_ghost;
+  const AdjChores* chores;
+};
+// Wall model of the listed wall cells of `epoch` (jac: with Jacobians);
+// next (nullable): a geometry launch run by further workgroups of the same
+// launch.
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int64_t step, int epoch, double* jac = nullptr,
-                       int count_stats = 1);
+                       double* ut_new, uint8_t* act_new, int epoch, double* jac = nullptr, int count_stats = 1,
+                       const NextGeometry* next = nullptr);
 // Step sweep of every cell: pull, moments, collision (porosity, solid and
 // wall-model velocities in the FSI tiles), store, per-tag momentum partials.
 hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
