@@ -64,7 +64,7 @@ int64_t pop_stride_c(const hlbm_desc* d) {
 struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
       wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b, blist,
-      trig, lam0, lam1, utb0, utb1, ubar, side, jac, scr_ut, scr_act, scr_actb, total;
+      trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -121,7 +121,7 @@ Layout layout(const hlbm_desc* d) {
   L.utb1 = take(adj ? B * 8 : 0);
   L.ubar = take(adj ? 3 * N * 8 : 0);
   L.side = take(adj ? 9 * plane * cs : 0);
-  L.jac = take(adj ? B * 40 * 8 : 0);
+  L.sideb = take(adj ? 9 * plane * cs : 0);
   L.scr_ut = take(adj ? B * 8 : 0);
   L.scr_act = take(adj ? B : 0);
   L.scr_actb = take(adj ? B : 0);
@@ -734,9 +734,10 @@ bool probe_reaches_inlet(hlbm_handle h) {
 // step; given, the wall-model launch also computes the geometry of step
 // n + 1, which resets it.
 hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, const double* ut_prev,
-                       const uint8_t* act_prev, double* ut_new, uint8_t* act_new, uint8_t* act_ahead) {
+                       const uint8_t* act_prev, double* ut_new, uint8_t* act_new, uint8_t* act_ahead,
+                       bool record = true) {
   select_step(h, n);
-  const bool diag = h->params.diag_every > 0 && n % h->params.diag_every == 0;
+  const bool diag = record && h->params.diag_every > 0 && n % h->params.diag_every == 0;
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   // the inflow plane is written by the geometry launch, unless a wall-model
   // probe can reach the inlet: then it must be complete before the wall launch
@@ -759,7 +760,7 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
       const BladeTrig* trig1 = nullptr;
       e = trig_of(h, n + 1, &trig1);
       L1 = launch_of(h, n + 1);
-      ng = NextGeometry{&L1, n + 1, trig1, next_epoch(h), act_ahead, !inlet, nullptr};
+      ng = NextGeometry{&L1, n + 1, trig1, next_epoch(h), act_ahead, !inlet};
     }
     if (e == hipSuccess)
       e = timed(h, HLBM_KERNEL_WALL, [&] {
@@ -770,6 +771,11 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
       h->ahead_step = n + 1;
       h->ahead_epoch = ng.epoch;
     }
+  }
+  if (!record) {
+    // a recomputed step: its records exist, the partials go unreduced
+    if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, false); });
+    return e;
   }
   // force partials (and mass partials of a diagnostics step) into this step's slice
   if (e == hipSuccess && h->pending == h->batch) e = flush(h);
@@ -923,7 +929,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
   void* lam[2] = {ws + Y.lam0, ws + Y.lam1};
   double* utb[2] = {reinterpret_cast<double*>(ws + Y.utb0), reinterpret_cast<double*>(ws + Y.utb1)};
   double* ubar = reinterpret_cast<double*>(ws + Y.ubar);
-  double* jac = reinterpret_cast<double*>(ws + Y.jac);
+  void* side[2] = {ws + Y.side, ws + Y.sideb};
   double* scr_ut = reinterpret_cast<double*>(ws + Y.scr_ut);
   // activity written by the wall model of a reverse step, by step parity
   uint8_t* scr_act[2] = {reinterpret_cast<uint8_t*>(ws + Y.scr_act), reinterpret_cast<uint8_t*>(ws + Y.scr_actb)};
@@ -931,16 +937,17 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   const int cs = elem_size(h->desc.compute);
   const int64_t lam_bytes = 27 * pop_stride_c(&h->desc) * cs;
-  hipError_t e = hipMemsetAsync(lam[0], 0, lam_bytes, h->stream);
+  hipError_t e = flush(h);
+  if (e == hipSuccess) e = hipMemsetAsync(lam[0], 0, lam_bytes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(utb[0], 0, B * 8, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(utb[1], 0, B * 8, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(ubar, 0, 3 * N * 8, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(G, 0, N * 8, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint init");
   const int64_t nseg = (h->rec.nsteps + ce - 1) / ce;
   int cur = 0;
-  // the outflow fix-up of each reverse step's lam and the zeroing of the
-  // next u_tau adjoint run inside the following geometry or wall launch
-  bool fix_pending = false;
+  // the outflow share of lam (side) of the previous reverse step, if any
+  bool have_side = false;
   const double w = gJ / double(h->rec.t1 - h->rec.t0);
   char* st = static_cast<char*>(stack);
   h->ahead_step = -1;
@@ -956,78 +963,64 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       uint8_t* ahead = k + 2 < b ? reinterpret_cast<uint8_t*>(s1 + sl.bytes + sl.act) : scr_act[(h->rec.n0 + k + 1) & 1];
       e = forward_one(h, h->rec.n0 + k, s0, s1, reinterpret_cast<double*>(s0 + sl.ut),
                       reinterpret_cast<uint8_t*>(s0 + sl.act), reinterpret_cast<double*>(s1 + sl.ut),
-                      reinterpret_cast<uint8_t*>(s1 + sl.act), wall ? ahead : nullptr);
+                      reinterpret_cast<uint8_t*>(s1 + sl.act), wall ? ahead : nullptr, false);
     }
-    if (e == hipSuccess) e = flush(h);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint recompute");
     for (int64_t k = b - 1; k >= a; --k) {
       const int64_t n = h->rec.n0 + k;
       char* s0 = st + (k - a) * sl.bytes;
       const double* ut0 = reinterpret_cast<const double*>(s0 + sl.ut);
       const uint8_t* ac0 = reinterpret_cast<const uint8_t*>(s0 + sl.act);
-      // geometry, inflow and wall model of step n (with Jacobians)
-      select_step(h, n);
-      const bool inlet = probe_reaches_inlet(h);
-      if (inlet) e = launch_prologue(h->L, n);
-      AdjChores ch{};
-      ch.lam = fix_pending ? lam[cur] : nullptr;
-      ch.side = ws + Y.side;
-      ch.lstride = pop_stride_c(&h->desc);
-      ch.zero = utb[1 - cur];
-      ch.nzero = B;
-      bool chores_done = false;
-      int epoch = h->ahead_epoch;
-      if (h->ahead_step != n) {
-        const BladeTrig* trig = nullptr;
-        if (e == hipSuccess) e = trig_of(h, n, &trig);
-        epoch = next_epoch(h);
-        if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act[n & 1], !inlet, &ch);
-        chores_done = true;
-      }
-      h->ahead_step = -1;
-      // the wall launch also runs the geometry of step n - 1 when it is in
-      // this segment, and the chores if the geometry of step n did not
-      NextGeometry ng{};
-      Launch L1;
-      bool with_next = false;
-      if (e == hipSuccess && wall && k > a) {
-        const BladeTrig* trig1 = nullptr;
-        e = trig_of(h, n - 1, &trig1);
-        L1 = launch_of(h, n - 1);
-        ng = NextGeometry{&L1, n - 1, trig1, next_epoch(h), scr_act[(n - 1) & 1], !inlet, chores_done ? nullptr : &ch};
-        with_next = true;
-      } else if (!chores_done) {
-        L1 = h->L;
-        L1.nrot = 0;  // chores only: no box slots, no inflow plane
-        ng = NextGeometry{&L1, n, nullptr, 0, nullptr, false, &ch};
-        with_next = true;
-      }
-      if (e == hipSuccess && wall)
-        e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act[n & 1], epoch, jac, 0, with_next ? &ng : nullptr);
-      else if (e == hipSuccess && with_next)
-        e = launch_geometry(L1, ng.step, ng.trig, ng.epoch, ng.act_new, ng.with_ghost, ng.chores);
-      if (e == hipSuccess && wall && k > a) {
-        h->ahead_step = n - 1;
-        h->ahead_epoch = ng.epoch;
-      }
       AdjLaunch A{};
       A.src = s0;
       A.lam_in = lam[cur];
       A.lam_out = lam[1 - cur];
-      A.side = ws + Y.side;
+      A.side = side[cur];
+      A.side_in = have_side ? side[1 - cur] : nullptr;
       A.ubar = ubar;
       A.G = G;
-      A.jac = jac;
       A.ut_bar_in = utb[cur];
       A.ut_bar_out = utb[1 - cur];
       A.obj_w = (k >= h->rec.t0 && k < h->rec.t1) ? w : 0.0;
       A.obj_tag = h->rec.obj_tag;
       A.lstride = pop_stride_c(&h->desc);
-      A.epoch = epoch;
-      if (e == hipSuccess && wall) e = launch_adjoint_wall(h->L, A);
-      if (e == hipSuccess) e = launch_adjoint_sweep(h->L, A, false);
+      // the adjoint of u_tau read by this step is consumed: zero it for the
+      // writes of the next reverse step
+      A.zero = wall ? utb[cur] : nullptr;
+      A.nzero = B;
+      // geometry and inflow of step n (unless computed ahead), then the wall
+      // model with its adjoint, and the geometry of step n - 1 when it is in
+      // this segment
+      select_step(h, n);
+      const bool inlet = probe_reaches_inlet(h);
+      if (inlet) e = launch_prologue(h->L, n);
+      int epoch = h->ahead_epoch;
+      if (h->ahead_step != n) {
+        const BladeTrig* trig = nullptr;
+        if (e == hipSuccess) e = trig_of(h, n, &trig);
+        epoch = next_epoch(h);
+        if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act[n & 1], !inlet);
+      }
+      h->ahead_step = -1;
+      if (e == hipSuccess && wall) {
+        NextGeometry ng{};
+        Launch L1;
+        if (k > a) {
+          const BladeTrig* trig1 = nullptr;
+          e = trig_of(h, n - 1, &trig1);
+          L1 = launch_of(h, n - 1);
+          ng = NextGeometry{&L1, n - 1, trig1, next_epoch(h), scr_act[(n - 1) & 1], !inlet};
+        }
+        if (e == hipSuccess)
+          e = launch_wall(h->L, s0, ut0, ac0, scr_ut, scr_act[n & 1], epoch, &A, 0, k > a ? &ng : nullptr);
+        if (e == hipSuccess && k > a) {
+          h->ahead_step = n - 1;
+          h->ahead_epoch = ng.epoch;
+        }
+      }
+      if (e == hipSuccess) e = launch_adjoint_sweep(h->L, A);
       if (e != hipSuccess) return hip_fail(h, e, "adjoint step");
-      fix_pending = true;
+      have_side = h->L.g.bc_x != 0;
       cur = 1 - cur;
     }
   }

@@ -488,6 +488,21 @@ __device__ __forceinline__ void group8_sum(double us[3]) {
 // cell: lane j pulls the populations of probe corner j and forms its
 // velocity; the trilinear sum is reduced over the eight lanes; lane 0 runs
 // the two Newton solves and writes u_wm, S_wm, sigma and the u_tau state.
+// Adjoint of the torque objective with respect to the momentum exchange of
+// a cell of tag t: d(e . (r x dP)) / d dP = e x r, weighted by w.
+template <class CT>
+__device__ __forceinline__ void objective_dp(const RotorTable& rt, int t, int obj_tag, double w, int x, int y, int z,
+                                             CT pb[3]) {
+  pb[0] = pb[1] = pb[2] = CT(0);
+  if (w == 0.0 || t == 0 || (obj_tag != 0 && obj_tag != t)) return;
+  const double* fr = rt.frame[t];
+  const double rx = x - fr[0], ry = y - fr[1], rz = z - fr[2];
+  // d(e . (r x dP)) / d dP = e x r
+  pb[0] = CT(w * (fr[4] * rz - fr[5] * ry));
+  pb[1] = CT(w * (fr[5] * rx - fr[3] * rz));
+  pb[2] = CT(w * (fr[3] * ry - fr[4] * rx));
+}
+
 template <class CT>
 struct WallArgs {
   const RotorTable* rot;
@@ -505,13 +520,29 @@ struct WallArgs {
   CT* wall_out;              // [10][total]
   unsigned long long* stats; // Newton statistics (count_stats != 0)
   const double* ghost;       // FP64 inflow plane of the step
-  double* jac;               // [count][40] (the Jacobian instantiation)
   int32_t count_stats;
+  // adjoint instantiation only: the transposed wall-model Jacobian applied
+  // at each active wall cell (the adjoint wall step)
+  const CT* lam_in;          // adjoint of the state after the step, [27][lstride]
+  int64_t lstride;
+  const CT* side_in;         // outflow share of lam_in on the last x plane (nullable)
+  const CT* d_eff;
+  const uint8_t* tag;
+  const CT* ghost_ct;        // inflow plane in the compute type
+  const double* ut_bar_in;   // adjoint of the friction velocity written by the step
+  double* ut_bar_out;        // adjoint of the friction velocity read by the step
+  double* ubar;              // [3][N] probe-velocity adjoints, scattered atomically
+  double obj_w;              // weight of this step's torque in J
+  int32_t obj_tag;
 };
 
 // Workgroup `blk` of `nblk` doing the wall model: a persistent loop over the
-// device-side wall-cell count.
-template <class ST, class CT, bool kPeriodicX, bool kJac>
+// device-side wall-cell count.  kAdj: also the adjoint wall step of the
+// discrete adjoint: the wall model with its 10 x 4 Jacobian (dual numbers),
+// the collision VJP at the wall cell for the adjoint of (u_wm, S), the
+// transposed Jacobian giving the adjoints of the probe velocity (scattered to
+// the eight probe corners with the trilinear weights) and of u_tau^prev.
+template <class ST, class CT, bool kPeriodicX, bool kAdj>
 __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, uint32_t nblk) {
   const RotorTable& rt = *a.rot;
   const Geometry& g = a.g;
@@ -525,7 +556,6 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
   double* __restrict__ ut_new = a.ut_new;
   uint8_t* __restrict__ act_new = a.act_new;
   CT* __restrict__ wall_out = a.wall_out;
-  double* __restrict__ jac = a.jac;
   const int corner = threadIdx.x & 7;
   const int count = *a.wcount;
   // each wave takes 8 consecutive list entries per iteration; the trip count
@@ -545,21 +575,20 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
     double us[3] = {pr.wgt * (mo.jx / rho), pr.wgt * (mo.jy / rho), pr.wgt * (mo.jz / rho)};
     group8_sum(us);
     int it1 = 0, done = 0;
+    double usb[3] = {0.0, 0.0, 0.0};
     if (corner == 0 && live) {
       const int64_t T = total;
       bool active;
       double out[10];
-      if constexpr (kJac) {
+      D4 o4[kAdj ? 10 : 1];
+      if constexpr (kAdj) {
         // values and the 10 x 4 Jacobian with respect to (us, u_tau^prev)
-        D4 ud[3], o4[10];
-        for (int a = 0; a < 3; ++a) { ud[a] = mk(us[a]); ud[a].g[a] = 1.0; }
+        D4 ud[3];
+        for (int q = 0; q < 3; ++q) { ud[q] = mk(us[q]); ud[q].g[q] = 1.0; }
         D4 up = mk(ut_prev[s]);
         up.g[3] = 1.0;
         active = wall_solve<D4>(ud, pr.uw, pr.nn, pr.y1, up, act_prev[s] != 0, m, o4, it1);
-        for (int q = 0; q < 10; ++q) {
-          out[q] = o4[q].v;
-          for (int r = 0; r < 4; ++r) jac[w * 40 + q * 4 + r] = active ? o4[q].g[r] : 0.0;
-        }
+        for (int q = 0; q < 10; ++q) out[q] = o4[q].v;
       } else {
         active = wall_solve<double>(us, pr.uw, pr.nn, pr.y1, ut_prev[s], act_prev[s] != 0, m, out, it1);
       }
@@ -573,6 +602,58 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
         ut_new[s] = out[9];
         act_new[s] = 1;
         done = 1;
+      }
+      if constexpr (kAdj) {
+        if (active) {
+          const int x = pr.x, y = pr.y, z = pr.z;
+          const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+          CT hc[27];
+          pull_cell<ST, CT, kPeriodicX>(src, g, x, y, z, a.ghost_ct, hc);
+          const Moments<CT> mc = moments_of<CT>(hc);
+          // adjoint of the state after the step at this cell; on the last
+          // x plane lam_in also holds the outflow share of the c_x = -1 states
+          const bool fix = !kPeriodicX && a.side_in && x == g.nx - 1;
+          const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
+          CT gb[27];
+          for (int i = 0; i < 27; ++i) {
+            CT l = a.lam_in[int64_t(i) * a.lstride + c];
+            if (fix && i < 9) l += a.side_in[i * plane + k];
+            gb[i] = CT(w_of(i)) * l;
+          }
+          // the FSI inputs of the cell as the sweep of the step read them
+          const uint8_t tb = a.tag[c];
+          const CT d = a.d_eff[c];
+          const double rx = x - R.c[0], ry = y - R.c[1], rz = z - R.c[2];
+          const CT b[3] = {CT(R.omega * (R.e[1] * rz - R.e[2] * ry)) + CT(out[0]),
+                           CT(R.omega * (R.e[2] * rx - R.e[0] * rz)) + CT(out[1]),
+                           CT(R.omega * (R.e[0] * ry - R.e[1] * rx)) + CT(out[2])};
+          CT S[6];
+          for (int q = 0; q < 6; ++q) S[q] = CT(out[3 + q]);
+          CT pb[3];
+          objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
+          Moments<CT> mb;
+          CT db, bb[3], Sb[6];
+          collide_vjp<CT>(mc, d, b[0], b[1], b[2], CT(0), S, CT(m.tau0), CT(m.smag), gb, pb, mb, db, bb, Sb);
+          double ob[10];
+          for (int q = 0; q < 3; ++q) ob[q] = double(bb[q]);
+          for (int q = 0; q < 6; ++q) ob[3 + q] = double(Sb[q]);
+          ob[9] = a.ut_bar_in[s];
+          double ib[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int q = 0; q < 10; ++q)
+            for (int r = 0; r < 4; ++r) ib[r] += ob[q] * o4[q].g[r];
+          usb[0] = ib[0]; usb[1] = ib[1]; usb[2] = ib[2];
+          a.ut_bar_out[s] = ib[3];
+        }
+      }
+    }
+    if constexpr (kAdj) {
+      // broadcast the probe adjoint of the group's lane 0 and scatter per corner
+      const int lead = int(threadIdx.x & 63) & ~7;
+      double v[3];
+      for (int q = 0; q < 3; ++q) v[q] = __shfl(usb[q], lead, 64);
+      if (live && (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0)) {
+        const int64_t cc = (int64_t(pr.q[2]) * g.ny + pr.q[1]) * g.nx + pr.q[0];
+        for (int q = 0; q < 3; ++q) atomicAdd(&a.ubar[q * g.N + cc], pr.wgt * v[q]);
       }
     }
     // Newton statistics (diagnostics steps): one atomic per wave
@@ -591,9 +672,9 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
   }
 }
 
-template <class ST, class CT, bool kPeriodicX, bool kJac>
+template <class ST, class CT, bool kPeriodicX, bool kAdj>
 __global__ __launch_bounds__(256) void k_wall(WallArgs<CT> a) {
-  wall_cells<ST, CT, kPeriodicX, kJac>(a, blockIdx.x, gridDim.x);
+  wall_cells<ST, CT, kPeriodicX, kAdj>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- geometry
@@ -622,18 +703,10 @@ struct GeoArgs {
   CT* ghost;
   double* ghost64;
   int32_t ghost_blocks;
-  // adjoint bookkeeping done by further workgroups (nullable): the outflow
-  // fix-up of the previous reverse step's lam, and zeroing an FP64 buffer
-  CT* fix_lam;
-  const CT* fix_side;
-  int64_t fix_lstride;
-  int32_t fix_blocks;
-  double* zero;
-  int64_t nzero;
 };
 
 // Workgroup `bid` of the geometry work: box slots first, then the extra
-// workgroups (inflow plane, adjoint chores).
+// workgroups of the inflow plane.
 template <class CT>
 __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bid) {
   const Geometry& g = a.g;
@@ -641,27 +714,8 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
   const uint32_t nbw = uint32_t((a.total + 255) / 256);
   if (bid >= nbw) {
     const int64_t plane = int64_t(g.ny) * g.nz;
-    int64_t b = int64_t(bid) - nbw;
-    if (b < a.ghost_blocks) {
-      const int64_t k = b * 256 + threadIdx.x;
-      if (k < plane) inflow_plane_cell<CT>(g, m, a.step, k, a.ghost, a.ghost64);
-      return;
-    }
-    b -= a.ghost_blocks;
-    if (b < a.fix_blocks) {
-      // outflow: the state at (nx-1, y', z') for c_x = -1 feeds both
-      // (nx-2, .) and the clamped read of (nx-1, .): add the second share
-      const int64_t k = b * 256 + threadIdx.x;
-      if (k < plane) {
-        const int z = int(k / g.ny), y = int(k - int64_t(z) * g.ny);
-        const int64_t c = (int64_t(z) * g.ny + y) * g.nx + (g.nx - 1);
-        for (int i = 0; i < 9; ++i) a.fix_lam[int64_t(i) * a.fix_lstride + c] += a.fix_side[i * plane + k];
-      }
-      return;
-    }
-    b -= a.fix_blocks;
-    const int64_t k = b * 256 + threadIdx.x;
-    if (k < a.nzero) a.zero[k] = 0.0;
+    const int64_t k = (int64_t(bid) - nbw) * 256 + threadIdx.x;
+    if (k < plane) inflow_plane_cell<CT>(g, m, a.step, k, a.ghost, a.ghost64);
     return;
   }
   __shared__ int wl_count, wl_base;
@@ -732,9 +786,9 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
 // of the next step (the remaining workgroups) in one launch: the two are
 // independent when the geometry writes the other buffer set, and both are
 // latency-bound chains that overlap well.
-template <class ST, class CT, bool kPeriodicX, bool kJac>
+template <class ST, class CT, bool kPeriodicX, bool kAdj>
 __global__ __launch_bounds__(256) void k_wall_geometry(WallArgs<CT> w, GeoArgs<CT> ga, uint32_t wall_blocks) {
-  if (blockIdx.x < wall_blocks) wall_cells<ST, CT, kPeriodicX, kJac>(w, blockIdx.x, wall_blocks);
+  if (blockIdx.x < wall_blocks) wall_cells<ST, CT, kPeriodicX, kAdj>(w, blockIdx.x, wall_blocks);
   else geometry_block<CT>(ga, blockIdx.x - wall_blocks);
 }
 
@@ -1102,7 +1156,8 @@ struct AdjArgs {
   const void* src;          // state at step n (storage type)
   const CT* lam_in;         // adjoint of the state after step n, [27][stride]
   CT* lam_out;              // adjoint of the state at step n, [27][stride]
-  CT* side;                 // outflow side buffer [9][nz][ny]
+  CT* side;                 // outflow side buffer of this step [9][nz][ny]
+  const CT* side_in;        // that of the next step, nullable: see k_adj_sweep
   int64_t lstride;          // elements between the 27 arrays of lam
   Geometry g;
   Model m;
@@ -1119,20 +1174,9 @@ struct AdjArgs {
   double obj_w;             // weight of this step's torque in J (0 outside the window)
   int32_t obj_tag;
   int64_t nblocks;
+  double* zero;             // zeroed by the workgroups past nblocks
+  int64_t nzero;
 };
-
-template <class CT>
-__device__ __forceinline__ void objective_dp(const RotorTable& rt, int t, int obj_tag, double w, int x, int y, int z,
-                                             CT pb[3]) {
-  pb[0] = pb[1] = pb[2] = CT(0);
-  if (w == 0.0 || t == 0 || (obj_tag != 0 && obj_tag != t)) return;
-  const double* fr = rt.frame[t];
-  const double rx = x - fr[0], ry = y - fr[1], rz = z - fr[2];
-  // d(e . (r x dP)) / d dP = e x r
-  pb[0] = CT(w * (fr[4] * rz - fr[5] * ry));
-  pb[1] = CT(w * (fr[5] * rx - fr[3] * rz));
-  pb[2] = CT(w * (fr[3] * ry - fr[4] * rx));
-}
 
 // Homogenization inputs of an FSI cell: porosity, b = u^B + u_wm, S, sigma.
 template <class CT>
@@ -1165,11 +1209,20 @@ __device__ __forceinline__ void fsi_inputs(const AdjArgs<CT>& a, const RotorTabl
 
 // Adjoint sweep over all cells: collision VJP from the local adjoint of the
 // next state, the probe-velocity adjoints gathered from the wall cells, and
-// the transpose of the pull (lam_out_i(x - c_i) = mu_i(x)).
+// the transpose of the pull (lam_out_i(x - c_i) = mu_i(x)).  Outflow: the
+// state at (nx-1, y', z') with c_x = -1 is read by (nx-2, .) and by the
+// clamped read of (nx-1, .); the second share goes to `side`, and the reader
+// of lam (this sweep of the previous step, and the adjoint wall step) adds
+// it on the last plane.  Workgroups past nblocks zero `zero`.
 template <class ST, class CT, bool kPeriodicX>
 __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const Geometry& g = a.g;
   const int64_t blk = blockIdx.x;
+  if (blk >= a.nblocks) {
+    const int64_t k = (blk - a.nblocks) * kBlock + threadIdx.x;
+    if (k < a.nzero) a.zero[k] = 0.0;
+    return;
+  }
   // tile ids and counts fit 32 bits (fewer than 2^31 cells, 256 per tile)
   const uint32_t tpz = uint32_t(g.ntx) * uint32_t(g.nty);
   const int z = int(uint32_t(blk) / tpz);
@@ -1186,7 +1239,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const uint32_t o4 = uint32_t(c) * uint32_t(sizeof(CT));
   CT gb[27];
 #pragma unroll
-  for (int i = 0; i < 27; ++i) gb[i] = CT(w_of(i)) * *at_bytes(a.lam_in + int64_t(i) * a.lstride, o4);
+  for (int i = 0; i < 27; ++i) gb[i] = *at_bytes(a.lam_in + int64_t(i) * a.lstride, o4);
+  if (!kPeriodicX && a.side_in && x == g.nx - 1) {
+    const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
+    for (int i = 0; i < 9; ++i) gb[i] += a.side_in[i * plane + k];
+  }
+#pragma unroll
+  for (int i = 0; i < 27; ++i) gb[i] *= CT(w_of(i));
   const RotorTable& rt = *a.rot;
   CT d = CT(0), b[3] = {CT(0), CT(0), CT(0)}, S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)}, sigma = CT(1);
   CT pb[3] = {CT(0), CT(0), CT(0)};
@@ -1265,77 +1324,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   }
 }
 
-// Outflow: the state at (nx-1, y', z') for c_x = -1 feeds both (nx-2, .) and
-// the clamped read of (nx-1, .); add the second reader's share.
-template <class CT>
-__global__ __launch_bounds__(256) void k_adj_fixup(Geometry g, int64_t lstride, const CT* __restrict__ side,
-                                                   CT* __restrict__ lam) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t plane = int64_t(g.ny) * g.nz;
-  if (k >= plane) return;
-  const int z = int(k / g.ny), y = int(k - int64_t(z) * g.ny);
-  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + (g.nx - 1);
-  for (int i = 0; i < 9; ++i) lam[int64_t(i) * lstride + c] += side[i * plane + k];
-}
-
-// Wall cells: collision VJP for the adjoints of u_wm and S, then the
-// transposed wall-model Jacobian: probe-velocity adjoint scattered to the
-// eight corners (FP64 atomics) and the adjoint of the previous u_tau.
-template <class ST, class CT, bool kPeriodicX>
-__global__ __launch_bounds__(256) void k_adj_wall(AdjArgs<CT> a, const double* __restrict__ geo,
-                                                  const int32_t* __restrict__ wlist, const int32_t* __restrict__ wcount,
-                                                  const double* __restrict__ jac, const double* __restrict__ ut_bar_in,
-                                                  double* __restrict__ ut_bar_out) {
-  const Geometry& g = a.g;
-  const RotorTable& rt = *a.rot;
-  const int corner = threadIdx.x & 7;
-  const int count = *wcount;
-  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
-  const int64_t T = a.bbox_total;
-  for (int64_t wb = wave * 8; wb < count; wb += nwaves * 8) {
-    const int64_t w = wb + ((threadIdx.x & 63) >> 3);
-    const bool live = w < count;
-    const int64_t s = wlist[live ? w : wb];
-    const RotorDev& R = rt.r[rotor_of_slot(rt, s)];
-    const Probe pr = probe_of(R, g, a.m, geo, T, s, corner, kPeriodicX);
-    double us_b[3] = {0.0, 0.0, 0.0};
-    if (corner == 0 && live && a.wall_out[9 * T + s] == CT(0)) {
-      const int x = pr.x, y = pr.y, z = pr.z;
-      const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
-      CT h[27];
-      pull_cell<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
-      const Moments<CT> mo = moments_of<CT>(h);
-      CT gb[27];
-      for (int i = 0; i < 27; ++i) gb[i] = CT(w_of(i)) * a.lam_in[int64_t(i) * a.lstride + c];
-      const uint8_t tb = a.tag[c];
-      CT d, b[3], S[6], sigma, pb[3];
-      fsi_inputs(a, rt, c, x, y, z, tb, d, b, S, sigma);
-      objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
-      Moments<CT> mb;
-      CT db, bb[3], Sb[6];
-      collide_vjp<CT>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
-      double ob[10];
-      for (int q = 0; q < 3; ++q) ob[q] = double(bb[q]);
-      for (int q = 0; q < 6; ++q) ob[3 + q] = double(Sb[q]);
-      ob[9] = ut_bar_in[s];
-      double ib[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int q = 0; q < 10; ++q)
-        for (int r = 0; r < 4; ++r) ib[r] += ob[q] * jac[w * 40 + q * 4 + r];
-      us_b[0] = ib[0]; us_b[1] = ib[1]; us_b[2] = ib[2];
-      ut_bar_out[s] = ib[3];
-    }
-    // broadcast the probe adjoint of the group's lane 0 and scatter per corner
-    const int lead = int(threadIdx.x & 63) & ~7;
-    double v[3];
-    for (int q = 0; q < 3; ++q) v[q] = __shfl(us_b[q], lead, 64);
-    if (live && (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0)) {
-      const int64_t cc = (int64_t(pr.q[2]) * g.ny + pr.q[1]) * g.nx + pr.q[0];
-      for (int q = 0; q < 3; ++q) atomicAdd(&a.ubar[q * g.N + cc], pr.wgt * v[q]);
-    }
-  }
-}
-
 // ================================================================ launchers
 static inline dim3 grid1(int64_t n, int b) { return dim3(unsigned((n + b - 1) / b)); }
 
@@ -1358,12 +1346,10 @@ static hipError_t by_compute(int compute, F&& f) {
 // Arguments of the geometry launch of `step` and its workgroup count.
 template <class CT>
 static GeoArgs<CT> geo_args(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
-                            bool with_ghost, const AdjChores* chores, int64_t* blocks) {
+                            bool with_ghost, int64_t* blocks) {
   const int64_t nbw = L.nrot > 0 ? (L.bbox_total + 255) / 256 : 0;
   const int64_t plane = int64_t(L.g.ny) * L.g.nz;
   const int64_t nghost = (with_ghost && L.g.bc_x != 0) ? (plane + 255) / 256 : 0;
-  const int64_t nfix = (chores && chores->lam && L.g.bc_x != 0) ? (plane + 255) / 256 : 0;
-  const int64_t nzero = (chores && chores->zero) ? (chores->nzero + 255) / 256 : 0;
   GeoArgs<CT> a{};
   a.rot = L.rot; a.g = L.g; a.m = L.m; a.trig = trig; a.total = nbw > 0 ? L.bbox_total : 0;
   a.d_static = (const CT*)L.d_static; a.tag_static = L.tag_static; a.dd = (const CT*)L.dd;
@@ -1373,21 +1359,16 @@ static GeoArgs<CT> geo_args(const Launch& L, int64_t step, const BladeTrig* trig
   // the wall model samples in FP64: also fill the FP64 plane when it differs
   a.ghost64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
   a.ghost_blocks = int32_t(nghost);
-  if (nfix) {
-    a.fix_lam = (CT*)chores->lam; a.fix_side = (const CT*)chores->side; a.fix_lstride = chores->lstride;
-  }
-  a.fix_blocks = int32_t(nfix);
-  if (nzero) { a.zero = chores->zero; a.nzero = chores->nzero; }
-  *blocks = nbw + nghost + nfix + nzero;
+  *blocks = nbw + nghost;
   return a;
 }
 
 hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
-                           bool with_ghost, const AdjChores* chores) {
+                           bool with_ghost) {
   return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
     int64_t blocks = 0;
-    const GeoArgs<CT> a = geo_args<CT>(L, step, trig, epoch, act_new, with_ghost, chores, &blocks);
+    const GeoArgs<CT> a = geo_args<CT>(L, step, trig, epoch, act_new, with_ghost, &blocks);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_geometry<CT>, dim3(unsigned(blocks)), dim3(256), 0, L.stream, a);
     return hipGetLastError();
@@ -1395,12 +1376,11 @@ hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig,
 }
 
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int epoch, double* jac, int count_stats,
+                       double* ut_new, uint8_t* act_new, int epoch, const AdjLaunch* adj, int count_stats,
                        const NextGeometry* next) {
   if (L.nrot == 0 || L.bbox_total == 0) {
     if (!next) return hipSuccess;
-    return launch_geometry(*next->L, next->step, next->trig, next->epoch, next->act_new, next->with_ghost,
-                           next->chores);
+    return launch_geometry(*next->L, next->step, next->trig, next->epoch, next->act_new, next->with_ghost);
   }
   // persistent grid over the (device-side) wall-cell count, 32 cells per workgroup
   int64_t wall_blocks = (L.bbox_total + 31) / 32;
@@ -1411,13 +1391,18 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
     WallArgs<CT> w{};
     w.rot = L.rot; w.g = L.g; w.m = L.m; w.total = L.bbox_total; w.src = src; w.geo = L.geo; w.wlist = L.wlist;
     w.wcount = L.wcount + epoch % kCounters; w.ut_prev = ut_prev; w.act_prev = act_prev; w.ut_new = ut_new;
-    w.act_new = act_new; w.wall_out = (CT*)L.wall_out; w.stats = L.stats; w.ghost = L.ghost64; w.jac = jac;
+    w.act_new = act_new; w.wall_out = (CT*)L.wall_out; w.stats = L.stats; w.ghost = L.ghost64;
     w.count_stats = count_stats;
+    if (adj) {
+      w.lam_in = (const CT*)adj->lam_in; w.lstride = adj->lstride; w.side_in = (const CT*)adj->side_in;
+      w.d_eff = (const CT*)L.d_eff; w.tag = L.tag; w.ghost_ct = (const CT*)L.ghost;
+      w.ut_bar_in = adj->ut_bar_in; w.ut_bar_out = adj->ut_bar_out; w.ubar = adj->ubar;
+      w.obj_w = adj->obj_w; w.obj_tag = adj->obj_tag;
+    }
     int64_t geo_blocks = 0;
     GeoArgs<CT> ga{};
     if (next)
-      ga = geo_args<CT>(*next->L, next->step, next->trig, next->epoch, next->act_new, next->with_ghost, next->chores,
-                        &geo_blocks);
+      ga = geo_args<CT>(*next->L, next->step, next->trig, next->epoch, next->act_new, next->with_ghost, &geo_blocks);
     auto go = [&](auto wall_kernel, auto fused_kernel) {
       if (geo_blocks == 0)
         hipLaunchKernelGGL(wall_kernel, dim3(unsigned(wall_blocks)), dim3(256), 0, L.stream, w);
@@ -1426,10 +1411,10 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
                            uint32_t(wall_blocks));
     };
     if (L.g.bc_x == 0) {
-      if (jac) go(k_wall<ST, CT, true, true>, k_wall_geometry<ST, CT, true, true>);
+      if (adj) go(k_wall<ST, CT, true, true>, k_wall_geometry<ST, CT, true, true>);
       else go(k_wall<ST, CT, true, false>, k_wall_geometry<ST, CT, true, false>);
     } else {
-      if (jac) go(k_wall<ST, CT, false, true>, k_wall_geometry<ST, CT, false, true>);
+      if (adj) go(k_wall<ST, CT, false, true>, k_wall_geometry<ST, CT, false, true>);
       else go(k_wall<ST, CT, false, false>, k_wall_geometry<ST, CT, false, false>);
     }
     return hipGetLastError();
@@ -1507,47 +1492,24 @@ template <class CT>
 static AdjArgs<CT> adj_args(const Launch& L, const AdjLaunch& A) {
   AdjArgs<CT> a{};
   a.src = A.src; a.lam_in = (const CT*)A.lam_in; a.lam_out = (CT*)A.lam_out; a.side = (CT*)A.side;
-  a.lstride = A.lstride;
+  a.side_in = (const CT*)A.side_in; a.lstride = A.lstride;
   a.g = L.g; a.m = L.m; a.blk_slot = L.blk_slot; a.d_eff = (const CT*)L.d_eff; a.tag = L.tag;
   a.wall_out = (const CT*)L.wall_out; a.bbox_total = L.bbox_total; a.rot = L.rot;
   a.uB_static = (const CT*)L.uB_static; a.ghost = (const CT*)L.ghost; a.ubar = A.ubar; a.G = A.G;
   a.obj_w = A.obj_w; a.obj_tag = A.obj_tag; a.nblocks = L.nblocks;
+  a.zero = A.zero; a.nzero = A.zero ? A.nzero : 0;
   return a;
 }
 
-hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A) {
-  if (L.nrot == 0 || L.bbox_total == 0) return hipSuccess;
-  int64_t blocks = (L.bbox_total + 31) / 32;
-  if (blocks > 1024) blocks = 1024;
+hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A) {
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
     AdjArgs<CT> a = adj_args<CT>(L, A);
-    if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_adj_wall<ST, CT, true>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo, L.wlist,
-                         L.wcount + A.epoch % kCounters, A.jac, A.ut_bar_in, A.ut_bar_out);
-    else
-      hipLaunchKernelGGL((k_adj_wall<ST, CT, false>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a, L.geo,
-                         L.wlist, L.wcount + A.epoch % kCounters, A.jac, A.ut_bar_in, A.ut_bar_out);
-    return hipGetLastError();
-  });
-}
-
-hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A, bool fixup) {
-  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
-    using ST = std::remove_pointer_t<decltype(st)>;
-    using CT = std::remove_pointer_t<decltype(ct)>;
-    AdjArgs<CT> a = adj_args<CT>(L, A);
-    if (L.g.bc_x == 0) {
-      hipLaunchKernelGGL((k_adj_sweep<ST, CT, true>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
-      return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_adj_sweep<ST, CT, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !fixup) return e;
-    const int64_t plane = int64_t(L.g.ny) * L.g.nz;
-    hipLaunchKernelGGL(k_adj_fixup<CT>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, A.lstride,
-                       (const CT*)A.side, (CT*)A.lam_out);
+    const int64_t nzb = A.zero ? (A.nzero + kBlock - 1) / kBlock : 0;
+    const dim3 grid(unsigned(L.nblocks + nzb));
+    if (L.g.bc_x == 0) hipLaunchKernelGGL((k_adj_sweep<ST, CT, true>), grid, dim3(kBlock), 0, L.stream, a);
+    else hipLaunchKernelGGL((k_adj_sweep<ST, CT, false>), grid, dim3(kBlock), 0, L.stream, a);
     return hipGetLastError();
   });
 }

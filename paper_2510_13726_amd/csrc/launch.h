@@ -47,16 +47,6 @@ struct Launch {
   double* ghost64;           // same in FP64 for the wall model
 };
 
-// Adjoint bookkeeping folded into the geometry launch of a reverse step:
-// the outflow fix-up of the previous reverse step's lam (lam += side on the
-// last x plane, skipped when lam is null) and zeroing nzero doubles.
-struct AdjChores {
-  void* lam;
-  const void* side;
-  int64_t lstride;
-  double* zero;
-  int64_t nzero;
-};
 // Wall-list counters: a geometry launch of epoch e (0 <= e < kCounters)
 // counts into counter e and zeroes counter e + 1 (mod kCounters) for the
 // next launch.  Three of them let the geometry of one step run beside the
@@ -64,10 +54,9 @@ struct AdjChores {
 constexpr int kCounters = 3;
 
 // Rotor geometry of the step on the box slots and the wall-cell list
-// (counter `epoch`); with_ghost: also the step's inflow plane; chores
-// (nullable): see above.
+// (counter `epoch`); with_ghost: also the step's inflow plane.
 hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig, int epoch, uint8_t* act_new,
-                           bool with_ghost, const AdjChores* chores = nullptr);
+                           bool with_ghost);
 // A geometry launch folded into a wall-model launch: the arguments of
 // launch_geometry, with L giving the buffer set and inflow plane it writes
 // (which the wall model must not read).
@@ -78,14 +67,14 @@ struct NextGeometry {
   int epoch;
   uint8_t* act_new;
   bool with_ghost;
-  const AdjChores* chores;
 };
-// Wall model of the listed wall cells of `epoch` (jac: with Jacobians);
-// next (nullable): a geometry launch run by further workgroups of the same
-// launch.
+struct AdjLaunch;
+// Wall model of the listed wall cells of `epoch`; adj (nullable): also the
+// adjoint wall step of a reverse step; next (nullable): a geometry launch run
+// by further workgroups of the same launch.
 hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, const uint8_t* act_prev,
-                       double* ut_new, uint8_t* act_new, int epoch, double* jac = nullptr, int count_stats = 1,
-                       const NextGeometry* next = nullptr);
+                       double* ut_new, uint8_t* act_new, int epoch, const AdjLaunch* adj = nullptr,
+                       int count_stats = 1, const NextGeometry* next = nullptr);
 // Step sweep of every cell: pull, moments, collision (porosity, solid and
 // wall-model velocities in the FSI tiles), store, per-tag momentum partials.
 hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
@@ -108,20 +97,20 @@ struct AdjLaunch {
   const void* src;          // state at the step (storage type)
   const void* lam_in;       // adjoint of the next state (compute type)
   void* lam_out;            // adjoint of this state
-  void* side;               // outflow side buffer [9][nz][ny]
+  void* side;               // outflow side buffer of this step [9][nz][ny]
+  const void* side_in;      // that of the next step (added to lam_in on the last plane); nullable
   int64_t lstride;          // elements between the 27 arrays of lam
   double* ubar;             // [3][N] FP64, zero on entry of the sweep except wall scatter
   double* G;                // [N] FP64 gradient accumulator
-  const double* jac;        // wall Jacobians of the listed wall cells [count][40]
   const double* ut_bar_in;  // adjoint of the friction velocity written by the step
   double* ut_bar_out;       // adjoint of the friction velocity read by the step
   double obj_w;
   int32_t obj_tag;
-  int32_t epoch;            // wall-list counter of the step's geometry launch
+  double* zero;             // zeroed by the adjoint sweep (nullable), nzero doubles
+  int64_t nzero;
 };
-hipError_t launch_adjoint_wall(const Launch& L, const AdjLaunch& A);
-// fixup: apply the outflow fix-up now (else a later geometry launch does).
-hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A, bool fixup);
+// The adjoint wall step runs inside launch_wall (adj); then this sweep.
+hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A);
 hipError_t launch_refill_porosity(const Launch& L);
 hipError_t launch_fill_rest(const Launch& L, void* dst);
 
