@@ -319,9 +319,29 @@ __device__ __forceinline__ D4 sqrt(D4 a) { D4 r; r.v = ::sqrt(a.v); for (int q =
 __device__ __forceinline__ D4 exp(D4 a) { D4 r; r.v = ::exp(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] * r.v; return r; }
 __device__ __forceinline__ D4 log(D4 a) { D4 r; r.v = ::log(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] / a.v; return r; }
 __device__ __forceinline__ double val(D4 a) { return a.v; }
+__device__ __forceinline__ D4 rcp_nr(D4 a) { return 1.0 / a; }
+__device__ __forceinline__ D4 div_nr(D4 a, D4 b) { return a / b; }
 }  // namespace dual
 using dual::D4;
 using dual::mk;
+// FP64 reciprocal and quotient for the positive or negative, normal operands
+// of the wall law (no zeros, infinities or denormals): the hardware
+// reciprocal estimate refined by two Newton-Raphson steps for 1/x,
+// r <- r + r (1 - x r), each of which squares the relative error; the
+// quotient q = a r then gets one residual correction q <- q + r (a - b q).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double div_nr(double a, double b) {
+  const double r = rcp_nr(b);
+  const double q = a * r;
+  return fma(r, fma(-b, q, a), q);
+}
+using dual::rcp_nr;
+using dual::div_nr;
 __device__ __forceinline__ double val(double a) { return a; }
 using dual::val;
 template <class R> __device__ __forceinline__ R cst(double v);
@@ -349,7 +369,7 @@ __device__ __forceinline__ R newton(R u, F&& fdf, double tol, int maxit, int& it
   fdf(u, fu, du);
   int it = 0;
   for (; it < maxit; ++it) {
-    R un = u - fu / du;
+    R un = u - div_nr(fu, du);
     if (val(un) <= 0.0) un = 0.5 * u;
     R fn, dn;
     fdf(un, fn, dn);
@@ -392,7 +412,7 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   const R ut = newton(
       guess,
       [&](R u, R& f, R& df) {
-        const R iu = 1.0 / u;
+        const R iu = rcp_nr(u);
         const R p = U * iu;
         const R k = kap * p;
         const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
@@ -432,8 +452,8 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   return true;
 }
 
-// Probe corner `corner` (0..7) of wall slot s: its cell and trilinear weight,
-// the cell position and the foot-point wall velocity.
+// Probe corner `corner` (0..7) of wall slot s at list position w: its cell
+// and trilinear weight, the cell position and the foot-point wall velocity.
 struct Probe {
   int x, y, z;        // wall cell
   int q[3];           // this lane's corner cell
@@ -441,12 +461,12 @@ struct Probe {
   double y1, nn[3], uw[3];
 };
 __device__ __forceinline__ Probe probe_of(const RotorDev& R, const Geometry& g, const Model& m,
-                                          const double* __restrict__ geo, int64_t total, int64_t s, int corner,
-                                          bool periodic_x) {
+                                          const double* __restrict__ geo, int64_t total, int64_t s, int64_t w,
+                                          int corner, bool periodic_x) {
   Probe p;
   slot_cell(R, s, p.x, p.y, p.z);
-  p.y1 = -geo[s];
-  p.nn[0] = geo[total + s]; p.nn[1] = geo[2 * total + s]; p.nn[2] = geo[3 * total + s];
+  p.y1 = -geo[w];
+  p.nn[0] = geo[total + w]; p.nn[1] = geo[2 * total + w]; p.nn[2] = geo[3 * total + w];
   const double X[3] = {double(p.x), double(p.y), double(p.z)};
   double xw[3], xs[3];
   for (int a = 0; a < 3; ++a) {
@@ -562,12 +582,22 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
   // is uniform over the wave so that every lane takes part in the shuffles
   const int64_t wave = (int64_t(blk) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (int64_t(nblk) * blockDim.x) >> 6;
+  const int64_t lw = (threadIdx.x & 63) >> 3;
+  // the first entry is read before the count arrives: the list holds total
+  // entries, so the clamped read is in bounds, and lanes past the count only
+  // compute on a valid (stale) entry whose results are dropped
+  const int64_t w0 = wave * 8 + lw < total ? wave * 8 + lw : total - 1;
+  const int32_t s0 = min(wlist[w0], int32_t(total - 1));
   for (int64_t wb = wave * 8; wb < count; wb += nwaves * 8) {
-    const int64_t w = wb + ((threadIdx.x & 63) >> 3);
+    const int64_t w = wb + lw;
     const bool live = w < count;
-    const int64_t s = wlist[live ? w : wb];
+    const int64_t wr = wb == wave * 8 ? w0 : (live ? w : wb);
+    const int64_t s = wb == wave * 8 ? s0 : wlist[wr];
+    // state of the previous step, loaded early (used by the Newton guess)
+    const double utp = ut_prev[s];
+    const bool actp = act_prev[s] != 0;
     const RotorDev& R = rt.r[rotor_of_slot(rt, s)];
-    const Probe pr = probe_of(R, g, m, geo, total, s, corner, kPeriodicX);
+    const Probe pr = probe_of(R, g, m, geo, total, s, wr, corner, kPeriodicX);
     double h[27];
     pull_cell<ST, double, kPeriodicX>(src, g, pr.q[0], pr.q[1], pr.q[2], a.ghost, h);
     const Moments<double> mo = moments_of<double>(h);
@@ -585,12 +615,12 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
         // values and the 10 x 4 Jacobian with respect to (us, u_tau^prev)
         D4 ud[3];
         for (int q = 0; q < 3; ++q) { ud[q] = mk(us[q]); ud[q].g[q] = 1.0; }
-        D4 up = mk(ut_prev[s]);
+        D4 up = mk(utp);
         up.g[3] = 1.0;
-        active = wall_solve<D4>(ud, pr.uw, pr.nn, pr.y1, up, act_prev[s] != 0, m, o4, it1);
+        active = wall_solve<D4>(ud, pr.uw, pr.nn, pr.y1, up, actp, m, o4, it1);
         for (int q = 0; q < 10; ++q) out[q] = o4[q].v;
       } else {
-        active = wall_solve<double>(us, pr.uw, pr.nn, pr.y1, ut_prev[s], act_prev[s] != 0, m, out, it1);
+        active = wall_solve<double>(us, pr.uw, pr.nn, pr.y1, utp, actp, m, out, it1);
       }
       if (!active) {
         for (int q = 0; q < 9; ++q) wall_out[q * T + s] = CT(0);
@@ -694,7 +724,7 @@ struct GeoArgs {
   const CT* dd;              // nullable
   CT* d_eff;
   uint8_t* tag;
-  double* geo;               // [4][total]: phi, n
+  double* geo;               // [4][total]: phi, n of the listed wall cells, by list position
   uint8_t* act_new;          // wall-state slots, reset to inactive
   int32_t* wlist;
   int32_t* wcount;           // this launch's counter (zero on entry)
@@ -768,13 +798,16 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
   __syncthreads();
   if (threadIdx.x == 0) wl_base = wl_count ? atomicAdd(a.wcount, wl_count) : 0;
   __syncthreads();
-  if (mine) a.wlist[wl_base + rank] = int32_t(s);
-  if (!live) return;
-  const double inv = gn > 0 ? 1.0 / gn : 0.0;
-  a.geo[s] = best;
-  a.geo[a.total + s] = -gr[0] * inv;
-  a.geo[2 * a.total + s] = -gr[1] * inv;
-  a.geo[3 * a.total + s] = -gr[2] * inv;
+  if (!mine) return;
+  // the wall cell's distance and normal beside its list entry, so that the
+  // wall model reads both with one dependent load
+  const int64_t pos = wl_base + rank;
+  const double inv = 1.0 / gn;
+  a.wlist[pos] = int32_t(s);
+  a.geo[pos] = best;
+  a.geo[a.total + pos] = -gr[0] * inv;
+  a.geo[2 * a.total + pos] = -gr[1] * inv;
+  a.geo[3 * a.total + pos] = -gr[2] * inv;
 }
 
 template <class CT>
