@@ -152,6 +152,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 struct RotorPhi {
   double phi;
   int piece;
+  double sb, cb;  // sin and cos of the winning blade's pitch at the point
 };
 
 // Blade b in its own frame: radial r, tangential q, axial a of the point;
@@ -169,15 +170,18 @@ __device__ __forceinline__ void blade_frame(const RotorDev& r, double ct, double
   f.qq = rel[0] * f.ep[0] + rel[1] * f.ep[1] + rel[2] * f.ep[2];
   f.ax = ax;
 }
-__device__ __forceinline__ void blade_box(const RotorDev& r, BladeFrame& f) {
+// with_pitch: compute sin and cos of the pitch, else take f.sb, f.cb as given
+__device__ __forceinline__ void blade_box(const RotorDev& r, BladeFrame& f, bool with_pitch = true) {
   const double span = r.R - r.r_hub;
   double frac = (f.rr - r.r_hub) / span;
   f.dbeta = 0.0;
   if (frac <= 0.0) frac = 0.0;
   else if (frac >= 1.0) frac = 1.0;
   else f.dbeta = (r.tw_tip - r.tw_root) / span;
-  const double beta = r.tw_root + (r.tw_tip - r.tw_root) * frac;
-  sincos(beta, &f.sb, &f.cb);
+  if (with_pitch) {
+    const double beta = r.tw_root + (r.tw_tip - r.tw_root) * frac;
+    sincos(beta, &f.sb, &f.cb);
+  }
   f.p[0] = f.rr - 0.5 * (r.R + r.r_hub);
   f.p[1] = -f.cb * f.qq + f.sb * f.ax;
   f.p[2] = f.cb * f.ax + f.sb * f.qq;
@@ -190,6 +194,8 @@ __device__ __forceinline__ RotorPhi rotor_phi(const RotorDev& r, const double* c
   const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
   o.phi = r.r_hub - dist;
   o.piece = -1;
+  o.sb = 0.0;
+  o.cb = 1.0;
   const double ax = rel[0] * r.e[0] + rel[1] * r.e[1] + rel[2] * r.e[2];
   const double span = r.R - r.r_hub;
   const double half[3] = {0.5 * span, 0.5 * r.chord, 0.5 * r.thick};
@@ -215,14 +221,18 @@ __device__ __forceinline__ RotorPhi rotor_phi(const RotorDev& r, const double* c
     if (phi > o.phi) {
       o.phi = phi;
       o.piece = b;
+      o.sb = f.sb;
+      o.cb = f.cb;
     }
   }
   return o;
 }
 
-// Gradient of the rotor distance at (x, y, z) for the piece found by rotor_phi.
+// Gradient of the rotor distance at (x, y, z) for the piece found by rotor_phi
+// (with the pitch sine and cosine that pass computed there).
 __device__ __forceinline__ void rotor_grad(const RotorDev& r, const double* ctab, const double* stab, double x,
-                                           double y, double z, int piece, double grad[3]) {
+                                           double y, double z, const RotorPhi& w, double grad[3]) {
+  const int piece = w.piece;
   const double rel[3] = {x - r.c[0], y - r.c[1], z - r.c[2]};
   const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
   if (piece < 0) {
@@ -234,7 +244,9 @@ __device__ __forceinline__ void rotor_grad(const RotorDev& r, const double* ctab
   const double half[3] = {0.5 * span, 0.5 * r.chord, 0.5 * r.thick};
   BladeFrame f;
   blade_frame(r, ctab[piece], stab[piece], rel, ax, f);
-  blade_box(r, f);
+  f.sb = w.sb;
+  f.cb = w.cb;
+  blade_box(r, f, false);
   double q[3], qp[3], qn2 = 0.0;
   for (int k = 0; k < 3; ++k) {
     q[k] = fabs(f.p[k]) - half[k];
@@ -763,17 +775,20 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
   slot_cell(rt.r[k], s, x, y, z);
   const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
   double best = -1e300, gr[3] = {0, 0, 0};
-  int br = -1, piece = -1;
+  int br = -1;
+  RotorPhi win{};
   for (int j = 0; j < rt.n; ++j) {
     if (!in_box(rt.r[j], x, y, z)) continue;
     RotorPhi p = rotor_phi(rt.r[j], a.trig->c[j], a.trig->s[j], double(x), double(y), double(z), 0.5 * m.eps_h + 1.0);
     if (p.phi > best) {
       best = p.phi;
       br = j;
-      piece = p.piece;
+      win = p;
     }
   }
-  if (br >= 0) rotor_grad(rt.r[br], a.trig->c[br], a.trig->s[br], double(x), double(y), double(z), piece, gr);
+  // the normal is needed by wall-cell candidates only (band -eps_h/2 < phi < 0)
+  if (br >= 0 && m.wall_model && best > -0.5 * m.eps_h && best < 0.0)
+    rotor_grad(rt.r[br], a.trig->c[br], a.trig->s[br], double(x), double(y), double(z), win, gr);
   const double drot = br >= 0 ? transition(best, m.eps_h, m.transition) : 0.0;
   const double ds = double(a.d_static[c]);
   const double base = ds > drot ? ds : drot;
