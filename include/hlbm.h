@@ -157,7 +157,12 @@ int hlbm_set_tag_frame(hlbm_handle h, int32_t tag, const double center[3], const
  * 0.  Resets the step counter, the wall-model state and the history. */
 int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u);
 
-/* Advance n >= 0 steps (asynchronous unless check_nonfinite is set). */
+/* Advance n >= 0 steps (asynchronous unless check_nonfinite is set).  A
+ * step is the algorithm of Sec. 3.2: rotor geometry, wall model, fused
+ * stream-collide sweep with force records.  The wall-model launch of each
+ * step also computes the geometry of the next one (kept for the next call
+ * unless a call in between changes the geometry inputs or reads moments);
+ * results do not depend on how steps are split over calls. */
 int hlbm_step(hlbm_handle h, int64_t n);
 
 /* Current step counter. */
@@ -217,9 +222,12 @@ int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
  * (HLBM_KERNEL_*).  hlbm_profile_enable(h, 1) starts a fresh count;
  * hlbm_profile_read synchronizes and returns the number of timed launches
  * and their summed duration in milliseconds.  For benchmarks and tests. */
-/* SWEEP: stream-collide sweep; WALL: wall model; RASTERIZE: rotor geometry
- * (with the step's inflow plane); OTHER: batched force reductions and
- * separately launched inflow planes. */
+/* SWEEP: stream-collide sweep; WALL: wall model (whose launch also computes
+ * the rotor geometry and inflow plane of the next step); RASTERIZE: rotor
+ * geometry (with the step's inflow plane) launched on its own, which happens
+ * on the first step of a run and after a call that changes the geometry
+ * inputs, or every step without the wall model; OTHER: batched force
+ * reductions and separately launched inflow planes. */
 enum hlbm_kernel { HLBM_KERNEL_SWEEP = 0, HLBM_KERNEL_WALL = 1, HLBM_KERNEL_RASTERIZE = 2, HLBM_KERNEL_OTHER = 3 };
 int hlbm_profile_enable(hlbm_handle h, int32_t enable);
 int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* total_ms);
