@@ -109,7 +109,10 @@ typedef struct {
   int32_t n_blades, tag;
 } hlbm_rotor;
 
-/* Bytes of one population buffer (27 arrays, each padded). */
+/* Bytes of one population buffer.  Its layout is internal (the canonical
+ * arrays go through hlbm_get/set_populations): each (y, z) row is cut into
+ * blocks of 64 consecutive x cells holding the 27 populations of those cells
+ * as 27 runs of 64 values, the last block padded. */
 int64_t hlbm_population_bytes(const hlbm_desc* desc);
 /* Bytes of the workspace for this description. */
 int64_t hlbm_workspace_bytes(const hlbm_desc* desc);

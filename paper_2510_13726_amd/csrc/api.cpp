@@ -28,9 +28,11 @@ bool desc_ok(const hlbm_desc* d, std::string* why) {
   if (d->nx < 2 || d->ny < 1 || d->nz < 1) { *why = "lattice needs nx >= 2, ny >= 1, nz >= 1"; return false; }
   const int64_t N = int64_t(d->nx) * d->ny * d->nz;
   if (N >= (int64_t(1) << 31)) { *why = "lattice above 2^31 cells"; return false; }
-  // kernels address inside one population array with 32-bit byte offsets
-  if (d->storage >= HLBM_F64 && d->storage <= HLBM_BF16 && N * elem_size(d->storage) > (int64_t(1) << 32) - 65536) {
-    *why = "one population array above 4 GiB (F64 storage above 536 million cells)";
+  // the adjoint addresses inside one array of its state adjoint with 32-bit
+  // byte offsets
+  if ((d->flags & HLBM_WITH_ADJOINT) && (d->compute == HLBM_F64 || d->compute == HLBM_F32) &&
+      N * elem_size(d->compute) > (int64_t(1) << 32) - 65536) {
+    *why = "adjoint state array above 4 GiB (adjoint above 536 million cells in F64, 1073 million in F32)";
     return false;
   }
   if (d->compute != HLBM_F64 && d->compute != HLBM_F32) { *why = "compute must be F64 or F32"; return false; }
@@ -44,16 +46,11 @@ bool desc_ok(const hlbm_desc* d, std::string* why) {
 
 int64_t cells_of(const hlbm_desc* d) { return int64_t(d->nx) * d->ny * d->nz; }
 
-// Elements between the 27 population arrays: the array size rounded up to a
-// page plus a skew of 8448 bytes (33 x 256), so the arrays do not all start
-// on the same DRAM channel (the fastest of the skews measured on MI355X).
-int64_t pop_stride(const hlbm_desc* d) {
-  const int es = elem_size(d->storage);
-  int64_t pad = 8448;
-  if (const char* e = std::getenv("HLBM_POP_SKEW")) pad = std::atoll(e);
-  const int64_t bytes = align_up(cells_of(d) * es, 4096) + pad;
-  return bytes / es;
-}
+// Population elements per (y, z) row in the blocked layout: the row's x
+// extent rounded up to whole blocks of kTileX cells, 27 populations each.
+int64_t pop_row(const hlbm_desc* d) { return int64_t((d->nx + kTileX - 1) / kTileX) * 27 * kTileX; }
+// Elements of one population buffer.
+int64_t pop_elems(const hlbm_desc* d) { return pop_row(d) * d->ny * d->nz; }
 
 // Elements between the 27 arrays of the state adjoint (compute type).
 int64_t pop_stride_c(const hlbm_desc* d) {
@@ -63,7 +60,7 @@ int64_t pop_stride_c(const hlbm_desc* d) {
 
 struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
-      wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b, blist,
+      wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b,
       trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, total;
 };
 
@@ -111,7 +108,6 @@ Layout layout(const hlbm_desc* d) {
   L.ghost64 = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
   L.ghostb = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * cs : 0);
   L.ghost64b = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
-  L.blist = take(nb * 4);
   L.trig = take(d->bbox_cells > 0 ? int64_t(kTrigSteps) * int64_t(sizeof(BladeTrig)) : 0);
   const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
   const int64_t lam_bytes = adj ? 27 * pop_stride_c(d) * cs : 0;
@@ -300,17 +296,7 @@ int rebuild_slots(hlbm_handle h) {
   h->nslots = n;
   // the partial buffer holds nblocks slots: as many steps of slices as fit
   h->batch = int32_t(std::max<int64_t>(1, std::min<int64_t>(kMaxBatch, h->L.nblocks / std::max<int32_t>(n, 1))));
-  // Launch order.  Workgroup i runs on XCD i mod 8, in the order of i: list
-  // entry 8j + k is the j-th tile of XCD k.  Each XCD sweeps one contiguous
-  // eighth of the tiles, so the lines shared by neighbouring tiles stay in
-  // its L2 (measured fastest, ahead of spreading the FSI tiles first).
-  const int64_t T = int64_t(flags.size());
-  const int64_t q = T / kXcds;
-  std::vector<int32_t> order(T);
-  for (int64_t i = 0; i < T; ++i) order[i] = int32_t(i >= q * kXcds ? i : (i % kXcds) * q + i / kXcds);
   e = hipMemcpyAsync(h->L.blk_slot, flags.data(), sizeof(int32_t) * flags.size(), hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(h->L.blist, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "write block slots");
   return HLBM_OK;
@@ -399,7 +385,7 @@ extern "C" {
 int64_t hlbm_population_bytes(const hlbm_desc* d) {
   std::string why;
   if (!desc_ok(d, &why)) return -1;
-  return 27 * pop_stride(d) * elem_size(d->storage);
+  return pop_elems(d) * elem_size(d->storage);
 }
 
 int64_t hlbm_workspace_bytes(const hlbm_desc* d) {
@@ -442,7 +428,7 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.compute = d->compute;
   L.g.nx = d->nx; L.g.ny = d->ny; L.g.nz = d->nz; L.g.bc_x = d->bc_x;
   L.g.N = cells_of(d);
-  L.g.stride = pop_stride(d);
+  L.g.row = pop_row(d);
   L.g.ntx = (d->nx + kTileX - 1) / kTileX;
   L.g.nty = (d->ny + kTileY - 1) / kTileY;
   L.nblocks = int64_t(L.g.ntx) * L.g.nty * d->nz;
@@ -489,7 +475,6 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   }
   L.ghost = h->ghost[0];
   L.ghost64 = h->ghost64[0];
-  L.blist = reinterpret_cast<int32_t*>(base + Y.blist);
   L.trig_tab = d->bbox_cells > 0 ? reinterpret_cast<BladeTrig*>(base + Y.trig) : nullptr;
   // defaults: Smagorinsky-free BGK-like relaxation at tau0 = 1 until set_params
   hlbm_params p{};
@@ -505,6 +490,7 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   h->rot.n = 0;
   hipError_t e = hipMemsetAsync(ws, 0, Y.total, h->stream);
   if (e == hipSuccess) e = launch_fill_rest(L, h->pop[0]);
+  if (e == hipSuccess) e = launch_fill_rest(L, h->pop[1]);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     hip_fail(nullptr, e, "create");
@@ -808,7 +794,7 @@ struct StateLayout {
 StateLayout state_layout(hlbm_handle h) {
   StateLayout s;
   const int64_t B = h->L.bbox_total;
-  s.pops = 27 * h->L.g.stride * elem_size(h->desc.storage);
+  s.pops = pop_elems(&h->desc) * elem_size(h->desc.storage);
   s.ut = align_up(s.pops, 256);
   s.act = s.ut + align_up(B * 8, 256);
   s.bytes = s.act + align_up(std::max<int64_t>(B, 1), 256);
@@ -1081,14 +1067,14 @@ int hlbm_get_populations_at(hlbm_handle h, const int64_t* cells, int64_t count, 
 int64_t hlbm_state_bytes(hlbm_handle h) {
   if (!h) return -1;
   const int64_t B = h->L.bbox_total;
-  return 256 + 27 * h->L.g.stride * elem_size(h->desc.storage) + align_up(B * 8, 256) + align_up(B, 256);
+  return 256 + pop_elems(&h->desc) * elem_size(h->desc.storage) + align_up(B * 8, 256) + align_up(B, 256);
 }
 
 int hlbm_get_state(hlbm_handle h, void* dst) {
   if (!h || !dst) return h ? fail(h, HLBM_ERR_INVALID, "dst is NULL") : HLBM_ERR_INVALID;
   char* p = static_cast<char*>(dst);
   const int64_t B = h->L.bbox_total;
-  const int64_t pb = 27 * h->L.g.stride * elem_size(h->desc.storage);
+  const int64_t pb = pop_elems(&h->desc) * elem_size(h->desc.storage);
   int64_t head[32] = {0};
   head[0] = h->step;
   head[1] = B;
@@ -1113,7 +1099,7 @@ int hlbm_set_state(hlbm_handle h, const void* src) {
   if (e != hipSuccess) return hip_fail(h, e, "read state header");
   const int64_t B = h->L.bbox_total;
   if (head[2] != 0x484c424d || head[1] != B) return fail(h, HLBM_ERR_INVALID, "state blob does not match this lattice");
-  const int64_t pb = 27 * h->L.g.stride * elem_size(h->desc.storage);
+  const int64_t pb = pop_elems(&h->desc) * elem_size(h->desc.storage);
   e = hipMemcpyAsync(h->pop[h->cur], p + 256, pb, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && B) e = hipMemcpyAsync(h->ut[h->wcur], p + 256 + pb, B * 8, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && B)

@@ -58,18 +58,28 @@ struct Model {
 struct Geometry {
   int32_t nx, ny, nz, bc_x;
   int64_t N;
-  int64_t stride;      // elements between population arrays
+  int64_t row;         // population elements per (y, z) row: ntx blocks of 27 x kTileX
   int32_t ntx, nty;    // sweep tiles along x and y
 };
+
+// Blocked population layout: a row of the lattice is cut into blocks of
+// kTileX consecutive x cells (one sweep wave); a block holds its cells' 27
+// populations as 27 runs of kTileX values, so a wave's 27 loads and 27
+// stores each touch one contiguous 256-byte run (FP32) of a few blocks.
+// Element (i, x, y, z) of a population buffer:
+__host__ __device__ inline int64_t pop_at(const Geometry& g, int i, int x, int y, int z) {
+  return (int64_t(z) * g.ny + y) * g.row + int64_t(x / kTileX) * (27 * kTileX) + i * kTileX + x % kTileX;
+}
+// Offset of cell x inside its row, population 0 (add i * kTileX for population i).
+__host__ __device__ inline uint32_t pop_x(int x) {
+  return uint32_t(x / kTileX) * uint32_t(27 * kTileX) + uint32_t(x % kTileX);
+}
 
 // cos and sin of every blade angle of every rotor at the current step
 struct BladeTrig {
   double c[kMaxRotors][kMaxBlades];
   double s[kMaxRotors][kMaxBlades];
 };
-// Accelerator complex dies of MI355X: consecutive workgroups of a launch are
-// dispatched round-robin over them.
-constexpr int kXcds = 8;
 // Steps of blade angles held on the device at once (uploaded in chunks).
 constexpr int kTrigSteps = 2048;
 

@@ -28,7 +28,6 @@ __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >
 template <class ST, class CT, bool kPeriodicX>
 __device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geometry& g, int x, int y, int z,
                                           const CT* __restrict__ ghost, CT h[27]) {
-  const uint32_t nx = g.nx, nxy = uint32_t(g.nx) * uint32_t(g.ny);
   const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
   const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
   int xp, xm;
@@ -40,13 +39,14 @@ __device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geom
     xm = x == 0 ? 0 : x - 1;         // inflow plane is replaced below
   }
   // source of velocity c is x - c: c = -1 -> +1 neighbour, c = +1 -> -1 neighbour
-  const uint32_t oz[3] = {uint32_t(zp) * nxy, uint32_t(z) * nxy, uint32_t(zm) * nxy};
-  const uint32_t oy[3] = {uint32_t(yp) * nx, uint32_t(y) * nx, uint32_t(ym) * nx};
-  const uint32_t ox[3] = {uint32_t(xp), uint32_t(x), uint32_t(xm)};
+  const int64_t rb[3][3] = {{(int64_t(zp) * g.ny + yp) * g.row, (int64_t(zp) * g.ny + y) * g.row, (int64_t(zp) * g.ny + ym) * g.row},
+                            {(int64_t(z) * g.ny + yp) * g.row, (int64_t(z) * g.ny + y) * g.row, (int64_t(z) * g.ny + ym) * g.row},
+                            {(int64_t(zm) * g.ny + yp) * g.row, (int64_t(zm) * g.ny + y) * g.row, (int64_t(zm) * g.ny + ym) * g.row}};
+  const uint32_t ox[3] = {pop_x(xp), pop_x(x), pop_x(xm)};
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    const ST* p = src + int64_t(i) * g.stride;
-    const uint32_t o = (oz[cz_of(i) + 1] + oy[cy_of(i) + 1] + ox[cx_of(i) + 1]) * uint32_t(sizeof(ST));
+    const ST* p = src + rb[cz_of(i) + 1][cy_of(i) + 1];
+    const uint32_t o = (ox[cx_of(i) + 1] + uint32_t(i * kTileX)) * uint32_t(sizeof(ST));
     h[i] = CT(w_of(i)) * Store<ST>::template load<CT>(at_bytes(p, o));
   }
   if (!kPeriodicX && x == 0) {
@@ -69,7 +69,6 @@ typedef __attribute__((address_space(1))) char* gbytes;
 template <class ST, class CT, bool kPeriodicX>
 __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geometry& g, int x, int y, int z,
                                          const CT* __restrict__ ghost, CT h[27]) {
-  const int64_t nx = g.nx, nxy = int64_t(g.nx) * g.ny;
   const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
   const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
   int xp, xm;
@@ -80,21 +79,20 @@ __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geome
     xp = x + 1 == g.nx ? x : x + 1;  // outflow: copy of the last plane
     xm = x == 0 ? 0 : x - 1;         // inflow plane is replaced below
   }
-  // byte offsets inside one population array fit 32 bits
+  // the nine source rows (y - c_y, z - c_z) start at wave-uniform byte
+  // offsets; inside a row, a lane's offset is one of three 32-bit values
   constexpr uint32_t es = sizeof(ST);
-  const uint32_t oz[3] = {uint32_t(zp * nxy) * es, uint32_t(z * nxy) * es, uint32_t(zm * nxy) * es};
-  const uint32_t oy[3] = {uint32_t(yp * nx) * es, uint32_t(y * nx) * es, uint32_t(ym * nx) * es};
-  const uint32_t ox[3] = {uint32_t(xp) * es, uint32_t(x) * es, uint32_t(xm) * es};
-  const uint64_t step = uint64_t(g.stride) * es;
+  const uint64_t rs = uint64_t(g.row) * es;
+  const uint64_t rz[3] = {uint64_t(zp) * g.ny, uint64_t(z) * g.ny, uint64_t(zm) * g.ny};
+  const uint32_t ry[3] = {uint32_t(yp), uint32_t(y), uint32_t(ym)};
+  const uint32_t ox[3] = {pop_x(xp) * es, pop_x(x) * es, pop_x(xm) * es};
   gconst_bytes p = (gconst_bytes)src;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    gconst_bytes q = p + (oz[cz_of(i) + 1] + oy[cy_of(i) + 1]);
+    gconst_bytes q = p + ((rz[cz_of(i) + 1] + ry[cy_of(i) + 1]) * rs + uint64_t(i * kTileX) * es);
+    // kept in scalar registers: one load of a scalar base plus a lane offset
+    asm("" : "+s"(q));
     h[i] = CT(w_of(i)) * Store<ST>::template load<CT>((const ST*)(q + ox[cx_of(i) + 1]));
-    // next array: a scalar pointer increment (kept from being folded into
-    // a multiply of the array index)
-    p += step;
-    asm("" : "+s"(p));
   }
   if (!kPeriodicX && x == 0) {
     const int64_t plane = int64_t(g.ny) * g.nz;
@@ -860,8 +858,6 @@ struct SweepArgs {
   const CT* ghost;
   int64_t step;
   int64_t nblocks;
-  const int32_t* blist;      // optional list of the workgroups to run (FSI or bulk part)
-  int64_t nlist;
   CT* out_rho;
   CT* out_u;
   CT* out_uhat;
@@ -888,8 +884,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   const bool row_ok = yr < g.ny;
   const bool valid = xr < g.nx && row_ok;
   const int x = valid ? xr : 0, y = row_ok ? yr : 0;
-  const int64_t row = (int64_t(z) * g.ny + y) * g.nx;
-  const int64_t c = row + x;
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
   const int32_t slot = a.blk_slot[blk];
 
   CT h[27];
@@ -996,13 +991,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   }
   if (!kMoments) {
     if (valid) {
-      gbytes p = (gbytes)(static_cast<ST*>(a.dst) + row);
-      const uint32_t o = uint32_t(x) * uint32_t(sizeof(ST));
-      const uint64_t step = uint64_t(g.stride) * sizeof(ST);
+      // this wave's block: contiguous, 27 runs of kTileX cells
+      gbytes p = (gbytes)(static_cast<ST*>(a.dst) + (int64_t(z) * g.ny + y) * g.row + int64_t(tx) * (27 * kTileX));
+      const uint32_t o = uint32_t(x % kTileX) * uint32_t(sizeof(ST));
 #pragma unroll
       for (int i = 0; i < 27; ++i) {
         Store<ST>::template store<CT>((ST*)(p + o), g2[i]);
-        p += step;
+        p += kTileX * sizeof(ST);
         asm("" : "+s"(p));
       }
     }
@@ -1018,12 +1013,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   }
 }
 
-// One workgroup per entry of the tile list (all tiles, or the FSI / bulk
-// part), XCD-aware order.
+// One workgroup per tile, in lattice order (x fastest): with the blocked
+// population layout this runs faster than orders that hand each XCD a
+// contiguous range of tiles.
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   __shared__ double lds[4][kPartial];
-  const uint32_t blk = a.blist ? uint32_t(a.blist[blockIdx.x]) : uint32_t(blockIdx.x);
+  const uint32_t blk = blockIdx.x;
   sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
 }
 
@@ -1107,26 +1103,29 @@ __global__ __launch_bounds__(256) void k_init_eq(ST* __restrict__ dst, Geometry 
   const CT ux = u ? u[c] : CT(0), uy = u ? u[g.N + c] : CT(0), uz = u ? u[2 * g.N + c] : CT(0);
   CT ge[27];
   equilibrium_dev<CT>(r, ux, uy, uz, ge);
+  const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
 #pragma unroll
-  for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(dst + int64_t(i) * g.stride + c, ge[i]);
+  for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(dst + pop_at(g, i, x, y, z), ge[i]);
 }
 
 template <class ST>
 __global__ __launch_bounds__(256) void k_get_pop(const ST* __restrict__ src, Geometry g, double* __restrict__ dst) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= g.N) return;
+  const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
 #pragma unroll
   for (int i = 0; i < 27; ++i)
-    dst[int64_t(i) * g.N + c] = w_of(i) * Store<ST>::template load<double>(src + int64_t(i) * g.stride + c);
+    dst[int64_t(i) * g.N + c] = w_of(i) * Store<ST>::template load<double>(src + pop_at(g, i, x, y, z));
 }
 
 template <class ST>
 __global__ __launch_bounds__(256) void k_set_pop(ST* __restrict__ dst, Geometry g, const double* __restrict__ src) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= g.N) return;
+  const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
 #pragma unroll
   for (int i = 0; i < 27; ++i)
-    Store<ST>::template store<double>(dst + int64_t(i) * g.stride + c, src[int64_t(i) * g.N + c] / w_of(i));
+    Store<ST>::template store<double>(dst + pop_at(g, i, x, y, z), src[int64_t(i) * g.N + c] / w_of(i));
 }
 
 template <class ST>
@@ -1140,16 +1139,17 @@ __global__ __launch_bounds__(256) void k_get_pop_at(const ST* __restrict__ src, 
     for (int i = 0; i < 27; ++i) dst[k * 27 + i] = __builtin_nan("");
     return;
   }
+  const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
 #pragma unroll
-  for (int i = 0; i < 27; ++i) dst[k * 27 + i] = w_of(i) * Store<ST>::template load<double>(src + int64_t(i) * g.stride + c);
+  for (int i = 0; i < 27; ++i) dst[k * 27 + i] = w_of(i) * Store<ST>::template load<double>(src + pop_at(g, i, x, y, z));
 }
 
+// Every element of a population buffer (cells and the unused tail of the
+// last block of each row) set to the rest state g = 0.
 template <class ST>
-__global__ __launch_bounds__(256) void k_fill_rest(ST* __restrict__ dst, Geometry g) {
-  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= g.N) return;
-#pragma unroll
-  for (int i = 0; i < 27; ++i) Store<ST>::template store<double>(dst + int64_t(i) * g.stride + c, 0.0);
+__global__ __launch_bounds__(256) void k_fill_rest(ST* __restrict__ dst, int64_t count) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < count) Store<ST>::template store<double>(dst + e, 0.0);
 }
 
 // FSI workgroups (bit 0): any cell in a rotor box, or with static porosity,
@@ -1488,9 +1488,6 @@ hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t ste
     using CT = std::remove_pointer_t<decltype(ct)>;
     SweepArgs<CT> a = sweep_args<CT>(L, src, dst, step);
     if (diag) a.mass_part = L.mass_part;
-    // the host's XCD-balanced order (FSI tiles first on every XCD)
-    a.blist = L.blist;
-    a.nlist = L.nblocks;
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
     else
@@ -1602,7 +1599,8 @@ hipError_t launch_get_populations_at(const Launch& L, const void* src, const int
 hipError_t launch_fill_rest(const Launch& L, void* dst) {
   return by_types(L.storage, L.compute, [&](auto* st, auto*) {
     using ST = std::remove_pointer_t<decltype(st)>;
-    hipLaunchKernelGGL(k_fill_rest<ST>, grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g);
+    const int64_t count = L.g.row * L.g.ny * L.g.nz;
+    hipLaunchKernelGGL(k_fill_rest<ST>, grid1(count, 256), dim3(256), 0, L.stream, (ST*)dst, count);
     return hipGetLastError();
   });
 }

@@ -15,7 +15,6 @@ struct Launch {
   Geometry g;
   Model m;
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
-  int32_t* blist;            // launch order of the tiles
   BladeTrig* trig_tab;       // blade angles of kTrigSteps consecutive steps
   // fields
   void* d_eff;

@@ -39,9 +39,12 @@ def test_host_size_helpers():
     d = hlbm.make_desc(256, 128, 128, hlbm.F32)
     pb = L.hlbm_population_bytes(C.byref(d))
     N = 256 * 128 * 128
-    assert 27 * N * 4 <= pb <= 27 * (N * 4 + 4096 + 8448)  # page rounding + channel skew
+    assert pb == 27 * N * 4  # blocks of 64 x cells: no padding when 64 divides nx
     d16 = hlbm.make_desc(256, 128, 128, hlbm.F16)
-    assert L.hlbm_population_bytes(C.byref(d16)) < pb / 1.9
+    assert L.hlbm_population_bytes(C.byref(d16)) == pb // 2
+    # a ragged row is padded to whole blocks of 64 cells
+    dr = hlbm.make_desc(100, 3, 2, hlbm.F64)
+    assert L.hlbm_population_bytes(C.byref(dr)) == 27 * 128 * 3 * 2 * 8
     assert L.hlbm_workspace_bytes(C.byref(d)) > 0
     bad = hlbm.make_desc(1, 4, 4, hlbm.F32)
     assert L.hlbm_population_bytes(C.byref(bad)) == -1
