@@ -301,39 +301,44 @@ __device__ __forceinline__ bool in_box(const RotorDev& r, int x, int y, int z) {
 }
 
 // ---------------------------------------------------------------- wall model
-// Forward-mode dual number with four directions (probe velocity, previous
-// friction velocity): differentiates the wall model exactly as executed.
+// Forward-mode dual numbers with K directions: differentiate the wall model
+// exactly as executed.  Four directions (probe velocity, previous friction
+// velocity) for the model, two (tangential slip U, previous friction
+// velocity) inside the Newton solves, which depend on those two only.
 namespace dual {
-struct D4 {
-  double v, g[4];
+template <int K>
+struct Dual {
+  double v, g[K];
 };
-__device__ __forceinline__ D4 mk(double v) { D4 r; r.v = v; r.g[0] = r.g[1] = r.g[2] = r.g[3] = 0.0; return r; }
-__device__ __forceinline__ D4 operator+(D4 a, D4 b) { D4 r; r.v = a.v + b.v; for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] + b.g[q]; return r; }
-__device__ __forceinline__ D4 operator-(D4 a, D4 b) { D4 r; r.v = a.v - b.v; for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] - b.g[q]; return r; }
-__device__ __forceinline__ D4 operator*(D4 a, D4 b) { D4 r; r.v = a.v * b.v; for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] * b.v + a.v * b.g[q]; return r; }
-__device__ __forceinline__ D4 operator/(D4 a, D4 b) {
-  D4 r; r.v = a.v / b.v;
+template <int K> __device__ __forceinline__ Dual<K> mk(double v) { Dual<K> r; r.v = v; for (int q = 0; q < K; ++q) r.g[q] = 0.0; return r; }
+template <int K> __device__ __forceinline__ Dual<K> operator+(Dual<K> a, Dual<K> b) { Dual<K> r; r.v = a.v + b.v; for (int q = 0; q < K; ++q) r.g[q] = a.g[q] + b.g[q]; return r; }
+template <int K> __device__ __forceinline__ Dual<K> operator-(Dual<K> a, Dual<K> b) { Dual<K> r; r.v = a.v - b.v; for (int q = 0; q < K; ++q) r.g[q] = a.g[q] - b.g[q]; return r; }
+template <int K> __device__ __forceinline__ Dual<K> operator*(Dual<K> a, Dual<K> b) { Dual<K> r; r.v = a.v * b.v; for (int q = 0; q < K; ++q) r.g[q] = a.g[q] * b.v + a.v * b.g[q]; return r; }
+template <int K> __device__ __forceinline__ Dual<K> operator/(Dual<K> a, Dual<K> b) {
+  Dual<K> r; r.v = a.v / b.v;
   const double ib = 1.0 / (b.v * b.v);
-  for (int q = 0; q < 4; ++q) r.g[q] = (a.g[q] * b.v - a.v * b.g[q]) * ib;
+  for (int q = 0; q < K; ++q) r.g[q] = (a.g[q] * b.v - a.v * b.g[q]) * ib;
   return r;
 }
-__device__ __forceinline__ D4 operator+(D4 a, double b) { return a + mk(b); }
-__device__ __forceinline__ D4 operator-(D4 a, double b) { return a - mk(b); }
-__device__ __forceinline__ D4 operator-(double a, D4 b) { return mk(a) - b; }
-__device__ __forceinline__ D4 operator*(double a, D4 b) { return mk(a) * b; }
-__device__ __forceinline__ D4 operator*(D4 a, double b) { return a * mk(b); }
-__device__ __forceinline__ D4 operator/(D4 a, double b) { return a / mk(b); }
-__device__ __forceinline__ D4 operator/(double a, D4 b) { return mk(a) / b; }
-__device__ __forceinline__ D4 operator+(double a, D4 b) { return mk(a) + b; }
-__device__ __forceinline__ D4 sqrt(D4 a) { D4 r; r.v = ::sqrt(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] / (2.0 * r.v); return r; }
-__device__ __forceinline__ D4 exp(D4 a) { D4 r; r.v = ::exp(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] * r.v; return r; }
-__device__ __forceinline__ D4 log(D4 a) { D4 r; r.v = ::log(a.v); for (int q = 0; q < 4; ++q) r.g[q] = a.g[q] / a.v; return r; }
-__device__ __forceinline__ double val(D4 a) { return a.v; }
-__device__ __forceinline__ D4 rcp_nr(D4 a) { return 1.0 / a; }
-__device__ __forceinline__ D4 div_nr(D4 a, D4 b) { return a / b; }
+template <int K> __device__ __forceinline__ Dual<K> operator+(Dual<K> a, double b) { return a + mk<K>(b); }
+template <int K> __device__ __forceinline__ Dual<K> operator-(Dual<K> a, double b) { return a - mk<K>(b); }
+template <int K> __device__ __forceinline__ Dual<K> operator-(double a, Dual<K> b) { return mk<K>(a) - b; }
+template <int K> __device__ __forceinline__ Dual<K> operator*(double a, Dual<K> b) { return mk<K>(a) * b; }
+template <int K> __device__ __forceinline__ Dual<K> operator*(Dual<K> a, double b) { return a * mk<K>(b); }
+template <int K> __device__ __forceinline__ Dual<K> operator/(Dual<K> a, double b) { return a / mk<K>(b); }
+template <int K> __device__ __forceinline__ Dual<K> operator/(double a, Dual<K> b) { return mk<K>(a) / b; }
+template <int K> __device__ __forceinline__ Dual<K> operator+(double a, Dual<K> b) { return mk<K>(a) + b; }
+template <int K> __device__ __forceinline__ Dual<K> sqrt(Dual<K> a) { Dual<K> r; r.v = ::sqrt(a.v); for (int q = 0; q < K; ++q) r.g[q] = a.g[q] / (2.0 * r.v); return r; }
+template <int K> __device__ __forceinline__ Dual<K> exp(Dual<K> a) { Dual<K> r; r.v = ::exp(a.v); for (int q = 0; q < K; ++q) r.g[q] = a.g[q] * r.v; return r; }
+template <int K> __device__ __forceinline__ Dual<K> log(Dual<K> a) { Dual<K> r; r.v = ::log(a.v); for (int q = 0; q < K; ++q) r.g[q] = a.g[q] / a.v; return r; }
+template <int K> __device__ __forceinline__ double val(Dual<K> a) { return a.v; }
+template <int K> __device__ __forceinline__ Dual<K> rcp_nr(Dual<K> a) { return 1.0 / a; }
+template <int K> __device__ __forceinline__ Dual<K> div_nr(Dual<K> a, Dual<K> b) { return a / b; }
+using D4 = Dual<4>;
+using D2 = Dual<2>;
 }  // namespace dual
 using dual::D4;
-using dual::mk;
+using dual::D2;
 // FP64 reciprocal and quotient for the positive or negative, normal operands
 // of the wall law (no zeros, infinities or denormals): the hardware
 // reciprocal estimate refined by two Newton-Raphson steps for 1/x,
@@ -354,9 +359,31 @@ using dual::rcp_nr;
 using dual::div_nr;
 __device__ __forceinline__ double val(double a) { return a; }
 using dual::val;
-template <class R> __device__ __forceinline__ R cst(double v);
-template <> __device__ __forceinline__ double cst<double>(double v) { return v; }
-template <> __device__ __forceinline__ D4 cst<D4>(double v) { return mk(v); }
+template <class R> struct Cst;
+template <> struct Cst<double> { __device__ static double make(double v) { return v; } };
+template <int K> struct Cst<dual::Dual<K>> { __device__ static dual::Dual<K> make(double v) { return dual::mk<K>(v); } };
+template <class R> __device__ __forceinline__ R cst(double v) { return Cst<R>::make(v); }
+
+// The Newton solves of the wall model in plain FP64, or with the two
+// directions (U, u_tau^prev) when the model carries four: seeds and the
+// chain rule back to the model's directions.
+template <class R> struct NewtonType { using type = R; };
+template <> struct NewtonType<D4> { using type = D2; };
+__device__ __forceinline__ double seed_newton(double a, int) { return a; }
+__device__ __forceinline__ D2 seed_newton(const D4& a, int dir) {
+  D2 r;
+  r.v = a.v;
+  r.g[0] = dir == 0 ? 1.0 : 0.0;
+  r.g[1] = dir == 1 ? 1.0 : 0.0;
+  return r;
+}
+__device__ __forceinline__ double lift_newton(double a, double, double) { return a; }
+__device__ __forceinline__ D4 lift_newton(const D2& a, const D4& U, const D4& utp) {
+  D4 r;
+  r.v = a.v;
+  for (int q = 0; q < 4; ++q) r.g[q] = a.g[0] * U.g[q] + a.g[1] * utp.g[q];
+  return r;
+}
 
 // Truncated Spalding bracket e^k - 1 - k - k^2/2 - k^3/6 (eq. spalding) with
 // the exponential capped at e^80, and its derivative.
@@ -418,36 +445,40 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   // the Newton chains run on one lane per wall cell: every division is a
   // long dependent sequence in FP64, so the constants enter as reciprocals
   const double sixth = 1.0 / 6.0;
-  const R guess = prev_active ? utp : sqrt(m.nu_ys * U);
-  const R ut = newton(
+  using RN = typename NewtonType<R>::type;
+  const RN Un = seed_newton(U, 0);
+  const RN utpn = seed_newton(utp, 1);
+  const RN guess = prev_active ? utpn : sqrt(m.nu_ys * Un);
+  const RN utn = newton(
       guess,
-      [&](R u, R& f, R& df) {
-        const R iu = rcp_nr(u);
-        const R p = U * iu;
-        const R k = kap * p;
-        const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
-        const R dek = val(k) > 80.0 ? cst<R>(0.0) : ek;
-        const R poly = 1.0 + k + k * k * 0.5;
+      [&](RN u, RN& f, RN& df) {
+        const RN iu = rcp_nr(u);
+        const RN p = Un * iu;
+        const RN k = kap * p;
+        const RN ek = val(k) > 80.0 ? cst<RN>(::exp(80.0)) : exp(k);
+        const RN dek = val(k) > 80.0 ? cst<RN>(0.0) : ek;
+        const RN poly = 1.0 + k + k * k * 0.5;
         f = p + (ek - poly - k * k * k * sixth) * m.inv_E - m.ys_nu * u;
         df = 0.0 - (p * iu) * (1.0 + m.kappa_E * (dek - poly)) - m.ys_nu;
       },
       m.tol, m.maxit, it1);
-  const R yp = y1 * ut * m.inv_nu;
-  const R ylog = val(yp) > 1.0 ? yp : cst<R>(1.0);
-  const R ulog = log(E * ylog) * m.inv_kappa;
+  const RN yp = y1 * utn * m.inv_nu;
+  const RN ylog = val(yp) > 1.0 ? yp : cst<RN>(1.0);
+  const RN ulog = log(E * ylog) * m.inv_kappa;
   int it2 = 0;
-  const R up = newton(
+  const RN upn = newton(
       val(ulog) < val(yp) ? ulog : yp,
-      [&](R u, R& f, R& df) {
-        const R k = kap * u;
-        const R ek = val(k) > 80.0 ? cst<R>(::exp(80.0)) : exp(k);
-        const R dek = val(k) > 80.0 ? cst<R>(0.0) : ek;
-        const R poly = 1.0 + k + k * k * 0.5;
+      [&](RN u, RN& f, RN& df) {
+        const RN k = kap * u;
+        const RN ek = val(k) > 80.0 ? cst<RN>(::exp(80.0)) : exp(k);
+        const RN dek = val(k) > 80.0 ? cst<RN>(0.0) : ek;
+        const RN poly = 1.0 + k + k * k * 0.5;
         f = u + (ek - poly - k * k * k * sixth) * m.inv_E - yp;
         df = 1.0 + m.kappa_E * (dek - poly);
       },
       m.tol, m.maxit, it2);
-  const R qv = ut * up;
+  const R ut = lift_newton(utn, U, utp);
+  const R qv = lift_newton(utn * upn, U, utp);
   const R hd = 0.5 * ((U - qv) / (ys - y1));
   out[0] = qv * t[0];
   out[1] = qv * t[1];
@@ -624,8 +655,8 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
       if constexpr (kAdj) {
         // values and the 10 x 4 Jacobian with respect to (us, u_tau^prev)
         D4 ud[3];
-        for (int q = 0; q < 3; ++q) { ud[q] = mk(us[q]); ud[q].g[q] = 1.0; }
-        D4 up = mk(utp);
+        for (int q = 0; q < 3; ++q) { ud[q] = dual::mk<4>(us[q]); ud[q].g[q] = 1.0; }
+        D4 up = dual::mk<4>(utp);
         up.g[3] = 1.0;
         active = wall_solve<D4>(ud, pr.uw, pr.nn, pr.y1, up, actp, m, o4, it1);
         for (int q = 0; q < 10; ++q) out[q] = o4[q].v;
