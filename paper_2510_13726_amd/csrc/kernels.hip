@@ -1308,12 +1308,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const uint32_t trem = uint32_t(blk) - uint32_t(z) * tpz;
   const int ty = int(trem / uint32_t(g.ntx)), tx = int(trem - uint32_t(ty) * uint32_t(g.ntx));
   const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
-  const int yr = ty * kTileY + int(threadIdx.x >> 6);
+  // one row per wave: y is uniform over the wave
+  const int yr = __builtin_amdgcn_readfirstlane(ty * kTileY + int(threadIdx.x >> 6));
   if (xr >= g.nx || yr >= g.ny) return;
   const int x = xr, y = yr;
   const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
   CT h[27];
-  pull_cell<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+  pull_row<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
   const Moments<CT> mo = moments_of<CT>(h);
   const uint32_t o4 = uint32_t(c) * uint32_t(sizeof(CT));
   CT gb[27];
