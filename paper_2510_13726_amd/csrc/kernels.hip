@@ -1044,13 +1044,23 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   }
 }
 
-// One workgroup per tile, in lattice order (x fastest): with the blocked
-// population layout this runs faster than orders that hand each XCD a
-// contiguous range of tiles.
+// Tile of workgroup i.  Consecutive workgroups are dispatched round-robin
+// over the eight XCDs (i mod 8), each with its own L2: XCD k gets whole rows
+// of ntx tiles, so the blocks that the x-shifted loads of neighbouring tiles
+// share are fetched into one L2, while the eight XCDs sweep eight adjacent
+// tile rows of the lattice at a time.  Workgroups past the last full group
+// of eight rows keep lattice order.
+__device__ __forceinline__ uint32_t tile_of(uint32_t i, uint32_t ntiles, uint32_t ntx) {
+  const uint32_t span = 8u * ntx;
+  if (i >= (ntiles / span) * span) return i;
+  const uint32_t c = i / span, r = i - c * span;
+  return c * span + (r % 8u) * ntx + r / 8u;
+}
+
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   __shared__ double lds[4][kPartial];
-  const uint32_t blk = blockIdx.x;
+  const uint32_t blk = tile_of(blockIdx.x, gridDim.x, uint32_t(a.g.ntx));
   sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
 }
 
@@ -1296,12 +1306,12 @@ __device__ __forceinline__ void fsi_inputs(const AdjArgs<CT>& a, const RotorTabl
 template <class ST, class CT, bool kPeriodicX>
 __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const Geometry& g = a.g;
-  const int64_t blk = blockIdx.x;
-  if (blk >= a.nblocks) {
-    const int64_t k = (blk - a.nblocks) * kBlock + threadIdx.x;
+  if (int64_t(blockIdx.x) >= a.nblocks) {
+    const int64_t k = (int64_t(blockIdx.x) - a.nblocks) * kBlock + threadIdx.x;
     if (k < a.nzero) a.zero[k] = 0.0;
     return;
   }
+  const int64_t blk = tile_of(blockIdx.x, uint32_t(a.nblocks), uint32_t(g.ntx));
   // tile ids and counts fit 32 bits (fewer than 2^31 cells, 256 per tile)
   const uint32_t tpz = uint32_t(g.ntx) * uint32_t(g.nty);
   const int z = int(uint32_t(blk) / tpz);
