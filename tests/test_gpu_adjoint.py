@@ -93,3 +93,26 @@ def test_adjoint_independent_of_checkpoint_spacing():
         assert J == J4
         # the probe-velocity adjoints are summed with atomics: equal up to rounding order
         assert np.abs(G - G4).max() <= 1e-13 * np.abs(G4).max()
+
+
+def test_adjoint_across_blade_angle_table_reload():
+    """A recorded window across step 2048, where the device table of blade
+    angles (2048 steps) is reloaded: forwards in the recorded run, backwards
+    during the reverse sweep."""
+    hl = _hl()
+    w, _, _, _ = _cases()["rotor"]
+    n0, n, t0, t1 = 2040, 16, 2, 16
+    o = O.setup(w)
+    o.step(n0)
+    J_or, G_or = o.adjoint_run(n, t0, t1, obj_tag=0, ckpt_every=4)
+    lat = hl.setup(w, storage="f64", flags=hl.WITH_ADJOINT)
+    lat.step(n0)
+    J = lat.forward_record(n, t0, t1, obj_tag=0, ckpt_every=4)
+    G = lat.adjoint(1.0).cpu().numpy()
+    hist = o.history()
+    scale = max(abs(J_or), np.abs(hist[:, 1:].reshape(len(hist), 15, 6)[:, :, :3]).max() * w.nx)
+    eJ = abs(J - J_or) / scale
+    eG = np.abs(G - G_or).max() / np.abs(G_or).max()
+    print(f"[adjoint] steps {n0}..{n0 + n}: J rel {eJ:.2e}, G rel err {eG:.2e}", flush=True)
+    assert eJ < 1e-12
+    assert eG < 1e-11
