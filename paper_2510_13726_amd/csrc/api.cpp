@@ -28,13 +28,6 @@ bool desc_ok(const hlbm_desc* d, std::string* why) {
   if (d->nx < 2 || d->ny < 1 || d->nz < 1) { *why = "lattice needs nx >= 2, ny >= 1, nz >= 1"; return false; }
   const int64_t N = int64_t(d->nx) * d->ny * d->nz;
   if (N >= (int64_t(1) << 31)) { *why = "lattice above 2^31 cells"; return false; }
-  // the adjoint addresses inside one array of its state adjoint with 32-bit
-  // byte offsets
-  if ((d->flags & HLBM_WITH_ADJOINT) && (d->compute == HLBM_F64 || d->compute == HLBM_F32) &&
-      N * elem_size(d->compute) > (int64_t(1) << 32) - 65536) {
-    *why = "adjoint state array above 4 GiB (adjoint above 536 million cells in F64, 1073 million in F32)";
-    return false;
-  }
   if (d->compute != HLBM_F64 && d->compute != HLBM_F32) { *why = "compute must be F64 or F32"; return false; }
   if (d->storage < HLBM_F64 || d->storage > HLBM_BF16) { *why = "unknown storage type"; return false; }
   if (d->compute == HLBM_F64 && d->storage != HLBM_F64) { *why = "F64 compute needs F64 storage"; return false; }
@@ -52,11 +45,6 @@ int64_t pop_row(const hlbm_desc* d) { return int64_t((d->nx + kTileX - 1) / kTil
 // Elements of one population buffer.
 int64_t pop_elems(const hlbm_desc* d) { return pop_row(d) * d->ny * d->nz; }
 
-// Elements between the 27 arrays of the state adjoint (compute type).
-int64_t pop_stride_c(const hlbm_desc* d) {
-  const int es = elem_size(d->compute);
-  return (align_up(cells_of(d) * es, 4096) + 8448) / es;
-}
 
 struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
@@ -110,7 +98,7 @@ Layout layout(const hlbm_desc* d) {
   L.ghost64b = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
   L.trig = take(d->bbox_cells > 0 ? int64_t(kTrigSteps) * int64_t(sizeof(BladeTrig)) : 0);
   const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
-  const int64_t lam_bytes = adj ? 27 * pop_stride_c(d) * cs : 0;
+  const int64_t lam_bytes = adj ? pop_elems(d) * cs : 0;
   L.lam0 = take(lam_bytes);
   L.lam1 = take(lam_bytes);
   L.utb0 = take(adj ? B * 8 : 0);
@@ -922,7 +910,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
   const int64_t N = h->L.g.N, B = std::max<int64_t>(h->L.bbox_total, 1);
   const bool wall = h->params.wall_model && h->L.nrot > 0;
   const int cs = elem_size(h->desc.compute);
-  const int64_t lam_bytes = 27 * pop_stride_c(&h->desc) * cs;
+  const int64_t lam_bytes = pop_elems(&h->desc) * cs;
   hipError_t e = flush(h);
   if (e == hipSuccess) e = hipMemsetAsync(lam[0], 0, lam_bytes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(utb[0], 0, B * 8, h->stream);
@@ -969,7 +957,6 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
       A.ut_bar_out = utb[1 - cur];
       A.obj_w = (k >= h->rec.t0 && k < h->rec.t1) ? w : 0.0;
       A.obj_tag = h->rec.obj_tag;
-      A.lstride = pop_stride_c(&h->desc);
       // the adjoint of u_tau read by this step is consumed: zero it for the
       // writes of the next reverse step
       A.zero = wall ? utb[cur] : nullptr;

@@ -584,8 +584,7 @@ struct WallArgs {
   int32_t count_stats;
   // adjoint instantiation only: the transposed wall-model Jacobian applied
   // at each active wall cell (the adjoint wall step)
-  const CT* lam_in;          // adjoint of the state after the step, [27][lstride]
-  int64_t lstride;
+  const CT* lam_in;          // adjoint of the state after the step (blocked layout)
   const CT* side_in;         // outflow share of lam_in on the last x plane (nullable)
   const CT* d_eff;
   const uint8_t* tag;
@@ -687,7 +686,7 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
           const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
           CT gb[27];
           for (int i = 0; i < 27; ++i) {
-            CT l = a.lam_in[int64_t(i) * a.lstride + c];
+            CT l = a.lam_in[pop_at(g, i, x, y, z)];
             if (fix && i < 9) l += a.side_in[i * plane + k];
             gb[i] = CT(w_of(i)) * l;
           }
@@ -1247,7 +1246,6 @@ struct AdjArgs {
   CT* lam_out;              // adjoint of the state at step n, [27][stride]
   CT* side;                 // outflow side buffer of this step [9][nz][ny]
   const CT* side_in;        // that of the next step, nullable: see k_adj_sweep
-  int64_t lstride;          // elements between the 27 arrays of lam
   Geometry g;
   Model m;
   const int32_t* blk_slot;
@@ -1326,10 +1324,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   CT h[27];
   pull_row<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
   const Moments<CT> mo = moments_of<CT>(h);
-  const uint32_t o4 = uint32_t(c) * uint32_t(sizeof(CT));
+  // lam in the blocked layout of the populations: this wave's block, and the
+  // nine rows the transposed pull writes into
+  constexpr uint32_t cs = sizeof(CT);
+  const uint64_t rs = uint64_t(g.row) * cs;
+  const uint32_t o4 = pop_x(x) * cs;
   CT gb[27];
+  {
+    typedef __attribute__((address_space(1))) const char* gcb;
+    gcb q = (gcb)a.lam_in + (uint64_t(z) * g.ny + y) * rs;
 #pragma unroll
-  for (int i = 0; i < 27; ++i) gb[i] = *at_bytes(a.lam_in + int64_t(i) * a.lstride, o4);
+    for (int i = 0; i < 27; ++i) gb[i] = *(const CT*)(q + (o4 + uint32_t(i * kTileX) * cs));
+  }
   if (!kPeriodicX && a.side_in && x == g.nx - 1) {
     const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
     for (int i = 0; i < 9; ++i) gb[i] += a.side_in[i * plane + k];
@@ -1369,7 +1375,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   }
   a.G[c] += double(db);
   // transpose of the pull: the state read by f_i(x) is at x - c_i
-  const uint32_t nx = g.nx, nxy = uint32_t(g.nx) * uint32_t(g.ny);
   const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
   const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
   int xp, xm;
@@ -1380,9 +1385,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
     xp = x + 1 == g.nx ? x : x + 1;
     xm = x == 0 ? 0 : x - 1;
   }
-  const uint32_t oz[3] = {uint32_t(zp) * nxy, uint32_t(z) * nxy, uint32_t(zm) * nxy};
-  const uint32_t oy[3] = {uint32_t(yp) * nx, uint32_t(y) * nx, uint32_t(ym) * nx};
-  const uint32_t ox[3] = {uint32_t(xp), uint32_t(x), uint32_t(xm)};
+  const uint64_t rz[3] = {uint64_t(zp) * g.ny, uint64_t(z) * g.ny, uint64_t(zm) * g.ny};
+  const uint32_t ry[3] = {uint32_t(yp), uint32_t(y), uint32_t(ym)};
+  const uint32_t ox[3] = {pop_x(xp) * cs, pop_x(x) * cs, pop_x(xm) * cs};
   const int64_t plane = int64_t(g.ny) * g.nz;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
@@ -1390,7 +1395,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
     const CT mu = mb.drho + CT(cx) * mb.jx + CT(cy) * mb.jy + CT(cz) * mb.jz + CT(cx * cx) * mb.pxx +
                   CT(cy * cy) * mb.pyy + CT(cz * cz) * mb.pzz + CT(cx * cy) * mb.pxy + CT(cx * cz) * mb.pxz +
                   CT(cy * cz) * mb.pyz;
-    CT* base = a.lam_out + int64_t(i) * a.lstride;
+    typedef __attribute__((address_space(1))) char* gb_t;
+    gb_t base = (gb_t)a.lam_out + ((rz[cz + 1] + ry[cy + 1]) * rs + uint64_t(i * kTileX) * cs);
     if (!kPeriodicX) {
       if (cx == 1 && x == 0) {
         continue;  // read the inflow ghost, not the state
@@ -1402,15 +1408,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
         continue;
       }
     }
-    const uint32_t o = (oz[cz + 1] + oy[cy + 1] + ox[cx + 1]) * uint32_t(sizeof(CT));
-    *at_bytes(base, o) = mu;
+    *(CT*)(base + ox[cx + 1]) = mu;
   }
   if (!kPeriodicX) {
     // states nobody reads: (nx-1, *) for c_x = +1 and (0, *) for c_x = -1
     if (x == g.nx - 1)
-      for (int i = 18; i < 27; ++i) a.lam_out[int64_t(i) * a.lstride + c] = CT(0);
+      for (int i = 18; i < 27; ++i) a.lam_out[pop_at(g, i, x, y, z)] = CT(0);
     if (x == 0)
-      for (int i = 0; i < 9; ++i) a.lam_out[int64_t(i) * a.lstride + c] = CT(0);
+      for (int i = 0; i < 9; ++i) a.lam_out[pop_at(g, i, x, y, z)] = CT(0);
   }
 }
 
@@ -1484,7 +1489,7 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
     w.act_new = act_new; w.wall_out = (CT*)L.wall_out; w.stats = L.stats; w.ghost = L.ghost64;
     w.count_stats = count_stats;
     if (adj) {
-      w.lam_in = (const CT*)adj->lam_in; w.lstride = adj->lstride; w.side_in = (const CT*)adj->side_in;
+      w.lam_in = (const CT*)adj->lam_in; w.side_in = (const CT*)adj->side_in;
       w.d_eff = (const CT*)L.d_eff; w.tag = L.tag; w.ghost_ct = (const CT*)L.ghost;
       w.ut_bar_in = adj->ut_bar_in; w.ut_bar_out = adj->ut_bar_out; w.ubar = adj->ubar;
       w.obj_w = adj->obj_w; w.obj_tag = adj->obj_tag;
@@ -1579,7 +1584,7 @@ template <class CT>
 static AdjArgs<CT> adj_args(const Launch& L, const AdjLaunch& A) {
   AdjArgs<CT> a{};
   a.src = A.src; a.lam_in = (const CT*)A.lam_in; a.lam_out = (CT*)A.lam_out; a.side = (CT*)A.side;
-  a.side_in = (const CT*)A.side_in; a.lstride = A.lstride;
+  a.side_in = (const CT*)A.side_in;
   a.g = L.g; a.m = L.m; a.blk_slot = L.blk_slot; a.d_eff = (const CT*)L.d_eff; a.tag = L.tag;
   a.wall_out = (const CT*)L.wall_out; a.bbox_total = L.bbox_total; a.rot = L.rot;
   a.uB_static = (const CT*)L.uB_static; a.ghost = (const CT*)L.ghost; a.ubar = A.ubar; a.G = A.G;

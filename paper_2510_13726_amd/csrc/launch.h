@@ -94,11 +94,10 @@ hipError_t launch_mark_blocks(const Launch& L);
 // One reverse step of the discrete adjoint.
 struct AdjLaunch {
   const void* src;          // state at the step (storage type)
-  const void* lam_in;       // adjoint of the next state (compute type)
+  const void* lam_in;       // adjoint of the next state (compute type, blocked layout of the populations)
   void* lam_out;            // adjoint of this state
   void* side;               // outflow side buffer of this step [9][nz][ny]
   const void* side_in;      // that of the next step (added to lam_in on the last plane); nullable
-  int64_t lstride;          // elements between the 27 arrays of lam
   double* ubar;             // [3][N] FP64, zero on entry of the sweep except wall scatter
   double* G;                // [N] FP64 gradient accumulator
   const double* ut_bar_in;  // adjoint of the friction velocity written by the step
