@@ -1,10 +1,14 @@
 // HIP kernels of libhlbm for gfx950 (CDNA4, wave64).
 //
-//  k_rasterize  rotor porosity embedding on the rotors' fixed bounding boxes
-//  k_wall       wall model on the wall cells (probe interpolation, Newton)
-//  k_sweep      fused pull-stream + moments + HLBM collision + store, with
-//               per-tag force/torque partials on FSI workgroups
-//  k_finalize   deterministic reduction of the partials into the history
+//  k_wall_geometry  wall model of a step (probe interpolation, Newton) in the
+//                   first workgroups, rotor porosity embedding and inflow
+//                   plane of the next step in the others; the adjoint
+//                   instantiation adds the adjoint wall step
+//  k_geometry       the geometry alone (first step of a run)
+//  k_sweep          fused pull-stream + moments + HLBM collision + store, with
+//                   per-tag force/torque partials on FSI workgroups
+//  k_reduce_l1/l2   deterministic reduction of the partials into the history
+//  k_adj_sweep      reverse sweep of the discrete adjoint
 // plus initialisation, conversion and bookkeeping kernels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -1242,8 +1246,8 @@ __global__ __launch_bounds__(256) void k_refill(Geometry g, const CT* __restrict
 template <class CT>
 struct AdjArgs {
   const void* src;          // state at step n (storage type)
-  const CT* lam_in;         // adjoint of the state after step n, [27][stride]
-  CT* lam_out;              // adjoint of the state at step n, [27][stride]
+  const CT* lam_in;         // adjoint of the state after step n (blocked layout)
+  CT* lam_out;              // adjoint of the state at step n (blocked layout)
   CT* side;                 // outflow side buffer of this step [9][nz][ny]
   const CT* side_in;        // that of the next step, nullable: see k_adj_sweep
   Geometry g;
