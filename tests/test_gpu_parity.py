@@ -129,6 +129,26 @@ def test_periodic_rotor_parity_fp64():
         assert np.abs(ho[:, sl]).max() > 0
 
 
+@pytest.mark.parametrize("dims,bc", [((2, 1, 1), W.BC_PERIODIC), ((3, 2, 1), W.BC_PERIODIC),
+                                     ((65, 3, 2), W.BC_PERIODIC), ((2, 3, 2), W.BC_INFLOW_OUTFLOW),
+                                     ((130, 1, 3), W.BC_INFLOW_OUTFLOW)])
+def test_degenerate_lattices(dims, bc):
+    """Lattices of one or two cells along an axis (the neighbour is the cell
+    itself or the cell on both sides), a row of one full block plus one
+    cell, and two blocks plus two cells with inflow and outflow, from a
+    seeded non-equilibrium state: FP64 parity with the oracle."""
+    nx, ny, nz = dims
+    p = W.Params(tau0=0.6, cs_smag=0.12, eps_h=2.0, wall_model=0, u_in=(0.03, 0.01, 0.0), turb_I=0.05, seed=11)
+    w = W.Workload(f"degenerate_{nx}x{ny}x{nz}", nx, ny, nz, bc, p, [], 12, init="uniform", u0=0.02,
+                   noise_seed=3, noise_amp=1e-3)
+    lat, o, errs = run_both(w, "f64", 12, check_every=4)
+    assert max(errs) < TOL["f64"], errs
+    rho_g, u_g = (t.cpu().numpy() for t in lat.moments())
+    rho_o, u_o = o.moments()
+    assert np.abs(rho_g - rho_o).max() < 1e-14
+    assert rel(u_g, u_o) < TOL["f64"]
+
+
 def test_restart_is_bitwise_and_deterministic():
     """get_state / set_state continue the trajectory bit for bit; two runs of
     the same input agree bit for bit."""
