@@ -340,9 +340,11 @@ template <int K> __device__ __forceinline__ Dual<K> rcp_nr(Dual<K> a) { return 1
 template <int K> __device__ __forceinline__ Dual<K> div_nr(Dual<K> a, Dual<K> b) { return a / b; }
 using D4 = Dual<4>;
 using D2 = Dual<2>;
+using D1 = Dual<1>;
 }  // namespace dual
 using dual::D4;
 using dual::D2;
+using dual::D1;
 // FP64 reciprocal and quotient for the positive or negative, normal operands
 // of the wall law (no zeros, infinities or denormals): the hardware
 // reciprocal estimate refined by two Newton-Raphson steps for 1/x,
@@ -427,33 +429,35 @@ __device__ __forceinline__ R newton(R u, F&& fdf, double tol, int maxit, int& it
   return u;
 }
 
-// Wall model of one cell given its probe velocity us, wall velocity uw,
-// outward normal nn, wall distance y1 and the previous friction velocity:
-// out = (u_wm[3], S[6] as xx yy zz xy xz yz, u_tau).  Returns false when the
-// tangential slip is below 1e-6 (cell treated as a plain cell): the slip
-// direction is undefined as the slip vanishes (by symmetry on a rotor axis),
-// and the bound sits above FP32 rounding noise in the probe velocity.
+// Tangential slip U and its direction t of the probe velocity us relative
+// to the wall velocity uw (outward normal nn).  False when U is below 1e-6
+// (cell treated as a plain cell): the slip direction is undefined as the
+// slip vanishes (by symmetry on a rotor axis), and the bound sits above FP32
+// rounding noise in the probe velocity.
 template <class R>
-__device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], const double nn[3], double y1,
-                                           R utp, bool prev_active, const Model& m, R out[10], int& it1) {
+__device__ __forceinline__ bool wall_slip(const R us[3], const double uw[3], const double nn[3], R& U, R t[3]) {
   R v[3] = {us[0] - uw[0], us[1] - uw[1], us[2] - uw[2]};
   const R vn = v[0] * nn[0] + v[1] * nn[1] + v[2] * nn[2];
   R vt[3] = {v[0] - vn * nn[0], v[1] - vn * nn[1], v[2] - vn * nn[2]};
   const R U2 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
-  it1 = 0;
   if (!(::sqrt(val(U2)) >= 1e-6)) return false;
-  const R U = sqrt(U2);
+  U = sqrt(U2);
   const R iU = 1.0 / U;
-  const R t[3] = {vt[0] * iU, vt[1] * iU, vt[2] * iU};
-  const double ys = m.y_s, E = m.E, kap = m.kappa;
+  for (int a = 0; a < 3; ++a) t[a] = vt[a] * iU;
+  return true;
+}
+
+// The two Newton solves: u_tau from the slip U (guess: the previous u_tau,
+// else the laminar estimate), then u+ at y1+.
+template <class RN>
+__device__ __forceinline__ void wall_newtons(RN Un, RN utpn, bool prev_active, double y1, const Model& m, RN& utn,
+                                             RN& upn, int& it1) {
+  const double E = m.E, kap = m.kappa;
   // the Newton chains run on one lane per wall cell: every division is a
   // long dependent sequence in FP64, so the constants enter as reciprocals
   const double sixth = 1.0 / 6.0;
-  using RN = typename NewtonType<R>::type;
-  const RN Un = seed_newton(U, 0);
-  const RN utpn = seed_newton(utp, 1);
   const RN guess = prev_active ? utpn : sqrt(m.nu_ys * Un);
-  const RN utn = newton(
+  utn = newton(
       guess,
       [&](RN u, RN& f, RN& df) {
         const RN iu = rcp_nr(u);
@@ -470,7 +474,7 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   const RN ylog = val(yp) > 1.0 ? yp : cst<RN>(1.0);
   const RN ulog = log(E * ylog) * m.inv_kappa;
   int it2 = 0;
-  const RN upn = newton(
+  upn = newton(
       val(ulog) < val(yp) ? ulog : yp,
       [&](RN u, RN& f, RN& df) {
         const RN k = kap * u;
@@ -481,9 +485,13 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
         df = 1.0 + m.kappa_E * (dek - poly);
       },
       m.tol, m.maxit, it2);
-  const R ut = lift_newton(utn, U, utp);
-  const R qv = lift_newton(utn * upn, U, utp);
-  const R hd = 0.5 * ((U - qv) / (ys - y1));
+}
+
+// u_wm = u_tau u+ t, S_wm = (U - u_tau u+) / (2 (y_s - y1)) (t n + n t), u_tau.
+template <class R>
+__device__ __forceinline__ void wall_outputs(R U, const R t[3], R qv, R ut, const double nn[3], double y1,
+                                             const Model& m, R out[10]) {
+  const R hd = 0.5 * ((U - qv) / (m.y_s - y1));
   out[0] = qv * t[0];
   out[1] = qv * t[1];
   out[2] = qv * t[2];
@@ -494,6 +502,21 @@ __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], co
   out[7] = hd * (t[0] * nn[2] + nn[0] * t[2]);
   out[8] = hd * (t[1] * nn[2] + nn[1] * t[2]);
   out[9] = ut;
+}
+
+// Wall model of one cell given its probe velocity us, wall velocity uw,
+// outward normal nn, wall distance y1 and the previous friction velocity:
+// out = (u_wm[3], S[6] as xx yy zz xy xz yz, u_tau); false for a plain cell.
+template <class R>
+__device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], const double nn[3], double y1,
+                                           R utp, bool prev_active, const Model& m, R out[10], int& it1) {
+  it1 = 0;
+  R U, t[3];
+  if (!wall_slip<R>(us, uw, nn, U, t)) return false;
+  using RN = typename NewtonType<R>::type;
+  RN utn, upn;
+  wall_newtons<RN>(seed_newton(U, 0), seed_newton(utp, 1), prev_active, y1, m, utn, upn, it1);
+  wall_outputs<R>(U, t, lift_newton(utn * upn, U, utp), lift_newton(utn, U, utp), nn, y1, m, out);
   return true;
 }
 
@@ -650,18 +673,45 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
     group8_sum(us);
     int it1 = 0, done = 0;
     double usb[3] = {0.0, 0.0, 0.0};
+    // adjoint: the model with its 10 x 4 Jacobian with respect to (us,
+    // u_tau^prev).  The Newton solves depend on (U, u_tau^prev) only; lanes
+    // 0 and 1 of the group run them with one derivative direction each (the
+    // same value chain), and lane 0 takes lane 1's derivatives.
+    D4 o4[kAdj ? 10 : 1] = {};
+    bool slip = false;
+    if constexpr (kAdj) {
+      D4 ud[3];
+      for (int q = 0; q < 3; ++q) { ud[q] = dual::mk<4>(us[q]); ud[q].g[q] = 1.0; }
+      D4 up = dual::mk<4>(utp);
+      up.g[3] = 1.0;
+      D4 Ud, td[3];
+      D1 ut1{}, up1{};
+      if (corner < 2 && live) {
+        slip = wall_slip<D4>(ud, pr.uw, pr.nn, Ud, td);
+        if (slip) {
+          D1 Un, utpn;
+          Un.v = Ud.v;
+          Un.g[0] = corner == 0 ? 1.0 : 0.0;
+          utpn.v = utp;
+          utpn.g[0] = corner == 1 ? 1.0 : 0.0;
+          wall_newtons<D1>(Un, utpn, actp, pr.y1, m, ut1, up1, it1);
+        }
+      }
+      const int lead = int(threadIdx.x & 63) & ~7;
+      const double dut = __shfl(ut1.g[0], lead + 1, 64), dup = __shfl(up1.g[0], lead + 1, 64);
+      if (corner == 0 && live && slip) {
+        D2 ut2, up2;
+        ut2.v = ut1.v; ut2.g[0] = ut1.g[0]; ut2.g[1] = dut;
+        up2.v = up1.v; up2.g[0] = up1.g[0]; up2.g[1] = dup;
+        wall_outputs<D4>(Ud, td, lift_newton(ut2 * up2, Ud, up), lift_newton(ut2, Ud, up), pr.nn, pr.y1, m, o4);
+      }
+    }
     if (corner == 0 && live) {
       const int64_t T = total;
       bool active;
       double out[10];
-      D4 o4[kAdj ? 10 : 1];
       if constexpr (kAdj) {
-        // values and the 10 x 4 Jacobian with respect to (us, u_tau^prev)
-        D4 ud[3];
-        for (int q = 0; q < 3; ++q) { ud[q] = dual::mk<4>(us[q]); ud[q].g[q] = 1.0; }
-        D4 up = dual::mk<4>(utp);
-        up.g[3] = 1.0;
-        active = wall_solve<D4>(ud, pr.uw, pr.nn, pr.y1, up, actp, m, o4, it1);
+        active = slip;
         for (int q = 0; q < 10; ++q) out[q] = o4[q].v;
       } else {
         active = wall_solve<double>(us, pr.uw, pr.nn, pr.y1, utp, actp, m, out, it1);
