@@ -45,6 +45,13 @@ int64_t pop_row(const hlbm_desc* d) { return int64_t((d->nx + kTileX - 1) / kTil
 // Elements of one population buffer.
 int64_t pop_elems(const hlbm_desc* d) { return pop_row(d) * d->ny * d->nz; }
 
+// Force-partial slots of the workspace (kPartial FP64 each): one step's FSI
+// workgroups take at most one slot per sweep workgroup; up to kMaxBatch
+// steps' worth, capped at 2^20 slots (768 MiB) unless one step needs more.
+int64_t partial_slots(int64_t nblocks) {
+  return std::min<int64_t>(int64_t(kMaxBatch) * nblocks, std::max<int64_t>(nblocks, int64_t(1) << 20));
+}
+
 
 struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
@@ -72,7 +79,7 @@ Layout layout(const hlbm_desc* d) {
   L.uB = take((d->flags & HLBM_WITH_SOLID_VELOCITY) ? 3 * N * cs : 0);
   L.dd = take((d->flags & HLBM_WITH_CONTROL) ? N * cs : 0);
   L.blk = take(nb * 4);
-  L.partial = take(nb * kPartial * 8);
+  L.partial = take(partial_slots(nb) * kPartial * 8);
   L.partl1 = take(int64_t(kMaxBatch) * kPartL1 * kPartial * 8);
   L.mass = take(int64_t(kMaxBatch) * nb * 8);
   L.massl1 = take(int64_t(kMaxBatch) * kPartL1 * 8);
@@ -282,8 +289,9 @@ int rebuild_slots(hlbm_handle h) {
   int32_t n = 0;
   for (auto& f : flags) f = (f & 1) ? n++ : (f & 2) ? -2 : -1;
   h->nslots = n;
-  // the partial buffer holds nblocks slots: as many steps of slices as fit
-  h->batch = int32_t(std::max<int64_t>(1, std::min<int64_t>(kMaxBatch, h->L.nblocks / std::max<int32_t>(n, 1))));
+  // as many steps of slices as the partial buffer holds, at most kMaxBatch
+  h->batch = int32_t(
+      std::max<int64_t>(1, std::min<int64_t>(kMaxBatch, partial_slots(h->L.nblocks) / std::max<int32_t>(n, 1))));
   e = hipMemcpyAsync(h->L.blk_slot, flags.data(), sizeof(int32_t) * flags.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "write block slots");
