@@ -428,6 +428,10 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.g.ntx = (d->nx + kTileX - 1) / kTileX;
   L.g.nty = (d->ny + kTileY - 1) / kTileY;
   L.nblocks = int64_t(L.g.ntx) * L.g.nty * d->nz;
+  L.g.by_ntx = make_udiv(uint32_t(L.g.ntx));
+  L.g.by_plane = make_udiv(uint32_t(L.g.ntx) * uint32_t(L.g.nty));
+  L.g.by_span = make_udiv(8u * uint32_t(L.g.ntx));
+  L.g.grouped = uint32_t(L.nblocks / (8 * int64_t(L.g.ntx)) * (8 * int64_t(L.g.ntx)));
   const Layout& Y = h->lay;
   h->ws = base;
   h->set[0] = {base + Y.d_eff, reinterpret_cast<uint8_t*>(base + Y.tag), reinterpret_cast<double*>(base + Y.geo),

@@ -55,11 +55,36 @@ struct Model {
   uint64_t seed;
 };
 
+// Quotient of a 32-bit unsigned dividend by an invariant divisor d > 0 from
+// one multiply-high, a subtraction and two shifts, exact for every dividend
+// (Granlund and Montgomery, Division by invariant integers using
+// multiplication, PLDI 1994, Sec. 4): with l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, t = mulhi(m, n),
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0).
+struct Udiv {
+  uint32_t m, s1, s2;
+};
+inline Udiv make_udiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  // 2^l - d < 2^(l-1), so the product stays below 2^63
+  const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+  return Udiv{uint32_t(m), l < 1 ? l : 1u, l > 1 ? l - 1 : 0u};
+}
+__host__ __device__ inline uint32_t udiv(uint32_t n, const Udiv& v) {
+  const uint32_t t = uint32_t((uint64_t(v.m) * n) >> 32);
+  return (t + ((n - t) >> v.s1)) >> v.s2;
+}
+
 struct Geometry {
   int32_t nx, ny, nz, bc_x;
   int64_t N;
   int64_t row;         // population elements per (y, z) row: ntx blocks of 27 x kTileX
   int32_t ntx, nty;    // sweep tiles along x and y
+  // sweep tile order: divisors ntx, ntx nty (tiles per z plane) and 8 ntx
+  // (eight tile rows), and the tiles in whole groups of eight rows
+  Udiv by_ntx, by_plane, by_span;
+  uint32_t grouped;
 };
 
 // Blocked population layout: a row of the lattice is cut into blocks of

@@ -83,21 +83,31 @@ __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geome
     xp = x + 1 == g.nx ? x : x + 1;  // outflow: copy of the last plane
     xm = x == 0 ? 0 : x - 1;         // inflow plane is replaced below
   }
-  // the nine source rows (y - c_y, z - c_z) start at wave-uniform byte
-  // offsets; inside a row, a lane's offset is one of three 32-bit values
-  constexpr uint32_t es = sizeof(ST);
+  // The three velocities with the same (c_y, c_z) read the same source row
+  // (y - c_y, z - c_z), at population runs 9 apart.  Each of the nine rows
+  // gets one wave-uniform base (its start); a lane adds one of three 32-bit
+  // offsets, its source cell in the row plus 9 (c_x + 1) runs, and the load
+  // the constant 3 (c_y + 1) + (c_z + 1) runs as its immediate offset.
+  constexpr uint32_t es = sizeof(ST), run = kTileX * es;
   const uint64_t rs = uint64_t(g.row) * es;
-  const uint64_t rz[3] = {uint64_t(zp) * g.ny, uint64_t(z) * g.ny, uint64_t(zm) * g.ny};
-  const uint32_t ry[3] = {uint32_t(yp), uint32_t(y), uint32_t(ym)};
-  const uint32_t ox[3] = {pop_x(xp) * es, pop_x(x) * es, pop_x(xm) * es};
+  // index [c + 1] of each array: source z - c_z, y - c_y, x - c_x
+  const uint64_t zb[3] = {uint64_t(zp) * g.ny * rs, uint64_t(z) * g.ny * rs, uint64_t(zm) * g.ny * rs};
+  const uint64_t yb[3] = {uint64_t(yp) * rs, uint64_t(y) * rs, uint64_t(ym) * rs};
+  const uint32_t ox[3] = {pop_x(xp) * es, pop_x(x) * es + 9 * run, pop_x(xm) * es + 18 * run};
   gconst_bytes p = (gconst_bytes)src;
 #pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    gconst_bytes q = p + ((rz[cz_of(i) + 1] + ry[cy_of(i) + 1]) * rs + uint64_t(i * kTileX) * es);
-    // kept in scalar registers: one load of a scalar base plus a lane offset
-    asm("" : "+s"(q));
-    h[i] = CT(w_of(i)) * Store<ST>::template load<CT>((const ST*)(q + ox[cx_of(i) + 1]));
-  }
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gconst_bytes q = p + (zb[a] + yb[b]);
+      // kept in scalar registers: each load is this base plus a lane offset
+      asm("" : "+s"(q));
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int i = 9 * j + 3 * b + a;
+        h[i] = CT(w_of(i)) * Store<ST>::template load<CT>((const ST*)(q + ox[j] + (3 * b + a) * run));
+      }
+    }
   if (!kPeriodicX && x == 0) {
     const int64_t plane = int64_t(g.ny) * g.nz;
     const int64_t pz[3] = {int64_t(zp) * g.ny, int64_t(z) * g.ny, int64_t(zm) * g.ny};
@@ -105,6 +115,18 @@ __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geome
 #pragma unroll
     for (int i = 18; i < 27; ++i) h[i] = ghost[(i - 18) * plane + pz[cz_of(i) + 1] + py[cy_of(i) + 1]];
   }
+}
+
+// Position (z, tile row, tile column) of sweep tile blk; tile ids and counts
+// fit 32 bits (fewer than 2^31 cells, 256 per tile).
+struct TileId {
+  int z, ty, tx;
+};
+__device__ __forceinline__ TileId tile_id(const Geometry& g, uint32_t blk) {
+  const uint32_t z = udiv(blk, g.by_plane);
+  const uint32_t rem = blk - z * (uint32_t(g.ntx) * uint32_t(g.nty));
+  const uint32_t ty = udiv(rem, g.by_ntx);
+  return TileId{int(z), int(ty), int(rem - ty * uint32_t(g.ntx))};
 }
 
 // Inflow ghost plane of step n: h_i = f^eq_i(1, u_in(n, y, z)) - w_i for the
@@ -958,10 +980,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   const Geometry& g = a.g;
   // tile (tx, ty, z): 64 consecutive x-cells per wave, 4 y-rows per workgroup
   // tile ids and counts fit 32 bits (fewer than 2^31 cells, 256 per tile)
-  const uint32_t tpz = uint32_t(g.ntx) * uint32_t(g.nty);
-  const int z = int(uint32_t(blk) / tpz);
-  const uint32_t trem = uint32_t(blk) - uint32_t(z) * tpz;
-  const int ty = int(trem / uint32_t(g.ntx)), tx = int(trem - uint32_t(ty) * uint32_t(g.ntx));
+  const TileId ti = tile_id(g, blk);
+  const int z = ti.z, ty = ti.ty, tx = ti.tx;
   const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
   // one row per wave: y is uniform over the wave
   const int yr = __builtin_amdgcn_readfirstlane(ty * kTileY + int(threadIdx.x >> 6));
@@ -1076,13 +1096,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   if (!kMoments) {
     if (valid) {
       // this wave's block: contiguous, 27 runs of kTileX cells
-      gbytes p = (gbytes)(static_cast<ST*>(a.dst) + (int64_t(z) * g.ny + y) * g.row + int64_t(tx) * (27 * kTileX));
+      // one scalar base per group of runs that the 12-bit immediate offset
+      // of a store reaches (FP16 27 runs, FP32 16, FP64 8)
+      constexpr int run = kTileX * sizeof(ST), per = 4096 / run;
+      const gbytes p = (gbytes)(static_cast<ST*>(a.dst) + (int64_t(z) * g.ny + y) * g.row + int64_t(tx) * (27 * kTileX));
       const uint32_t o = uint32_t(x % kTileX) * uint32_t(sizeof(ST));
 #pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        Store<ST>::template store<CT>((ST*)(p + o), g2[i]);
-        p += kTileX * sizeof(ST);
-        asm("" : "+s"(p));
+      for (int i0 = 0; i0 < 27; i0 += per) {
+        gbytes q = p + int64_t(i0) * run;
+        asm("" : "+s"(q));
+#pragma unroll
+        for (int i = i0; i < 27 && i < i0 + per; ++i) Store<ST>::template store<CT>((ST*)(q + o + (i - i0) * run), g2[i]);
       }
     }
     if (a.mass_part) {
@@ -1103,17 +1127,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
 // share are fetched into one L2, while the eight XCDs sweep eight adjacent
 // tile rows of the lattice at a time.  Workgroups past the last full group
 // of eight rows keep lattice order.
-__device__ __forceinline__ uint32_t tile_of(uint32_t i, uint32_t ntiles, uint32_t ntx) {
-  const uint32_t span = 8u * ntx;
-  if (i >= (ntiles / span) * span) return i;
-  const uint32_t c = i / span, r = i - c * span;
-  return c * span + (r % 8u) * ntx + r / 8u;
+__device__ __forceinline__ uint32_t tile_of(uint32_t i, const Geometry& g) {
+  if (i >= g.grouped) return i;
+  const uint32_t ntx = uint32_t(g.ntx);
+  const uint32_t r = i - udiv(i, g.by_span) * (8u * ntx);
+  return i - r + (r % 8u) * ntx + r / 8u;
 }
 
 template <class ST, class CT, bool kPeriodicX, bool kMoments>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   __shared__ double lds[4][kPartial];
-  const uint32_t blk = tile_of(blockIdx.x, gridDim.x, uint32_t(a.g.ntx));
+  const uint32_t blk = tile_of(blockIdx.x, a.g);
   sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
 }
 
@@ -1363,12 +1387,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
     if (k < a.nzero) a.zero[k] = 0.0;
     return;
   }
-  const int64_t blk = tile_of(blockIdx.x, uint32_t(a.nblocks), uint32_t(g.ntx));
-  // tile ids and counts fit 32 bits (fewer than 2^31 cells, 256 per tile)
-  const uint32_t tpz = uint32_t(g.ntx) * uint32_t(g.nty);
-  const int z = int(uint32_t(blk) / tpz);
-  const uint32_t trem = uint32_t(blk) - uint32_t(z) * tpz;
-  const int ty = int(trem / uint32_t(g.ntx)), tx = int(trem - uint32_t(ty) * uint32_t(g.ntx));
+  const uint32_t blk = tile_of(blockIdx.x, g);
+  const TileId ti = tile_id(g, blk);
+  const int z = ti.z, ty = ti.ty, tx = ti.tx;
   const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
   // one row per wave: y is uniform over the wave
   const int yr = __builtin_amdgcn_readfirstlane(ty * kTileY + int(threadIdx.x >> 6));
