@@ -77,3 +77,77 @@ def test_storage_error_vs_fp64_oracle(case, storage):
     assert np.isfinite(hg).all()
     assert e_h < bound
     assert e_u < 4 * bound
+
+
+# D3Q27 weights in the canonical order i = 9 (cx + 1) + 3 (cy + 1) + (cz + 1)
+_C = np.array([(i // 9 - 1, (i // 3) % 3 - 1, i % 3 - 1) for i in range(27)])
+_WEIGHT = np.array([{0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}[int((c * c).sum())] for c in _C])[:, None]
+
+
+def _to_storage(storage, g):
+    """Nearest value representable in the storage type (FP16 or BF16)."""
+    if storage == "f16":
+        return g.astype(np.float16).astype(np.float64)
+    b = g.astype(np.float32).view(np.uint32)
+    r = ((b + np.uint32(0x7FFF) + ((b >> np.uint32(16)) & np.uint32(1))) >> np.uint32(16)) << np.uint32(16)
+    return r.view(np.float32).astype(np.float64)
+
+
+def _ulp(storage, g):
+    """Spacing of the storage type at |g| (at least its smallest subnormal)."""
+    a = np.abs(g)
+    if storage == "f16":
+        return np.spacing(a.astype(np.float16)).astype(np.float64)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+def _one_step_workloads():
+    w1 = W.config1(noise=True)
+    w2 = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    w2.noise_seed = 5
+    out = [w1, w2]
+    for (nx, ny, nz), bc in (((3, 2, 1), W.BC_PERIODIC), ((130, 1, 3), W.BC_INFLOW_OUTFLOW),
+                             ((65, 9, 5), W.BC_INFLOW_OUTFLOW)):
+        p = W.Params(tau0=0.6, cs_smag=0.12, eps_h=2.0, wall_model=0, u_in=(0.03, 0.01, 0.0), turb_I=0.05, seed=11)
+        out.append(W.Workload(f"plain_{nx}x{ny}x{nz}", nx, ny, nz, bc, p, [], 4, init="uniform", u0=0.02,
+                              noise_seed=3))
+    for w in out:
+        w.noise_amp = 2e-2
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("wi", range(5))
+def test_reduced_storage_one_step_is_rounded_oracle_step(wi, storage):
+    """From the same state, representable in the storage type (the oracle's
+    seeded initial state rounded with numpy), one step of the HIP path
+    stores the oracle's FP64 post-collision deviation g rounded once: within
+    one unit in the last place of the storage type at the value plus the
+    FP32 compute error, at every population of every cell.  A tile that the
+    sweep skipped or visited twice would be off by the whole step's change
+    (the seeded non-equilibrium part of amplitude 2e-2, relaxed by the
+    collision), which the test also requires to be far above the bound."""
+    from paper_2510_13726_amd import hlbm
+    w = _one_step_workloads()[wi]
+    print(f"[precision] one step {w.name} {w.nx}x{w.ny}x{w.nz} {storage}", flush=True)
+    o = O.setup(w)
+    g0 = _to_storage(storage, o.get_populations() / _WEIGHT)
+    h0 = g0 * _WEIGHT
+    o.set_populations(h0)
+    lat = hlbm.setup(w, storage=storage)
+    lat.set_populations(h0)
+    # the stored state is g0 (h / w and back round in the last FP64 place)
+    assert np.abs(lat.get_populations().cpu().numpy() / _WEIGHT - g0).max() <= 1e-14
+    lat.step(1)
+    o.step(1)
+    g_gpu = lat.get_populations().cpu().numpy() / _WEIGHT
+    g_ref = o.get_populations() / _WEIGHT
+    lat.close()
+    bound = _ulp(storage, g_ref) + 2e-5 * np.abs(g_ref).max()
+    err = np.abs(g_gpu - g_ref)
+    moved = np.abs(g_ref - g0) > 4 * bound
+    print(f"[precision] one step {w.name} {storage}: max err/bound {float((err / bound).max()):.3f} "
+          f"moved {float(moved.mean()):.3f}", flush=True)
+    assert (err <= bound).all()
+    assert moved.mean() > 0.5
