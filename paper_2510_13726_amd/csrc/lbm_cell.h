@@ -64,12 +64,11 @@ template <> struct Store<bf16_t> {
     uint32_t b = uint32_t(*reinterpret_cast<const uint16_t*>(p)) << 16;
     return CT(__uint_as_float(b));
   }
+  // FP32 -> BF16 in the hardware convert of gfx950 (round to nearest even,
+  // a NaN stays a NaN)
   template <class CT> __device__ static void store(bf16_t* p, CT v) {
-    float f = float(v);
-    uint32_t b = __float_as_uint(f);
-    uint32_t r = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
-    if ((b & 0x7fffffffu) > 0x7f800000u) r = (b >> 16) | 0x40u;  // keep NaN a NaN
-    __builtin_nontemporal_store(uint16_t(r), reinterpret_cast<uint16_t*>(p));
+    const __bf16 b = static_cast<__bf16>(float(v));
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, b), reinterpret_cast<uint16_t*>(p));
   }
 };
 
