@@ -86,7 +86,8 @@ typedef struct {
  * distance y_s, Newton tolerance tol on |f(u^{j+1}) - f(u^j)| and iteration
  * cap maxit; u_in inflow velocity, turb_I inflow turbulence intensity and its
  * seed; diag_every: every k-th step also reduces the total mass and checks
- * for non-finite densities (0 = never); check_nonfinite: hlbm_step
+ * for non-finite densities (0 = never); check_nonfinite: every step checks
+ * for non-finite densities (whatever diag_every is), and hlbm_step
  * synchronizes at its end and reports HLBM_ERR_NONFINITE. */
 typedef struct {
   double tau0, cs_smag, eps_h;
@@ -128,7 +129,11 @@ int hlbm_lattice_create(const hlbm_desc* desc, void* pop_a, void* pop_b, void* w
 /* Destroy a handle; never frees caller memory.  NULL is a no-op. */
 void hlbm_lattice_destroy(hlbm_handle h);
 
-/* Parameters (validated: tau0 > 1/2, cs_smag >= 0, eps_h > 0, maxit >= 1). */
+/* Parameters (validated: tau0 > 1/2, cs_smag >= 0, eps_h > 0, maxit >= 1).
+ * With rotors set, a change of eps_h, y_s or the wall-model switch can move
+ * the rotors' fixed boxes: cells leaving them return to the static field,
+ * and the per-cell wall-model state (u_tau^prev, active, Sec. 2.2.1) of
+ * every cell stays with that cell.  Invalidates a forward record. */
 int hlbm_set_params(hlbm_handle h, const hlbm_params* p);
 
 /* Rotors rasterized on the GPU every step (Sec. 3.1); n <= HLBM_MAX_ROTORS,
@@ -136,19 +141,27 @@ int hlbm_set_params(hlbm_handle h, const hlbm_params* p);
  * domain and within desc->bbox_cells.  n = 0 removes all rotors. */
 int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* rotors, int32_t n);
 
-/* Static porosity field d (device, compute type, N values, 0 <= d <= 1) and
- * tags (device, uint8, N values, 0..15); both are copied.  NULL d clears the
- * field (d = 0 everywhere), NULL tag sets tag 0. */
+/* Static porosity field: the lattice porosity d of Def. Lattice Porosity
+ * (Sec. 2.2.2) entering eq. convexVelocity, device, compute type, N values,
+ * 0 <= d <= 1 (1 solid, 0 fluid), and the tag of the solid element each cell
+ * belongs to (device, uint8, N values, 0..15; the per-element force and
+ * torque of Sec. 2.2.2 sum over one tag); both are copied.  NULL d clears
+ * the field (d = 0 everywhere), NULL tag sets tag 0.  Rotor cells override
+ * both where a rotor covers them (d = max(static, rotor)).  Invalidates a
+ * forward record. */
 int hlbm_set_porosity_field(hlbm_handle h, const void* d, const uint8_t* tag);
 
-/* Static solid velocity u^B (device, compute type, [3][N]) used where the
- * cell is not covered by a rotor; copied.  Needs HLBM_WITH_SOLID_VELOCITY.
- * NULL resets to zero. */
+/* Static solid velocity u^B of eq. convexVelocity (Sec. 2.2: the velocity
+ * toward which the porosity drives a cell), device, compute type, [3][N],
+ * used where the cell is not covered by a rotor (rotor cells take the rigid
+ * rotation Omega e x (x - x_c) of Sec. 3.1); copied.  Needs
+ * HLBM_WITH_SOLID_VELOCITY.  NULL resets to zero. */
 int hlbm_set_solid_velocity(hlbm_handle h, const void* uB);
 
 /* Porosity control delta_d (device, compute type, N values) added to the
  * porosity of every cell (d = max(d_static, d_rotor) + delta_d); copied.
- * Needs HLBM_WITH_CONTROL.  NULL resets to zero. */
+ * Needs HLBM_WITH_CONTROL.  NULL resets to zero.  Invalidates a forward
+ * record. */
 int hlbm_set_control(hlbm_handle h, const void* dd);
 
 /* Reference frame (torque centre, axis) of a tag set through the static
@@ -190,11 +203,18 @@ int hlbm_get_state(hlbm_handle h, void* dst);
 int hlbm_set_state(hlbm_handle h, const void* src);
 
 /* Force F and torque T (about the tag's centre) handed to the solid with
- * this tag by the last step, FP64 host (syncs). */
+ * this tag by the last step: the per-element force of Sec. 2.2.2 summed per
+ * tag as in Sec. 3.1 (here the momentum j - rho u_hat each cell's collision
+ * hands to the solid, eq. convexVelocity; T = sum (x - x_c) x that
+ * momentum), FP64 sums in a fixed order, host (syncs).  HLBM_ERR_STATE
+ * before the first step. */
 int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]);
 /* Records of steps [from, to) (absolute step numbers still in the ring),
- * HLBM_HIST_STRIDE doubles each, host (syncs).  Mass is NaN on steps
- * without diagnostics. */
+ * HLBM_HIST_STRIDE doubles each, host (syncs): per step the total mass
+ * sum rho, then for tags 1..15 the force and torque of hlbm_force_torque
+ * (the per-step force history of the time loop of Sec. 3.2, the thrust and
+ * torque histories of Sec. 4).  Mass is NaN on steps without diagnostics.
+ * HLBM_ERR_INVALID for steps outside the ring. */
 int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
 
 /* Discrete adjoint of the time stepping (gradient of the time-averaged
@@ -211,6 +231,10 @@ int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
  * differentiated as executed.  The lattice state is left unchanged. */
 int64_t hlbm_checkpoint_bytes(hlbm_handle h, int64_t nsteps, int32_t ckpt_every);
 int64_t hlbm_adjoint_stack_bytes(hlbm_handle h, int32_t ckpt_every);
+/* A record is invalidated by any call that steps the lattice or changes its
+ * state or inputs (hlbm_step, set_state, set_populations,
+ * init_equilibrium, set_params, set_rotors, set_porosity_field,
+ * set_control): hlbm_adjoint then returns HLBM_ERR_STATE. */
 int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, int32_t obj_tag, int32_t ckpt_every,
                         void* ckpt, int64_t ckpt_bytes, double* J);
 int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack_bytes);
@@ -219,6 +243,13 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
  * (every diag_every-th step): Newton iterations for u_tau and wall cells
  * solved (host, syncs). */
 int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
+
+/* Safeguards of the wall model's Newton iterations (Sec. 2.2.1) taken since
+ * creation on diagnostics steps: iterates that went non-positive and were
+ * replaced by half the previous one, and evaluations whose exponential
+ * argument exceeded 80 and took the cap (host, syncs).  Both stay zero on
+ * well-posed runs. */
+int hlbm_wall_safeguards(hlbm_handle h, int64_t* halvings, int64_t* caps);
 
 /* Opt-in kernel timing with HIP events recorded on the lattice's stream
  * around every launch of the given kernel class during hlbm_step

@@ -162,7 +162,28 @@ int oracle_history(void* h, int64_t from, int64_t to, double* dst) {
   return 0;
 }
 int64_t oracle_history_len(void* h) { return (int64_t)((SimD*)h)->hist.size() / HIST; }
-void oracle_clear_history(void* h) { ((SimD*)h)->hist.clear(); }
+void oracle_clear_history(void* h) { ((SimD*)h)->hist.clear(); ((SimD*)h)->hist_scale.clear(); }
+// Per recorded step [from, to) and tag 1..15: sum of |dP| and of |r x dP|
+// over the tag's cells (30 doubles per step).
+int oracle_history_scale(void* h, int64_t from, int64_t to, double* dst) {
+  SimD* s = (SimD*)h;
+  int64_t n = (int64_t)s->hist_scale.size() / 30;
+  if (from < 0 || to > n || from > to) return 1;
+  std::memcpy(dst, s->hist_scale.data() + from * 30, sizeof(double) * 30 * (to - from));
+  return 0;
+}
+// Newton halvings, exponential caps and near-threshold slips since creation.
+void oracle_wall_safeguards(void* h, int64_t* out) {
+  const WallStats& w = ((SimD*)h)->wstats;
+  out[0] = w.halvings;
+  out[1] = w.capped;
+  out[2] = w.near_threshold;
+}
+// Trilinear sample of a scalar field q ([z][y][x]) at X with the wall model's
+// boundary handling (periodic y, z; x periodic or clamped).
+double oracle_trilinear(const double* q, int nx, int ny, int nz, int bc_x, const double* X) {
+  return trilinear(q, nx, ny, nz, bc_x, X);
+}
 int64_t oracle_wall_newton_iters(void* h) { return ((SimD*)h)->wstats.newton_iters; }
 int64_t oracle_wall_calls(void* h) { return ((SimD*)h)->wstats.calls; }
 
@@ -200,7 +221,8 @@ void oracle_collide_cell(const double* m, double d, const double* uB, const doub
 }
 void oracle_moments_of(const double* f, double* m) { moments_of(f, m); }
 double oracle_spalding_yplus(double up, double E, double kappa) { return up + spalding_bracket(kappa * up) / E; }
-// out = (uwm[3], S[6], utau, active); returns Newton iterations for u_tau.
+// out = (uwm[3], S[6], utau, active, Newton halvings, exponential caps);
+// returns Newton iterations for u_tau.
 int oracle_wall_cell(const double* us, const double* uw, const double* n, double y1, double utau_prev,
                      int prev_active, const or_params* q, double* out, int* iters_plus) {
   Params p = to_params(q);
@@ -210,6 +232,8 @@ int oracle_wall_cell(const double* us, const double* uw, const double* n, double
   for (int k = 0; k < 6; ++k) out[3 + k] = o.S[k];
   out[9] = o.utau;
   out[10] = o.active ? 1.0 : 0.0;
+  out[11] = o.halvings;
+  out[12] = o.capped;
   if (iters_plus) *iters_plus = o.iters_plus;
   return o.iters_tau;
 }

@@ -222,18 +222,32 @@ T spalding_dbracket(const T& k) {  // d/dk of the bracket (the capped exponentia
   return ek - 1.0 - k - k * k / 2.0;
 }
 
-struct WallStats { int64_t newton_iters = 0; int64_t calls = 0; int64_t capped = 0; };
+// Counters of the wall model: Newton iterations for u_tau and cells solved;
+// the safeguards of the Newton iterations (a non-positive iterate halved,
+// an exponential argument capped at 80), which the parity cases must never
+// reach; wall cells whose tangential slip lies within a factor two of the
+// 1e-6 activity bound (where FP32 and FP64 could take different branches).
+struct WallStats {
+  int64_t newton_iters = 0;
+  int64_t calls = 0;
+  int64_t halvings = 0;
+  int64_t capped = 0;
+  int64_t near_threshold = 0;
+};
 
 // Newton-Raphson with the paper's stop rule |f(u^{j+1}) - f(u^j)| < tol, at most
 // maxit iterations (Sec. 2.2.1); a non-positive iterate is replaced by half the
-// previous one.
+// previous one (counted in *halvings).
 template <class T, class F, class DF>
-T newton(T u, F f, DF df, double tol, int maxit, int* iters) {
+T newton(T u, F f, DF df, double tol, int maxit, int* iters, int* halvings = nullptr) {
   T fu = f(u);
   int it = 0;
   for (; it < maxit; ++it) {
     T un = u - fu / df(u);
-    if (re(un) <= 0.0) un = 0.5 * u;
+    if (re(un) <= 0.0) {
+      un = 0.5 * u;
+      if (halvings) ++*halvings;
+    }
     T fn = f(un);
     bool done = std::fabs(re(fn) - re(fu)) < tol;
     u = un;
@@ -264,6 +278,8 @@ struct WallOut {
   T utau;
   bool active;
   int iters_tau, iters_plus;
+  double slip;          // tangential slip U (also for an inactive cell)
+  int halvings, capped; // Newton safeguards taken (both solves)
 };
 
 // Wall model at one wall cell (Sec. 2.2.1 and Sec. 3.2):
@@ -284,6 +300,8 @@ WallOut<T> wall_model_cell(const T us[3], const double uw[3], const double n[3],
   for (int a = 0; a < 3; ++a) vt[a] = v[a] - vn * n[a];
   T U2 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
   o.iters_tau = o.iters_plus = 0;
+  o.halvings = o.capped = 0;
+  o.slip = std::sqrt(re(U2));
   // below a tangential slip of 1e-6 lattice units (2e-5 of the free-stream
   // speed of the rotor workloads) the wall law is not applied: the slip
   // direction t is undefined as U -> 0 (on a rotor axis U vanishes by
@@ -300,9 +318,11 @@ WallOut<T> wall_model_cell(const T us[3], const double uw[3], const double n[3],
   for (int a = 0; a < 3; ++a) t[a] = vt[a] / U;
   const double ys = p.y_s, E = p.E, kap = p.kappa;
   T guess = prev_active ? utau_prev : sqrt(nu * U / ys);
+  // an evaluation whose exponential argument exceeds 80 takes the cap
+  auto cap = [&](const T& k) { if (re(k) > 80.0) ++o.capped; };
   T ut = newton(
-      guess, [&](const T& x) { return wall_f(x, U, ys, nu, E, kap); },
-      [&](const T& x) { return wall_df(x, U, ys, nu, E, kap); }, p.tol, p.maxit, &o.iters_tau);
+      guess, [&](const T& x) { cap(kap * (U / x)); return wall_f(x, U, ys, nu, E, kap); },
+      [&](const T& x) { return wall_df(x, U, ys, nu, E, kap); }, p.tol, p.maxit, &o.iters_tau, &o.halvings);
   // u+ at the cell: Newton on Spalding's law from the two-layer estimate
   // min(y+, ln(E max(y+,1))/kappa) (viscous sublayer below y+ ~ 11, log law above)
   using std::log;
@@ -311,9 +331,9 @@ WallOut<T> wall_model_cell(const T us[3], const double uw[3], const double n[3],
   T ulog = log(E * yl) / kap;
   T up0 = re(ulog) < re(yp) ? ulog : yp;
   T up = newton(
-      up0, [&](const T& x) { return x + spalding_bracket(kap * x) / E - yp; },
+      up0, [&](const T& x) { cap(kap * x); return x + spalding_bracket(kap * x) / E - yp; },
       [&](const T& x) { return 1.0 + kap * spalding_dbracket(kap * x) / E; }, p.tol, p.maxit,
-      &o.iters_plus);
+      &o.iters_plus, &o.halvings);
   T q = ut * up;
   for (int a = 0; a < 3; ++a) o.uwm[a] = q * t[a];
   T dudn = (U - q) / (ys - y1);

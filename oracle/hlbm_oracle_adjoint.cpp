@@ -224,7 +224,7 @@ int oracle_adjoint_run(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int obj
   s.obj_on = false;
   *J_out = s.J;
   const Snapshot fin = snap(s);
-  const size_t hist_len = s.hist.size();
+  const size_t hist_len = s.hist.size(), scale_len = s.hist_scale.size();
   const double wgt = 1.0 / double(t1 - t0);
   std::vector<double> lam((size_t)Q * N, 0.0), lam2((size_t)Q * N), UT(N, 0.0), UT2(N);
   for (int64_t c = 0; c < N; ++c) G[c] = 0.0;
@@ -246,6 +246,7 @@ int oracle_adjoint_run(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int obj
   }
   restore(s, fin);
   s.hist.resize(hist_len);
+  s.hist_scale.resize(scale_len);
   return 0;
 }
 

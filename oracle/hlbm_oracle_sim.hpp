@@ -18,6 +18,34 @@ namespace oracle {
 constexpr int NTAG = 16;         // tags 0..15; tag 0 means "no solid element"
 constexpr int HIST = 1 + 15 * 6; // per step: mass, then (F, T) for tags 1..15
 
+// Trilinear interpolation of a cell-centred field q (layout [z][y][x]) at
+// point X (Sec. 3.2: the wall model samples the velocity at a configurable
+// distance from the wall): the eight cells around X weighted by products of
+// the fractional offsets, y and z periodic, x periodic or clamped to the
+// first and last plane (inflow/outflow lattices).
+template <class T>
+T trilinear(const T* q, int nx, int ny, int nz, int bc_x, const double X[3]) {
+  const int n3[3] = {nx, ny, nz};
+  int i0[3];
+  double fr[3];
+  for (int a = 0; a < 3; ++a) { double fl = std::floor(X[a]); i0[a] = (int)fl; fr[a] = X[a] - fl; }
+  T acc = T(0.0);
+  for (int corner = 0; corner < 8; ++corner) {
+    int c[3];
+    double wgt = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      int bit = (corner >> a) & 1;
+      c[a] = i0[a] + bit;
+      wgt *= bit ? fr[a] : 1.0 - fr[a];
+    }
+    for (int a = 1; a < 3; ++a) c[a] = ((c[a] % n3[a]) + n3[a]) % n3[a];
+    if (bc_x == 0) c[0] = ((c[0] % nx) + nx) % nx;
+    else c[0] = c[0] < 0 ? 0 : (c[0] > nx - 1 ? nx - 1 : c[0]);
+    acc = acc + wgt * q[((int64_t)c[2] * ny + c[1]) * nx + c[0]];
+  }
+  return acc;
+}
+
 template <class T>
 struct Sim {
   int nx = 0, ny = 0, nz = 0, bc_x = 0;  // bc_x: 0 periodic, 1 inflow at x=0 / outflow at x=nx-1
@@ -34,6 +62,9 @@ struct Sim {
   std::vector<uint8_t> active;
   int64_t step = 0;
   std::vector<double> hist;               // HIST doubles per recorded step
+  // per recorded step and tag 1..15: sum over the tag's cells of |dP| and of
+  // |(x - x_c) x dP| (the scales of the force and torque sums)
+  std::vector<double> hist_scale;
   WallStats wstats;
   int nthreads = 1;
 
@@ -173,26 +204,7 @@ struct Sim {
 
   // trilinear interpolation of the fluid velocity at a point
   void sample_u(const double X[3], T us[3]) const {
-    const int n3[3] = {nx, ny, nz};
-    int i0[3];
-    double fr[3];
-    for (int a = 0; a < 3; ++a) { double fl = std::floor(X[a]); i0[a] = (int)fl; fr[a] = X[a] - fl; }
-    for (int a = 0; a < 3; ++a) us[a] = T(0.0);
-    for (int corner = 0; corner < 8; ++corner) {
-      int q[3];
-      double wgt = 1.0;
-      for (int a = 0; a < 3; ++a) {
-        int bit = (corner >> a) & 1;
-        q[a] = i0[a] + bit;
-        wgt *= bit ? fr[a] : 1.0 - fr[a];
-      }
-      q[1] = wrap(q[1], n3[1]);
-      q[2] = wrap(q[2], n3[2]);
-      if (bc_x == 0) q[0] = wrap(q[0], n3[0]);
-      else q[0] = q[0] < 0 ? 0 : (q[0] > nx - 1 ? nx - 1 : q[0]);
-      const int64_t cc = idx(q[0], q[1], q[2]);
-      for (int a = 0; a < 3; ++a) us[a] = us[a] + wgt * u[(size_t)a * N + cc];
-    }
+    for (int a = 0; a < 3; ++a) us[a] = trilinear(&u[(size_t)a * N], nx, ny, nz, bc_x, X);
   }
 
   // -------------------------------------------------- 4. wall model
@@ -203,8 +215,8 @@ struct Sim {
     const double nu = CS2 * (p.tau0 - 0.5);
     std::vector<T> ut_new(N, T(0.0));
     std::vector<uint8_t> act_new(N, 0);
-    int64_t iters = 0, calls = 0;
-#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(+ : iters, calls)
+    int64_t iters = 0, calls = 0, halv = 0, capd = 0, near = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(+ : iters, calls, halv, capd, near)
     for (int64_t c = 0; c < N; ++c) {
       if (!g_wall[c]) continue;
       const int x = int(c % nx), y = int((c / nx) % ny), z = int(c / ((int64_t)nx * ny));
@@ -222,6 +234,9 @@ struct Sim {
       T us[3];
       sample_u(xs, us);
       WallOut<T> o = wall_model_cell(us, uw, nn, y1, utau[c], active[c] != 0, p, nu);
+      halv += o.halvings;
+      capd += o.capped;
+      if (o.slip >= 0.5e-6 && o.slip <= 2e-6) near += 1;
       if (o.active) {
         for (int a = 0; a < 3; ++a) uwm[(size_t)a * N + c] = o.uwm[a];
         for (int k = 0; k < 6; ++k) Swm[(size_t)k * N + c] = o.S[k];
@@ -234,6 +249,9 @@ struct Sim {
     }
     wstats.newton_iters += iters;
     wstats.calls += calls;
+    wstats.halvings += halv;
+    wstats.capped += capd;
+    wstats.near_threshold += near;
     utau.swap(ut_new);
     active.swap(act_new);
   }
@@ -255,7 +273,7 @@ struct Sim {
       rho[c] = m[0];
     }
     // fixed (z, y, x) order FP64 sums
-    std::vector<double> rec(HIST, 0.0);
+    std::vector<double> rec(HIST, 0.0), scl(2 * 15, 0.0);
     T Tax = T(0.0);
     T mass = T(0.0);
     for (int z = 0; z < nz; ++z)
@@ -270,11 +288,14 @@ struct Sim {
           const T tq[3] = {r[1] * dp[2] - r[2] * dp[1], r[2] * dp[0] - r[0] * dp[2], r[0] * dp[1] - r[1] * dp[0]};
           double* o = &rec[1 + 6 * (t - 1)];
           for (int a = 0; a < 3; ++a) { o[a] += re(dp[a]); o[3 + a] += re(tq[a]); }
+          scl[2 * (t - 1)] += std::sqrt(re(dp[0]) * re(dp[0]) + re(dp[1]) * re(dp[1]) + re(dp[2]) * re(dp[2]));
+          scl[2 * (t - 1) + 1] += std::sqrt(re(tq[0]) * re(tq[0]) + re(tq[1]) * re(tq[1]) + re(tq[2]) * re(tq[2]));
           if (obj_on && (obj_tag == 0 || obj_tag == t))
             Tax = Tax + tag_axis[t][0] * tq[0] + tag_axis[t][1] * tq[1] + tag_axis[t][2] * tq[2];
         }
     rec[0] = re(mass);
     hist.insert(hist.end(), rec.begin(), rec.end());
+    hist_scale.insert(hist_scale.end(), scl.begin(), scl.end());
     if (obj_on && step >= obj_t0 && step < obj_t1) J = J + Tax / double(obj_t1 - obj_t0);
   }
 
@@ -302,6 +323,7 @@ struct Sim {
     std::fill(active.begin(), active.end(), 0);
     step = 0;
     hist.clear();
+    hist_scale.clear();
   }
 };
 

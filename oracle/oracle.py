@@ -67,6 +67,11 @@ def lib():
         L.oracle_wall_calls.restype = C.c_int64
         L.oracle_wall_calls.argtypes = [C.c_void_p]
         L.oracle_geometry.argtypes = [C.c_void_p, _D, _U8, _U8, _D, _D, _D]
+        L.oracle_history_scale.restype = C.c_int
+        L.oracle_history_scale.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _D]
+        L.oracle_wall_safeguards.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.oracle_trilinear.restype = C.c_double
+        L.oracle_trilinear.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_int, _D]
         L.oracle_lattice.argtypes = [C.POINTER(C.c_int32), _D]
         L.oracle_equilibrium.argtypes = [C.c_double, _D, _D]
         L.oracle_collide_cell.argtypes = [_D, C.c_double, _D, _D, _D, C.c_double, C.c_double, C.c_double, _D, _D]
@@ -219,6 +224,21 @@ class OracleLattice:
             self.L.oracle_history(self.h, 0, n, _p(out))
         return out
 
+    def history_scale(self):
+        """Per recorded step, (15, 2): sum over each tag's cells of |dP| and of
+        |(x - x_c) x dP| -- the scales of the force and torque sums."""
+        n = self.L.oracle_history_len(self.h)
+        out = np.empty((n, 15, 2))
+        if n:
+            self.L.oracle_history_scale(self.h, 0, n, _p(out))
+        return out
+
+    def wall_safeguards(self):
+        """(Newton halvings, exponential caps, wall cells with slip in [0.5e-6, 2e-6])."""
+        out = np.zeros(3, dtype=np.int64)
+        self.L.oracle_wall_safeguards(self.h, out.ctypes.data_as(C.POINTER(C.c_int64)))
+        return tuple(int(v) for v in out)
+
     def clear_history(self):
         self.L.oracle_clear_history(self.h)
 
@@ -312,12 +332,12 @@ def spalding_yplus(uplus, E=9.8, kappa=0.41):
 def wall_cell(us, uw, n, y1, params, utau_prev=0.0, prev_active=False):
     q = make_params(params)
     us, uw, n = (_f64(np.asarray(v, dtype=np.float64)) for v in (us, uw, n))
-    out = np.empty(11)
+    out = np.empty(13)
     ip = C.c_int(0)
     it = lib().oracle_wall_cell(_p(us), _p(uw), _p(n), float(y1), float(utau_prev), int(prev_active),
                                 C.byref(q), _p(out), C.byref(ip))
     return dict(uwm=out[0:3].copy(), S=out[3:9].copy(), utau=out[9], active=bool(out[10]),
-                iters=it, iters_plus=ip.value)
+                iters=it, iters_plus=ip.value, halvings=int(out[11]), capped=int(out[12]))
 
 
 def rotor_phi(rotor, x, n=0):
@@ -326,6 +346,14 @@ def rotor_phi(rotor, x, n=0):
     g = np.empty(3)
     phi = lib().oracle_rotor_phi(C.byref(r), _p(x), int(n), _p(g))
     return phi, g
+
+
+def trilinear(q, shape, bc_x, X):
+    """The wall model's trilinear probe sample of a scalar field q (nz, ny, nx)."""
+    nx, ny, nz = shape
+    q = _f64(np.asarray(q).reshape(-1))
+    X = _f64(np.asarray(X, dtype=np.float64))
+    return lib().oracle_trilinear(_p(q), nx, ny, nz, int(bc_x), _p(X))
 
 
 def transition(phi, eps=2.0, kind=0):

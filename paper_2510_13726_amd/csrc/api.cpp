@@ -275,6 +275,65 @@ hipError_t refill_porosity(hlbm_handle h) {
   return hipSuccess;
 }
 
+// Zero the wall-list counters and restart their rotation: a geometry launch
+// counts from zero into its own counter, also after a call that changed the
+// rotor boxes or skipped the geometry (no rotors).
+hipError_t reset_counters(hlbm_handle h) {
+  h->wc_epoch = 0;
+  h->ahead_step = -1;
+  return hipMemsetAsync(h->L.wcount, 0, sizeof(int32_t) * kCounters, h->stream);
+}
+
+// Carry the wall-model state (u_tau, active) of every cell that lies in the
+// box of the same rotor in both tables from the old slot layout to the new
+// one (the state is per cell); cells new to a box start inactive.  Host
+// round trip, set-up time only.
+int remap_wall_state(hlbm_handle h, const RotorTable& old_t, int64_t old_total, const RotorTable& new_t,
+                     int64_t new_total) {
+  std::vector<double> ut_old(std::max<int64_t>(old_total, 1)), ut_new(std::max<int64_t>(new_total, 1), 0.0);
+  std::vector<uint8_t> ac_old(std::max<int64_t>(old_total, 1)), ac_new(std::max<int64_t>(new_total, 1), 0);
+  hipError_t e = hipSuccess;
+  if (old_total > 0) {
+    e = hipMemcpyAsync(ut_old.data(), h->ut[h->wcur], old_total * 8, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ac_old.data(), h->act[h->acur], old_total, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "read wall state");
+  }
+  for (int k = 0; k < new_t.n && k < old_t.n; ++k) {
+    const RotorDev& a = old_t.r[k];
+    const RotorDev& b = new_t.r[k];
+    for (int z = 0; z < b.bn[2]; ++z)
+      for (int y = 0; y < b.bn[1]; ++y)
+        for (int x = 0; x < b.bn[0]; ++x) {
+          const int X = b.b0[0] + x, Y = b.b0[1] + y, Z = b.b0[2] + z;
+          const int ox = X - a.b0[0], oy = Y - a.b0[1], oz = Z - a.b0[2];
+          if (ox < 0 || oy < 0 || oz < 0 || ox >= a.bn[0] || oy >= a.bn[1] || oz >= a.bn[2]) continue;
+          const int64_t so = a.off + (int64_t(oz) * a.bn[1] + oy) * a.bn[0] + ox;
+          const int64_t sn = b.off + (int64_t(z) * b.bn[1] + y) * b.bn[0] + x;
+          ut_new[sn] = ut_old[so];
+          ac_new[sn] = ac_old[so];
+        }
+  }
+  const int64_t B = std::max<int64_t>(new_total, 1);
+  e = hipMemcpyAsync(h->ut[h->wcur], ut_new.data(), B * 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->act[h->acur], ac_new.data(), B, hipMemcpyHostToDevice, h->stream);
+  for (int k = 1; k < 3 && e == hipSuccess; ++k) e = hipMemsetAsync(h->act[(h->acur + k) % 3], 0, B, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "write wall state");
+  return HLBM_OK;
+}
+
+bool same_boxes(const RotorTable& a, const RotorTable& b) {
+  if (a.n != b.n) return false;
+  for (int k = 0; k < a.n; ++k)
+    for (int q = 0; q < 3; ++q)
+      if (a.r[k].b0[q] != b.r[k].b0[q] || a.r[k].bn[q] != b.r[k].bn[q] || a.r[k].mb0[q] != b.r[k].mb0[q] ||
+          a.r[k].mbn[q] != b.r[k].mbn[q])
+        return false;
+  return true;
+}
+
 // Mark FSI workgroups and number them (host round trip; set-up time only).
 int rebuild_slots(hlbm_handle h) {
   hipError_t e = launch_mark_blocks(h->L);
@@ -530,14 +589,28 @@ int hlbm_set_params(hlbm_handle h, const hlbm_params* p) {
     int64_t total;
     int rc = build_rotor_table(h, h->rotors.data(), int32_t(h->rotors.size()), &t, &total);
     if (rc != HLBM_OK) { h->params = old; return rc; }
+    // the boxes depend on eps_h (transition band) and the marking boxes on
+    // the wall model's probe reach: when they move, the per-cell wall state
+    // follows its cells into the new slots, cells of the old boxes return to
+    // the static field, and the wall lists restart
+    const bool moved = !same_boxes(h->rot, t);
+    const RotorTable old_t = h->rot;
+    const int64_t old_total = h->L.bbox_total;
+    if (moved && (rc = remap_wall_state(h, old_t, old_total, t, total)) != HLBM_OK) return rc;
     h->rot = t;
     h->L.bbox_total = total;
+    if (moved) {
+      hipError_t e = refill_porosity(h);
+      if (e == hipSuccess) e = reset_counters(h);
+      if (e != hipSuccess) return hip_fail(h, e, "reset rotor boxes");
+    }
     if ((rc = upload_rotors(h)) != HLBM_OK) return rc;
     if ((rc = rebuild_slots(h)) != HLBM_OK) return rc;
   }
   set_model(h);
   h->have_params = true;
   h->ahead_step = -1;
+  h->rec.valid = false;
   return HLBM_OK;
 }
 
@@ -557,7 +630,9 @@ int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* r, int32_t n) {
   hipError_t e = refill_porosity(h);
   if (e != hipSuccess) return hip_fail(h, e, "refill porosity");
   for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMemsetAsync(h->act[k], 0, std::max<int64_t>(total, 1), h->stream);
+  if (e == hipSuccess) e = reset_counters(h);
   if (e != hipSuccess) return hip_fail(h, e, "reset wall state");
+  h->rec.valid = false;
   if ((rc = upload_rotors(h)) != HLBM_OK) return rc;
   return rebuild_slots(h);
 }
@@ -573,6 +648,7 @@ int hlbm_set_porosity_field(hlbm_handle h, const void* d, const uint8_t* tag) {
             : hipMemsetAsync(h->L.tag_static, 0, N, h->stream);
   if (e == hipSuccess) e = refill_porosity(h);
   if (e != hipSuccess) return hip_fail(h, e, "set porosity field");
+  h->rec.valid = false;
   return rebuild_slots(h);
 }
 
@@ -599,6 +675,7 @@ int hlbm_set_control(hlbm_handle h, const void* dd) {
   h->L.dd = dd ? dst : nullptr;
   e = refill_porosity(h);
   if (e != hipSuccess) return hip_fail(h, e, "refill porosity");
+  h->rec.valid = false;  // a recorded forward run belongs to the old control
   return rebuild_slots(h);
 }
 
@@ -621,6 +698,7 @@ int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u) {
   h->ahead_step = -1;
   h->step = 0;
   h->hist_start = 0;
+  h->rec.valid = false;
   return HLBM_OK;
 }
 
@@ -760,7 +838,7 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
   }
   if (!record) {
     // a recomputed step: its records exist, the partials go unreduced
-    if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, false); });
+    if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, false, false); });
     return e;
   }
   // force partials (and mass partials of a diagnostics step) into this step's slice
@@ -770,7 +848,8 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
   Launch Ls = h->L;
   Ls.partial = h->L.partial + int64_t(j) * std::max<int32_t>(h->nslots, 1) * kPartial;
   Ls.mass_part = h->L.mass_part + int64_t(j) * h->L.nblocks;
-  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(Ls, src, dst, n, diag); });
+  const bool check = diag || h->params.check_nonfinite;
+  if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(Ls, src, dst, n, diag, check); });
   if (e == hipSuccess) ++h->pending;
   return e;
 }
@@ -1051,6 +1130,7 @@ int hlbm_set_populations(hlbm_handle h, const double* src) {
   if (!h || !src) return h ? fail(h, HLBM_ERR_INVALID, "src is NULL") : HLBM_ERR_INVALID;
   hipError_t e = launch_set_populations(h->L, h->pop[h->cur], src);
   if (e != hipSuccess) return hip_fail(h, e, "set populations");
+  h->rec.valid = false;
   return HLBM_OK;
 }
 
@@ -1107,6 +1187,7 @@ int hlbm_set_state(hlbm_handle h, const void* src) {
   h->ahead_step = -1;
   h->step = head[0];
   h->hist_start = head[0];
+  h->rec.valid = false;
   return HLBM_OK;
 }
 
@@ -1146,6 +1227,17 @@ int hlbm_wall_stats(hlbm_handle h, int64_t* iters, int64_t* cells) {
   if (e != hipSuccess) return hip_fail(h, e, "wall stats");
   if (iters) *iters = int64_t(s[0]);
   if (cells) *cells = int64_t(s[1]);
+  return HLBM_OK;
+}
+
+int hlbm_wall_safeguards(hlbm_handle h, int64_t* halvings, int64_t* caps) {
+  if (!h) return HLBM_ERR_INVALID;
+  unsigned long long s[4];
+  hipError_t e = hipMemcpyAsync(s, h->L.stats, sizeof(s), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "wall safeguards");
+  if (halvings) *halvings = int64_t(s[2]);
+  if (caps) *caps = int64_t(s[3]);
   return HLBM_OK;
 }
 

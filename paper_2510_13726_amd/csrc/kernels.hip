@@ -427,15 +427,18 @@ __device__ __forceinline__ R spalding_dbracket(R k) {
 }
 
 // Newton iteration of Sec. 2.2.1 (stop when |f(u^{j+1}) - f(u^j)| < tol or
-// after maxit steps, halving a non-positive iterate).
+// after maxit steps, halving a non-positive iterate, counted in halvings).
 template <class R, class F>
-__device__ __forceinline__ R newton(R u, F&& fdf, double tol, int maxit, int& iters) {
+__device__ __forceinline__ R newton(R u, F&& fdf, double tol, int maxit, int& iters, int& halvings) {
   R fu, du;
   fdf(u, fu, du);
   int it = 0;
   for (; it < maxit; ++it) {
     R un = u - div_nr(fu, du);
-    if (val(un) <= 0.0) un = 0.5 * u;
+    if (val(un) <= 0.0) {
+      un = 0.5 * u;
+      ++halvings;
+    }
     R fn, dn;
     fdf(un, fn, dn);
     const bool done = fabs(val(fn) - val(fu)) < tol;
@@ -470,10 +473,14 @@ __device__ __forceinline__ bool wall_slip(const R us[3], const double uw[3], con
 }
 
 // The two Newton solves: u_tau from the slip U (guess: the previous u_tau,
-// else the laminar estimate), then u+ at y1+.
+// else the laminar estimate), then u+ at y1+.  safe: Newton halvings and
+// evaluations whose exponential argument took the cap at 80.
+struct Safeguards {
+  int halvings = 0, caps = 0;
+};
 template <class RN>
 __device__ __forceinline__ void wall_newtons(RN Un, RN utpn, bool prev_active, double y1, const Model& m, RN& utn,
-                                             RN& upn, int& it1) {
+                                             RN& upn, int& it1, Safeguards& safe) {
   const double E = m.E, kap = m.kappa;
   // the Newton chains run on one lane per wall cell: every division is a
   // long dependent sequence in FP64, so the constants enter as reciprocals
@@ -485,13 +492,14 @@ __device__ __forceinline__ void wall_newtons(RN Un, RN utpn, bool prev_active, d
         const RN iu = rcp_nr(u);
         const RN p = Un * iu;
         const RN k = kap * p;
+        if (val(k) > 80.0) ++safe.caps;
         const RN ek = val(k) > 80.0 ? cst<RN>(::exp(80.0)) : exp(k);
         const RN dek = val(k) > 80.0 ? cst<RN>(0.0) : ek;
         const RN poly = 1.0 + k + k * k * 0.5;
         f = p + (ek - poly - k * k * k * sixth) * m.inv_E - m.ys_nu * u;
         df = 0.0 - (p * iu) * (1.0 + m.kappa_E * (dek - poly)) - m.ys_nu;
       },
-      m.tol, m.maxit, it1);
+      m.tol, m.maxit, it1, safe.halvings);
   const RN yp = y1 * utn * m.inv_nu;
   const RN ylog = val(yp) > 1.0 ? yp : cst<RN>(1.0);
   const RN ulog = log(E * ylog) * m.inv_kappa;
@@ -500,13 +508,14 @@ __device__ __forceinline__ void wall_newtons(RN Un, RN utpn, bool prev_active, d
       val(ulog) < val(yp) ? ulog : yp,
       [&](RN u, RN& f, RN& df) {
         const RN k = kap * u;
+        if (val(k) > 80.0) ++safe.caps;
         const RN ek = val(k) > 80.0 ? cst<RN>(::exp(80.0)) : exp(k);
         const RN dek = val(k) > 80.0 ? cst<RN>(0.0) : ek;
         const RN poly = 1.0 + k + k * k * 0.5;
         f = u + (ek - poly - k * k * k * sixth) * m.inv_E - yp;
         df = 1.0 + m.kappa_E * (dek - poly);
       },
-      m.tol, m.maxit, it2);
+      m.tol, m.maxit, it2, safe.halvings);
 }
 
 // u_wm = u_tau u+ t, S_wm = (U - u_tau u+) / (2 (y_s - y1)) (t n + n t), u_tau.
@@ -531,13 +540,14 @@ __device__ __forceinline__ void wall_outputs(R U, const R t[3], R qv, R ut, cons
 // out = (u_wm[3], S[6] as xx yy zz xy xz yz, u_tau); false for a plain cell.
 template <class R>
 __device__ __forceinline__ bool wall_solve(const R us[3], const double uw[3], const double nn[3], double y1,
-                                           R utp, bool prev_active, const Model& m, R out[10], int& it1) {
+                                           R utp, bool prev_active, const Model& m, R out[10], int& it1,
+                                           Safeguards& safe) {
   it1 = 0;
   R U, t[3];
   if (!wall_slip<R>(us, uw, nn, U, t)) return false;
   using RN = typename NewtonType<R>::type;
   RN utn, upn;
-  wall_newtons<RN>(seed_newton(U, 0), seed_newton(utp, 1), prev_active, y1, m, utn, upn, it1);
+  wall_newtons<RN>(seed_newton(U, 0), seed_newton(utp, 1), prev_active, y1, m, utn, upn, it1, safe);
   wall_outputs<R>(U, t, lift_newton(utn * upn, U, utp), lift_newton(utn, U, utp), nn, y1, m, out);
   return true;
 }
@@ -681,7 +691,8 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
     const int64_t w = wb + lw;
     const bool live = w < count;
     const int64_t wr = wb == wave * 8 ? w0 : (live ? w : wb);
-    const int64_t s = wb == wave * 8 ? s0 : wlist[wr];
+    // every entry is a box slot; the clamp keeps a corrupt entry in bounds
+    const int64_t s = wb == wave * 8 ? s0 : min(wlist[wr], int32_t(total - 1));
     // state of the previous step, loaded early (used by the Newton guess)
     const double utp = ut_prev[s];
     const bool actp = act_prev[s] != 0;
@@ -694,6 +705,7 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
     double us[3] = {pr.wgt * (mo.jx / rho), pr.wgt * (mo.jy / rho), pr.wgt * (mo.jz / rho)};
     group8_sum(us);
     int it1 = 0, done = 0;
+    Safeguards safe;
     double usb[3] = {0.0, 0.0, 0.0};
     // adjoint: the model with its 10 x 4 Jacobian with respect to (us,
     // u_tau^prev).  The Newton solves depend on (U, u_tau^prev) only; lanes
@@ -716,7 +728,7 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
           Un.g[0] = corner == 0 ? 1.0 : 0.0;
           utpn.v = utp;
           utpn.g[0] = corner == 1 ? 1.0 : 0.0;
-          wall_newtons<D1>(Un, utpn, actp, pr.y1, m, ut1, up1, it1);
+          wall_newtons<D1>(Un, utpn, actp, pr.y1, m, ut1, up1, it1, safe);
         }
       }
       const int lead = int(threadIdx.x & 63) & ~7;
@@ -736,7 +748,7 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
         active = slip;
         for (int q = 0; q < 10; ++q) out[q] = o4[q].v;
       } else {
-        active = wall_solve<double>(us, pr.uw, pr.nn, pr.y1, utp, actp, m, out, it1);
+        active = wall_solve<double>(us, pr.uw, pr.nn, pr.y1, utp, actp, m, out, it1, safe);
       }
       if (!active) {
         for (int q = 0; q < 9; ++q) wall_out[q * T + s] = CT(0);
@@ -802,17 +814,25 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
         for (int q = 0; q < 3; ++q) atomicAdd(&a.ubar[q * g.N + cc], pr.wgt * v[q]);
       }
     }
-    // Newton statistics (diagnostics steps): one atomic per wave
+    // Newton statistics (diagnostics steps): one atomic per wave; the
+    // safeguards of the solves run by lane 0 of each group
     if (a.count_stats) {
-      int a1 = it1, a2 = done;
+      const bool lead_live = corner == 0 && live;
+      int a1 = it1, a2 = done, a3 = lead_live ? safe.halvings : 0, a4 = lead_live ? safe.caps : 0;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         a1 += __shfl_xor(a1, o, 64);
         a2 += __shfl_xor(a2, o, 64);
+        a3 += __shfl_xor(a3, o, 64);
+        a4 += __shfl_xor(a4, o, 64);
       }
       if ((threadIdx.x & 63) == 0 && a2) {
         atomicAdd(&a.stats[0], (unsigned long long)a1);
         atomicAdd(&a.stats[1], (unsigned long long)a2);
+      }
+      if ((threadIdx.x & 63) == 0 && (a3 | a4)) {
+        atomicAdd(&a.stats[2], (unsigned long long)a3);
+        atomicAdd(&a.stats[3], (unsigned long long)a4);
       }
     }
   }
@@ -1109,9 +1129,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
         for (int i = i0; i < 27 && i < i0 + per; ++i) Store<ST>::template store<CT>((ST*)(q + o + (i - i0) * run), g2[i]);
       }
     }
+    // a non-finite density raises the flag (steps that check)
+    if (a.flag && valid && !(rho == rho && fabs(double(rho)) < 1e300)) atomicOr(a.flag, 1);
     if (a.mass_part) {
       const double mrho = valid ? double(rho) : 0.0;
-      if (valid && !(mrho == mrho && fabs(mrho) < 1e300)) atomicOr(a.flag, 1);
       const double ws = wave_sum(mrho);
       __syncthreads();
       if ((threadIdx.x & 63) == 0) lds[0][threadIdx.x >> 6] = ws;
@@ -1597,19 +1618,20 @@ static SweepArgs<CT> sweep_args(const Launch& L, const void* src, void* dst, int
   a.src = src; a.dst = dst; a.g = L.g; a.m = L.m;
   a.blk_slot = L.blk_slot; a.d_eff = (const CT*)L.d_eff; a.tag = L.tag;
   a.wall_out = (const CT*)L.wall_out; a.bbox_total = L.bbox_total; a.rot = L.rot;
-  a.uB_static = (const CT*)L.uB_static; a.partial = L.partial; a.mass_part = nullptr; a.flag = L.flag;
+  a.uB_static = (const CT*)L.uB_static; a.partial = L.partial; a.mass_part = nullptr; a.flag = nullptr;
   a.step = step; a.nblocks = L.nblocks;
   a.ghost = (const CT*)L.ghost;
   return a;
 }
 
-hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag) {
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag, bool check) {
   if (L.nblocks == 0) return hipSuccess;
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
     SweepArgs<CT> a = sweep_args<CT>(L, src, dst, step);
     if (diag) a.mass_part = L.mass_part;
+    if (check) a.flag = L.flag;
     if (L.g.bc_x == 0)
       hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
     else

@@ -34,7 +34,7 @@ struct Launch {
   int32_t* wlist;            // wall cells of the step (box slots)
   int32_t* wcount;           // [kCounters] wall-list counters, in turn by launch
   int32_t* flag;
-  unsigned long long* stats; // [0] Newton iterations, [1] wall cells
+  unsigned long long* stats; // [0] Newton iterations, [1] wall cells, [2] Newton halvings, [3] exponential caps
   RotorTable* rot;           // device copy
   int32_t nrot;
   int64_t bbox_total;
@@ -76,7 +76,9 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
                        int count_stats = 1, const NextGeometry* next = nullptr);
 // Step sweep of every cell: pull, moments, collision (porosity, solid and
 // wall-model velocities in the FSI tiles), store, per-tag momentum partials.
-hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag);
+// diag: also the step's mass partials; check: raise the non-finite flag for
+// a non-finite density.
+hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t step, bool diag, bool check);
 hipError_t launch_prologue(const Launch& L, int64_t step);
 // Records of steps n0 .. n0 + count - 1 from their partial slices (slice j:
 // force partials at partial + j nslots kPartial, mass partials at

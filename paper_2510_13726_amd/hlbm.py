@@ -82,6 +82,7 @@ SIGNATURES = [
     ("hlbm_force_torque", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("hlbm_history", C.c_int, [_H, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
     ("hlbm_wall_stats", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hlbm_wall_safeguards", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("hlbm_checkpoint_bytes", C.c_int64, [_H, C.c_int64, C.c_int32]),
     ("hlbm_adjoint_stack_bytes", C.c_int64, [_H, C.c_int32]),
     ("hlbm_forward_record", C.c_int, [_H, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _V, C.c_int64,
@@ -315,6 +316,9 @@ class Lattice:
         self._check(self.L.hlbm_forward_record(self.h, nsteps, t0, t1, obj_tag, ckpt_every,
                                                C.c_void_p(self._ckpt.data_ptr()), self._ckpt.numel(), C.byref(J)))
         self._ckpt_every = ckpt_every
+        # each record gets a number: a backward pass checks that it still
+        # differentiates the record its forward pass made
+        self.record_id = getattr(self, "record_id", 0) + 1
         return J.value
 
     def adjoint(self, gJ=1.0):
@@ -332,6 +336,13 @@ class Lattice:
         n = C.c_int64()
         self._check(self.L.hlbm_wall_stats(self.h, C.byref(it), C.byref(n)))
         return it.value, n.value
+
+    def wall_safeguards(self):
+        """(Newton halvings, exponential caps) of the wall model since creation."""
+        a = C.c_int64()
+        b = C.c_int64()
+        self._check(self.L.hlbm_wall_safeguards(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
 
 KERNEL_SWEEP, KERNEL_WALL, KERNEL_RASTERIZE, KERNEL_OTHER = range(4)
@@ -395,11 +406,15 @@ def torque_objective_function():
             lat.set_control(delta_d.detach())
             J = lat.forward_record(nsteps, t0, t1, obj_tag, ckpt_every)
             ctx.lat = lat
+            ctx.record_id = lat.record_id
             ctx.dshape, ctx.ddtype = delta_d.shape, delta_d.dtype
             return torch.tensor(J, dtype=torch.float64, device=delta_d.device)
 
         @staticmethod
         def backward(ctx, gJ):
+            if getattr(ctx.lat, "record_id", None) != ctx.record_id:
+                raise HlbmError(HLBM_ERR_STATE, "the lattice has recorded another forward run since this "
+                                                "objective was evaluated; evaluate it again before backward")
             G = ctx.lat.adjoint(float(gJ.item()))
             return G.to(ctx.ddtype).reshape(ctx.dshape), None, None, None, None, None, None, None
 

@@ -16,6 +16,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2510_13726_amd import workloads as W
+from parity_metrics import force_torque_error
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +52,7 @@ def test_rotor_channel_full_domain(storage, diag):
     hg = lat.get_populations().cpu().numpy()
     it_g, nw_g = lat.wall_stats()
     hist_g = lat.history() if diag else None
+    safe_g = lat.wall_safeguards()
     _free(lat)
     o = O.setup(w, threads=THREADS)
     o.step(n)
@@ -58,11 +60,15 @@ def test_rotor_channel_full_domain(storage, diag):
     e = rel(hg, ho)
     print(f"[fullsize] {w.name} {storage}: h rel err {e:.3e}", flush=True)
     assert e < TOL[storage]
+    halv, caps, near = o.wall_safeguards()
+    print(f"[fullsize] oracle Newton halvings {halv}, caps {caps}; slips within [0.5e-6, 2e-6]: {near}", flush=True)
+    assert (halv, caps) == (0, 0)
     if diag:
-        hist_o = o.history()
-        eF = rel(hist_g[:, 1:7], hist_o[:, 1:7])
-        print(f"[fullsize] F,T rel err {eF:.3e}; newton {it_g}/{o.newton_stats()[0]} wall cells {nw_g}", flush=True)
-        assert eF < 10 * TOL[storage]
+        eF, eT = force_torque_error(hist_g, o.history(), o.history_scale())
+        print(f"[fullsize] F err {eF:.3e} T err {eT:.3e}; newton {it_g}/{o.newton_stats()[0]} wall cells {nw_g}",
+              flush=True)
+        assert eF < TOL[storage] and eT < TOL[storage]
+        assert safe_g == (0, 0)
         assert (it_g, nw_g) == o.newton_stats()
         assert nw_g > 1000
 
@@ -91,8 +97,11 @@ def _slab_case(w, x0, length, n, storage, box):
     lc = ((zz * s.ny + yy) * s.nx + (xx - x0)).reshape(-1)
     ho = ho[:, lc].T
     e = rel(hg, ho)
+    halv, caps, near = o.wall_safeguards()
     print(f"[fullsize] {w.name} {storage}: h rel err {e:.3e} (max |h| {np.abs(ho).max():.3e}); "
-          f"slab newton {o.newton_stats()}", flush=True)
+          f"slab newton {o.newton_stats()}, halvings {halv}, caps {caps}, slips within [0.5e-6, 2e-6]: {near}",
+          flush=True)
+    assert (halv, caps) == (0, 0)
     if e >= TOL[storage]:
         err = np.abs(hg - ho).max(axis=1)
         bad = np.argsort(-err)[:8]

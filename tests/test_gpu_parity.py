@@ -1,15 +1,17 @@
 """HIP path vs the FP64 oracle on the same seeded inputs, element by element.
 
-Tolerances (relative to the largest magnitude of the compared field):
-FP64 compute 1e-12, FP32 compute 2e-5.  Populations are compared as the
-deviations h = f* - w; forces and torques against the largest value of the
-history.
+Tolerances: FP64 compute 1e-12, FP32 compute 2e-5.  Populations are
+compared as the deviations h = f* - w relative to their largest magnitude;
+forces and torques per step and tag relative to the sums of |dP| and of
+|(x - x_c) x dP| over the tag's cells (tests/parity_metrics.py).  The wall
+model's Newton safeguards (halving, exponential cap) are never taken.
 """
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2510_13726_amd import workloads as W
+from parity_metrics import force_torque_error
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +25,20 @@ def _hl():
 
 def rel(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def check_forces(lat, o, storage, tags=None):
+    """Force and torque parity at the stated tolerance; returns (eF, eT)."""
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale(), tags)
+    assert eF < TOL[storage] and eT < TOL[storage], (eF, eT)
+    return eF, eT
+
+
+def check_safeguards(lat, o):
+    assert lat.wall_safeguards() == (0, 0)
+    halv, caps, near = o.wall_safeguards()
+    assert (halv, caps) == (0, 0)
+    return near
 
 
 def run_both(w, storage, steps, check_every=None, flags=0):
@@ -49,13 +65,13 @@ def test_tgv_sphere_parity(storage):
     assert max(errs) < TOL[storage], errs
     hg, ho = lat.history(), o.history()
     assert hg.shape == ho.shape == (100, 91)
-    assert rel(hg[:, 1:7], ho[:, 1:7]) < 10 * TOL[storage]
+    eF, eT = check_forces(lat, o, storage)
     # total mass: sums of 32768 densities in different orders (and FP32 densities)
     assert rel(hg[:, 0], ho[:, 0]) < (1e-13 if storage == "f64" else 1e-6)
     rho_g, u_g, uh_g = (t.cpu().numpy().astype(np.float64) for t in lat.moments(uhat=True))
     rho_o, u_o, uh_o = o.moments(uhat=True)
     e_rho = np.abs(rho_g - rho_o).max()
-    print(f"[parity] errors h {max(errs):.3e} F,T {rel(hg[:, 1:7], ho[:, 1:7]):.3e} rho(abs) {e_rho:.3e} "
+    print(f"[parity] errors h {max(errs):.3e} F {eF:.3e} T {eT:.3e} rho(abs) {e_rho:.3e} "
           f"u {rel(u_g, u_o):.3e} uhat {rel(uh_g, uh_o):.3e}", flush=True)
     # rho ~ 1: the oracle forms it as sum f with f = O(1), so compare on the scale of 1
     assert e_rho < (1e-14 if storage == "f64" else 1.2e-7)
@@ -70,8 +86,8 @@ def test_rotor_wall_model_parity(storage):
     w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
     lat, o, errs = run_both(w, storage, 24, check_every=8)
     assert max(errs) < TOL[storage], errs
-    hg, ho = lat.history(), o.history()
-    assert rel(hg[:, 1:7], ho[:, 1:7]) < 10 * TOL[storage]
+    eF, eT = check_forces(lat, o, storage)
+    near = check_safeguards(lat, o)
     it_g, n_g = lat.wall_stats()
     it_o, n_o = o.newton_stats()
     assert n_g == n_o and n_g > 100
@@ -79,9 +95,9 @@ def test_rotor_wall_model_parity(storage):
         assert it_g == it_o
     rho_g, u_g, uh_g = (t.cpu().numpy().astype(np.float64) for t in lat.moments(uhat=True))
     rho_o, u_o, uh_o = o.moments(uhat=True)
-    print(f"[parity] errors h {max(errs):.3e} F,T {rel(hg[:, 1:7], ho[:, 1:7]):.3e} rho(abs) "
+    print(f"[parity] errors h {max(errs):.3e} F {eF:.3e} T {eT:.3e} rho(abs) "
           f"{np.abs(rho_g - rho_o).max():.3e} u {rel(u_g, u_o):.3e} uhat {rel(uh_g, uh_o):.3e} "
-          f"newton {it_g}/{it_o} wall cells {n_g}", flush=True)
+          f"newton {it_g}/{it_o} wall cells {n_g}, slips near the 1e-6 bound {near}", flush=True)
     assert rel(u_g, u_o) < TOL[storage]
     assert rel(uh_g, uh_o) < TOL[storage]
 
@@ -98,13 +114,14 @@ def test_two_rotor_wall_model_parity(storage):
                  phase0=1.7, tag=2)
     w.rotors.append(r1)
     lat, o, errs = run_both(w, storage, 16, check_every=8)
-    hg, ho = lat.history(), o.history()
     it_g, n_g = lat.wall_stats()
     it_o, n_o = o.newton_stats()
-    print(f"[parity] two rotors {storage}: h {max(errs):.3e} F,T {rel(hg[:, 1:13], ho[:, 1:13]):.3e} "
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    print(f"[parity] two rotors {storage}: h {max(errs):.3e} F {eF:.3e} T {eT:.3e} "
           f"newton {it_g}/{it_o} wall cells {n_g}/{n_o}", flush=True)
     assert max(errs) < TOL[storage], errs
-    assert rel(hg[:, 1:13], ho[:, 1:13]) < 10 * TOL[storage]
+    check_forces(lat, o, storage, tags=(1, 2))
+    check_safeguards(lat, o)
     assert n_g == n_o and n_g > 200
     if storage == "f64":
         assert it_g == it_o
@@ -122,11 +139,11 @@ def test_periodic_rotor_parity_fp64():
     w.u0 = 0.03
     lat, o, errs = run_both(w, "f64", 16)
     assert max(errs) < 1e-12, errs
-    hg, ho = lat.history(), o.history()
+    eF, eT = check_forces(lat, o, "f64", tags=(1, 5))
+    print(f"[parity] periodic two rotors: h {max(errs):.3e} F {eF:.3e} T {eT:.3e}", flush=True)
+    ho = o.history()
     for t in (1, 5):
-        sl = slice(1 + 6 * (t - 1), 7 + 6 * (t - 1))
-        assert rel(hg[:, sl], ho[:, sl]) < 1e-10
-        assert np.abs(ho[:, sl]).max() > 0
+        assert np.abs(ho[:, 1 + 6 * (t - 1):7 + 6 * (t - 1)]).max() > 0
 
 
 @pytest.mark.parametrize("dims,bc", [((2, 1, 1), W.BC_PERIODIC), ((3, 2, 1), W.BC_PERIODIC),

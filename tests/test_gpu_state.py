@@ -1,0 +1,112 @@
+"""Host-side state handling of the library against the oracle: non-finite
+detection without diagnostics steps, parameter and rotor changes in the
+middle of a run, and the invalidation of a recorded forward run."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_13726_amd import workloads as W
+from parity_metrics import force_torque_error, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _hl():
+    from paper_2510_13726_amd import hlbm
+    return hlbm
+
+
+def test_nonfinite_detected_without_diagnostics():
+    """check_nonfinite checks every step, also with diag_every = 0."""
+    hl = _hl()
+    w = W.small_rotor(nx=40, ny=32, nz=32, R=8.0, chord=3.0, hub=1.5)
+    lat = hl.setup(w, storage="f32", diag_every=0, check_nonfinite=1)
+    lat.step(2)
+    h = lat.get_populations()
+    h[5, 1234] = float("nan")
+    lat.set_populations(h)
+    with pytest.raises(hl.HlbmError) as e:
+        lat.step(3)
+    assert e.value.code == hl.HLBM_ERR_NONFINITE
+    # without the check the step runs on
+    lat2 = hl.setup(w, storage="f32", diag_every=0, check_nonfinite=0)
+    lat2.set_populations(h)
+    lat2.step(1)
+
+
+def test_eps_change_mid_run_fp64():
+    """eps_h raised from 2 to 3 after 6 steps moves the rotor boxes: the
+    lattice continues exactly as the oracle, whose wall-model state is per
+    cell."""
+    hl = _hl()
+    w = W.small_rotor(nx=56, ny=44, nz=40, R=10.0, chord=3.0, hub=2.0, tau0=0.51, turb=0.05)
+    lat = hl.setup(w, storage="f64", check_nonfinite=1)
+    o = O.setup(w)
+    lat.step(6)
+    o.step(6)
+    w.params.eps_h = 3.0
+    lat.set_params(w.params, check_nonfinite=1)
+    o.set_params(w.params)
+    lat.step(6)
+    o.step(6)
+    e = rel(lat.get_populations().cpu().numpy(), o.get_populations())
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    it_g, n_g = lat.wall_stats()
+    print(f"[state] eps_h 2 -> 3: h {e:.2e} F {eF:.2e} T {eT:.2e} newton {it_g}/{o.newton_stats()[0]}", flush=True)
+    assert e < 1e-12 and eF < 1e-12 and eT < 1e-12
+    assert (it_g, n_g) == o.newton_stats()
+
+
+def test_rotors_removed_and_restored_fp64():
+    """Rotors, then none for three steps, then the rotors again (the wall-list
+    counters restart): FP64 parity with the oracle throughout."""
+    hl = _hl()
+    w = W.small_rotor(nx=56, ny=44, nz=40, R=10.0, chord=3.0, hub=2.0, tau0=0.51)
+    lat = hl.setup(w, storage="f64", check_nonfinite=1)
+    o = O.setup(w)
+    lat.step(5)
+    o.step(5)
+    lat.set_rotors([])
+    o.set_rotors([])
+    lat.step(3)
+    o.step(3)
+    lat.set_rotors(w.rotors)
+    o.set_rotors(w.rotors)
+    lat.step(5)
+    o.step(5)
+    e = rel(lat.get_populations().cpu().numpy(), o.get_populations())
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    print(f"[state] rotors off and on: h {e:.2e} F {eF:.2e} T {eT:.2e}", flush=True)
+    assert e < 1e-12 and eF < 1e-12 and eT < 1e-12
+    assert lat.wall_stats() == o.newton_stats()
+
+
+def test_record_invalidated_by_input_changes():
+    """hlbm_adjoint refuses a record made before a change of the control or
+    the state; the autograd objective refuses to differentiate an older
+    evaluation once another has been recorded."""
+    hl = _hl()
+    torch = pytest.importorskip("torch")
+    w = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52)
+    lat = hl.setup(w, storage="f64", flags=hl.WITH_ADJOINT | hl.WITH_CONTROL)
+    state0 = lat.get_state().clone()
+    lat.forward_record(6, 2, 6, 0, 3)
+    lat.set_control(np.zeros(w.cells))
+    with pytest.raises(hl.HlbmError) as e:
+        lat.adjoint(1.0)
+    assert e.value.code == hl.HLBM_ERR_STATE
+    lat.set_state(state0)
+    lat.forward_record(6, 2, 6, 0, 3)
+    lat.set_state(state0)
+    with pytest.raises(hl.HlbmError) as e:
+        lat.adjoint(1.0)
+    assert e.value.code == hl.HLBM_ERR_STATE
+    TorqueObjective = hl.torque_objective_function()
+    d1 = torch.zeros(w.cells, dtype=torch.float64, device=lat.device, requires_grad=True)
+    d2 = torch.full((w.cells,), 1e-3, dtype=torch.float64, device=lat.device, requires_grad=True)
+    J1 = TorqueObjective.apply(d1, lat, state0, 6, 2, 6, 0, 3)
+    J2 = TorqueObjective.apply(d2, lat, state0, 6, 2, 6, 0, 3)
+    with pytest.raises(hl.HlbmError):
+        J1.backward()
+    J2.backward()
+    assert torch.isfinite(d2.grad).all()

@@ -391,3 +391,32 @@ def test_inflow_gaussian_statistics():
     assert abs(np.mean(xs ** 4) - 3) < 0.1
     assert O.gaussian(3, 5, 2, 1, 0, 16, 16) == O.gaussian(3, 5, 2, 1, 0, 16, 16)
     assert O.gaussian(3, 5, 2, 1, 0, 16, 16) != O.gaussian(3, 5, 2, 1, 1, 16, 16)
+
+
+def test_newton_safeguard_counters():
+    """The safeguards of the wall-law Newton iterations (Sec. 2.2.1; a
+    non-positive iterate is halved, an exponential argument above 80 is
+    capped) are counted: a wildly wrong previous friction velocity takes them,
+    the guesses of the method do not."""
+    p = W.Params(tau0=0.5005, wall_model=1)
+    good = O.wall_cell((0.05, 0.0, 0.0), (0, 0, 0), (0, 1, 0), 1.0, p)
+    assert good["active"] and good["halvings"] == 0 and good["capped"] == 0
+    prev = O.wall_cell((0.05, 0.0, 0.0), (0, 0, 0), (0, 1, 0), 1.0, p, utau_prev=good["utau"], prev_active=True)
+    assert prev["halvings"] == 0 and prev["capped"] == 0
+    big = O.wall_cell((0.05, 0.0, 0.0), (0, 0, 0), (0, 1, 0), 1.0, p, utau_prev=10.0, prev_active=True)
+    assert big["halvings"] >= 1 and big["capped"] >= 1
+    tiny = O.wall_cell((0.05, 0.0, 0.0), (0, 0, 0), (0, 1, 0), 1.0, p, utau_prev=1e-8, prev_active=True)
+    assert tiny["capped"] >= 1
+
+
+def test_rotor_run_takes_no_newton_safeguard():
+    """On a rotor channel with the wall model and inflow turbulence the
+    Newton solves never need the halving or the cap (reading of the stop
+    rule: they are safeguards only)."""
+    w = W.small_rotor(nx=48, ny=36, nz=36, R=9.0, chord=3.0, hub=2.0, tau0=0.51, turb=0.05)
+    o = O.setup(w)
+    o.step(12)
+    halv, caps, near = o.wall_safeguards()
+    it, cells = o.newton_stats()
+    assert cells > 100
+    assert (halv, caps) == (0, 0)
