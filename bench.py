@@ -1,11 +1,13 @@
 #!/usr/bin/env python
 """Benchmark of the fused HLBM step on one MI355X.
 
-One step = the whole hot path for one time step of the rotor channel
-(256 x 128 x 128 D3Q27 cells, rotating 3-blade rotor with the wall model,
-inflow / outflow): rotor rasterization, inflow ghost plane, wall model, the
-fused pull-stream / moments / collision sweep and the per-tag force/torque
-reduction.  Populations are resident in HBM before the timed region.
+One step = the whole hot path for one time step of the rotor array (1536 x
+768 x 256 D3Q27 cells, eight rotating 3-blade rotors with the wall model,
+inflow / outflow; the largest workload): rotor rasterization, inflow ghost
+plane, wall model, the fused pull-stream / moments / collision sweep and the
+per-tag force/torque reduction, with the total mass reduced and the
+densities checked for non-finite values every step.  Populations are
+resident in HBM before the timed region.
 
 Prints one JSON line: MLUPS of the FP32-storage path (value), the roofline
 of the dominant kernel (the sweep) from HIP events around its launches, the
@@ -41,11 +43,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_storage(w, storage, steps, warmup):
-    """(MLUPS, ms/step, sweep launches, sweep avg ms) of `steps` timed steps."""
+def time_storage(w, storage, steps, warmup, diag_every=1):
+    """(MLUPS, ms/step, sweep launches, sweep avg ms) of `steps` timed steps;
+    every diag_every-th step also reduces the total mass, and every step
+    checks for non-finite densities (hlbm_step fails on one)."""
     import torch
     from paper_2510_13726_amd import hlbm
-    lat = hlbm.setup(w, storage=storage, diag_every=0)
+    lat = hlbm.setup(w, storage=storage, diag_every=diag_every, check_nonfinite=1)
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -63,12 +67,13 @@ def time_storage(w, storage, steps, warmup):
     sweep_cells = w.cells
     it, cells = lat.wall_stats()
     ok = bool(torch.isfinite(lat.moments()[0]).all().item())
+    mass = lat.history(lat.step_count - 1, lat.step_count)[0, 0] if diag_every == 1 else None
     lat.close()
     del lat
     torch.cuda.empty_cache()
     return dict(mlups=w.cells * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, sweep_launches=n,
                 sweep_avg_ms=ms / max(n, 1), sweep_cells=sweep_cells, fsi_cells=fsi_cells, finite=ok,
-                wall_cells=cells, newton_iters=it)
+                wall_cells=cells, newton_iters=it, mass_per_cell=None if mass is None else mass / w.cells)
 
 
 def roofline(w, storage, sweep_avg_ms, sweep_cells):
@@ -145,18 +150,6 @@ def copy_bandwidth(gib=2.0, reps=20):
     return {"bytes_per_copy": 2 * n * 4, "avg_ms": round(ms, 4), "GB_s": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
-def cpu_baseline(w, steps):
-    from oracle import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    o = O.setup(w, threads=threads)
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    return {"value": round(w.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} steps of {w.name} ({w.cells * steps} cell updates), FP64 oracle, "
-                      f"OpenMP over z-planes, {dt:.1f} s"}
-
-
 CACHE_RESIDENT_BYTES = 256 << 20   # MI355X Infinity Cache
 
 
@@ -214,12 +207,14 @@ def cpu_sample(w, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
-    ap.add_argument("--config", default="2", help="workload: 1..5 (3 and 5 are full size)")
+    ap.add_argument("--config", default="5", help="workload: 1..5 (3 and 5 are full size)")
     ap.add_argument("--variants", default="f16,bf16", help="extra storage types timed on the same workload")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0 = skip)")
+    ap.add_argument("--diag-every", type=int, default=1, help="mass reduction every k-th step in the timed runs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="seconds of the FP64 oracle on a sample of the workload (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint ratio run (0 = skip)")
     ap.add_argument("--copy-reference", type=int, default=1, help="time a plain copy kernel (0 = skip)")
     ap.add_argument("--configs", default="1,2,3,4,5", help="workloads timed for the per-config table ('' = skip)")
@@ -241,12 +236,12 @@ def main():
     torch.cuda.set_device(0)
     w = W.ALL[args.config]()
     log(f"workload {w.name}: {w.cells} cells, storage {args.storage}, {args.steps} steps after {args.warmup}")
-    main_run = time_storage(w, args.storage, args.steps, args.warmup)
+    main_run = time_storage(w, args.storage, args.steps, args.warmup, args.diag_every)
     log(f"main: {main_run}")
     variants = {}
     raw = {args.storage: main_run}
     for st in [s for s in args.variants.split(",") if s and s != args.storage]:
-        r = time_storage(w, st, args.steps, args.warmup)
+        r = time_storage(w, st, args.steps, args.warmup, args.diag_every)
         raw[st] = r
         log(f"{st}: {r}")
         variants[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
@@ -264,9 +259,9 @@ def main():
     if copy_ref:
         log(f"copy reference: {copy_ref}")
     cpu = None
-    if args.cpu_steps > 0:
-        log(f"cpu baseline: {args.cpu_steps} oracle steps")
-        cpu = cpu_baseline(w, args.cpu_steps)
+    if args.cpu_seconds > 0:
+        log(f"cpu baseline: {args.cpu_seconds} s of the oracle")
+        cpu = cpu_sample(w, args.cpu_seconds)
         log(f"cpu: {cpu}")
     out = {
         "metric": METRIC,
@@ -283,7 +278,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "cells": w.cells, "storage": args.storage,
                    "compute": "f64" if args.storage == "f64" else "f32", "rotors": len(w.rotors),
-                   "wall_model": bool(w.params.wall_model), "tau0": w.params.tau0, "cs_smag": w.params.cs_smag},
+                   "wall_model": bool(w.params.wall_model), "tau0": w.params.tau0, "cs_smag": w.params.cs_smag,
+                   "diag_every": args.diag_every, "check_nonfinite": True},
         "roofline": roofline(w, args.storage, main_run["sweep_avg_ms"], main_run["sweep_cells"]),
         "cpu_baseline": cpu,
         "storage_variants": variants,
@@ -292,6 +288,7 @@ def main():
         "adjoint": adj,
         "copy_reference": copy_ref,
         "finite": main_run["finite"],
+        "mass_per_cell": main_run["mass_per_cell"],
         "wall_cells_processed": main_run["wall_cells"],
         "kernel_hash": kernel_hash(),
     }

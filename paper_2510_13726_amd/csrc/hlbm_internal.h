@@ -81,9 +81,15 @@ struct Geometry {
   int64_t N;
   int64_t row;         // population elements per (y, z) row: ntx blocks of 27 x kTileX
   int32_t ntx, nty;    // sweep tiles along x and y
-  // sweep tile order: divisors ntx, ntx nty (tiles per z plane) and 8 ntx
-  // (eight tile rows), and the tiles in whole groups of eight rows
-  Udiv by_ntx, by_plane, by_span;
+  // Sweep tile order: the rows of tiles along y are cut into bands of `band`
+  // rows (the last band holds the remainder); band by band, z by z, the
+  // band's rows, x fastest.  band = nty is the plain lattice order (z
+  // slowest); band = 1 sweeps each row of tiles through all z.  Divisors:
+  // ntx, band ntx, band ntx nz, the last band's rows times ntx, and 8 ntx
+  // (eight tile rows); tiles in whole bands, tiles in whole groups of eight
+  // rows.
+  Udiv by_ntx, by_bandrow, by_band, by_tailrow, by_span;
+  uint32_t band, full_tiles;
   uint32_t grouped;
 };
 

@@ -117,16 +117,36 @@ __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geome
   }
 }
 
-// Position (z, tile row, tile column) of sweep tile blk; tile ids and counts
-// fit 32 bits (fewer than 2^31 cells, 256 per tile).
+// Position (z, tile row, tile column) of sweep tile blk, and its index in
+// lattice order ((z nty + ty) ntx + tx, the index of its FSI slot and mass
+// partial).  Bands of `band` tile rows along y are swept one after the
+// other, each z plane by plane, so that the three z planes that read a
+// source row are swept close together in time.  Tile ids and counts fit
+// 32 bits (fewer than 2^31 cells, 256 per tile).
 struct TileId {
   int z, ty, tx;
+  uint32_t canon;
 };
 __device__ __forceinline__ TileId tile_id(const Geometry& g, uint32_t blk) {
-  const uint32_t z = udiv(blk, g.by_plane);
-  const uint32_t rem = blk - z * (uint32_t(g.ntx) * uint32_t(g.nty));
-  const uint32_t ty = udiv(rem, g.by_ntx);
-  return TileId{int(z), int(ty), int(rem - ty * uint32_t(g.ntx))};
+  const uint32_t ntx = uint32_t(g.ntx);
+  uint32_t ty0, rem, z, ri;
+  if (blk < g.full_tiles) {
+    const uint32_t b = udiv(blk, g.by_band);
+    rem = blk - b * (g.band * ntx * uint32_t(g.nz));
+    z = udiv(rem, g.by_bandrow);
+    rem -= z * (g.band * ntx);
+    ty0 = b * g.band;
+  } else {
+    // the last band, of nty - (full bands) band rows
+    const uint32_t rows = uint32_t(g.nty) - (g.full_tiles / (ntx * uint32_t(g.nz)));
+    rem = blk - g.full_tiles;
+    z = udiv(rem, g.by_tailrow);
+    rem -= z * (rows * ntx);
+    ty0 = uint32_t(g.nty) - rows;
+  }
+  ri = udiv(rem, g.by_ntx);
+  const uint32_t ty = ty0 + ri, tx = rem - ri * ntx;
+  return TileId{int(z), int(ty), int(tx), (z * uint32_t(g.nty) + ty) * ntx + tx};
 }
 
 // Inflow ghost plane of step n: h_i = f^eq_i(1, u_in(n, y, z)) - w_i for the
@@ -1009,7 +1029,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   const bool valid = xr < g.nx && row_ok;
   const int x = valid ? xr : 0, y = row_ok ? yr : 0;
   const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
-  const int32_t slot = a.blk_slot[blk];
+  const int32_t slot = a.blk_slot[ti.canon];
 
   CT h[27];
   pull_row<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
@@ -1137,7 +1157,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
       __syncthreads();
       if ((threadIdx.x & 63) == 0) lds[0][threadIdx.x >> 6] = ws;
       __syncthreads();
-      if (threadIdx.x == 0) a.mass_part[blk] = (lds[0][0] + lds[0][1]) + (lds[0][2] + lds[0][3]);
+      if (threadIdx.x == 0) a.mass_part[ti.canon] = (lds[0][0] + lds[0][1]) + (lds[0][2] + lds[0][3]);
     }
   }
 }
@@ -1442,7 +1462,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   CT d = CT(0), b[3] = {CT(0), CT(0), CT(0)}, S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)}, sigma = CT(1);
   CT pb[3] = {CT(0), CT(0), CT(0)};
   double ub[3] = {0.0, 0.0, 0.0};
-  const int32_t slot = a.blk_slot[blk];
+  const int32_t slot = a.blk_slot[ti.canon];
   const bool fsi = slot >= 0, gather = slot != -1;
   if (gather) {
     for (int q = 0; q < 3; ++q) {
