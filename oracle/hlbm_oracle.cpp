@@ -51,6 +51,11 @@ void* oracle_create(int nx, int ny, int nz, int bc_x) {
   if (nx < 2 || ny < 1 || nz < 1) return nullptr;
   return new SimD(nx, ny, nz, bc_x);
 }
+// The same on velocity set q (27 or 19).
+void* oracle_create_q(int nx, int ny, int nz, int bc_x, int q) {
+  if (nx < 2 || ny < 1 || nz < 1 || (q != 27 && q != 19)) return nullptr;
+  return new SimD(nx, ny, nz, bc_x, q);
+}
 void oracle_destroy(void* h) { delete (SimD*)h; }
 void oracle_set_threads(void* h, int n) { ((SimD*)h)->nthreads = n > 0 ? n : 1; }
 
@@ -133,12 +138,12 @@ int oracle_moments(void* h, double* rho, double* u, double* uhat) {
 
 int oracle_get_populations(void* h, double* dst) {
   SimD* s = (SimD*)h;
-  std::memcpy(dst, s->h.data(), sizeof(double) * Q * s->N);
+  std::memcpy(dst, s->h.data(), sizeof(double) * s->q * s->N);
   return 0;
 }
 int oracle_set_populations(void* h, const double* src) {
   SimD* s = (SimD*)h;
-  std::memcpy(s->h.data(), src, sizeof(double) * Q * s->N);
+  std::memcpy(s->h.data(), src, sizeof(double) * s->q * s->N);
   return 0;
 }
 int oracle_get_wall_state(void* h, double* utau, uint8_t* active) {
@@ -208,18 +213,33 @@ int oracle_geometry(void* h, double* d, uint8_t* tag, uint8_t* wall, double* phi
 
 // ----------------------------------------------------- cell-level entry points
 void oracle_lattice(int32_t* c, double* w) {
-  const Lattice27& L = lat();
-  for (int i = 0; i < Q; ++i) {
+  const Lattice& L = lat();
+  for (int i = 0; i < L.q; ++i) {
     for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];
     w[i] = L.w[i];
   }
 }
+// Velocities and weights of set q (27 or 19); returns its size.
+int oracle_lattice_q(int q, int32_t* c, double* w) {
+  const Lattice& L = lattice(q);
+  for (int i = 0; i < L.q; ++i) {
+    for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];
+    w[i] = L.w[i];
+  }
+  return L.q;
+}
 void oracle_equilibrium(double rho, const double* u, double* feq) { equilibrium(rho, u, feq); }
+void oracle_equilibrium_q(int q, double rho, const double* u, double* feq) { equilibrium(rho, u, feq, lattice(q)); }
 void oracle_collide_cell(const double* m, double d, const double* uB, const double* uwm, const double* S,
                          double sigma, double tau0, double Cs, double* fstar, double* dP) {
   collide_cell(m, d, uB, uwm, S, sigma, tau0, Cs, fstar, dP);
 }
+void oracle_collide_cell_q(int q, const double* m, double d, const double* uB, const double* uwm, const double* S,
+                           double sigma, double tau0, double Cs, double* fstar, double* dP) {
+  collide_cell(m, d, uB, uwm, S, sigma, tau0, Cs, fstar, dP, lattice(q));
+}
 void oracle_moments_of(const double* f, double* m) { moments_of(f, m); }
+void oracle_moments_of_q(int q, const double* f, double* m) { moments_of(f, m, lattice(q)); }
 double oracle_spalding_yplus(double up, double E, double kappa) { return up + spalding_bracket(kappa * up) / E; }
 // out = (uwm[3], S[6], utau, active, Newton halvings, exponential caps);
 // returns Newton iterations for u_tau.

@@ -55,22 +55,27 @@ inline double re(const std::complex<double>& x) { return x.real(); }
 template <int N> inline double re(const Dual<N>& x) { return x.v; }
 
 // ------------------------------------------------------------ constants
-// D3Q27 velocity set, canonical order i = 9(cx+1) + 3(cy+1) + (cz+1); the
-// paper uses D3Q19 (Sec. 2.2, Fig. 2); this oracle follows the 27-velocity
-// cube so that all third-order Hermite polynomials are represented.
+// Velocity sets.  D3Q27: c in {-1,0,1}^3, canonical order
+// i = 9(cx+1) + 3(cy+1) + (cz+1), weights 8/27, 2/27, 1/54, 1/216 by |c|^2.
+// D3Q19 (the paper's stencil, Sec. 2.2, Fig. 2): the same order restricted
+// to |c|^2 <= 2, weights 1/3, 1/18, 1/36.  Q is the largest set (array
+// bounds); a lattice's own count is q.
 constexpr int Q = 27;
 constexpr double CS2 = 1.0 / 3.0;
 
-struct Lattice27 {
+struct Lattice {
+  int q;
   int c[Q][3];
   double w[Q];
-  Lattice27() {
-    for (int i = 0; i < Q; ++i) {
-      c[i][0] = i / 9 - 1;
-      c[i][1] = (i / 3) % 3 - 1;
-      c[i][2] = i % 3 - 1;
-      int n2 = c[i][0] * c[i][0] + c[i][1] * c[i][1] + c[i][2] * c[i][2];
-      w[i] = n2 == 0 ? 8.0 / 27.0 : n2 == 1 ? 2.0 / 27.0 : n2 == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+  explicit Lattice(int nq) : q(0) {
+    for (int i = 0; i < 27; ++i) {
+      const int cx = i / 9 - 1, cy = (i / 3) % 3 - 1, cz = i % 3 - 1;
+      const int n2 = cx * cx + cy * cy + cz * cz;
+      if (nq == 19 && n2 == 3) continue;
+      c[q][0] = cx; c[q][1] = cy; c[q][2] = cz;
+      if (nq == 19) w[q] = n2 == 0 ? 1.0 / 3.0 : n2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+      else w[q] = n2 == 0 ? 8.0 / 27.0 : n2 == 1 ? 2.0 / 27.0 : n2 == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+      ++q;
     }
   }
   // Second Hermite polynomial H^(2)_ab = c_a c_b - cs^2 delta_ab.
@@ -80,9 +85,39 @@ struct Lattice27 {
     return c[i][a] * c[i][b] * c[i][cc] -
            CS2 * (c[i][a] * (b == cc) + c[i][b] * (a == cc) + c[i][cc] * (a == b));
   }
+  // Third-order term of a Hermite expansion at velocity i for the
+  // coefficient tensor a3 (Sec. 2.2: equilibrium and recursive f^(1)).
+  // D3Q27 holds every third-order polynomial: the full series term
+  // H3 : a3 / (6 cs^6).  D3Q19 holds neither H_aaa (zero on any velocity
+  // set in {-1,0,1}) nor H_xyz, and its H_aab, H_ccb are not orthogonal
+  // under its weights; the recursive-regularized schemes the paper builds on
+  // (Coreixas et al. 2017, Jacob et al. 2018) project onto the orthogonal
+  // pairs H_aab + H_ccb and H_aab - H_ccb (b the odd index, a and c the
+  // other two axes), whose D3Q19 norms are 2 cs^6 and 6 cs^6.
+  template <class T>
+  T third(int i, const T a3[3][3][3]) const {
+    T s = T(0.0);
+    if (q == 27) {
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          for (int cc = 0; cc < 3; ++cc) s = s + H3(i, a, b, cc) * a3[a][b][cc];
+      return s / (6.0 * CS2 * CS2 * CS2);
+    }
+    for (int b = 0; b < 3; ++b) {
+      const int a = b == 0 ? 1 : 0, cc = b == 2 ? 1 : 2;
+      const double hp = H3(i, a, a, b) + H3(i, cc, cc, b), hm = H3(i, a, a, b) - H3(i, cc, cc, b);
+      s = s + hp * (a3[a][a][b] + a3[cc][cc][b]) / (2.0 * CS2 * CS2 * CS2) +
+          hm * (a3[a][a][b] - a3[cc][cc][b]) / (6.0 * CS2 * CS2 * CS2);
+    }
+    return s;
+  }
 };
 
-inline const Lattice27& lat() { static const Lattice27 L; return L; }
+inline const Lattice& lattice(int q) {
+  static const Lattice L27(27), L19(19);
+  return q == 19 ? L19 : L27;
+}
+inline const Lattice& lat() { return lattice(27); }
 
 // ------------------------------------------------------------ parameters
 struct Params {
@@ -108,30 +143,30 @@ struct Rotor {
 
 // ------------------------------------------------------------ equilibrium
 // Third-order Hermite equilibrium (Sec. 2.2, equilibrium definition) with
-// a0^(n) = rho u^n, written as the full Hermite series 1/(n! cs^(2n)) H^(n):a^(n).
+// a0^(n) = rho u^n: the Hermite series 1/(n! cs^(2n)) H^(n):a^(n), its
+// third-order term as the lattice holds it (Lattice::third).
 template <class T>
-void equilibrium(const T& rho, const T u[3], T feq[Q]) {
-  const Lattice27& L = lat();
-  for (int i = 0; i < Q; ++i) {
-    T s1 = T(0.0), s2 = T(0.0), s3 = T(0.0);
+void equilibrium(const T& rho, const T u[3], T feq[Q], const Lattice& L = lat()) {
+  T a3[3][3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int cc = 0; cc < 3; ++cc) a3[a][b][cc] = u[a] * u[b] * u[cc];
+  for (int i = 0; i < L.q; ++i) {
+    T s1 = T(0.0), s2 = T(0.0);
     for (int a = 0; a < 3; ++a) {
       s1 = s1 + double(L.c[i][a]) * u[a];
-      for (int b = 0; b < 3; ++b) {
-        s2 = s2 + L.H2(i, a, b) * u[a] * u[b];
-        for (int cc = 0; cc < 3; ++cc) s3 = s3 + L.H3(i, a, b, cc) * u[a] * u[b] * u[cc];
-      }
+      for (int b = 0; b < 3; ++b) s2 = s2 + L.H2(i, a, b) * u[a] * u[b];
     }
-    feq[i] = L.w[i] * rho * (1.0 + s1 / CS2 + s2 / (2.0 * CS2 * CS2) + s3 / (6.0 * CS2 * CS2 * CS2));
+    feq[i] = L.w[i] * rho * (1.0 + s1 / CS2 + s2 / (2.0 * CS2 * CS2) + L.third(i, a3));
   }
 }
 
 // Moments: rho = sum f, j = sum c f, P = sum c c f.  m = (rho, jx, jy, jz,
 // Pxx, Pyy, Pzz, Pxy, Pxz, Pyz).
 template <class T>
-void moments_of(const T f[Q], T m[10]) {
-  const Lattice27& L = lat();
+void moments_of(const T f[Q], T m[10], const Lattice& L = lat()) {
   for (int k = 0; k < 10; ++k) m[k] = T(0.0);
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < L.q; ++i) {
     const int* c = L.c[i];
     m[0] = m[0] + f[i];
     m[1] = m[1] + double(c[0]) * f[i];
@@ -164,9 +199,8 @@ inline void sym_index(int a, int b, int& k) {
 //   dP    = j - rho u_hat    (momentum handed to the solid this step)
 template <class T>
 void collide_cell(const T m[10], const T& d, const double uB[3], const T uwm[3], const T Swm[6],
-                  double sigma, double tau0, double Cs, T fstar[Q], T dP[3]) {
+                  double sigma, double tau0, double Cs, T fstar[Q], T dP[3], const Lattice& L = lat()) {
   using std::sqrt;
-  const Lattice27& L = lat();
   const T rho = m[0];
   T u[3], uh[3];
   for (int a = 0; a < 3; ++a) u[a] = m[1 + a] / rho;
@@ -189,16 +223,15 @@ void collide_cell(const T m[10], const T& d, const double uB[3], const T uwm[3],
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 3; ++c) a3[a][b][c] = uh[a] * Pi[b][c] + uh[b] * Pi[a][c] + uh[c] * Pi[a][b];
   T feq[Q];
-  equilibrium(rho, uh, feq);
-  for (int i = 0; i < Q; ++i) {
-    T h2pi = T(0.0), h3a = T(0.0), h2s = T(0.0);
+  equilibrium(rho, uh, feq, L);
+  for (int i = 0; i < L.q; ++i) {
+    T h2pi = T(0.0), h2s = T(0.0);
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
         h2pi = h2pi + L.H2(i, a, b) * Pi[a][b];
         h2s = h2s + L.H2(i, a, b) * S[a][b];
-        for (int c = 0; c < 3; ++c) h3a = h3a + L.H3(i, a, b, c) * a3[a][b][c];
       }
-    T f1 = L.w[i] * (h2pi / (2.0 * CS2 * CS2) + h3a / (6.0 * CS2 * CS2 * CS2));
+    T f1 = L.w[i] * (h2pi / (2.0 * CS2 * CS2) + L.third(i, a3));
     T f1fd = L.w[i] * rho * tau / CS2 * h2s;
     T ftil = sigma * f1 - (1.0 - sigma) * f1fd;
     fstar[i] = feq[i] + (1.0 - 1.0 / tau) * ftil;

@@ -47,7 +47,7 @@ typedef Dual<4> D4;
 void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, const std::vector<double>& lam,
                   const std::vector<double>& UT, std::vector<double>& lam_out, std::vector<double>& UT_out,
                   double* G) {
-  const Lattice27& L = lat();
+  const Lattice& L = lat();
   const int64_t N = s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   s.geometry(n);
@@ -210,6 +210,7 @@ int oracle_adjoint_run(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int obj
                        double* G) {
   Sim<double>& s = *(Sim<double>*)hp;
   if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1) return 1;
+  if (s.q != 27) return 1;  // the adjoint is written for the 27-velocity set
   const int64_t n0 = s.step, N = s.N;
   s.obj_on = true;
   s.obj_t0 = n0 + t0;
@@ -257,7 +258,7 @@ int oracle_complex_step_J(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int 
   typedef std::complex<double> C;
   const Sim<double>& s = *(const Sim<double>*)hp;
   if (cell < 0 || cell >= s.N || t1 <= t0 || t0 < 0) return 1;
-  Sim<C> z(s.nx, s.ny, s.nz, s.bc_x);
+  Sim<C> z(s.nx, s.ny, s.nz, s.bc_x, s.q);
   z.p = s.p;
   z.set_rotors(s.rotors.data(), (int)s.rotors.size());
   for (int t = 0; t < NTAG; ++t)

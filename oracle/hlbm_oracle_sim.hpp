@@ -57,7 +57,9 @@ struct Sim {
   std::vector<uint8_t> tag_static;
   std::vector<T> dd;                      // porosity control added to d
   double tag_center[NTAG][3]{}, tag_axis[NTAG][3]{};
-  std::vector<T> h;                       // [27][N] post-collision state minus weights
+  const Lattice* lat_ = &lattice(27);     // velocity set
+  int q = 27;
+  std::vector<T> h;                       // [q][N] post-collision state minus weights
   std::vector<T> utau;                    // wall state per cell
   std::vector<uint8_t> active;
   int64_t step = 0;
@@ -81,9 +83,11 @@ struct Sim {
   std::vector<T> f, mom, u, uwm, Swm, dP, d;
   std::vector<double> sigma;
 
-  Sim(int nx_, int ny_, int nz_, int bcx) : nx(nx_), ny(ny_), nz(nz_), bc_x(bcx) {
+  Sim(int nx_, int ny_, int nz_, int bcx, int nq = 27) : nx(nx_), ny(ny_), nz(nz_), bc_x(bcx) {
     N = (int64_t)nx * ny * nz;
-    h.assign((size_t)Q * N, T(0.0));
+    lat_ = &lattice(nq);
+    q = lat_->q;
+    h.assign((size_t)q * N, T(0.0));
     utau.assign(N, T(0.0));
     active.assign(N, 0);
     for (int t = 0; t < NTAG; ++t) {
@@ -160,14 +164,14 @@ struct Sim {
   }
 
   void pull(int64_t n) {
-    const Lattice27& L = lat();
-    f.assign((size_t)Q * N, T(0.0));
+    const Lattice& L = *lat_;
+    f.assign((size_t)q * N, T(0.0));
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
           const int64_t c = idx(x, y, z);
-          for (int i = 0; i < Q; ++i) {
+          for (int i = 0; i < q; ++i) {
             int xs = x - L.c[i][0];
             int ys = wrap(y - L.c[i][1], ny), zs = wrap(z - L.c[i][2], nz);
             if (bc_x == 0) {
@@ -177,7 +181,7 @@ struct Sim {
               inflow_velocity(n, ys, zs, uin);
               T ui[3] = {T(uin[0]), T(uin[1]), T(uin[2])};
               T feq[Q];
-              equilibrium(T(1.0), ui, feq);
+              equilibrium(T(1.0), ui, feq, L);
               f[(size_t)i * N + c] = feq[i];
               continue;
             } else if (xs > nx - 1) {
@@ -195,8 +199,8 @@ struct Sim {
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int64_t c = 0; c < N; ++c) {
       T fc[Q], m[10];
-      for (int i = 0; i < Q; ++i) fc[i] = f[(size_t)i * N + c];
-      moments_of(fc, m);
+      for (int i = 0; i < q; ++i) fc[i] = f[(size_t)i * N + c];
+      moments_of(fc, m, *lat_);
       for (int k = 0; k < 10; ++k) mom[(size_t)k * N + c] = m[k];
       for (int a = 0; a < 3; ++a) u[(size_t)a * N + c] = m[1 + a] / m[0];
     }
@@ -258,7 +262,7 @@ struct Sim {
 
   // -------------------------------------------------- 5. collision + 6. new state
   void collide_and_record() {
-    const Lattice27& L = lat();
+    const Lattice& L = *lat_;
     dP.assign((size_t)3 * N, T(0.0));
     std::vector<T> rho(N);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
@@ -267,8 +271,8 @@ struct Sim {
       for (int k = 0; k < 10; ++k) m[k] = mom[(size_t)k * N + c];
       for (int a = 0; a < 3; ++a) uw3[a] = uwm[(size_t)a * N + c];
       for (int k = 0; k < 6; ++k) S6[k] = Swm[(size_t)k * N + c];
-      collide_cell(m, d[c], &g_uB[3 * c], uw3, S6, sigma[c], p.tau0, p.cs_smag, fs, dp);
-      for (int i = 0; i < Q; ++i) h[(size_t)i * N + c] = fs[i] - L.w[i];
+      collide_cell(m, d[c], &g_uB[3 * c], uw3, S6, sigma[c], p.tau0, p.cs_smag, fs, dp, L);
+      for (int i = 0; i < q; ++i) h[(size_t)i * N + c] = fs[i] - L.w[i];
       for (int a = 0; a < 3; ++a) dP[(size_t)a * N + c] = dp[a];
       rho[c] = m[0];
     }
@@ -310,14 +314,14 @@ struct Sim {
   }
 
   void init_equilibrium(const double* rho, const double* uu) {
-    const Lattice27& L = lat();
+    const Lattice& L = *lat_;
     for (int64_t c = 0; c < N; ++c) {
       T r = T(rho ? rho[c] : 1.0);
       T u3[3];
       for (int a = 0; a < 3; ++a) u3[a] = T(uu ? uu[(size_t)a * N + c] : 0.0);
       T feq[Q];
-      equilibrium(r, u3, feq);
-      for (int i = 0; i < Q; ++i) h[(size_t)i * N + c] = feq[i] - L.w[i];
+      equilibrium(r, u3, feq, L);
+      for (int i = 0; i < q; ++i) h[(size_t)i * N + c] = feq[i] - L.w[i];
     }
     std::fill(utau.begin(), utau.end(), T(0.0));
     std::fill(active.begin(), active.end(), 0);

@@ -41,6 +41,14 @@ def lib():
         L = C.CDLL(path)
         L.oracle_create.restype = C.c_void_p
         L.oracle_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        L.oracle_create_q.restype = C.c_void_p
+        L.oracle_create_q.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.oracle_lattice_q.restype = C.c_int
+        L.oracle_lattice_q.argtypes = [C.c_int, C.POINTER(C.c_int32), _D]
+        L.oracle_equilibrium_q.argtypes = [C.c_int, C.c_double, _D, _D]
+        L.oracle_collide_cell_q.argtypes = [C.c_int, _D, C.c_double, _D, _D, _D, C.c_double, C.c_double,
+                                            C.c_double, _D, _D]
+        L.oracle_moments_of_q.argtypes = [C.c_int, _D, _D]
         L.oracle_destroy.argtypes = [C.c_void_p]
         L.oracle_set_threads.argtypes = [C.c_void_p, C.c_int]
         L.oracle_set_params.argtypes = [C.c_void_p, C.POINTER(OrParams)]
@@ -135,11 +143,12 @@ def make_rotor(r) -> OrRotor:
 class OracleLattice:
     """FP64 host lattice; state = post-collision populations minus weights."""
 
-    def __init__(self, nx, ny, nz, bc_x=0, threads=None):
+    def __init__(self, nx, ny, nz, bc_x=0, threads=None, q=27):
         self.L = lib()
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
-        self.h = self.L.oracle_create(nx, ny, nz, bc_x)
+        self.q = q
+        self.h = self.L.oracle_create_q(nx, ny, nz, bc_x, q)
         if not self.h:
             raise ValueError("oracle_create failed")
         self.threads = threads or min(8, os.cpu_count() or 1)
@@ -198,7 +207,7 @@ class OracleLattice:
         return (rho, u, uh) if uhat else (rho, u)
 
     def get_populations(self):
-        out = np.empty((27, self.N))
+        out = np.empty((self.q, self.N))
         self.L.oracle_get_populations(self.h, _p(out))
         return out
 
@@ -278,7 +287,7 @@ class OracleLattice:
 def setup(w, threads=None) -> OracleLattice:
     """Oracle lattice loaded with a workload's inputs at step 0."""
     from paper_2510_13726_amd import workloads as W
-    o = OracleLattice(w.nx, w.ny, w.nz, w.bc_x, threads=threads)
+    o = OracleLattice(w.nx, w.ny, w.nz, w.bc_x, threads=threads, q=getattr(w, "q", 27))
     o.set_params(w.params)
     o.set_rotors(w.rotors)
     d, tag = W.static_porosity(w)
@@ -290,39 +299,40 @@ def setup(w, threads=None) -> OracleLattice:
     o.init_equilibrium(rho, u)
     noise = W.population_noise(w)
     if noise is not None:
-        o.set_populations(o.get_populations() + noise)
+        o.set_populations(o.get_populations() + noise[:o.q])
     return o
 
 
 # --------------------------------------------------------------- cell API
-def lattice_tables():
+def lattice_tables(q=27):
     c = np.zeros(81, dtype=np.int32)
     w = np.zeros(27)
-    lib().oracle_lattice(c.ctypes.data_as(C.POINTER(C.c_int32)), _p(w))
-    return c.reshape(27, 3), w
+    n = lib().oracle_lattice_q(q, c.ctypes.data_as(C.POINTER(C.c_int32)), _p(w))
+    return c.reshape(27, 3)[:n].copy(), w[:n].copy()
 
 
-def equilibrium(rho, u):
+def equilibrium(rho, u, q=27):
     u = _f64(np.asarray(u))
     out = np.empty(27)
-    lib().oracle_equilibrium(float(rho), _p(u), _p(out))
-    return out
+    lib().oracle_equilibrium_q(q, float(rho), _p(u), _p(out))
+    return out[:q].copy()
 
 
-def moments_of(f):
+def moments_of(f, q=None):
     f = _f64(np.asarray(f))
+    q = q or f.size
     m = np.empty(10)
-    lib().oracle_moments_of(_p(f), _p(m))
+    lib().oracle_moments_of_q(q, _p(f), _p(m))
     return m
 
 
-def collide_cell(m, d=0.0, uB=(0, 0, 0), uwm=(0, 0, 0), S=(0, 0, 0, 0, 0, 0), sigma=1.0, tau0=0.55, Cs=0.1):
+def collide_cell(m, d=0.0, uB=(0, 0, 0), uwm=(0, 0, 0), S=(0, 0, 0, 0, 0, 0), sigma=1.0, tau0=0.55, Cs=0.1, q=27):
     m, uB, uwm, S = (_f64(np.asarray(v, dtype=np.float64)) for v in (m, uB, uwm, S))
     fs = np.empty(27)
     dP = np.empty(3)
-    lib().oracle_collide_cell(_p(m), float(d), _p(uB), _p(uwm), _p(S), float(sigma), float(tau0), float(Cs),
-                              _p(fs), _p(dP))
-    return fs, dP
+    lib().oracle_collide_cell_q(q, _p(m), float(d), _p(uB), _p(uwm), _p(S), float(sigma), float(tau0), float(Cs),
+                                _p(fs), _p(dP))
+    return fs[:q].copy(), dP
 
 
 def spalding_yplus(uplus, E=9.8, kappa=0.41):

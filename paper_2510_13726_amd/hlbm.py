@@ -366,10 +366,11 @@ def sweep_partition(lat):
     return f.value, b.value
 
 
-def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None) -> "Lattice":
+def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None, history=1024) -> "Lattice":
     """Lattice loaded with a workload's inputs at step 0 (same recipe as the oracle)."""
     from . import workloads as W
-    lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device)
+    lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device,
+                  history=history)
     lat.set_params(w.params, diag_every=diag_every, check_nonfinite=check_nonfinite)
     lat.set_rotors(w.rotors)
     d, tag = W.static_porosity(w)

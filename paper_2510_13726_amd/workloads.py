@@ -74,6 +74,7 @@ class Workload:
     sphere: Optional[Tuple[float, float, float, float]] = None  # static sphere (cx, cy, cz, R), tag 1
     noise_seed: Optional[int] = None  # seeded non-equilibrium perturbation of the initial state
     noise_amp: float = 1e-5
+    q: int = 27                    # velocity set: 27 (D3Q27) or 19 (D3Q19)
 
     @property
     def cells(self) -> int:
