@@ -27,7 +27,12 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS and % HBM roofline (fwd FP32 vs FP16-storage); adjoint/forward cost ratio"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL = {"f64": 2 * 27 * 8, "f32": 2 * 27 * 4, "f16": 2 * 27 * 2, "bf16": 2 * 27 * 2}
+ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def bytes_per_cell(storage, q=27):
+    """Algorithmic bytes of one cell update: q populations read, q written."""
+    return 2 * q * ELEM_BYTES[storage]
 KERNEL_SOURCES = ["paper_2510_13726_amd/csrc/kernels.hip", "paper_2510_13726_amd/csrc/lbm_cell.h"]
 
 
@@ -77,10 +82,12 @@ def time_storage(w, storage, steps, warmup, diag_every=1):
 
 
 def roofline(w, storage, sweep_avg_ms, sweep_cells):
-    algo = BYTES_PER_CELL[storage] * sweep_cells
+    q = getattr(w, "q", 27)
+    algo = bytes_per_cell(storage, q) * sweep_cells
     achieved = algo / (sweep_avg_ms * 1e-3) / 1e9
     traffic = None
-    f = os.path.join(ROOT, "profiles", f"sweep_traffic_{w.name}_{storage}.json")
+    tag = "" if q == 27 else "_d3q19"
+    f = os.path.join(ROOT, "profiles", f"sweep_traffic_{w.name}{tag}_{storage}.json")
     if os.path.exists(f):
         with open(f) as fh:
             t = json.load(fh)
@@ -170,7 +177,7 @@ def config_sweep(keys, storages, main_key, main_results, cpu_seconds):
             rl = roofline(w, st, r["sweep_avg_ms"], r["sweep_cells"])
             row[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
                        "sweep_frac": rl["frac"], "sweep_GB_s": rl["achieved"], "finite": r["finite"],
-                       "cache_resident": BYTES_PER_CELL[st] // 2 * w.cells <= CACHE_RESIDENT_BYTES}
+                       "cache_resident": bytes_per_cell(st) // 2 * w.cells <= CACHE_RESIDENT_BYTES}
             log(f"config {k} {st}: {row[st]}")
         if cpu_seconds > 0:
             row["cpu_oracle"] = cpu_sample(w, cpu_seconds)
@@ -213,6 +220,7 @@ def main():
     ap.add_argument("--config", default="5", help="workload: 1..5 (3 and 5 are full size)")
     ap.add_argument("--variants", default="f16,bf16", help="extra storage types timed on the same workload")
     ap.add_argument("--diag-every", type=int, default=1, help="mass reduction every k-th step in the timed runs")
+    ap.add_argument("--d3q19", default="f32,f16", help="storage types timed on the D3Q19 lattice ('' = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="seconds of the FP64 oracle on a sample of the workload (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint ratio run (0 = skip)")
@@ -246,6 +254,15 @@ def main():
         log(f"{st}: {r}")
         variants[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
                         "roofline": roofline(w, st, r["sweep_avg_ms"], r["sweep_cells"]), "finite": r["finite"]}
+    d3q19 = {}
+    for st in [s for s in args.d3q19.split(",") if s]:
+        w19 = W.ALL[args.config]()
+        w19.q = 19
+        r = time_storage(w19, st, args.steps, args.warmup, args.diag_every)
+        log(f"d3q19 {st}: {r}")
+        d3q19[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+                     "bytes_per_cell": bytes_per_cell(st, 19),
+                     "roofline": roofline(w19, st, r["sweep_avg_ms"], r["sweep_cells"]), "finite": r["finite"]}
     per_config = None
     keys = [k for k in args.configs.split(",") if k]
     if keys:
@@ -283,6 +300,7 @@ def main():
         "roofline": roofline(w, args.storage, main_run["sweep_avg_ms"], main_run["sweep_cells"]),
         "cpu_baseline": cpu,
         "storage_variants": variants,
+        "d3q19": d3q19 or None,
         "per_config": per_config,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,

@@ -5,7 +5,8 @@
  * Boltzmann method with Smagorinsky LES and a Spalding wall model on moving
  * porous rotors ("Efficient Wall-Modelled Large Eddy Simulation of Rotors
  * using Homogenized Lattice Boltzmann Methods", Sec. 2.2 eq. hlbm, Sec. 2.2.1,
- * Sec. 2.2.2, Sec. 3) on a D3Q27 lattice, on one gfx950 GPU.
+ * Sec. 2.2.2, Sec. 3) on a D3Q27 lattice or on the paper's D3Q19 lattice
+ * (Sec. 2.2, Fig. 2), on one gfx950 GPU.
  *
  * Conventions used by every entry point:
  *  - Cells (x, y, z), x fastest; linear cell index c = (z*ny + y)*nx + x.
@@ -13,11 +14,15 @@
  *  - Velocities c_i in {-1,0,1}^3, canonical order i = 9(cx+1)+3(cy+1)+(cz+1),
  *    opposite of i is 26-i, rest population 13; weights 8/27, 2/27, 1/54,
  *    1/216 by |c_i|^2 = 0, 1, 2, 3; lattice units dx = dt = 1, cs^2 = 1/3.
+ *    D3Q19 (hlbm_desc.velocities = 19): the same order restricted to the 19
+ *    velocities with |c_i|^2 <= 2 (index k = 0..18, opposite 18-k, rest 9),
+ *    weights 1/3, 1/18, 1/36; its third-order Hermite terms are the
+ *    projection onto H_aab + H_ccb and H_aab - H_ccb.
  *  - State between steps: the post-collision populations f*_i(x) of the
  *    previous step.  Step n pulls f_i(x, n) = f*_i(x - c_i) (the streaming of
  *    eq. hlbm), applies the outer boundaries, collides and stores f*(x).
  *    Canonical population arrays exchanged through this ABI hold
- *    h_i(x) = f*_i(x) - w_i in FP64, layout [27][nz][ny][nx].
+ *    h_i(x) = f*_i(x) - w_i in FP64, layout [q][nz][ny][nx] (q = 27 or 19).
  *  - Porosity convention of eq. convexVelocity: d = 1 solid, d = 0 fluid.
  *  - "device" pointers are HIP device memory on the lattice's device; "host"
  *    pointers are ordinary host memory.  The library never frees memory it
@@ -66,6 +71,7 @@ typedef struct hlbm_lattice* hlbm_handle;
  * only with compute = HLBM_F32); compute: arithmetic type of the sweep
  * (HLBM_F64 or HLBM_F32).  bc_x: x faces periodic, or equilibrium inflow at
  * x = 0 and zero-gradient outflow at x = nx-1 (y and z are periodic).
+ * velocities: 27 (or 0) for D3Q27, 19 for D3Q19 (no HLBM_WITH_ADJOINT).
  * bbox_cells: total cells of the rotors' bounding boxes the workspace must
  * hold (from hlbm_rotor_bbox_cells); history: steps kept in the force ring. */
 typedef struct {
@@ -74,7 +80,7 @@ typedef struct {
   int32_t compute;
   int32_t bc_x;
   int32_t flags;
-  int32_t pad0;
+  int32_t velocities;
   int64_t bbox_cells;
   int64_t history;
   void* stream;              /* hipStream_t; NULL = the null stream */
@@ -112,8 +118,8 @@ typedef struct {
 
 /* Bytes of one population buffer.  Its layout is internal (the canonical
  * arrays go through hlbm_get/set_populations): each (y, z) row is cut into
- * blocks of 64 consecutive x cells holding the 27 populations of those cells
- * as 27 runs of 64 values, the last block padded. */
+ * blocks of 64 consecutive x cells holding the q populations of those cells
+ * as q runs of 64 values, the last block padded. */
 int64_t hlbm_population_bytes(const hlbm_desc* desc);
 /* Bytes of the workspace for this description. */
 int64_t hlbm_workspace_bytes(const hlbm_desc* desc);
@@ -190,10 +196,11 @@ int64_t hlbm_get_step(hlbm_handle h);
  * state is not changed. */
 int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat);
 
-/* Canonical state h = f* - w, FP64, device, [27][N]. */
+/* Canonical state h = f* - w, FP64, device, [q][N]. */
 int hlbm_get_populations(hlbm_handle h, double* dst);
 int hlbm_set_populations(hlbm_handle h, const double* src);
-/* Canonical state at selected cells: dst[k*27 + i] for cell cells[k] (both device). */
+/* Canonical state at selected cells: dst[k*q + i] for cell cells[k] (both
+ * device); NaN for a cell index outside the lattice. */
 int hlbm_get_populations_at(hlbm_handle h, const int64_t* cells, int64_t count, double* dst);
 
 /* Complete restartable state (populations in storage format, wall-model
@@ -218,7 +225,7 @@ int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]);
 int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
 
 /* Discrete adjoint of the time stepping (gradient of the time-averaged
- * rotor torque with respect to the porosity control delta_d).
+ * rotor torque with respect to the porosity control delta_d), D3Q27 only.
  * Objective: J = 1/(t1-t0) sum over steps k in [t0, t1) of the record of
  * the axial torque e_tag . T_tag (obj_tag 0 = all tags), with T from the
  * momentum handed to the solid (Sec. 2.2.2).  Needs HLBM_WITH_ADJOINT.

@@ -34,14 +34,25 @@ bool desc_ok(const hlbm_desc* d, std::string* why) {
   if (d->compute == HLBM_F32 && d->storage == HLBM_F64) { *why = "F64 storage needs F64 compute"; return false; }
   if (d->bc_x != HLBM_BC_PERIODIC && d->bc_x != HLBM_BC_INFLOW_OUTFLOW) { *why = "unknown bc_x"; return false; }
   if (d->bbox_cells < 0 || d->history < 0) { *why = "negative bbox_cells or history"; return false; }
+  if (d->velocities != 0 && d->velocities != 27 && d->velocities != 19) {
+    *why = "velocities must be 27 (or 0) or 19";
+    return false;
+  }
+  if (d->velocities == 19 && (d->flags & HLBM_WITH_ADJOINT)) {
+    *why = "the discrete adjoint is available on the 27-velocity set only";
+    return false;
+  }
   return true;
 }
+
+// Velocities of the lattice's set: 27 or 19.
+int vel_of(const hlbm_desc* d) { return d->velocities == 19 ? 19 : 27; }
 
 int64_t cells_of(const hlbm_desc* d) { return int64_t(d->nx) * d->ny * d->nz; }
 
 // Population elements per (y, z) row in the blocked layout: the row's x
-// extent rounded up to whole blocks of kTileX cells, 27 populations each.
-int64_t pop_row(const hlbm_desc* d) { return int64_t((d->nx + kTileX - 1) / kTileX) * 27 * kTileX; }
+// extent rounded up to whole blocks of kTileX cells, q populations each.
+int64_t pop_row(const hlbm_desc* d) { return int64_t((d->nx + kTileX - 1) / kTileX) * vel_of(d) * kTileX; }
 // Elements of one population buffer.
 int64_t pop_elems(const hlbm_desc* d) { return pop_row(d) * d->ny * d->nz; }
 
@@ -510,6 +521,7 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.stream = h->stream;
   L.storage = d->storage;
   L.compute = d->compute;
+  L.q = vel_of(d);
   L.g.nx = d->nx; L.g.ny = d->ny; L.g.nz = d->nz; L.g.bc_x = d->bc_x;
   L.g.N = cells_of(d);
   L.g.row = pop_row(d);

@@ -94,16 +94,18 @@ struct Geometry {
 };
 
 // Blocked population layout: a row of the lattice is cut into blocks of
-// kTileX consecutive x cells (one sweep wave); a block holds its cells' 27
-// populations as 27 runs of kTileX values, so a wave's 27 loads and 27
-// stores each touch one contiguous 256-byte run (FP32) of a few blocks.
-// Element (i, x, y, z) of a population buffer:
+// kTileX consecutive x cells (one sweep wave); a block holds its cells' Q
+// populations (27 or 19) as Q runs of kTileX values, so each of a wave's Q
+// loads and Q stores touches one contiguous 256-byte run (FP32) of a few
+// blocks.  Element (i, x, y, z) of a population buffer:
+template <int Q = 27>
 __host__ __device__ inline int64_t pop_at(const Geometry& g, int i, int x, int y, int z) {
-  return (int64_t(z) * g.ny + y) * g.row + int64_t(x / kTileX) * (27 * kTileX) + i * kTileX + x % kTileX;
+  return (int64_t(z) * g.ny + y) * g.row + int64_t(x / kTileX) * (Q * kTileX) + i * kTileX + x % kTileX;
 }
 // Offset of cell x inside its row, population 0 (add i * kTileX for population i).
+template <int Q = 27>
 __host__ __device__ inline uint32_t pop_x(int x) {
-  return uint32_t(x / kTileX) * uint32_t(27 * kTileX) + uint32_t(x % kTileX);
+  return uint32_t(x / kTileX) * uint32_t(Q * kTileX) + uint32_t(x % kTileX);
 }
 
 // cos and sin of every blade angle of every rotor at the current step

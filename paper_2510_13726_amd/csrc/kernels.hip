@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "hlbm_internal.h"
 #include "launch.h"
@@ -24,14 +25,25 @@ namespace hlbm {
 // ================================================================ helpers
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>): loop
+// bodies whose velocity index is a compile-time constant.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // Pre-collision deviations h_i = f_i - w_i of cell (x, y, z):
 // f_i(x) = f*_i(x - c_i) with periodic y, z; in x periodic, or the
 // equilibrium inflow ghost plane at x = -1 (precomputed for the step in
 // `ghost`, [9][nz][ny] for the velocities with c_x = +1) and the
 // zero-gradient copy at x = nx.
-template <class ST, class CT, bool kPeriodicX>
+template <class ST, class CT, bool kPeriodicX, int Q = 27>
 __device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geometry& g, int x, int y, int z,
-                                          const CT* __restrict__ ghost, CT h[27]) {
+                                          const CT* __restrict__ ghost, CT h[Q]) {
   const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
   const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
   int xp, xm;
@@ -46,19 +58,23 @@ __device__ __forceinline__ void pull_cell(const ST* __restrict__ src, const Geom
   const int64_t rb[3][3] = {{(int64_t(zp) * g.ny + yp) * g.row, (int64_t(zp) * g.ny + y) * g.row, (int64_t(zp) * g.ny + ym) * g.row},
                             {(int64_t(z) * g.ny + yp) * g.row, (int64_t(z) * g.ny + y) * g.row, (int64_t(z) * g.ny + ym) * g.row},
                             {(int64_t(zm) * g.ny + yp) * g.row, (int64_t(zm) * g.ny + y) * g.row, (int64_t(zm) * g.ny + ym) * g.row}};
-  const uint32_t ox[3] = {pop_x(xp), pop_x(x), pop_x(xm)};
-#pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const ST* p = src + rb[cz_of(i) + 1][cy_of(i) + 1];
-    const uint32_t o = (ox[cx_of(i) + 1] + uint32_t(i * kTileX)) * uint32_t(sizeof(ST));
-    h[i] = CT(w_of(i)) * Store<ST>::template load<CT>(at_bytes(p, o));
-  }
+  const uint32_t ox[3] = {pop_x<Q>(xp), pop_x<Q>(x), pop_x<Q>(xm)};
+  static_for<Q>([&](auto I) {
+    constexpr int i = I;
+    const ST* p = src + rb[czq<Q>(i) + 1][cyq<Q>(i) + 1];
+    const uint32_t o = (ox[cxq<Q>(i) + 1] + uint32_t(i * kTileX)) * uint32_t(sizeof(ST));
+    h[i] = CT(wq<Q>(i)) * Store<ST>::template load<CT>(at_bytes(p, o));
+  });
   if (!kPeriodicX && x == 0) {
+    // the inflow plane holds the nine c_x = +1 directions by m = 3 (c_y + 1) + (c_z + 1)
     const uint32_t pz[3] = {uint32_t(zp) * g.ny, uint32_t(z) * g.ny, uint32_t(zm) * g.ny};
     const uint32_t py[3] = {uint32_t(yp), uint32_t(y), uint32_t(ym)};
     const int64_t plane = int64_t(g.ny) * g.nz;
-#pragma unroll
-    for (int i = 18; i < 27; ++i) h[i] = ghost[(i - 18) * plane + pz[cz_of(i) + 1] + py[cy_of(i) + 1]];
+    static_for<9>([&](auto M) {
+      constexpr int m = M;
+      constexpr int k = kq<Q>(1, m / 3 - 1, m % 3 - 1);
+      if constexpr (k >= 0) h[k] = ghost[m * plane + pz[m % 3] + py[m / 3]];
+    });
   }
 }
 
@@ -70,9 +86,9 @@ typedef __attribute__((address_space(1))) char* gbytes;
 // pull_cell for a wave whose 64 lanes share y and z (uniform values): the
 // y/z part of every source address is a scalar, the per-lane part is one of
 // three x offsets, so each load is a scalar base plus a 32-bit lane offset.
-template <class ST, class CT, bool kPeriodicX>
+template <class ST, class CT, bool kPeriodicX, int Q = 27>
 __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geometry& g, int x, int y, int z,
-                                         const CT* __restrict__ ghost, CT h[27]) {
+                                         const CT* __restrict__ ghost, CT h[Q]) {
   const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
   const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
   int xp, xm;
@@ -83,37 +99,43 @@ __device__ __forceinline__ void pull_row(const ST* __restrict__ src, const Geome
     xp = x + 1 == g.nx ? x : x + 1;  // outflow: copy of the last plane
     xm = x == 0 ? 0 : x - 1;         // inflow plane is replaced below
   }
-  // The three velocities with the same (c_y, c_z) read the same source row
-  // (y - c_y, z - c_z), at population runs 9 apart.  Each of the nine rows
-  // gets one wave-uniform base (its start); a lane adds one of three 32-bit
-  // offsets, its source cell in the row plus 9 (c_x + 1) runs, and the load
-  // the constant 3 (c_y + 1) + (c_z + 1) runs as its immediate offset.
+  // The velocities with the same (c_y, c_z) read the same source row
+  // (y - c_y, z - c_z), each from the run of its own index.  Each of the
+  // nine rows gets one wave-uniform base (its start); a lane adds one of
+  // three 32-bit offsets, its source cell in the row plus the first run of
+  // the velocities with its c_x, and the load the velocity's rank among those
+  // runs as its immediate offset.
   constexpr uint32_t es = sizeof(ST), run = kTileX * es;
   const uint64_t rs = uint64_t(g.row) * es;
   // index [c + 1] of each array: source z - c_z, y - c_y, x - c_x
   const uint64_t zb[3] = {uint64_t(zp) * g.ny * rs, uint64_t(z) * g.ny * rs, uint64_t(zm) * g.ny * rs};
   const uint64_t yb[3] = {uint64_t(yp) * rs, uint64_t(y) * rs, uint64_t(ym) * rs};
-  const uint32_t ox[3] = {pop_x(xp) * es, pop_x(x) * es + 9 * run, pop_x(xm) * es + 18 * run};
+  const uint32_t ox[3] = {pop_x<Q>(xp) * es + xgroup_of<Q>(0) * run, pop_x<Q>(x) * es + xgroup_of<Q>(1) * run,
+                          pop_x<Q>(xm) * es + xgroup_of<Q>(2) * run};
   gconst_bytes p = (gconst_bytes)src;
-#pragma unroll
-  for (int b = 0; b < 3; ++b)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      gconst_bytes q = p + (zb[a] + yb[b]);
-      // kept in scalar registers: each load is this base plus a lane offset
-      asm("" : "+s"(q));
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int i = 9 * j + 3 * b + a;
-        h[i] = CT(w_of(i)) * Store<ST>::template load<CT>((const ST*)(q + ox[j] + (3 * b + a) * run));
+  static_for<9>([&](auto R) {
+    constexpr int b = R / 3, a = R % 3;  // c_y + 1, c_z + 1
+    gconst_bytes q = p + (zb[a] + yb[b]);
+    // kept in scalar registers: each load is this base plus a lane offset
+    asm("" : "+s"(q));
+    static_for<3>([&](auto J) {
+      constexpr int j = J;
+      constexpr int k = kq<Q>(j - 1, b - 1, a - 1);
+      if constexpr (k >= 0) {
+        constexpr uint32_t rank = uint32_t(k - xgroup_of<Q>(j));
+        h[k] = CT(wq<Q>(k)) * Store<ST>::template load<CT>((const ST*)(q + ox[j] + rank * run));
       }
-    }
+    });
+  });
   if (!kPeriodicX && x == 0) {
     const int64_t plane = int64_t(g.ny) * g.nz;
     const int64_t pz[3] = {int64_t(zp) * g.ny, int64_t(z) * g.ny, int64_t(zm) * g.ny};
     const int py[3] = {yp, y, ym};
-#pragma unroll
-    for (int i = 18; i < 27; ++i) h[i] = ghost[(i - 18) * plane + pz[cz_of(i) + 1] + py[cy_of(i) + 1]];
+    static_for<9>([&](auto M) {
+      constexpr int m = M;
+      constexpr int k = kq<Q>(1, m / 3 - 1, m % 3 - 1);
+      if constexpr (k >= 0) h[k] = ghost[m * plane + pz[m % 3] + py[m / 3]];
+    });
   }
 }
 
@@ -152,7 +174,7 @@ __device__ __forceinline__ TileId tile_id(const Geometry& g, uint32_t blk) {
 // Inflow ghost plane of step n: h_i = f^eq_i(1, u_in(n, y, z)) - w_i for the
 // nine velocities with c_x = +1, u_in = U + I |U| xi with seeded normals xi.
 // Cell k = z ny + y of the plane; ghost64 (nullable) gets the FP64 values.
-template <class CT>
+template <class CT, int Q = 27>
 __device__ __forceinline__ void inflow_plane_cell(const Geometry& g, const Model& m, int64_t n, int64_t k,
                                                   CT* __restrict__ ghost, double* __restrict__ ghost64) {
   const int64_t plane = int64_t(g.ny) * g.nz;
@@ -160,24 +182,29 @@ __device__ __forceinline__ void inflow_plane_cell(const Geometry& g, const Model
   double u[3] = {m.u_in[0], m.u_in[1], m.u_in[2]};
   if (m.turb_amp != 0.0)
     for (int a = 0; a < 3; ++a) u[a] += m.turb_amp * inflow_normal(m.seed, n, y, z, a, g.ny, g.nz);
-  CT ge[27];
-  equilibrium_dev_unit<CT>(CT(u[0]), CT(u[1]), CT(u[2]), ge);
-#pragma unroll
-  for (int i = 18; i < 27; ++i) ghost[(i - 18) * plane + k] = CT(w_of(i)) * ge[i];
+  // the c_x = +1 directions, by m = 3 (c_y + 1) + (c_z + 1)
+  CT ge[Q];
+  equilibrium_dev_unit<CT, Q>(CT(u[0]), CT(u[1]), CT(u[2]), ge);
+  static_for<9>([&](auto M) {
+    constexpr int kk = kq<Q>(1, M / 3 - 1, M % 3 - 1);
+    if constexpr (kk >= 0) ghost[M * plane + k] = CT(wq<Q>(kk)) * ge[kk];
+  });
   if (ghost64) {
-    double gd[27];
-    equilibrium_dev_unit<double>(u[0], u[1], u[2], gd);
-#pragma unroll
-    for (int i = 18; i < 27; ++i) ghost64[(i - 18) * plane + k] = w_of(i) * gd[i];
+    double gd[Q];
+    equilibrium_dev_unit<double, Q>(u[0], u[1], u[2], gd);
+    static_for<9>([&](auto M) {
+      constexpr int kk = kq<Q>(1, M / 3 - 1, M % 3 - 1);
+      if constexpr (kk >= 0) ghost64[M * plane + k] = wq<Q>(kk) * gd[kk];
+    });
   }
 }
 
-template <class CT>
+template <class CT, int Q>
 __global__ __launch_bounds__(256) void k_prologue(Geometry g, Model m, int64_t n, CT* __restrict__ ghost,
                                                   double* __restrict__ ghost64) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g.bc_x == 0 || k >= int64_t(g.ny) * g.nz) return;
-  inflow_plane_cell<CT>(g, m, n, k, ghost, ghost64);
+  inflow_plane_cell<CT, Q>(g, m, n, k, ghost, ghost64);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -681,8 +708,9 @@ struct WallArgs {
 // the collision VJP at the wall cell for the adjoint of (u_wm, S), the
 // transposed Jacobian giving the adjoints of the probe velocity (scattered to
 // the eight probe corners with the trilinear weights) and of u_tau^prev.
-template <class ST, class CT, bool kPeriodicX, bool kAdj>
+template <class ST, class CT, bool kPeriodicX, bool kAdj, int Q = 27>
 __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, uint32_t nblk) {
+  static_assert(!kAdj || Q == 27, "the adjoint wall step is written for the 27-velocity set");
   const RotorTable& rt = *a.rot;
   const Geometry& g = a.g;
   const Model& m = a.m;
@@ -718,9 +746,9 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
     const bool actp = act_prev[s] != 0;
     const RotorDev& R = rt.r[rotor_of_slot(rt, s)];
     const Probe pr = probe_of(R, g, m, geo, total, s, wr, corner, kPeriodicX);
-    double h[27];
-    pull_cell<ST, double, kPeriodicX>(src, g, pr.q[0], pr.q[1], pr.q[2], a.ghost, h);
-    const Moments<double> mo = moments_of<double>(h);
+    double h[Q];
+    pull_cell<ST, double, kPeriodicX, Q>(src, g, pr.q[0], pr.q[1], pr.q[2], a.ghost, h);
+    const Moments<double> mo = moments_q<Q, double>(h);
     const double rho = 1.0 + mo.drho;
     double us[3] = {pr.wgt * (mo.jx / rho), pr.wgt * (mo.jy / rho), pr.wgt * (mo.jz / rho)};
     group8_sum(us);
@@ -858,9 +886,9 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
   }
 }
 
-template <class ST, class CT, bool kPeriodicX, bool kAdj>
+template <class ST, class CT, bool kPeriodicX, bool kAdj, int Q>
 __global__ __launch_bounds__(256) void k_wall(WallArgs<CT> a) {
-  wall_cells<ST, CT, kPeriodicX, kAdj>(a, blockIdx.x, gridDim.x);
+  wall_cells<ST, CT, kPeriodicX, kAdj, Q>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- geometry
@@ -893,7 +921,7 @@ struct GeoArgs {
 
 // Workgroup `bid` of the geometry work: box slots first, then the extra
 // workgroups of the inflow plane.
-template <class CT>
+template <class CT, int Q = 27>
 __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bid) {
   const Geometry& g = a.g;
   const Model& m = a.m;
@@ -901,7 +929,7 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
   if (bid >= nbw) {
     const int64_t plane = int64_t(g.ny) * g.nz;
     const int64_t k = (int64_t(bid) - nbw) * 256 + threadIdx.x;
-    if (k < plane) inflow_plane_cell<CT>(g, m, a.step, k, a.ghost, a.ghost64);
+    if (k < plane) inflow_plane_cell<CT, Q>(g, m, a.step, k, a.ghost, a.ghost64);
     return;
   }
   __shared__ int wl_count, wl_base;
@@ -969,19 +997,19 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
   a.geo[3 * a.total + pos] = -gr[2] * inv;
 }
 
-template <class CT>
+template <class CT, int Q>
 __global__ __launch_bounds__(256) void k_geometry(GeoArgs<CT> a) {
-  geometry_block<CT>(a, blockIdx.x);
+  geometry_block<CT, Q>(a, blockIdx.x);
 }
 
 // The wall model of one step (workgroups [0, wall_blocks)) and the geometry
 // of the next step (the remaining workgroups) in one launch: the two are
 // independent when the geometry writes the other buffer set, and both are
 // latency-bound chains that overlap well.
-template <class ST, class CT, bool kPeriodicX, bool kAdj>
+template <class ST, class CT, bool kPeriodicX, bool kAdj, int Q>
 __global__ __launch_bounds__(256) void k_wall_geometry(WallArgs<CT> w, GeoArgs<CT> ga, uint32_t wall_blocks) {
-  if (blockIdx.x < wall_blocks) wall_cells<ST, CT, kPeriodicX, kAdj>(w, blockIdx.x, wall_blocks);
-  else geometry_block<CT>(ga, blockIdx.x - wall_blocks);
+  if (blockIdx.x < wall_blocks) wall_cells<ST, CT, kPeriodicX, kAdj, Q>(w, blockIdx.x, wall_blocks);
+  else geometry_block<CT, Q>(ga, blockIdx.x - wall_blocks);
 }
 
 // ================================================================ fused sweep
@@ -1015,7 +1043,7 @@ struct SweepArgs {
 // porous region (blk_slot >= 0) read porosity and tags, apply the
 // homogenized velocity and the wall model outputs and reduce the momentum
 // handed to each tag; the others run the plain bulk collision.
-template <class ST, class CT, bool kPeriodicX, bool kMoments>
+template <class ST, class CT, bool kPeriodicX, bool kMoments, int Q = 27>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk, double (&lds)[4][kPartial]) {
   const Geometry& g = a.g;
   // tile (tx, ty, z): 64 consecutive x-cells per wave, 4 y-rows per workgroup
@@ -1031,15 +1059,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
   const int32_t slot = a.blk_slot[ti.canon];
 
-  CT h[27];
-  pull_row<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
-  const Moments<CT> mo = moments_of<CT>(h);
+  CT h[Q];
+  pull_row<ST, CT, kPeriodicX, Q>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+  const Moments<CT> mo = moments_q<Q, CT>(h);
   const CT rho = CT(1) + mo.drho;
   const CT irho = rcp_ct(rho);
   const CT ux = mo.jx * irho, uy = mo.jy * irho, uz = mo.jz * irho;
   const CT tau0 = CT(a.m.tau0), smag = CT(a.m.smag);
 
-  CT g2[27];
+  CT g2[Q];
   if (slot < 0) {
     if (kMoments) {
       if (valid) {
@@ -1050,7 +1078,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
       return;
     }
     const CT S0[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)};
-    collide<CT, false>(mo, rho, ux, uy, uz, CT(1), S0, tau0, smag, g2);
+    collide<CT, false, Q>(mo, rho, ux, uy, uz, CT(1), S0, tau0, smag, g2);
   } else {
     CT d = CT(0);
     uint8_t tb = 0;
@@ -1094,7 +1122,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
       }
       return;
     }
-    collide<CT, true>(mo, rho, hx, hy, hz, sigma, S, tau0, smag, g2);
+    collide<CT, true, Q>(mo, rho, hx, hy, hz, sigma, S, tau0, smag, g2);
     // momentum handed to the solid and its torque, per tag (FP64)
     double v[6] = {0, 0, 0, 0, 0, 0};
     if (t != 0 && valid) {
@@ -1135,18 +1163,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
   }
   if (!kMoments) {
     if (valid) {
-      // this wave's block: contiguous, 27 runs of kTileX cells
+      // this wave's block: contiguous, Q runs of kTileX cells
       // one scalar base per group of runs that the 12-bit immediate offset
-      // of a store reaches (FP16 27 runs, FP32 16, FP64 8)
+      // of a store reaches (FP16 32 runs, FP32 16, FP64 8)
       constexpr int run = kTileX * sizeof(ST), per = 4096 / run;
-      const gbytes p = (gbytes)(static_cast<ST*>(a.dst) + (int64_t(z) * g.ny + y) * g.row + int64_t(tx) * (27 * kTileX));
+      const gbytes p = (gbytes)(static_cast<ST*>(a.dst) + (int64_t(z) * g.ny + y) * g.row + int64_t(tx) * (Q * kTileX));
       const uint32_t o = uint32_t(x % kTileX) * uint32_t(sizeof(ST));
 #pragma unroll
-      for (int i0 = 0; i0 < 27; i0 += per) {
+      for (int i0 = 0; i0 < Q; i0 += per) {
         gbytes q = p + int64_t(i0) * run;
         asm("" : "+s"(q));
 #pragma unroll
-        for (int i = i0; i < 27 && i < i0 + per; ++i) Store<ST>::template store<CT>((ST*)(q + o + (i - i0) * run), g2[i]);
+        for (int i = i0; i < Q && i < i0 + per; ++i) Store<ST>::template store<CT>((ST*)(q + o + (i - i0) * run), g2[i]);
       }
     }
     // a non-finite density raises the flag (steps that check)
@@ -1175,11 +1203,11 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t i, const Geometry& g) {
   return i - r + (r % 8u) * ntx + r / 8u;
 }
 
-template <class ST, class CT, bool kPeriodicX, bool kMoments>
+template <class ST, class CT, bool kPeriodicX, bool kMoments, int Q>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<CT> a) {
   __shared__ double lds[4][kPartial];
   const uint32_t blk = tile_of(blockIdx.x, a.g);
-  sweep_tile<ST, CT, kPeriodicX, kMoments>(a, blk, lds);
+  sweep_tile<ST, CT, kPeriodicX, kMoments, Q>(a, blk, lds);
 }
 
 // Force / torque / mass reduction, level 1: workgroup (b, j) sums the force
@@ -1253,41 +1281,43 @@ __global__ __launch_bounds__(256) void k_reduce_l2(const double* __restrict__ l1
 }
 
 // ---------------------------------------------------------------- state I/O
-template <class ST, class CT>
+template <class ST, class CT, int Q>
 __global__ __launch_bounds__(256) void k_init_eq(ST* __restrict__ dst, Geometry g, const CT* __restrict__ rho,
                                                  const CT* __restrict__ u) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= g.N) return;
   const CT r = rho ? rho[c] : CT(1);
   const CT ux = u ? u[c] : CT(0), uy = u ? u[g.N + c] : CT(0), uz = u ? u[2 * g.N + c] : CT(0);
-  CT ge[27];
-  equilibrium_dev<CT>(r, ux, uy, uz, ge);
+  CT ge[Q];
+  equilibrium_dev<CT, Q>(r, ux, uy, uz, ge);
   const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
 #pragma unroll
-  for (int i = 0; i < 27; ++i) Store<ST>::template store<CT>(dst + pop_at(g, i, x, y, z), ge[i]);
+  for (int i = 0; i < Q; ++i) Store<ST>::template store<CT>(dst + pop_at<Q>(g, i, x, y, z), ge[i]);
 }
 
-template <class ST>
+template <class ST, int Q>
 __global__ __launch_bounds__(256) void k_get_pop(const ST* __restrict__ src, Geometry g, double* __restrict__ dst) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= g.N) return;
   const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
-#pragma unroll
-  for (int i = 0; i < 27; ++i)
-    dst[int64_t(i) * g.N + c] = w_of(i) * Store<ST>::template load<double>(src + pop_at(g, i, x, y, z));
+  static_for<Q>([&](auto I) {
+    constexpr int i = I;
+    dst[int64_t(i) * g.N + c] = wq<Q>(i) * Store<ST>::template load<double>(src + pop_at<Q>(g, i, x, y, z));
+  });
 }
 
-template <class ST>
+template <class ST, int Q>
 __global__ __launch_bounds__(256) void k_set_pop(ST* __restrict__ dst, Geometry g, const double* __restrict__ src) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= g.N) return;
   const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
-#pragma unroll
-  for (int i = 0; i < 27; ++i)
-    Store<ST>::template store<double>(dst + pop_at(g, i, x, y, z), src[int64_t(i) * g.N + c] / w_of(i));
+  static_for<Q>([&](auto I) {
+    constexpr int i = I;
+    Store<ST>::template store<double>(dst + pop_at<Q>(g, i, x, y, z), src[int64_t(i) * g.N + c] / wq<Q>(i));
+  });
 }
 
-template <class ST>
+template <class ST, int Q>
 __global__ __launch_bounds__(256) void k_get_pop_at(const ST* __restrict__ src, Geometry g,
                                                     const int64_t* __restrict__ cells, int64_t count,
                                                     double* __restrict__ dst) {
@@ -1295,12 +1325,14 @@ __global__ __launch_bounds__(256) void k_get_pop_at(const ST* __restrict__ src, 
   if (k >= count) return;
   const int64_t c = cells[k];
   if (c < 0 || c >= g.N) {
-    for (int i = 0; i < 27; ++i) dst[k * 27 + i] = __builtin_nan("");
+    for (int i = 0; i < Q; ++i) dst[k * Q + i] = __builtin_nan("");
     return;
   }
   const int x = int(c % g.nx), y = int((c / g.nx) % g.ny), z = int(c / (int64_t(g.nx) * g.ny));
-#pragma unroll
-  for (int i = 0; i < 27; ++i) dst[k * 27 + i] = w_of(i) * Store<ST>::template load<double>(src + pop_at(g, i, x, y, z));
+  static_for<Q>([&](auto I) {
+    constexpr int i = I;
+    dst[k * Q + i] = wq<Q>(i) * Store<ST>::template load<double>(src + pop_at<Q>(g, i, x, y, z));
+  });
 }
 
 // Every element of a population buffer (cells and the unused tail of the
@@ -1547,6 +1579,13 @@ static hipError_t by_types(int storage, int compute, F&& f) {
   return hipErrorInvalidValue;
 }
 
+// f(integral_constant<int, Q>) for the lattice's velocity set.
+template <class F>
+static hipError_t by_q(int q, F&& f) {
+  if (q == 19) return f(std::integral_constant<int, 19>{});
+  return f(std::integral_constant<int, 27>{});
+}
+
 template <class F>
 static hipError_t by_compute(int compute, F&& f) {
   if (compute == 0) return f((double*)nullptr);
@@ -1581,8 +1620,10 @@ hipError_t launch_geometry(const Launch& L, int64_t step, const BladeTrig* trig,
     int64_t blocks = 0;
     const GeoArgs<CT> a = geo_args<CT>(L, step, trig, epoch, act_new, with_ghost, &blocks);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_geometry<CT>, dim3(unsigned(blocks)), dim3(256), 0, L.stream, a);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      hipLaunchKernelGGL((k_geometry<CT, QC.value>), dim3(unsigned(blocks)), dim3(256), 0, L.stream, a);
+      return hipGetLastError();
+    });
   });
 }
 
@@ -1621,12 +1662,16 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
         hipLaunchKernelGGL(fused_kernel, dim3(unsigned(wall_blocks + geo_blocks)), dim3(256), 0, L.stream, w, ga,
                            uint32_t(wall_blocks));
     };
-    if (L.g.bc_x == 0) {
-      if (adj) go(k_wall<ST, CT, true, true>, k_wall_geometry<ST, CT, true, true>);
-      else go(k_wall<ST, CT, true, false>, k_wall_geometry<ST, CT, true, false>);
+    if (adj && L.q != 27) return hipErrorInvalidValue;  // the adjoint needs the 27-velocity set
+    if (L.q == 19) {
+      if (L.g.bc_x == 0) go(k_wall<ST, CT, true, false, 19>, k_wall_geometry<ST, CT, true, false, 19>);
+      else go(k_wall<ST, CT, false, false, 19>, k_wall_geometry<ST, CT, false, false, 19>);
+    } else if (L.g.bc_x == 0) {
+      if (adj) go(k_wall<ST, CT, true, true, 27>, k_wall_geometry<ST, CT, true, true, 27>);
+      else go(k_wall<ST, CT, true, false, 27>, k_wall_geometry<ST, CT, true, false, 27>);
     } else {
-      if (adj) go(k_wall<ST, CT, false, true>, k_wall_geometry<ST, CT, false, true>);
-      else go(k_wall<ST, CT, false, false>, k_wall_geometry<ST, CT, false, false>);
+      if (adj) go(k_wall<ST, CT, false, true, 27>, k_wall_geometry<ST, CT, false, true, 27>);
+      else go(k_wall<ST, CT, false, false, 27>, k_wall_geometry<ST, CT, false, false, 27>);
     }
     return hipGetLastError();
   });
@@ -1652,11 +1697,15 @@ hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t ste
     SweepArgs<CT> a = sweep_args<CT>(L, src, dst, step);
     if (diag) a.mass_part = L.mass_part;
     if (check) a.flag = L.flag;
-    if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_sweep<ST, CT, true, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
-    else
-      hipLaunchKernelGGL((k_sweep<ST, CT, false, false>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      constexpr int Q = QC.value;
+      if (L.g.bc_x == 0)
+        hipLaunchKernelGGL((k_sweep<ST, CT, true, false, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+      else
+        hipLaunchKernelGGL((k_sweep<ST, CT, false, false, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream,
+                           a);
+      return hipGetLastError();
+    });
   });
 }
 
@@ -1666,11 +1715,14 @@ hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* 
     using CT = std::remove_pointer_t<decltype(ct)>;
     SweepArgs<CT> a = sweep_args<CT>(L, src, nullptr, step);
     a.out_rho = (CT*)rho; a.out_u = (CT*)u; a.out_uhat = (CT*)uhat;
-    if (L.g.bc_x == 0)
-      hipLaunchKernelGGL((k_sweep<ST, CT, true, true>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
-    else
-      hipLaunchKernelGGL((k_sweep<ST, CT, false, true>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      constexpr int Q = QC.value;
+      if (L.g.bc_x == 0)
+        hipLaunchKernelGGL((k_sweep<ST, CT, true, true, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+      else
+        hipLaunchKernelGGL((k_sweep<ST, CT, false, true, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+      return hipGetLastError();
+    });
   });
 }
 
@@ -1681,8 +1733,11 @@ hipError_t launch_prologue(const Launch& L, int64_t step) {
   double* g64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
   return by_compute(L.compute, [&](auto* ct) {
     using CT = std::remove_pointer_t<decltype(ct)>;
-    hipLaunchKernelGGL(k_prologue<CT>, grid1(plane, 256), dim3(256), 0, L.stream, L.g, L.m, step, (CT*)L.ghost, g64);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      hipLaunchKernelGGL((k_prologue<CT, QC.value>), grid1(plane, 256), dim3(256), 0, L.stream, L.g, L.m, step,
+                         (CT*)L.ghost, g64);
+      return hipGetLastError();
+    });
   });
 }
 
@@ -1711,6 +1766,7 @@ static AdjArgs<CT> adj_args(const Launch& L, const AdjLaunch& A) {
 }
 
 hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A) {
+  if (L.q != 27) return hipErrorInvalidValue;  // the adjoint is written for the 27-velocity set
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
@@ -1727,25 +1783,32 @@ hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, 
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
-    hipLaunchKernelGGL((k_init_eq<ST, CT>), grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g,
-                       (const CT*)rho, (const CT*)u);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      hipLaunchKernelGGL((k_init_eq<ST, CT, QC.value>), grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g,
+                         (const CT*)rho, (const CT*)u);
+      return hipGetLastError();
+    });
   });
 }
 
 hipError_t launch_get_populations(const Launch& L, const void* src, double* dst) {
   return by_types(L.storage, L.compute, [&](auto* st, auto*) {
     using ST = std::remove_pointer_t<decltype(st)>;
-    hipLaunchKernelGGL(k_get_pop<ST>, grid1(L.g.N, 256), dim3(256), 0, L.stream, (const ST*)src, L.g, dst);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      hipLaunchKernelGGL((k_get_pop<ST, QC.value>), grid1(L.g.N, 256), dim3(256), 0, L.stream, (const ST*)src, L.g,
+                         dst);
+      return hipGetLastError();
+    });
   });
 }
 
 hipError_t launch_set_populations(const Launch& L, void* dst, const double* src) {
   return by_types(L.storage, L.compute, [&](auto* st, auto*) {
     using ST = std::remove_pointer_t<decltype(st)>;
-    hipLaunchKernelGGL(k_set_pop<ST>, grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g, src);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      hipLaunchKernelGGL((k_set_pop<ST, QC.value>), grid1(L.g.N, 256), dim3(256), 0, L.stream, (ST*)dst, L.g, src);
+      return hipGetLastError();
+    });
   });
 }
 
@@ -1754,9 +1817,11 @@ hipError_t launch_get_populations_at(const Launch& L, const void* src, const int
   if (count == 0) return hipSuccess;
   return by_types(L.storage, L.compute, [&](auto* st, auto*) {
     using ST = std::remove_pointer_t<decltype(st)>;
-    hipLaunchKernelGGL(k_get_pop_at<ST>, grid1(count, 256), dim3(256), 0, L.stream, (const ST*)src, L.g, cells,
-                       count, dst);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      hipLaunchKernelGGL((k_get_pop_at<ST, QC.value>), grid1(count, 256), dim3(256), 0, L.stream, (const ST*)src, L.g,
+                         cells, count, dst);
+      return hipGetLastError();
+    });
   });
 }
 

@@ -12,6 +12,7 @@ namespace hlbm {
 struct Launch {
   hipStream_t stream;        // the caller's stream
   int storage, compute;      // hlbm_dtype values
+  int q;                     // velocity set: 27 or 19
   Geometry g;
   Model m;
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz

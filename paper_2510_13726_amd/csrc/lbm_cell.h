@@ -39,6 +39,42 @@ __host__ __device__ constexpr double w_of(int i) {
 }
 __host__ __device__ constexpr int idx_of(int cx, int cy, int cz) { return 9 * (cx + 1) + 3 * (cy + 1) + (cz + 1); }
 
+// Velocity sets: D3Q27 (index i = idx_of(c)) and D3Q19, the paper's stencil
+// (Sec. 2.2, Fig. 2): the 27-velocity order restricted to |c|^2 <= 2,
+// weights 1/3, 1/18, 1/36.  k indexes a set's own velocities; opposite of k
+// is Q - 1 - k in both.
+template <int Q>
+__host__ __device__ constexpr int i27_of(int k) {
+  if (Q == 27) return k;
+  int n = -1;
+  for (int i = 0; i < 27; ++i) {
+    const int c2 = cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_of(i) * cz_of(i);
+    if (c2 <= 2 && ++n == k) return i;
+  }
+  return -1;
+}
+template <int Q> __host__ __device__ constexpr int cxq(int k) { return cx_of(i27_of<Q>(k)); }
+template <int Q> __host__ __device__ constexpr int cyq(int k) { return cy_of(i27_of<Q>(k)); }
+template <int Q> __host__ __device__ constexpr int czq(int k) { return cz_of(i27_of<Q>(k)); }
+template <int Q>
+__host__ __device__ constexpr double wq(int k) {
+  if (Q == 27) return w_of(k);
+  const int c2 = cxq<Q>(k) * cxq<Q>(k) + cyq<Q>(k) * cyq<Q>(k) + czq<Q>(k) * czq<Q>(k);
+  return c2 == 0 ? 1.0 / 3.0 : c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+}
+// Index of velocity (cx, cy, cz) in set Q; -1 if the set does not hold it.
+template <int Q>
+__host__ __device__ constexpr int kq(int cx, int cy, int cz) {
+  for (int k = 0; k < Q; ++k)
+    if (cxq<Q>(k) == cx && cyq<Q>(k) == cy && czq<Q>(k) == cz) return k;
+  return -1;
+}
+// First index of the velocities with c_x = j - 1 (they are contiguous).
+template <int Q>
+__host__ __device__ constexpr int xgroup_of(int j) {
+  return Q == 27 ? 9 * j : (j == 0 ? 0 : j == 1 ? 5 : 14);
+}
+
 // ---------------------------------------------------------------- storage
 // Stored value of g = (f - w)/w: double, float, IEEE half (RNE) or bfloat16
 // (RNE on the upper 16 bits of the float).
@@ -130,6 +166,32 @@ __device__ __forceinline__ Moments<CT> moments_of(const CT h[27]) {
   return m;
 }
 
+// Deviation moments over the D3Q19 velocities (h indexed by k of set 19).
+template <class CT>
+__device__ __forceinline__ Moments<CT> moments_of19(const CT h[19]) {
+  Moments<CT> m{};
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const int cx = cxq<19>(k), cy = cyq<19>(k), cz = czq<19>(k);
+    m.drho += h[k];
+    if (cx) m.jx += CT(cx) * h[k];
+    if (cy) m.jy += CT(cy) * h[k];
+    if (cz) m.jz += CT(cz) * h[k];
+    if (cx) m.pxx += h[k];
+    if (cy) m.pyy += h[k];
+    if (cz) m.pzz += h[k];
+    if (cx * cy) m.pxy += CT(cx * cy) * h[k];
+    if (cx * cz) m.pxz += CT(cx * cz) * h[k];
+    if (cy * cz) m.pyz += CT(cy * cz) * h[k];
+  }
+  return m;
+}
+template <int Q, class CT>
+__device__ __forceinline__ Moments<CT> moments_q(const CT* h) {
+  if constexpr (Q == 27) return moments_of<CT>(h);
+  else return moments_of19<CT>(h);
+}
+
 // ---------------------------------------------------------------- reconstruction
 template <class CT>
 struct Coef {
@@ -210,34 +272,71 @@ __device__ __forceinline__ void finish_coef(Coef<CT>& k, CT drho, CT rho, CT ux,
   k.X = CT(6) * b3xyz;
 }
 
-// Normalized equilibrium deviation at rho = 1 (inflow ghost).
+// D3Q19 reconstruction.  The 19 velocities do not hold H_xyz, and their
+// third-order terms are the projection onto H_aab + H_ccb (norm 2 cs^6) and
+// H_aab - H_ccb (norm 6 cs^6), b the odd index: with the same B3 = 9/2 (rho
+// u u u + w' sigma a3) as the 27-velocity form this gives, per velocity,
+//   face s e_b:            -2 s sum_{a != b} B3_aab
+//   edge s_a e_a + s_b e_b: 2 s_b B3_aab + 2 s_a B3_bba
+// so g*_i = E0 + sum_a c_a^2 B2_aa + 2 sum_{a<b} c_a c_b B2_ab + 3 rho c.u
+// plus those terms.
 template <class CT>
-__device__ __forceinline__ void equilibrium_dev_unit(CT ux, CT uy, CT uz, CT g[27]) {
-  const CT c = CT(4.5);
-  Coef<CT> k;
-  finish_coef(k, CT(0), CT(1), ux, uy, uz, c * ux * ux, c * uy * uy, c * uz * uz, c * ux * uy, c * ux * uz,
-              c * uy * uz, c * ux * ux * uy, c * ux * ux * uz, c * uy * uy * ux, c * uy * uy * uz,
-              c * uz * uz * ux, c * uz * uz * uy, c * ux * uy * uz);
-  reconstruct(k, g);
+__device__ __forceinline__ void reconstruct19(CT drho, CT rho, CT ux, CT uy, CT uz, CT b2xx, CT b2yy, CT b2zz,
+                                              CT b2xy, CT b2xz, CT b2yz, CT b3xxy, CT b3xxz, CT b3yyx, CT b3yyz,
+                                              CT b3zzx, CT b3zzy, CT g[19]) {
+  const CT E0 = drho - (b2xx + b2yy + b2zz) * CT(1.0 / 3.0);
+  const CT r3 = CT(3) * rho;
+  const CT Ux = r3 * ux, Uy = r3 * uy, Uz = r3 * uz;
+  const CT ex = E0 + b2xx, ey = E0 + b2yy, ez = E0 + b2zz;
+  g[kq<19>(0, 0, 0)] = E0;
+  {
+    const CT vx = Ux - CT(2) * (b3yyx + b3zzx), vy = Uy - CT(2) * (b3xxy + b3zzy), vz = Uz - CT(2) * (b3xxz + b3yyz);
+    g[kq<19>(1, 0, 0)] = ex + vx; g[kq<19>(-1, 0, 0)] = ex - vx;
+    g[kq<19>(0, 1, 0)] = ey + vy; g[kq<19>(0, -1, 0)] = ey - vy;
+    g[kq<19>(0, 0, 1)] = ez + vz; g[kq<19>(0, 0, -1)] = ez - vz;
+  }
+  // edge (a, b): even E0 + B_aa + B_bb +- 2 B_ab, odd W_ab = U_a + 2 B3_bba
+  auto edge = [&](CT eab, CT Dab, CT Wa, CT Wb, int ia_pp, int ia_mm, int ia_pm, int ia_mp) {
+    const CT ep = eab + Dab, em = eab - Dab, op = Wa + Wb, om = Wa - Wb;
+    g[ia_pp] = ep + op; g[ia_mm] = ep - op;
+    g[ia_pm] = em + om; g[ia_mp] = em - om;
+  };
+  edge(ex + b2yy, CT(2) * b2xy, Ux + CT(2) * b3yyx, Uy + CT(2) * b3xxy, kq<19>(1, 1, 0), kq<19>(-1, -1, 0),
+       kq<19>(1, -1, 0), kq<19>(-1, 1, 0));
+  edge(ex + b2zz, CT(2) * b2xz, Ux + CT(2) * b3zzx, Uz + CT(2) * b3xxz, kq<19>(1, 0, 1), kq<19>(-1, 0, -1),
+       kq<19>(1, 0, -1), kq<19>(-1, 0, 1));
+  edge(ey + b2zz, CT(2) * b2yz, Uy + CT(2) * b3zzy, Uz + CT(2) * b3yyz, kq<19>(0, 1, 1), kq<19>(0, -1, -1),
+       kq<19>(0, 1, -1), kq<19>(0, -1, 1));
 }
 
-// Normalized equilibrium deviation at (rho, u).
-template <class CT>
-__device__ __forceinline__ void equilibrium_dev(CT rho, CT ux, CT uy, CT uz, CT g[27]) {
+// Normalized equilibrium deviation at (rho, u) on set Q (unit: rho = 1, the
+// inflow ghost).
+template <class CT, int Q = 27>
+__device__ __forceinline__ void equilibrium_dev(CT rho, CT ux, CT uy, CT uz, CT g[Q]) {
   const CT c = CT(4.5) * rho;
-  Coef<CT> k;
-  finish_coef(k, rho - CT(1), rho, ux, uy, uz, c * ux * ux, c * uy * uy, c * uz * uz, c * ux * uy, c * ux * uz,
-              c * uy * uz, c * ux * ux * uy, c * ux * ux * uz, c * uy * uy * ux, c * uy * uy * uz,
-              c * uz * uz * ux, c * uz * uz * uy, c * ux * uy * uz);
-  reconstruct(k, g);
+  if constexpr (Q == 27) {
+    Coef<CT> k;
+    finish_coef(k, rho - CT(1), rho, ux, uy, uz, c * ux * ux, c * uy * uy, c * uz * uz, c * ux * uy, c * ux * uz,
+                c * uy * uz, c * ux * ux * uy, c * ux * ux * uz, c * uy * uy * ux, c * uy * uy * uz,
+                c * uz * uz * ux, c * uz * uz * uy, c * ux * uy * uz);
+    reconstruct(k, g);
+  } else {
+    reconstruct19(rho - CT(1), rho, ux, uy, uz, c * ux * ux, c * uy * uy, c * uz * uz, c * ux * uy, c * ux * uz,
+                  c * uy * uz, c * ux * ux * uy, c * ux * ux * uz, c * uy * uy * ux, c * uy * uy * uz,
+                  c * uz * uz * ux, c * uz * uz * uy, g);
+  }
+}
+template <class CT, int Q = 27>
+__device__ __forceinline__ void equilibrium_dev_unit(CT ux, CT uy, CT uz, CT g[Q]) {
+  equilibrium_dev<CT, Q>(CT(1), ux, uy, uz, g);
 }
 
 // Collision of one cell (Sec. 2.2, eq. hlbm).  Inputs: deviation moments m,
 // homogenized velocity (ux, uy, uz), sigma and the wall strain S (used when
 // sigma < 1), model constants.  Output: normalized post-collision deviations.
-template <class CT, bool kWall>
+template <class CT, bool kWall, int NQ = 27>
 __device__ __forceinline__ void collide(const Moments<CT>& m, CT rho, CT ux, CT uy, CT uz, CT sigma,
-                                        const CT S[6], CT tau0, CT smag, CT g[27]) {
+                                        const CT S[6], CT tau0, CT smag, CT g[NQ]) {
   const CT third = CT(1.0 / 3.0);
   const CT ru_x = rho * ux, ru_y = rho * uy, ru_z = rho * uz;
   const CT dd = m.drho * third;
@@ -281,11 +380,16 @@ __device__ __forceinline__ void collide(const Moments<CT>& m, CT rho, CT ux, CT 
   const CT b3yyz = c45 * ru_y * uy * uz + t * (CT(2) * uy * Pyz + uz * Pyy);
   const CT b3zzx = c45 * ru_z * uz * ux + t * (CT(2) * uz * Pxz + ux * Pzz);
   const CT b3zzy = c45 * ru_z * uz * uy + t * (CT(2) * uz * Pyz + uy * Pzz);
-  const CT b3xyz = c45 * ru_x * uy * uz + t * (ux * Pyz + uy * Pxz + uz * Pxy);
-  Coef<CT> k;
-  finish_coef(k, m.drho, rho, ux, uy, uz, b2xx, b2yy, b2zz, b2xy, b2xz, b2yz, b3xxy, b3xxz, b3yyx, b3yyz, b3zzx,
-              b3zzy, b3xyz);
-  reconstruct(k, g);
+  if constexpr (NQ == 27) {
+    const CT b3xyz = c45 * ru_x * uy * uz + t * (ux * Pyz + uy * Pxz + uz * Pxy);
+    Coef<CT> k;
+    finish_coef(k, m.drho, rho, ux, uy, uz, b2xx, b2yy, b2zz, b2xy, b2xz, b2yz, b3xxy, b3xxz, b3yyx, b3yyz, b3zzx,
+                b3zzy, b3xyz);
+    reconstruct(k, g);
+  } else {
+    reconstruct19(m.drho, rho, ux, uy, uz, b2xx, b2yy, b2zz, b2xy, b2xz, b2yz, b3xxy, b3xxz, b3yyx, b3yyz, b3zzx,
+                  b3zzy, g);
+  }
 }
 
 // ---------------------------------------------------------------- inflow noise

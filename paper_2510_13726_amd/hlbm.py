@@ -32,7 +32,7 @@ class HlbmError(RuntimeError):
 
 class Desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("storage", C.c_int32),
-                ("compute", C.c_int32), ("bc_x", C.c_int32), ("flags", C.c_int32), ("pad0", C.c_int32),
+                ("compute", C.c_int32), ("bc_x", C.c_int32), ("flags", C.c_int32), ("velocities", C.c_int32),
                 ("bbox_cells", C.c_int64), ("history", C.c_int64), ("stream", C.c_void_p)]
 
 
@@ -138,36 +138,40 @@ def _rotor_array(rotors):
 
 
 def make_desc(nx, ny, nz, storage=F32, compute=None, bc_x=BC_PERIODIC, flags=0, bbox_cells=0, history=1024,
-              stream=None) -> Desc:
+              stream=None, q=27) -> Desc:
     d = Desc()
     d.nx, d.ny, d.nz = nx, ny, nz
     d.storage = storage
     d.compute = compute if compute is not None else (F64 if storage == F64 else F32)
     d.bc_x, d.flags = bc_x, flags
+    d.velocities = int(q)
     d.bbox_cells, d.history = int(bbox_cells), int(history)
     d.stream = stream
     return d
 
 
 class Lattice:
-    """A D3Q27 HLBM lattice on the current GPU.  Device memory (two population
-    buffers and the workspace) is held in torch uint8 tensors."""
+    """A D3Q27 (q = 27) or D3Q19 (q = 19) HLBM lattice on the current GPU.
+    Device memory (two population buffers and the workspace) is held in
+    torch uint8 tensors."""
 
     def __init__(self, nx, ny, nz, storage="f32", bc_x=BC_PERIODIC, rotors: Sequence = (), flags=0,
-                 history=1024, device=None):
+                 history=1024, device=None, q=27):
         import torch
         self.torch = torch
         self.L = lib()
         self.device = torch.device(device or "cuda")
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
+        self.q = int(q)
         st = DTYPES[storage] if isinstance(storage, str) else storage
         self.storage = st
         self.compute = F64 if st == F64 else F32
         self.ct = torch.float64 if self.compute == F64 else torch.float32
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream()
-        d = make_desc(nx, ny, nz, st, self.compute, bc_x, flags, 0, history, C.c_void_p(self.stream.cuda_stream))
+        d = make_desc(nx, ny, nz, st, self.compute, bc_x, flags, 0, history, C.c_void_p(self.stream.cuda_stream),
+                      q=self.q)
         if rotors:
             arr = _rotor_array(rotors)
             bb = self.L.hlbm_rotor_bbox_cells(C.byref(d), arr, len(rotors))
@@ -266,18 +270,18 @@ class Lattice:
         return (rho, u, uh) if uhat else (rho, u)
 
     def get_populations(self):
-        out = self.torch.empty(27, self.N, dtype=self.torch.float64, device=self.device)
+        out = self.torch.empty(self.q, self.N, dtype=self.torch.float64, device=self.device)
         self._check(self.L.hlbm_get_populations(self.h, C.c_void_p(out.data_ptr())))
         return out
 
     def set_populations(self, h):
-        t, p = self._dev(h, dtype=self.torch.float64, shape=(27, self.N))
+        t, p = self._dev(h, dtype=self.torch.float64, shape=(self.q, self.N))
         self._check(self.L.hlbm_set_populations(self.h, p))
         self.stream.synchronize()
 
     def get_populations_at(self, cells):
         ct, cp = self._dev(cells, dtype=self.torch.int64)
-        out = self.torch.empty(ct.numel(), 27, dtype=self.torch.float64, device=self.device)
+        out = self.torch.empty(ct.numel(), self.q, dtype=self.torch.float64, device=self.device)
         self._check(self.L.hlbm_get_populations_at(self.h, cp, ct.numel(), C.c_void_p(out.data_ptr())))
         return out
 
@@ -370,7 +374,7 @@ def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=Non
     """Lattice loaded with a workload's inputs at step 0 (same recipe as the oracle)."""
     from . import workloads as W
     lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device,
-                  history=history)
+                  history=history, q=getattr(w, "q", 27))
     lat.set_params(w.params, diag_every=diag_every, check_nonfinite=check_nonfinite)
     lat.set_rotors(w.rotors)
     d, tag = W.static_porosity(w)
@@ -390,7 +394,7 @@ def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=Non
     noise = W.population_noise(w)
     if noise is not None:
         h = lat.get_populations()
-        lat.set_populations(h + lat.torch.as_tensor(noise, device=lat.device))
+        lat.set_populations(h + lat.torch.as_tensor(noise[:lat.q], device=lat.device))
     return lat
 
 

@@ -1,0 +1,116 @@
+"""D3Q19 instantiation of the fused step (the paper's stencil, Sec. 2.2,
+Fig. 2) against the oracle's D3Q19 lattice on the same seeded inputs:
+FP64 1e-12 and FP32 2e-5 on populations, velocities, forces and torques
+(tests/parity_metrics.py), wall-model Newton counts equal in FP64."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_13726_amd import workloads as W
+from parity_metrics import force_torque_error, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def _hl():
+    from paper_2510_13726_amd import hlbm
+    return hlbm
+
+
+def run_both(w, storage, steps, check_every=None):
+    hl = _hl()
+    print(f"[d3q19] {w.name} q={w.q} storage={storage} steps={steps}", flush=True)
+    lat = hl.setup(w, storage=storage, check_nonfinite=1)
+    o = O.setup(w)
+    assert lat.q == o.q == 19
+    errs = []
+    for k in ([check_every] * (steps // check_every) if check_every else [steps]):
+        lat.step(k)
+        o.step(k)
+        errs.append(rel(lat.get_populations().cpu().numpy(), o.get_populations()))
+    return lat, o, errs
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_d3q19_tgv_sphere(storage):
+    w = W.config1(noise=True)
+    w.q = 19
+    lat, o, errs = run_both(w, storage, 100, check_every=25)
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    rho_g, u_g, uh_g = (t.cpu().numpy().astype(np.float64) for t in lat.moments(uhat=True))
+    rho_o, u_o, uh_o = o.moments(uhat=True)
+    print(f"[d3q19] tgv sphere {storage}: h {max(errs):.3e} F {eF:.3e} T {eT:.3e} u {rel(u_g, u_o):.3e} "
+          f"uhat {rel(uh_g, uh_o):.3e}", flush=True)
+    assert max(errs) < TOL[storage]
+    assert eF < TOL[storage] and eT < TOL[storage]
+    assert rel(u_g, u_o) < TOL[storage] and rel(uh_g, uh_o) < TOL[storage]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_d3q19_rotor_wall_model(storage):
+    """Rotor channel with inflow turbulence, outflow and the wall model."""
+    w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    w.q = 19
+    lat, o, errs = run_both(w, storage, 24, check_every=8)
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    it_g, n_g = lat.wall_stats()
+    it_o, n_o = o.newton_stats()
+    print(f"[d3q19] rotor {storage}: h {max(errs):.3e} F {eF:.3e} T {eT:.3e} newton {it_g}/{it_o} wall cells "
+          f"{n_g}/{n_o}", flush=True)
+    assert max(errs) < TOL[storage]
+    assert eF < TOL[storage] and eT < TOL[storage]
+    assert n_g == n_o and n_g > 100
+    if storage == "f64":
+        assert it_g == it_o
+    assert lat.wall_safeguards() == (0, 0)
+
+
+@pytest.mark.parametrize("dims,bc", [((2, 1, 1), W.BC_PERIODIC), ((65, 3, 2), W.BC_PERIODIC),
+                                     ((130, 1, 3), W.BC_INFLOW_OUTFLOW)])
+def test_d3q19_degenerate_lattices(dims, bc):
+    nx, ny, nz = dims
+    p = W.Params(tau0=0.6, cs_smag=0.12, eps_h=2.0, wall_model=0, u_in=(0.03, 0.01, 0.0), turb_I=0.05, seed=11)
+    w = W.Workload(f"degenerate_{nx}x{ny}x{nz}", nx, ny, nz, bc, p, [], 12, init="uniform", u0=0.02,
+                   noise_seed=3, noise_amp=1e-3, q=19)
+    lat, o, errs = run_both(w, "f64", 12, check_every=4)
+    assert max(errs) < TOL["f64"], errs
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_d3q19_reduced_storage(storage):
+    """FP16 / BF16 storage of the D3Q19 deviations: error stated against the
+    FP64 oracle and held to the linear-growth bound 4 n u |h|max."""
+    w = W.small_rotor(nx=64, ny=40, nz=40, R=10.0, chord=3.0, hub=2.0, tau0=0.51, turb=0.05)
+    w.q = 19
+    n = 10
+    lat, o, errs = run_both(w, storage, n)
+    u = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}[storage]
+    ho = o.get_populations()
+    print(f"[d3q19] rotor {storage}: h {errs[-1]:.3e}", flush=True)
+    assert errs[-1] * np.abs(ho).max() < 4 * n * u * np.abs(ho).max()
+
+
+def test_d3q19_full_channel_fp32():
+    """The 256x128x128 rotor channel on D3Q19, FP32, 6 steps."""
+    import os
+    w = W.config2()
+    w.q = 19
+    hl = _hl()
+    lat = hl.setup(w, storage="f32", diag_every=0)
+    lat.step(6)
+    hg = lat.get_populations().cpu().numpy()
+    lat.close()
+    o = O.setup(w, threads=min(16, os.cpu_count() or 1))
+    o.step(6)
+    e = rel(hg, o.get_populations())
+    print(f"[d3q19] {w.name} f32: h {e:.3e}", flush=True)
+    assert e < TOL["f32"]
+
+
+def test_d3q19_refuses_the_adjoint():
+    hl = _hl()
+    with pytest.raises(hl.HlbmError) as e:
+        hl.Lattice(16, 8, 8, storage="f64", flags=hl.WITH_ADJOINT, q=19)
+    assert e.value.code == hl.HLBM_ERR_INVALID
