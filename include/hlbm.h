@@ -135,6 +135,20 @@ int hlbm_lattice_create(const hlbm_desc* desc, void* pop_a, void* pop_b, void* w
 /* Destroy a handle; never frees caller memory.  NULL is a no-op. */
 void hlbm_lattice_destroy(hlbm_handle h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as hlbm_lattice_create, but the workspace is the library's own static
+ * device array of HLBM_STATIC_WORKSPACE_BYTES (32 MiB) on the current
+ * device, which each device holds until the process ends.  No call on the
+ * returned handle allocates device or pinned host memory.  The caller still
+ * passes both population buffers.  HLBM_ERR_INVALID when
+ * hlbm_workspace_bytes(desc) exceeds the array; HLBM_ERR_STATE while
+ * another lattice on the device uses it (one at a time per device:
+ * hlbm_lattice_destroy frees it for the next one).  The array keeps the
+ * previous lattice's contents; creation clears it. */
+#define HLBM_STATIC_WORKSPACE_BYTES (32 << 20)
+int hlbm_lattice_create_static(const hlbm_desc* desc, void* pop_a, void* pop_b, hlbm_handle* out);
+
 /* Parameters (validated: tau0 > 1/2, cs_smag >= 0, eps_h > 0, maxit >= 1).
  * With rotors set, a change of eps_h, y_s or the wall-model switch can move
  * the rotors' fixed boxes: cells leaving them return to the static field,

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -250,9 +251,24 @@ struct hlbm_lattice {
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[4];
   std::vector<hipEvent_t> pool;
+  int static_dev = -1;         // device whose static workspace this lattice uses, -1: caller's workspace
 };
 
 namespace {
+
+// Devices whose static workspace is in use by a lattice (one at a time).
+std::mutex g_static_lock;
+bool g_static_busy[64] = {};
+bool static_claim(int dev) {
+  std::lock_guard<std::mutex> g(g_static_lock);
+  if (dev < 0 || dev >= 64 || g_static_busy[dev]) return false;
+  g_static_busy[dev] = true;
+  return true;
+}
+void static_release(int dev) {
+  std::lock_guard<std::mutex> g(g_static_lock);
+  if (dev >= 0 && dev < 64) g_static_busy[dev] = false;
+}
 
 int fail(hlbm_handle h, int code, const std::string& msg) {
   if (h) h->err = msg; else g_create_error = msg;
@@ -615,8 +631,41 @@ void hlbm_lattice_destroy(hlbm_handle h) {
     for (auto& p : v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto e : h->pool) (void)hipEventDestroy(e);
   if (h->trig_ev) (void)hipEventDestroy(h->trig_ev);
-  if (h->trig_host) (void)hipHostFree(h->trig_host);
+  if (h->trig_host) {
+    if (h->static_dev >= 0) delete[] h->trig_host;
+    else (void)hipHostFree(h->trig_host);
+  }
+  if (h->static_dev >= 0) static_release(h->static_dev);
   delete h;
+}
+
+int hlbm_lattice_create_static(const hlbm_desc* d, void* pop_a, void* pop_b, hlbm_handle* out) {
+  std::string why;
+  if (!out) return fail(nullptr, HLBM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!desc_ok(d, &why)) return fail(nullptr, HLBM_ERR_INVALID, why);
+  const int64_t need = layout(d).total;
+  if (need > kStaticWorkspaceBytes)
+    return fail(nullptr, HLBM_ERR_INVALID,
+                "lattice needs " + std::to_string(need) + " bytes of workspace; the static workspace holds " +
+                    std::to_string(kStaticWorkspaceBytes) + " (use hlbm_lattice_create with a workspace buffer)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "create static");
+  if (!static_claim(dev)) return fail(nullptr, HLBM_ERR_STATE, "another lattice uses the static workspace of this device");
+  void* ws = nullptr;
+  e = static_workspace(&ws);
+  if (e != hipSuccess) {
+    static_release(dev);
+    return hip_fail(nullptr, e, "static workspace address");
+  }
+  const int rc = hlbm_lattice_create(d, pop_a, pop_b, ws, out);
+  if (rc != HLBM_OK) {
+    static_release(dev);
+    return rc;
+  }
+  (*out)->static_dev = dev;
+  return HLBM_OK;
 }
 
 int hlbm_set_params(hlbm_handle h, const hlbm_params* p) {
@@ -770,7 +819,10 @@ hipError_t trig_of(hlbm_handle h, int64_t n, const BladeTrig** out) {
   if (h->trig_base < 0 || n < h->trig_base || n >= h->trig_base + kTrigSteps) {
     hipError_t e = hipSuccess;
     if (!h->trig_host) {
-      e = hipHostMalloc(reinterpret_cast<void**>(&h->trig_host), sizeof(BladeTrig) * kTrigSteps, 0);
+      // a lattice on the static workspace stages from ordinary host memory
+      // (it makes no HIP allocation)
+      if (h->static_dev >= 0) h->trig_host = new BladeTrig[kTrigSteps];
+      else e = hipHostMalloc(reinterpret_cast<void**>(&h->trig_host), sizeof(BladeTrig) * kTrigSteps, 0);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&h->trig_ev, hipEventDisableTiming);
     } else {
       e = hipEventSynchronize(h->trig_ev);  // the previous copy has read the buffer

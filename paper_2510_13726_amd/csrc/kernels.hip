@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1565,6 +1566,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
     if (x == 0)
       for (int i = 0; i < 9; ++i) a.lam_out[pop_at(g, i, x, y, z)] = CT(0);
   }
+}
+
+// ================================================================ static workspace
+// Device memory of the lattices created by hlbm_lattice_create_static.  In
+// host code the array's name is not a device address: kernels and copies get
+// the address that hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+hipError_t static_workspace(void** ptr) {
+  constexpr int kDevices = 64;
+  static void* addr[kDevices] = {};
+  static std::mutex lock;
+  *ptr = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 // ================================================================ launchers

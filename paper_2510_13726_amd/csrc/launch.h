@@ -115,4 +115,11 @@ hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A);
 hipError_t launch_refill_porosity(const Launch& L);
 hipError_t launch_fill_rest(const Launch& L, void* dst);
 
+// Workspace for lattices created without a caller buffer: a file-scope
+// device array of kStaticWorkspaceBytes on every GPU the library runs on,
+// held until the process ends.  static_workspace returns its device address
+// on the current device (looked up once per device).
+constexpr int64_t kStaticWorkspaceBytes = int64_t(32) << 20;
+hipError_t static_workspace(void** ptr);
+
 }  // namespace hlbm

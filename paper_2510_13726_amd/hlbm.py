@@ -62,6 +62,7 @@ SIGNATURES = [
     ("hlbm_workspace_bytes", C.c_int64, [C.POINTER(Desc)]),
     ("hlbm_rotor_bbox_cells", C.c_int64, [C.POINTER(Desc), C.POINTER(Rotor), C.c_int32]),
     ("hlbm_lattice_create", C.c_int, [C.POINTER(Desc), _V, _V, _V, C.POINTER(_H)]),
+    ("hlbm_lattice_create_static", C.c_int, [C.POINTER(Desc), _V, _V, C.POINTER(_H)]),
     ("hlbm_lattice_destroy", None, [_H]),
     ("hlbm_set_params", C.c_int, [_H, C.POINTER(Params)]),
     ("hlbm_set_rotors", C.c_int, [_H, C.POINTER(Rotor), C.c_int32]),
@@ -156,7 +157,7 @@ class Lattice:
     torch uint8 tensors."""
 
     def __init__(self, nx, ny, nz, storage="f32", bc_x=BC_PERIODIC, rotors: Sequence = (), flags=0,
-                 history=1024, device=None, q=27):
+                 history=1024, device=None, q=27, static_workspace=False):
         import torch
         self.torch = torch
         self.L = lib()
@@ -185,11 +186,18 @@ class Lattice:
             raise HlbmError(HLBM_ERR_INVALID, "invalid lattice description")
         self.pop_a = torch.empty(pb, dtype=torch.uint8, device=self.device)
         self.pop_b = torch.empty(pb, dtype=torch.uint8, device=self.device)
-        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
-        rc = self.L.hlbm_lattice_create(C.byref(d), C.c_void_p(self.pop_a.data_ptr()),
-                                        C.c_void_p(self.pop_b.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
-                                        C.byref(h))
+        if static_workspace:
+            # the library's static device array is the workspace
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                rc = self.L.hlbm_lattice_create_static(C.byref(d), C.c_void_p(self.pop_a.data_ptr()),
+                                                       C.c_void_p(self.pop_b.data_ptr()), C.byref(h))
+        else:
+            self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
+            rc = self.L.hlbm_lattice_create(C.byref(d), C.c_void_p(self.pop_a.data_ptr()),
+                                            C.c_void_p(self.pop_b.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
+                                            C.byref(h))
         if rc:
             raise HlbmError(rc, self.L.hlbm_last_error(None).decode())
         self.h = h
@@ -370,11 +378,12 @@ def sweep_partition(lat):
     return f.value, b.value
 
 
-def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None, history=1024) -> "Lattice":
+def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None, history=1024,
+          static_workspace=False) -> "Lattice":
     """Lattice loaded with a workload's inputs at step 0 (same recipe as the oracle)."""
     from . import workloads as W
     lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device,
-                  history=history, q=getattr(w, "q", 27))
+                  history=history, q=getattr(w, "q", 27), static_workspace=static_workspace)
     lat.set_params(w.params, diag_every=diag_every, check_nonfinite=check_nonfinite)
     lat.set_rotors(w.rotors)
     d, tag = W.static_porosity(w)
