@@ -64,6 +64,7 @@ enum hlbm_transition { HLBM_TRANSITION_TANH = 0, HLBM_TRANSITION_LINEAR = 1 };
 #define HLBM_WITH_SOLID_VELOCITY 1   /* reserve a static solid-velocity field */
 #define HLBM_WITH_CONTROL 2          /* reserve a porosity control field (adjoint) */
 #define HLBM_WITH_ADJOINT 4          /* reserve the discrete-adjoint work arrays */
+#define HLBM_WITH_MOMENTUM_EXCHANGE 8 /* reserve the momentum-exchange force arrays */
 
 typedef struct hlbm_lattice* hlbm_handle;
 
@@ -94,7 +95,9 @@ typedef struct {
  * seed; diag_every: every k-th step also reduces the total mass and checks
  * for non-finite densities (0 = never); check_nonfinite: every step checks
  * for non-finite densities (whatever diag_every is), and hlbm_step
- * synchronizes at its end and reports HLBM_ERR_NONFINITE. */
+ * synchronizes at its end and reports HLBM_ERR_NONFINITE; force_mode bit 0:
+ * every step also records the momentum-exchange force of every element
+ * (hlbm_history_me; needs HLBM_WITH_MOMENTUM_EXCHANGE). */
 typedef struct {
   double tau0, cs_smag, eps_h;
   int32_t transition, wall_model;
@@ -103,7 +106,7 @@ typedef struct {
   double u_in[3];
   double turb_I;
   uint64_t seed;
-  int32_t check_nonfinite, pad0;
+  int32_t check_nonfinite, force_mode;
 } hlbm_params;
 
 /* Rotor of n_blades flat-plate blades (chord x thick, from r_hub to R,
@@ -264,6 +267,30 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
  * (every diag_every-th step): Newton iterations for u_tau and wall cells
  * solved (host, syncs). */
 int hlbm_wall_stats(hlbm_handle h, int64_t* newton_iters, int64_t* wall_cells);
+
+/* Momentum-exchange force on each element (Sec. 2.2.2: the paper's
+ * momentum-exchange sum after Wen et al., read per link and in its
+ * Galilean-invariant form): over the links joining a cell x of tag 0 to a
+ * neighbour x_b = x + c_i of tag T, F_T = sum (c_i - u_s) f*_i(x) +
+ * (c_i + u_s) f*_ibar(x_b), post-collision populations of the step, u_s the
+ * solid velocity at x_b; no links across the x faces of an inflow/outflow
+ * lattice; a tag-0 cell next to several elements gives its links to the
+ * first of them in velocity order.  It differs from hlbm_force_torque's
+ * force (the momentum the collision hands to the solid) by the change of
+ * the momentum inside the element, zero in a steady flow.  Records of steps
+ * [from, to) in the history ring, 45 doubles each (tags 1..15 x F[3]), FP64
+ * host (syncs); recorded while force_mode bit 0 is set, zero otherwise.
+ * HLBM_ERR_STATE without HLBM_WITH_MOMENTUM_EXCHANGE. */
+int hlbm_history_me(hlbm_handle h, int64_t from, int64_t to, double* dst);
+
+/* Thrust coefficient (Def. Thrust Coefficient, Sec. 4) of element tag per
+ * step of [from, to): C_T = T / (0.5 rho pi r^2 U^2) with T the axial force
+ * e . F on the element (e the tag frame's axis), F the force of
+ * hlbm_force_torque (source 0) or the momentum-exchange force (source 1);
+ * rho, u_inf, radius the reference density, free-stream speed and rotor
+ * radius (all > 0).  dst: to - from doubles, host (syncs). */
+int hlbm_thrust_coefficient(hlbm_handle h, int32_t tag, int64_t from, int64_t to, int32_t source, double rho,
+                            double u_inf, double radius, double* dst);
 
 /* Safeguards of the wall model's Newton iterations (Sec. 2.2.1) taken since
  * creation on diagnostics steps: iterates that went non-positive and were

@@ -167,7 +167,13 @@ int oracle_history(void* h, int64_t from, int64_t to, double* dst) {
   return 0;
 }
 int64_t oracle_history_len(void* h) { return (int64_t)((SimD*)h)->hist.size() / HIST; }
-void oracle_clear_history(void* h) { ((SimD*)h)->hist.clear(); ((SimD*)h)->hist_scale.clear(); }
+void oracle_clear_history(void* h) {
+  SimD* s = (SimD*)h;
+  s->hist.clear();
+  s->hist_scale.clear();
+  s->hist_me.clear();
+  s->hist_me_scale.clear();
+}
 // Per recorded step [from, to) and tag 1..15: sum of |dP| and of |r x dP|
 // over the tag's cells (30 doubles per step).
 int oracle_history_scale(void* h, int64_t from, int64_t to, double* dst) {
@@ -175,6 +181,27 @@ int oracle_history_scale(void* h, int64_t from, int64_t to, double* dst) {
   int64_t n = (int64_t)s->hist_scale.size() / 30;
   if (from < 0 || to > n || from > to) return 1;
   std::memcpy(dst, s->hist_scale.data() + from * 30, sizeof(double) * 30 * (to - from));
+  return 0;
+}
+// Momentum-exchange forces of the recorded steps [from, to) of a run with the
+// estimator switched on (oracle_set_force_mode), 45 doubles per step: tags
+// 1..15 x F_ME[3].
+void oracle_set_force_mode(void* h, int mode) { ((SimD*)h)->with_me = (mode & 1) != 0; }
+int64_t oracle_history_me_len(void* h) { return (int64_t)((SimD*)h)->hist_me.size() / 45; }
+// Per recorded step and tag: the sum of the magnitudes of the link terms of
+// the momentum-exchange force (15 doubles per step).
+int oracle_history_me_scale(void* h, int64_t from, int64_t to, double* dst) {
+  SimD* s = (SimD*)h;
+  int64_t n = (int64_t)s->hist_me_scale.size() / 15;
+  if (from < 0 || to > n || from > to) return 1;
+  std::memcpy(dst, s->hist_me_scale.data() + from * 15, sizeof(double) * 15 * (to - from));
+  return 0;
+}
+int oracle_history_me(void* h, int64_t from, int64_t to, double* dst) {
+  SimD* s = (SimD*)h;
+  int64_t n = (int64_t)s->hist_me.size() / 45;
+  if (from < 0 || to > n || from > to) return 1;
+  std::memcpy(dst, s->hist_me.data() + from * 45, sizeof(double) * 45 * (to - from));
   return 0;
 }
 // Newton halvings, exponential caps and near-threshold slips since creation.

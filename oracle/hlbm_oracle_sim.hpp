@@ -67,6 +67,10 @@ struct Sim {
   // per recorded step and tag 1..15: sum over the tag's cells of |dP| and of
   // |(x - x_c) x dP| (the scales of the force and torque sums)
   std::vector<double> hist_scale;
+  // per recorded step and tag 1..15: the momentum-exchange force (3 doubles)
+  // and the sum of the magnitudes of its link terms (its scale)
+  std::vector<double> hist_me, hist_me_scale;
+  bool with_me = false;
   WallStats wstats;
   int nthreads = 1;
 
@@ -300,7 +304,66 @@ struct Sim {
     rec[0] = re(mass);
     hist.insert(hist.end(), rec.begin(), rec.end());
     hist_scale.insert(hist_scale.end(), scl.begin(), scl.end());
+    if (with_me) momentum_exchange();
     if (obj_on && step >= obj_t0 && step < obj_t1) J = J + Tax / double(obj_t1 - obj_t0);
+  }
+
+  // Momentum-exchange force on each tagged element (Sec. 2.2.2, the
+  // momentum-exchange sum after Wen et al. 2014, read per link): the links
+  // join a cell x of tag 0 to a neighbour x_b = x + c_i of tag T != 0; the
+  // link carries f*_i(x) into the element and f*_ibar(x_b) out of it, and
+  // hands the element (c_i - u_s) f*_i(x) + (c_i + u_s) f*_ibar(x_b), u_s
+  // the solid velocity of x_b (Galilean-invariant form).  Post-collision
+  // populations of this step, tags of this step; x faces of an
+  // inflow/outflow lattice have no links beyond them.  A tag-0 cell next to
+  // several elements gives its links to the element of its first such
+  // neighbour in velocity order.
+  void momentum_exchange() {
+    const Lattice& L = *lat_;
+    std::vector<double> me(15 * 3, 0.0), mes(15, 0.0);
+    auto neighbour = [&](int x, int y, int z, int i, int64_t& cn) {
+      int xn = x + L.c[i][0];
+      const int yn = wrap(y + L.c[i][1], ny), zn = wrap(z + L.c[i][2], nz);
+      if (bc_x == 0) xn = wrap(xn, nx);
+      else if (xn < 0 || xn > nx - 1) return false;
+      cn = idx(xn, yn, zn);
+      return true;
+    };
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t c = idx(x, y, z);
+          const int t = g_tag[c];
+          int tme = t;
+          double acc[3] = {0.0, 0.0, 0.0}, mag = 0.0;
+          for (int i = 0; i < q; ++i) {
+            if (L.c[i][0] == 0 && L.c[i][1] == 0 && L.c[i][2] == 0) continue;
+            int64_t cn;
+            if (!neighbour(x, y, z, i, cn)) continue;
+            const int tn = g_tag[cn];
+            const double fs = re(h[(size_t)i * N + c]) + L.w[i];
+            double term[3];
+            if (t != 0 && tn == 0) {
+              // outflow of x across a link of its element: (u_s(x) - c_i) f*_i(x)
+              for (int a = 0; a < 3; ++a) term[a] = (g_uB[3 * c + a] - L.c[i][a]) * fs;
+            } else if (t == 0 && tn != 0) {
+              if (tme == 0) tme = tn;
+              if (tn != tme) continue;
+              // inflow into the element: (c_i - u_s(x_b)) f*_i(x)
+              for (int a = 0; a < 3; ++a) term[a] = (L.c[i][a] - g_uB[3 * cn + a]) * fs;
+            } else {
+              continue;
+            }
+            for (int a = 0; a < 3; ++a) acc[a] += term[a];
+            mag += std::sqrt(term[0] * term[0] + term[1] * term[1] + term[2] * term[2]);
+          }
+          if (tme != 0) {
+            for (int a = 0; a < 3; ++a) me[3 * (tme - 1) + a] += acc[a];
+            mes[tme - 1] += mag;
+          }
+        }
+    hist_me.insert(hist_me.end(), me.begin(), me.end());
+    hist_me_scale.insert(hist_me_scale.end(), mes.begin(), mes.end());
   }
 
   void do_step() {
@@ -328,6 +391,8 @@ struct Sim {
     step = 0;
     hist.clear();
     hist_scale.clear();
+    hist_me.clear();
+    hist_me_scale.clear();
   }
 };
 

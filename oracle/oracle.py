@@ -78,6 +78,13 @@ def lib():
         L.oracle_history_scale.restype = C.c_int
         L.oracle_history_scale.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _D]
         L.oracle_wall_safeguards.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.oracle_set_force_mode.argtypes = [C.c_void_p, C.c_int]
+        L.oracle_history_me_len.restype = C.c_int64
+        L.oracle_history_me_len.argtypes = [C.c_void_p]
+        L.oracle_history_me_scale.restype = C.c_int
+        L.oracle_history_me_scale.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _D]
+        L.oracle_history_me.restype = C.c_int
+        L.oracle_history_me.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _D]
         L.oracle_trilinear.restype = C.c_double
         L.oracle_trilinear.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_int, _D]
         L.oracle_lattice.argtypes = [C.POINTER(C.c_int32), _D]
@@ -242,6 +249,28 @@ class OracleLattice:
             self.L.oracle_history_scale(self.h, 0, n, _p(out))
         return out
 
+    def set_force_mode(self, mode):
+        """mode & 1: also record the momentum-exchange force of every element."""
+        self.L.oracle_set_force_mode(self.h, int(mode))
+
+    def history_me(self):
+        """Per recorded step (since the estimator was on), (15, 3): the
+        momentum-exchange force of tags 1..15."""
+        n = self.L.oracle_history_me_len(self.h)
+        out = np.empty((n, 45))
+        if n:
+            self.L.oracle_history_me(self.h, 0, n, _p(out))
+        return out.reshape(n, 15, 3)
+
+    def history_me_scale(self):
+        """Per recorded step, (15,): sum of |link term| of each tag's
+        momentum-exchange force (the scale of that sum)."""
+        n = self.L.oracle_history_me_len(self.h)
+        out = np.empty((n, 15))
+        if n:
+            self.L.oracle_history_me_scale(self.h, 0, n, _p(out))
+        return out
+
     def wall_safeguards(self):
         """(Newton halvings, exponential caps, wall cells with slip in [0.5e-6, 2e-6])."""
         out = np.zeros(3, dtype=np.int64)
@@ -289,6 +318,7 @@ def setup(w, threads=None) -> OracleLattice:
     from paper_2510_13726_amd import workloads as W
     o = OracleLattice(w.nx, w.ny, w.nz, w.bc_x, threads=threads, q=getattr(w, "q", 27))
     o.set_params(w.params)
+    o.set_force_mode(getattr(w.params, "force_mode", 0))
     o.set_rotors(w.rotors)
     d, tag = W.static_porosity(w)
     if d is not None:

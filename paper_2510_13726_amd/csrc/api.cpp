@@ -68,7 +68,8 @@ int64_t partial_slots(int64_t nblocks) {
 struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
       wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b,
-      trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, total;
+      trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, fsi_tiles, me_partial, me_l1,
+      hist_me, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -128,6 +129,11 @@ Layout layout(const hlbm_desc* d) {
   L.scr_ut = take(adj ? B * 8 : 0);
   L.scr_act = take(adj ? B : 0);
   L.scr_actb = take(adj ? B : 0);
+  const bool me = (d->flags & HLBM_WITH_MOMENTUM_EXCHANGE) != 0;
+  L.fsi_tiles = take(me ? nb * 4 : 0);
+  L.me_partial = take(me ? partial_slots(nb) * kMePartial * 8 : 0);
+  L.me_l1 = take(me ? int64_t(kMaxBatch) * kPartL1 * kMePartial * 8 : 0);
+  L.hist_me = take(me ? H * kHistMe * 8 : 0);
   L.total = o;
   return L;
 }
@@ -221,6 +227,7 @@ struct hlbm_lattice {
   hlbm_params params{};
   bool have_params = false;
   int32_t nslots = 0;
+  int32_t nme = 0;             // tiles of the momentum-exchange launch
   int64_t step = 0;
   int64_t hist_start = 0;      // first step recorded since init
   int64_t hist_cap = 0;
@@ -401,12 +408,43 @@ int rebuild_slots(hlbm_handle h) {
   // slot >= 0: FSI path (porosity, tags, wall-model outputs, force partial);
   // -2: plain path within the wall model's probe reach, where the adjoint
   // gathers the probe-velocity adjoints; -1: plain path.
+  // momentum-exchange tiles: the FSI tiles and their neighbours (a cell next
+  // to an element's cell lies in the same tile or an adjacent one)
+  std::vector<int32_t> tiles;
+  if (h->L.fsi_tiles) {
+    const Geometry& g = h->L.g;
+    const int ntx = g.ntx, nty = g.nty, nz = g.nz;
+    std::vector<uint8_t> near(flags.size(), 0);
+    for (size_t b = 0; b < flags.size(); ++b) {
+      if (!(flags[b] & 1)) continue;
+      const int tz = int(b / (size_t(ntx) * nty)), r = int(b % (size_t(ntx) * nty));
+      const int ty = r / ntx, tx = r % ntx;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            int X = tx + dx;
+            if (g.bc_x == 0) X = (X + ntx) % ntx;
+            else if (X < 0 || X >= ntx) continue;
+            const int Y = (ty + dy + nty) % nty, Z = (tz + dz + nz) % nz;
+            near[(size_t(Z) * nty + Y) * ntx + X] = 1;
+          }
+    }
+    for (size_t b = 0; b < near.size(); ++b)
+      if (near[b]) tiles.push_back(int32_t(b));
+  }
   int32_t n = 0;
   for (auto& f : flags) f = (f & 1) ? n++ : (f & 2) ? -2 : -1;
   h->nslots = n;
+  h->nme = int32_t(tiles.size());
+  if (h->L.fsi_tiles && h->nme > 0) {
+    e = hipMemcpyAsync(const_cast<int32_t*>(h->L.fsi_tiles), tiles.data(), sizeof(int32_t) * tiles.size(),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "write momentum-exchange tile list");
+  }
   // as many steps of slices as the partial buffer holds, at most kMaxBatch
-  h->batch = int32_t(
-      std::max<int64_t>(1, std::min<int64_t>(kMaxBatch, partial_slots(h->L.nblocks) / std::max<int32_t>(n, 1))));
+  h->batch = int32_t(std::max<int64_t>(
+      1, std::min<int64_t>(kMaxBatch, partial_slots(h->L.nblocks) / std::max<int32_t>(std::max(n, h->nme), 1))));
   e = hipMemcpyAsync(h->L.blk_slot, flags.data(), sizeof(int32_t) * flags.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "write block slots");
@@ -484,6 +522,7 @@ bool params_ok(const hlbm_params* p, std::string* why) {
     return false;
   }
   if (!(p->turb_I >= 0) || p->diag_every < 0) { *why = "turb_I and diag_every must be >= 0"; return false; }
+  if (p->force_mode < 0 || p->force_mode > 1) { *why = "force_mode must be 0 or 1"; return false; }
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->u_in[a])) { *why = "u_in not finite"; return false; }
   return true;
@@ -581,6 +620,11 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.wall_out = base + Y.wall;
   L.hist = reinterpret_cast<double*>(base + Y.hist);
   L.hist_cap = h->hist_cap;
+  const bool with_me = (d->flags & HLBM_WITH_MOMENTUM_EXCHANGE) != 0;
+  L.fsi_tiles = with_me ? reinterpret_cast<int32_t*>(base + Y.fsi_tiles) : nullptr;
+  L.me_partial = with_me ? reinterpret_cast<double*>(base + Y.me_partial) : nullptr;
+  L.me_l1 = with_me ? reinterpret_cast<double*>(base + Y.me_l1) : nullptr;
+  L.hist_me = with_me ? reinterpret_cast<double*>(base + Y.hist_me) : nullptr;
   h->ghost[0] = base + Y.ghost;
   h->ghost[1] = base + Y.ghostb;
   h->ghost64[0] = reinterpret_cast<double*>(base + Y.ghost64);
@@ -672,6 +716,8 @@ int hlbm_set_params(hlbm_handle h, const hlbm_params* p) {
   if (!h) return HLBM_ERR_INVALID;
   std::string why;
   if (!params_ok(p, &why)) return fail(h, HLBM_ERR_INVALID, why);
+  if ((p->force_mode & 1) && !(h->desc.flags & HLBM_WITH_MOMENTUM_EXCHANGE))
+    return fail(h, HLBM_ERR_STATE, "force_mode 1 needs a lattice created with HLBM_WITH_MOMENTUM_EXCHANGE");
   const hlbm_params old = h->params;
   h->params = *p;
   if (!h->rotors.empty()) {
@@ -871,7 +917,8 @@ hipError_t flush(hlbm_handle h) {
   const int32_t cnt = h->pending;
   h->pending = 0;
   return timed(h, HLBM_KERNEL_OTHER, [&] {
-    return launch_finalize(h->L, h->pend_n0, cnt, h->nslots, h->params.diag_every);
+    return launch_finalize(h->L, h->pend_n0, cnt, h->nslots, h->params.diag_every,
+                           (h->params.force_mode & 1) ? h->nme : -1);
   });
 }
 
@@ -943,6 +990,10 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
   Ls.mass_part = h->L.mass_part + int64_t(j) * h->L.nblocks;
   const bool check = diag || h->params.check_nonfinite;
   if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(Ls, src, dst, n, diag, check); });
+  if (e == hipSuccess && (h->params.force_mode & 1)) {
+    double* mp = h->L.me_partial + int64_t(j) * std::max<int32_t>(h->nme, 1) * kMePartial;
+    e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_momentum_exchange(h->L, dst, h->nme, mp); });
+  }
   if (e == hipSuccess) ++h->pending;
   return e;
 }
@@ -1298,6 +1349,41 @@ int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst) {
   }
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "history");
+  return HLBM_OK;
+}
+
+int hlbm_history_me(hlbm_handle h, int64_t from, int64_t to, double* dst) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (!h->L.hist_me) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_MOMENTUM_EXCHANGE");
+  const int64_t lo = std::max(h->hist_start, h->step - h->hist_cap);
+  if (from < lo || to > h->step || from > to || (to > from && !dst))
+    return fail(h, HLBM_ERR_INVALID, "steps not in the history ring");
+  hipError_t e = flush(h);
+  for (int64_t s = from; e == hipSuccess && s < to; ++s)
+    e = hipMemcpyAsync(dst + (s - from) * kHistMe, h->L.hist_me + (s % h->hist_cap) * kHistMe, kHistMe * 8,
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "momentum-exchange history");
+  return HLBM_OK;
+}
+
+int hlbm_thrust_coefficient(hlbm_handle h, int32_t tag, int64_t from, int64_t to, int32_t source, double rho,
+                            double u_inf, double radius, double* dst) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (tag < 1 || tag > 15 || (source != 0 && source != 1) || !(rho > 0) || !(u_inf > 0) || !(radius > 0) ||
+      (to > from && !dst))
+    return fail(h, HLBM_ERR_INVALID, "need tag 1..15, source 0 or 1, rho, u_inf, radius > 0");
+  const int64_t n = std::max<int64_t>(0, to - from);
+  const int stride = source == 0 ? kHist : kHistMe;
+  std::vector<double> rec(std::max<int64_t>(n, 1) * stride);
+  const int rc = source == 0 ? hlbm_history(h, from, to, rec.data()) : hlbm_history_me(h, from, to, rec.data());
+  if (rc != HLBM_OK) return rc;
+  const double* e = &h->rot.frame[tag][3];
+  const double q = 0.5 * rho * 3.14159265358979323846 * radius * radius * u_inf * u_inf;
+  for (int64_t k = 0; k < n; ++k) {
+    const double* F = rec.data() + k * stride + (source == 0 ? 1 + 6 * (tag - 1) : 3 * (tag - 1));
+    dst[k] = (e[0] * F[0] + e[1] * F[1] + e[2] * F[2]) / q;
+  }
   return HLBM_OK;
 }
 

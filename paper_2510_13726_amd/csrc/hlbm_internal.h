@@ -18,6 +18,8 @@ constexpr int kMassL1 = 256;         // first-level mass reduction width
 constexpr int kPartL1 = 64;          // first-level force reduction width
 constexpr int kMaxBatch = 8;         // steps whose reductions are launched together
 constexpr int kWallOut = 10;         // u_wm[3], S[6], sigma per wall slot
+constexpr int kMePartial = 48;       // per FSI block: [16 tags][F_ME 3]
+constexpr int kHistMe = 45;          // 15 x F_ME
 
 // Tag byte of a cell: bits 0-3 tag, bit 6 = covered by a rotor, bit 7 = wall cell.
 constexpr uint8_t kTagMask = 0x0f;

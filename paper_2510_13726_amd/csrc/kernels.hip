@@ -1281,6 +1281,153 @@ __global__ __launch_bounds__(256) void k_reduce_l2(const double* __restrict__ l1
   }
 }
 
+// ---------------------------------------------------------------- momentum exchange
+// Solid velocity of a cell with tag byte tb: rigid rotation of its rotor,
+// else the static solid velocity (if any), else zero.
+template <class CT>
+__device__ __forceinline__ void solid_velocity(const RotorTable& rt, uint8_t tb, const CT* uB_static, int64_t N,
+                                               int64_t c, int x, int y, int z, double u[3]) {
+  if (tb & kRotorBit) {
+    const RotorDev& R = rt.r[rt.tag2rot[tb & kTagMask]];
+    const double rx = x - R.c[0], ry = y - R.c[1], rz = z - R.c[2];
+    u[0] = R.omega * (R.e[1] * rz - R.e[2] * ry);
+    u[1] = R.omega * (R.e[2] * rx - R.e[0] * rz);
+    u[2] = R.omega * (R.e[0] * ry - R.e[1] * rx);
+  } else if (uB_static) {
+    u[0] = double(uB_static[c]);
+    u[1] = double(uB_static[N + c]);
+    u[2] = double(uB_static[2 * N + c]);
+  } else {
+    u[0] = u[1] = u[2] = 0.0;
+  }
+}
+
+template <class CT>
+struct MeArgs {
+  const void* state;         // post-collision populations of the step
+  Geometry g;
+  const uint8_t* tag;        // tags of the step
+  const RotorTable* rot;
+  const CT* uB_static;       // nullable
+  const int32_t* fsi_tiles;  // lattice-order tile of each slot
+  double* partial;           // [slot][kMePartial]
+};
+
+// Momentum-exchange force of the step (Sec. 2.2.2, per link between a tag-0
+// cell and a cell of an element, Galilean-invariant form), one workgroup per
+// tile of the list (FSI tiles and their neighbours): each cell adds the terms of its own post-collision populations
+// on its links -- an element's cell (c_i of the link pointing out of the
+// element) (u_s - c_i) f*_i, a tag-0 cell (c_i pointing into the element)
+// (c_i - u_s(x + c_i)) f*_i -- and the tile reduces them per tag in FP64.
+template <class ST, class CT, bool kPeriodicX, int Q>
+__global__ __launch_bounds__(kBlock) void k_momentum_exchange(MeArgs<CT> a) {
+  __shared__ double lds[4][kMePartial];
+  const Geometry& g = a.g;
+  const int32_t slot = blockIdx.x;
+  const uint32_t canon = uint32_t(a.fsi_tiles[slot]);
+  const uint32_t ntx = uint32_t(g.ntx), tpz = ntx * uint32_t(g.nty);
+  const int z = int(canon / tpz);
+  const uint32_t rem = canon - uint32_t(z) * tpz;
+  const int ty = int(rem / ntx), tx = int(rem - uint32_t(ty) * ntx);
+  const int x = tx * kTileX + int(threadIdx.x & (kTileX - 1));
+  const int y = ty * kTileY + int(threadIdx.x >> 6);
+  const bool valid = x < g.nx && y < g.ny;
+  const RotorTable& rt = *a.rot;
+  const ST* __restrict__ st = static_cast<const ST*>(a.state);
+  double acc[3] = {0.0, 0.0, 0.0};
+  int tme = 0;
+  if (valid) {
+    const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+    const uint8_t tb = a.tag[c];
+    const int t = tb & kTagMask;
+    tme = t;
+    double us[3] = {0.0, 0.0, 0.0};
+    if (t != 0) solid_velocity<CT>(rt, tb, a.uB_static, g.N, c, x, y, z, us);
+    static_for<Q>([&](auto I) {
+      constexpr int i = I;
+      constexpr int cx = cxq<Q>(i), cy = cyq<Q>(i), cz = czq<Q>(i);
+      if constexpr (cx != 0 || cy != 0 || cz != 0) {
+        int xn = x + cx;
+        const int yn = wrapi(y + cy, g.ny), zn = wrapi(z + cz, g.nz);
+        bool in = true;
+        if (kPeriodicX) xn = wrapi(xn, g.nx);
+        else in = xn >= 0 && xn < g.nx;
+        if (in) {
+          const int64_t cn = (int64_t(zn) * g.ny + yn) * g.nx + xn;
+          const uint8_t tbn = a.tag[cn];
+          const int tn = tbn & kTagMask;
+          if ((t != 0 && tn == 0) || (t == 0 && tn != 0 && (tme == 0 || tn == tme))) {
+            const double f = wq<Q>(i) * (1.0 + Store<ST>::template load<double>(st + pop_at<Q>(g, i, x, y, z)));
+            if (t != 0) {
+              acc[0] += (us[0] - cx) * f;
+              acc[1] += (us[1] - cy) * f;
+              acc[2] += (us[2] - cz) * f;
+            } else {
+              tme = tn;
+              double un[3];
+              solid_velocity<CT>(rt, tbn, a.uB_static, g.N, cn, xn, yn, zn, un);
+              acc[0] += (cx - un[0]) * f;
+              acc[1] += (cy - un[1]) * f;
+              acc[2] += (cz - un[2]) * f;
+            }
+          }
+        }
+      }
+    });
+  }
+  // per-tag sums over the tile in a fixed order: waves by ballot, then LDS
+  for (int q = threadIdx.x; q < 4 * kMePartial; q += kBlock) (&lds[0][0])[q] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t pending = __ballot(tme != 0);
+  while (pending) {
+    const int l0 = __ffsll((long long)pending) - 1;
+    const int cur = __shfl(tme, l0, 64);
+    const bool mine = tme == cur;
+    double s3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s3[k] = wave_sum(mine ? acc[k] : 0.0);
+    if (lane == 0)
+      for (int k = 0; k < 3; ++k) lds[wv][cur * 3 + k] = s3[k];
+    pending &= ~__ballot(mine);
+  }
+  __syncthreads();
+  if (threadIdx.x < kMePartial) {
+    const int q = threadIdx.x;
+    a.partial[int64_t(slot) * kMePartial + q] = (lds[0][q] + lds[1][q]) + (lds[2][q] + lds[3][q]);
+  }
+}
+
+// Momentum-exchange reduction, level 1: workgroup (b, j) sums the partials
+// b, b + G, ... of step slice j (five rows of slots, then the rows in order).
+__global__ __launch_bounds__(256) void k_reduce_me_l1(const double* __restrict__ partial, int32_t nslots,
+                                                      double* __restrict__ l1) {
+  __shared__ double s[5][kMePartial];
+  const int G = gridDim.x, b = blockIdx.x, j = blockIdx.y;
+  const double* P = partial + int64_t(j) * (nslots > 0 ? nslots : 1) * kMePartial;
+  const int k = threadIdx.x % kMePartial, r = threadIdx.x / kMePartial;  // r in 0..5; row 5 idle
+  if (r < 5) {
+    double acc = 0.0;
+    for (int32_t sl = b + r * G; sl < nslots; sl += 5 * G) acc += P[int64_t(sl) * kMePartial + k];
+    s[r][k] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMePartial)
+    l1[(int64_t(j) * G + b) * kMePartial + threadIdx.x] =
+        (((s[0][threadIdx.x] + s[1][threadIdx.x]) + s[2][threadIdx.x]) + s[3][threadIdx.x]) + s[4][threadIdx.x];
+}
+
+// Level 2: workgroup j adds the G level-1 results of slice j in order into
+// the momentum-exchange record of step n0 + j (tags 1..15).
+__global__ __launch_bounds__(64) void k_reduce_me_l2(const double* __restrict__ l1, int G, int64_t n0,
+                                                     double* __restrict__ hist_me, int64_t hist_cap) {
+  const int j = blockIdx.x, k = threadIdx.x;
+  if (k < 3 || k >= kMePartial) return;
+  double acc = 0.0;
+  for (int q = 0; q < G; ++q) acc += l1[(int64_t(j) * G + q) * kMePartial + k];
+  hist_me[((n0 + j) % hist_cap) * kHistMe + (k - 3)] = acc;
+}
+
 // ---------------------------------------------------------------- state I/O
 template <class ST, class CT, int Q>
 __global__ __launch_bounds__(256) void k_init_eq(ST* __restrict__ dst, Geometry g, const CT* __restrict__ rho,
@@ -1768,8 +1915,19 @@ hipError_t launch_prologue(const Launch& L, int64_t step) {
   });
 }
 
-hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t nslots, int32_t diag_every) {
+hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t nslots, int32_t diag_every,
+                           int32_t me_slots) {
   const int G = kPartL1;
+  if (me_slots >= 0 && L.me_partial) {
+    hipLaunchKernelGGL(k_reduce_me_l1, dim3(G, unsigned(count)), dim3(256), 0, L.stream, L.me_partial, me_slots,
+                       L.me_l1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_me_l2, dim3(unsigned(count)), dim3(64), 0, L.stream, L.me_l1, G, n0, L.hist_me,
+                       L.hist_cap);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_reduce_l1, dim3(G, unsigned(count)), dim3(256), 0, L.stream, L.partial, nslots, L.mass_part,
                      L.nblocks, n0, diag_every, L.part_l1, L.mass_l1);
   hipError_t e = hipGetLastError();
@@ -1777,6 +1935,27 @@ hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t n
   hipLaunchKernelGGL(k_reduce_l2, dim3(unsigned(count)), dim3(256), 0, L.stream, L.part_l1, L.mass_l1, G, n0,
                      diag_every, L.hist, L.hist_cap);
   return hipGetLastError();
+}
+
+hipError_t launch_momentum_exchange(const Launch& L, const void* state, int32_t nslots, double* me_partial) {
+  if (nslots <= 0 || !L.fsi_tiles) return hipSuccess;
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    MeArgs<CT> a{};
+    a.state = state; a.g = L.g; a.tag = L.tag; a.rot = L.rot; a.uB_static = (const CT*)L.uB_static;
+    a.fsi_tiles = L.fsi_tiles; a.partial = me_partial;
+    return by_q(L.q, [&](auto QC) {
+      constexpr int Q = QC.value;
+      if (L.g.bc_x == 0)
+        hipLaunchKernelGGL((k_momentum_exchange<ST, CT, true, Q>), dim3(unsigned(nslots)), dim3(kBlock), 0, L.stream,
+                           a);
+      else
+        hipLaunchKernelGGL((k_momentum_exchange<ST, CT, false, Q>), dim3(unsigned(nslots)), dim3(kBlock), 0,
+                           L.stream, a);
+      return hipGetLastError();
+    });
+  });
 }
 
 template <class CT>

@@ -43,6 +43,13 @@ struct Launch {
   void* wall_out;            // [10][bbox_total] compute type
   double* hist;
   int64_t hist_cap;
+  // momentum-exchange force (HLBM_WITH_MOMENTUM_EXCHANGE): the tiles of its
+  // launch (lattice-order index; the FSI tiles and their neighbours), their
+  // partials by step slice, level-1 results, history ring [hist_cap][kHistMe]
+  const int32_t* fsi_tiles;
+  double* me_partial;
+  double* me_l1;
+  double* hist_me;
   void* ghost;               // inflow ghost plane [9][nz][ny], compute type
   double* ghost64;           // same in FP64 for the wall model
 };
@@ -85,7 +92,12 @@ hipError_t launch_prologue(const Launch& L, int64_t step);
 // force partials at partial + j nslots kPartial, mass partials at
 // mass_part + j nblocks); the mass of the steps that are not diagnostics
 // steps is recorded as NaN.
-hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t nslots, int32_t diag_every);
+// me_slots >= 0: also the momentum-exchange records from that many slots per step.
+hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t nslots, int32_t diag_every,
+                           int32_t me_slots);
+// Momentum-exchange partials of the step whose post-collision state is
+// `state`, into me_partial (one slot per FSI tile).
+hipError_t launch_momentum_exchange(const Launch& L, const void* state, int32_t nslots, double* me_partial);
 hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* rho, void* u, void* uhat);
 hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, const void* u);
 hipError_t launch_get_populations(const Launch& L, const void* src, double* dst);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libhlbm.so")
 HLBM_OK, HLBM_ERR_INVALID, HLBM_ERR_HIP, HLBM_ERR_NONFINITE, HLBM_ERR_STATE = range(5)
 F64, F32, F16, BF16 = 0, 1, 2, 3
 BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
-WITH_SOLID_VELOCITY, WITH_CONTROL, WITH_ADJOINT = 1, 2, 4
+WITH_SOLID_VELOCITY, WITH_CONTROL, WITH_ADJOINT, WITH_MOMENTUM_EXCHANGE = 1, 2, 4, 8
 HIST_STRIDE = 91
 DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 
@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("E", C.c_double), ("kappa", C.c_double), ("y_s", C.c_double), ("tol", C.c_double),
                 ("maxit", C.c_int32), ("diag_every", C.c_int32),
                 ("u_in", C.c_double * 3), ("turb_I", C.c_double), ("seed", C.c_uint64),
-                ("check_nonfinite", C.c_int32), ("pad0", C.c_int32)]
+                ("check_nonfinite", C.c_int32), ("force_mode", C.c_int32)]
 
 
 class Rotor(C.Structure):
@@ -83,6 +83,9 @@ SIGNATURES = [
     ("hlbm_force_torque", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("hlbm_history", C.c_int, [_H, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
     ("hlbm_wall_stats", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hlbm_history_me", C.c_int, [_H, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
+    ("hlbm_thrust_coefficient", C.c_int, [_H, C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_double,
+                                          C.c_double, C.POINTER(C.c_double)]),
     ("hlbm_wall_safeguards", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("hlbm_checkpoint_bytes", C.c_int64, [_H, C.c_int64, C.c_int32]),
     ("hlbm_adjoint_stack_bytes", C.c_int64, [_H, C.c_int32]),
@@ -120,6 +123,7 @@ def make_params(p, diag_every=1, check_nonfinite=0) -> Params:
         q.u_in[a] = p.u_in[a]
     q.turb_I, q.seed = p.turb_I, int(p.seed)
     q.diag_every, q.check_nonfinite = int(diag_every), int(check_nonfinite)
+    q.force_mode = int(getattr(p, "force_mode", 0))
     return q
 
 
@@ -349,6 +353,20 @@ class Lattice:
         self._check(self.L.hlbm_wall_stats(self.h, C.byref(it), C.byref(n)))
         return it.value, n.value
 
+    def history_me(self, start=None, stop=None):
+        """Momentum-exchange force records (steps, 15, 3) of tags 1..15."""
+        stop = self.step_count if stop is None else stop
+        start = 0 if start is None else start
+        out = np.empty((max(0, stop - start), 45))
+        self._check(self.L.hlbm_history_me(self.h, start, stop, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(-1, 15, 3)
+
+    def thrust_coefficient(self, tag, start, stop, rho, u_inf, radius, source=0):
+        out = np.empty(max(0, stop - start))
+        self._check(self.L.hlbm_thrust_coefficient(self.h, tag, start, stop, source, float(rho), float(u_inf),
+                                                   float(radius), out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
     def wall_safeguards(self):
         """(Newton halvings, exponential caps) of the wall model since creation."""
         a = C.c_int64()
@@ -382,6 +400,8 @@ def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=Non
           static_workspace=False) -> "Lattice":
     """Lattice loaded with a workload's inputs at step 0 (same recipe as the oracle)."""
     from . import workloads as W
+    if getattr(w.params, "force_mode", 0) & 1:
+        flags |= WITH_MOMENTUM_EXCHANGE
     lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device,
                   history=history, q=getattr(w, "q", 27), static_workspace=static_workspace)
     lat.set_params(w.params, diag_every=diag_every, check_nonfinite=check_nonfinite)

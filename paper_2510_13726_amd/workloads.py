@@ -41,6 +41,7 @@ class Params:
     u_in: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     turb_I: float = 0.0
     seed: int = 0
+    force_mode: int = 0         # 1: also record the momentum-exchange force
 
 
 @dataclasses.dataclass
