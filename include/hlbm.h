@@ -65,6 +65,7 @@ enum hlbm_transition { HLBM_TRANSITION_TANH = 0, HLBM_TRANSITION_LINEAR = 1 };
 #define HLBM_WITH_CONTROL 2          /* reserve a porosity control field (adjoint) */
 #define HLBM_WITH_ADJOINT 4          /* reserve the discrete-adjoint work arrays */
 #define HLBM_WITH_MOMENTUM_EXCHANGE 8 /* reserve the momentum-exchange force arrays */
+#define HLBM_WITH_FD_STRAIN 16        /* reserve the finite-difference strain arrays */
 
 typedef struct hlbm_lattice* hlbm_handle;
 
@@ -97,7 +98,13 @@ typedef struct {
  * for non-finite densities (whatever diag_every is), and hlbm_step
  * synchronizes at its end and reports HLBM_ERR_NONFINITE; force_mode bit 0:
  * every step also records the momentum-exchange force of every element
- * (hlbm_history_me; needs HLBM_WITH_MOMENTUM_EXCHANGE). */
+ * (hlbm_history_me; needs HLBM_WITH_MOMENTUM_EXCHANGE); fd_share: the
+ * hybrid non-equilibrium of Sec. 2.2, f~(1) = sigma f(1) - (1 - sigma)
+ * f(1,FD), in the cells of an element (tag != 0) that are not active wall
+ * cells, with sigma = 1 - fd_share and f(1,FD) from the central-difference
+ * strain of the pre-collision velocity (y, z periodic; x periodic or clamped
+ * to the first and last plane); 0 (the default) keeps sigma = 1 there;
+ * fd_share > 0 needs HLBM_WITH_FD_STRAIN and excludes the adjoint. */
 typedef struct {
   double tau0, cs_smag, eps_h;
   int32_t transition, wall_model;
@@ -107,6 +114,7 @@ typedef struct {
   double turb_I;
   uint64_t seed;
   int32_t check_nonfinite, force_mode;
+  double fd_share;
 } hlbm_params;
 
 /* Rotor of n_blades flat-plate blades (chord x thick, from r_hub to R,

@@ -19,6 +19,7 @@ struct or_params {
   double u_in[3];
   double turb_I;
   uint64_t seed;
+  double fd_share;
 };
 
 struct or_rotor {
@@ -33,6 +34,7 @@ static Params to_params(const or_params* q) {
   p.wall_model = q->wall_model; p.E = q->E; p.kappa = q->kappa; p.y_s = q->y_s; p.tol = q->tol;
   p.maxit = q->maxit; for (int a = 0; a < 3; ++a) p.u_in[a] = q->u_in[a];
   p.turb_I = q->turb_I; p.seed = q->seed;
+  p.fd_share = q->fd_share;
   return p;
 }
 
@@ -60,7 +62,7 @@ void oracle_destroy(void* h) { delete (SimD*)h; }
 void oracle_set_threads(void* h, int n) { ((SimD*)h)->nthreads = n > 0 ? n : 1; }
 
 int oracle_set_params(void* h, const or_params* q) {
-  if (!(q->tau0 > 0.5) || q->maxit < 1 || !(q->eps_h > 0)) return 1;
+  if (!(q->tau0 > 0.5) || q->maxit < 1 || !(q->eps_h > 0) || !(q->fd_share >= 0 && q->fd_share <= 1)) return 1;
   ((SimD*)h)->p = to_params(q);
   return 0;
 }

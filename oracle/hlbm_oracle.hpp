@@ -133,6 +133,7 @@ struct Params {
   double u_in[3];     // inflow velocity
   double turb_I;      // inflow turbulence intensity (std of each component / |u_in|)
   uint64_t seed;      // inflow noise seed
+  double fd_share;    // 1 - sigma in an element's cells off the wall (hybrid f~(1)); 0: sigma = 1
 };
 
 struct Rotor {

@@ -211,6 +211,7 @@ int oracle_adjoint_run(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int obj
   Sim<double>& s = *(Sim<double>*)hp;
   if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1) return 1;
   if (s.q != 27) return 1;  // the adjoint is written for the 27-velocity set
+  if (s.p.fd_share > 0.0) return 1;  // and for the local non-equilibrium off the wall
   const int64_t n0 = s.step, N = s.N;
   s.obj_on = true;
   s.obj_t0 = n0 + t0;

@@ -366,12 +366,50 @@ struct Sim {
     hist_me_scale.insert(hist_me_scale.end(), mes.begin(), mes.end());
   }
 
+  // Hybrid non-equilibrium off the wall (Sec. 2.2: f~(1) = sigma f(1) -
+  // (1 - sigma) f(1,FD), f(1,FD) from a non-local finite-difference strain):
+  // in the cells of an element (tag != 0) that are not active wall cells,
+  // sigma = 1 - fd_share and S = S^FD, the central difference of the
+  // pre-collision velocity u = j / rho, S_ab = (d_a u_b + d_b u_a) / 2,
+  // d_b u_a = (u_a(x + e_b) - u_a(x - e_b)) / 2, y and z periodic, x periodic
+  // or clamped to the first and last plane.
+  void fd_strain() {
+    const double sig = 1.0 - p.fd_share;
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t c = idx(x, y, z);
+          if (g_tag[c] == 0 || sigma[c] != 1.0) continue;
+          int64_t nb[3][2];
+          const int xm = bc_x == 0 ? wrap(x - 1, nx) : (x > 0 ? x - 1 : 0);
+          const int xp = bc_x == 0 ? wrap(x + 1, nx) : (x < nx - 1 ? x + 1 : nx - 1);
+          nb[0][0] = idx(xm, y, z);
+          nb[0][1] = idx(xp, y, z);
+          nb[1][0] = idx(x, wrap(y - 1, ny), z);
+          nb[1][1] = idx(x, wrap(y + 1, ny), z);
+          nb[2][0] = idx(x, y, wrap(z - 1, nz));
+          nb[2][1] = idx(x, y, wrap(z + 1, nz));
+          T du[3][3];  // du[a][b] = d_b u_a
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              du[a][b] = 0.5 * (u[(size_t)a * N + nb[b][1]] - u[(size_t)a * N + nb[b][0]]);
+          for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) {
+              int k;
+              sym_index(a, b, k);
+              Swm[(size_t)k * N + c] = 0.5 * (du[a][b] + du[b][a]);
+            }
+          sigma[c] = sig;
+        }
+  }
+
   void do_step() {
     geometry(step);
     pull(step);
     moments();
     if (p.wall_model) wall_model();
     else { uwm.assign((size_t)3 * N, T(0.0)); Swm.assign((size_t)6 * N, T(0.0)); sigma.assign(N, 1.0); }
+    if (p.fd_share > 0.0) fd_strain();
     collide_and_record();
     ++step;
   }

@@ -20,7 +20,8 @@ class OrParams(C.Structure):
                 ("transition", C.c_int32), ("wall_model", C.c_int32),
                 ("E", C.c_double), ("kappa", C.c_double), ("y_s", C.c_double), ("tol", C.c_double),
                 ("maxit", C.c_int32), ("pad0", C.c_int32),
-                ("u_in", C.c_double * 3), ("turb_I", C.c_double), ("seed", C.c_uint64)]
+                ("u_in", C.c_double * 3), ("turb_I", C.c_double), ("seed", C.c_uint64),
+                ("fd_share", C.c_double)]
 
 
 class OrRotor(C.Structure):
@@ -133,6 +134,7 @@ def make_params(p) -> OrParams:
     for a in range(3):
         q.u_in[a] = p.u_in[a]
     q.turb_I, q.seed = p.turb_I, int(p.seed)
+    q.fd_share = float(getattr(p, "fd_share", 0.0))
     return q
 
 

@@ -69,7 +69,7 @@ struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
       wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b,
       trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, fsi_tiles, me_partial, me_l1,
-      hist_me, total;
+      hist_me, near_index, fd_u, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -130,7 +130,10 @@ Layout layout(const hlbm_desc* d) {
   L.scr_act = take(adj ? B : 0);
   L.scr_actb = take(adj ? B : 0);
   const bool me = (d->flags & HLBM_WITH_MOMENTUM_EXCHANGE) != 0;
-  L.fsi_tiles = take(me ? nb * 4 : 0);
+  const bool fd = (d->flags & HLBM_WITH_FD_STRAIN) != 0;
+  L.fsi_tiles = take(me || fd ? nb * 4 : 0);
+  L.near_index = take(fd ? nb * 4 : 0);
+  L.fd_u = take(fd ? nb * 3 * kBlock * cs : 0);
   L.me_partial = take(me ? partial_slots(nb) * kMePartial * 8 : 0);
   L.me_l1 = take(me ? int64_t(kMaxBatch) * kPartL1 * kMePartial * 8 : 0);
   L.hist_me = take(me ? H * kHistMe * 8 : 0);
@@ -306,6 +309,7 @@ void set_model(hlbm_handle h) {
   const double mag = std::sqrt(p.u_in[0] * p.u_in[0] + p.u_in[1] * p.u_in[1] + p.u_in[2] * p.u_in[2]);
   m.turb_amp = p.turb_I * mag;
   m.seed = p.seed;
+  m.fd_share = p.fd_share;
 }
 
 // The launch state with the geometry buffer set and inflow plane of step n.
@@ -435,12 +439,21 @@ int rebuild_slots(hlbm_handle h) {
   int32_t n = 0;
   for (auto& f : flags) f = (f & 1) ? n++ : (f & 2) ? -2 : -1;
   h->nslots = n;
-  h->nme = int32_t(tiles.size());
-  if (h->L.fsi_tiles && h->nme > 0) {
+  h->nme = (h->desc.flags & HLBM_WITH_MOMENTUM_EXCHANGE) ? int32_t(tiles.size()) : 0;
+  h->L.nnear = h->L.near_index ? int32_t(tiles.size()) : 0;
+  if (h->L.fsi_tiles && !tiles.empty()) {
     e = hipMemcpyAsync(const_cast<int32_t*>(h->L.fsi_tiles), tiles.data(), sizeof(int32_t) * tiles.size(),
                        hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "write momentum-exchange tile list");
+    if (e != hipSuccess) return hip_fail(h, e, "write FSI neighbourhood tile list");
+  }
+  if (h->L.near_index) {
+    std::vector<int32_t> index(flags.size(), -1);
+    for (size_t k = 0; k < tiles.size(); ++k) index[size_t(tiles[k])] = int32_t(k);
+    e = hipMemcpyAsync(h->L.near_index, index.data(), sizeof(int32_t) * index.size(), hipMemcpyHostToDevice,
+                       h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "write tile index");
   }
   // as many steps of slices as the partial buffer holds, at most kMaxBatch
   h->batch = int32_t(std::max<int64_t>(
@@ -523,6 +536,7 @@ bool params_ok(const hlbm_params* p, std::string* why) {
   }
   if (!(p->turb_I >= 0) || p->diag_every < 0) { *why = "turb_I and diag_every must be >= 0"; return false; }
   if (p->force_mode < 0 || p->force_mode > 1) { *why = "force_mode must be 0 or 1"; return false; }
+  if (!(p->fd_share >= 0.0 && p->fd_share <= 1.0)) { *why = "fd_share must be in [0, 1]"; return false; }
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->u_in[a])) { *why = "u_in not finite"; return false; }
   return true;
@@ -621,7 +635,11 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.hist = reinterpret_cast<double*>(base + Y.hist);
   L.hist_cap = h->hist_cap;
   const bool with_me = (d->flags & HLBM_WITH_MOMENTUM_EXCHANGE) != 0;
-  L.fsi_tiles = with_me ? reinterpret_cast<int32_t*>(base + Y.fsi_tiles) : nullptr;
+  const bool with_fd = (d->flags & HLBM_WITH_FD_STRAIN) != 0;
+  L.fsi_tiles = (with_me || with_fd) ? reinterpret_cast<int32_t*>(base + Y.fsi_tiles) : nullptr;
+  L.near_index = with_fd ? reinterpret_cast<int32_t*>(base + Y.near_index) : nullptr;
+  L.fd_u = with_fd ? base + Y.fd_u : nullptr;
+  L.nnear = 0;
   L.me_partial = with_me ? reinterpret_cast<double*>(base + Y.me_partial) : nullptr;
   L.me_l1 = with_me ? reinterpret_cast<double*>(base + Y.me_l1) : nullptr;
   L.hist_me = with_me ? reinterpret_cast<double*>(base + Y.hist_me) : nullptr;
@@ -718,6 +736,8 @@ int hlbm_set_params(hlbm_handle h, const hlbm_params* p) {
   if (!params_ok(p, &why)) return fail(h, HLBM_ERR_INVALID, why);
   if ((p->force_mode & 1) && !(h->desc.flags & HLBM_WITH_MOMENTUM_EXCHANGE))
     return fail(h, HLBM_ERR_STATE, "force_mode 1 needs a lattice created with HLBM_WITH_MOMENTUM_EXCHANGE");
+  if (p->fd_share > 0.0 && !(h->desc.flags & HLBM_WITH_FD_STRAIN))
+    return fail(h, HLBM_ERR_STATE, "fd_share > 0 needs a lattice created with HLBM_WITH_FD_STRAIN");
   const hlbm_params old = h->params;
   h->params = *p;
   if (!h->rotors.empty()) {
@@ -976,6 +996,8 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
       h->ahead_epoch = ng.epoch;
     }
   }
+  if (e == hipSuccess && h->params.fd_share > 0.0)
+    e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_fd_velocity(h->L, src, n); });
   if (!record) {
     // a recomputed step: its records exist, the partials go unreduced
     if (e == hipSuccess) e = timed(h, HLBM_KERNEL_SWEEP, [&] { return launch_sweep(h->L, src, dst, n, false, false); });
@@ -1086,6 +1108,8 @@ int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, i
   if (!(h->desc.flags & HLBM_WITH_ADJOINT)) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_ADJOINT");
   if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1 || obj_tag < 0 || obj_tag > 15 || !ckpt || !J)
     return fail(h, HLBM_ERR_INVALID, "need 0 <= t0 < t1 <= nsteps, ckpt_every >= 1, 0 <= obj_tag <= 15");
+  if (h->params.fd_share > 0.0)
+    return fail(h, HLBM_ERR_STATE, "the adjoint is written for the local non-equilibrium (fd_share = 0)");
   if (ckpt_bytes < hlbm_checkpoint_bytes(h, nsteps, ckpt_every))
     return fail(h, HLBM_ERR_INVALID, "checkpoint buffer too small");
   const StateLayout sl = state_layout(h);

@@ -55,6 +55,7 @@ struct Model {
   double u_in[3];
   double turb_amp;     // turb_I * |u_in|
   uint64_t seed;
+  double fd_share;     // 1 - sigma off the wall in element cells
 };
 
 // Quotient of a 32-bit unsigned dividend by an invariant divisor d > 0 from

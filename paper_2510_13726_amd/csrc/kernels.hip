@@ -1036,7 +1036,53 @@ struct SweepArgs {
   CT* out_rho;
   CT* out_u;
   CT* out_uhat;
+  // finite-difference strain (nullable fd_u: off)
+  const CT* fd_u;
+  const int32_t* near_index;
+  CT fd_share;
 };
+
+// Pre-collision velocity component a of cell (x, y, z) from the velocity
+// buffer of the listed tiles.
+template <class CT>
+__device__ __forceinline__ CT fd_velocity(const SweepArgs<CT>& s, int a, int x, int y, int z) {
+  const Geometry& g = s.g;
+  const int64_t canon = (int64_t(z) * g.nty + y / kTileY) * g.ntx + x / kTileX;
+  const int32_t k = s.near_index[canon];
+  return s.fd_u[(int64_t(k) * 3 + a) * kBlock + (y % kTileY) * kTileX + (x % kTileX)];
+}
+
+// Central-difference strain S_ab = (d_a u_b + d_b u_a) / 2 of the
+// pre-collision velocity at (x, y, z), d_b u_a = (u_a(x + e_b) - u_a(x - e_b))
+// / 2; y, z periodic, x periodic or clamped to the first and last plane.
+// Order xx, yy, zz, xy, xz, yz.
+template <class CT, bool kPeriodicX>
+__device__ __forceinline__ void fd_strain(const SweepArgs<CT>& s, int x, int y, int z, CT S[6]) {
+  const Geometry& g = s.g;
+  int xm, xp;
+  if (kPeriodicX) {
+    xm = x == 0 ? g.nx - 1 : x - 1;
+    xp = x + 1 == g.nx ? 0 : x + 1;
+  } else {
+    xm = x == 0 ? 0 : x - 1;
+    xp = x + 1 == g.nx ? x : x + 1;
+  }
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
+  const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z + 1 == g.nz ? 0 : z + 1;
+  CT d[3][3];  // d[a][b] = d_b u_a
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d[a][0] = CT(0.5) * (fd_velocity(s, a, xp, y, z) - fd_velocity(s, a, xm, y, z));
+    d[a][1] = CT(0.5) * (fd_velocity(s, a, x, yp, z) - fd_velocity(s, a, x, ym, z));
+    d[a][2] = CT(0.5) * (fd_velocity(s, a, x, y, zp) - fd_velocity(s, a, x, y, zm));
+  }
+  S[0] = d[0][0];
+  S[1] = d[1][1];
+  S[2] = d[2][2];
+  S[3] = CT(0.5) * (d[0][1] + d[1][0]);
+  S[4] = CT(0.5) * (d[0][2] + d[2][0]);
+  S[5] = CT(0.5) * (d[1][2] + d[2][1]);
+}
 
 // One workgroup = kBlock consecutive cells.  Every cell pulls its 27
 // populations, forms the moments, collides and writes its 27 post-collision
@@ -1113,6 +1159,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
 #pragma unroll
       for (int q = 0; q < 6; ++q) S[q] = a.wall_out[(3 + q) * T + ws];
       sigma = a.wall_out[9 * T + ws];
+    }
+    // hybrid non-equilibrium off the wall: element cells that are not
+    // active wall cells take sigma = 1 - fd_share and the non-local strain
+    if (!kMoments && a.fd_u && t != 0 && sigma == CT(1) && valid) {
+      sigma = CT(1) - a.fd_share;
+      fd_strain<CT, kPeriodicX>(a, x, y, z, S);
     }
     const CT hx = ux + d * (bx - ux), hy = uy + d * (by - uy), hz = uz + d * (bz - uz);
     if (kMoments) {
@@ -1279,6 +1331,32 @@ __global__ __launch_bounds__(256) void k_reduce_l2(const double* __restrict__ l1
       rec[0] = __builtin_nan("");
     }
   }
+}
+
+// ---------------------------------------------------------------- finite-difference strain
+// Pre-collision velocity u = j / rho of the cells of each listed tile (the
+// FSI tiles and their neighbours) into fd_u, for the strain of the sweep.
+template <class ST, class CT, bool kPeriodicX, int Q>
+__global__ __launch_bounds__(kBlock) void k_fd_velocity(const ST* __restrict__ src, Geometry g,
+                                                        const CT* __restrict__ ghost,
+                                                        const int32_t* __restrict__ tiles, CT* __restrict__ fd_u) {
+  const uint32_t canon = uint32_t(tiles[blockIdx.x]);
+  const uint32_t ntx = uint32_t(g.ntx), tpz = ntx * uint32_t(g.nty);
+  const int z = int(canon / tpz);
+  const uint32_t rem = canon - uint32_t(z) * tpz;
+  const int ty = int(rem / ntx), tx = int(rem - uint32_t(ty) * ntx);
+  const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
+  const int yr = __builtin_amdgcn_readfirstlane(ty * kTileY + int(threadIdx.x >> 6));
+  const bool row_ok = yr < g.ny;
+  const int x = xr < g.nx && row_ok ? xr : 0, y = row_ok ? yr : 0;
+  CT h[Q];
+  pull_row<ST, CT, kPeriodicX, Q>(src, g, x, y, z, ghost, h);
+  const Moments<CT> mo = moments_q<Q, CT>(h);
+  const CT irho = rcp_ct(CT(1) + mo.drho);
+  CT* o = fd_u + int64_t(blockIdx.x) * 3 * kBlock + threadIdx.x;
+  o[0] = mo.jx * irho;
+  o[kBlock] = mo.jy * irho;
+  o[2 * kBlock] = mo.jz * irho;
 }
 
 // ---------------------------------------------------------------- momentum exchange
@@ -1860,6 +1938,11 @@ static SweepArgs<CT> sweep_args(const Launch& L, const void* src, void* dst, int
   a.uB_static = (const CT*)L.uB_static; a.partial = L.partial; a.mass_part = nullptr; a.flag = nullptr;
   a.step = step; a.nblocks = L.nblocks;
   a.ghost = (const CT*)L.ghost;
+  if (L.m.fd_share > 0.0 && L.fd_u) {
+    a.fd_u = (const CT*)L.fd_u;
+    a.near_index = L.near_index;
+    a.fd_share = CT(L.m.fd_share);
+  }
   return a;
 }
 
@@ -1935,6 +2018,24 @@ hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t n
   hipLaunchKernelGGL(k_reduce_l2, dim3(unsigned(count)), dim3(256), 0, L.stream, L.part_l1, L.mass_l1, G, n0,
                      diag_every, L.hist, L.hist_cap);
   return hipGetLastError();
+}
+
+hipError_t launch_fd_velocity(const Launch& L, const void* src, int64_t) {
+  if (L.nnear <= 0 || !L.fd_u) return hipSuccess;
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    return by_q(L.q, [&](auto QC) {
+      constexpr int Q = QC.value;
+      if (L.g.bc_x == 0)
+        hipLaunchKernelGGL((k_fd_velocity<ST, CT, true, Q>), dim3(unsigned(L.nnear)), dim3(kBlock), 0, L.stream,
+                           (const ST*)src, L.g, (const CT*)L.ghost, L.fsi_tiles, (CT*)L.fd_u);
+      else
+        hipLaunchKernelGGL((k_fd_velocity<ST, CT, false, Q>), dim3(unsigned(L.nnear)), dim3(kBlock), 0, L.stream,
+                           (const ST*)src, L.g, (const CT*)L.ghost, L.fsi_tiles, (CT*)L.fd_u);
+      return hipGetLastError();
+    });
+  });
 }
 
 hipError_t launch_momentum_exchange(const Launch& L, const void* state, int32_t nslots, double* me_partial) {

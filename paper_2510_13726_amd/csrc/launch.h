@@ -47,6 +47,12 @@ struct Launch {
   // launch (lattice-order index; the FSI tiles and their neighbours), their
   // partials by step slice, level-1 results, history ring [hist_cap][kHistMe]
   const int32_t* fsi_tiles;
+  // finite-difference strain (HLBM_WITH_FD_STRAIN): index of each tile in
+  // that list (-1: not in it) and the pre-collision velocity of its cells,
+  // [index][3][kBlock] in the compute type
+  int32_t* near_index;
+  void* fd_u;
+  int32_t nnear;
   double* me_partial;
   double* me_l1;
   double* hist_me;
@@ -95,6 +101,9 @@ hipError_t launch_prologue(const Launch& L, int64_t step);
 // me_slots >= 0: also the momentum-exchange records from that many slots per step.
 hipError_t launch_finalize(const Launch& L, int64_t n0, int32_t count, int32_t nslots, int32_t diag_every,
                            int32_t me_slots);
+// Pre-collision velocity of the cells of the listed tiles (for the
+// finite-difference strain of the step's sweep).
+hipError_t launch_fd_velocity(const Launch& L, const void* src, int64_t step);
 // Momentum-exchange partials of the step whose post-collision state is
 // `state`, into me_partial (one slot per FSI tile).
 hipError_t launch_momentum_exchange(const Launch& L, const void* state, int32_t nslots, double* me_partial);

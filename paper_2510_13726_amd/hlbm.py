@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libhlbm.so")
 HLBM_OK, HLBM_ERR_INVALID, HLBM_ERR_HIP, HLBM_ERR_NONFINITE, HLBM_ERR_STATE = range(5)
 F64, F32, F16, BF16 = 0, 1, 2, 3
 BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
-WITH_SOLID_VELOCITY, WITH_CONTROL, WITH_ADJOINT, WITH_MOMENTUM_EXCHANGE = 1, 2, 4, 8
+WITH_SOLID_VELOCITY, WITH_CONTROL, WITH_ADJOINT, WITH_MOMENTUM_EXCHANGE, WITH_FD_STRAIN = 1, 2, 4, 8, 16
 HIST_STRIDE = 91
 DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 
@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("E", C.c_double), ("kappa", C.c_double), ("y_s", C.c_double), ("tol", C.c_double),
                 ("maxit", C.c_int32), ("diag_every", C.c_int32),
                 ("u_in", C.c_double * 3), ("turb_I", C.c_double), ("seed", C.c_uint64),
-                ("check_nonfinite", C.c_int32), ("force_mode", C.c_int32)]
+                ("check_nonfinite", C.c_int32), ("force_mode", C.c_int32), ("fd_share", C.c_double)]
 
 
 class Rotor(C.Structure):
@@ -124,6 +124,7 @@ def make_params(p, diag_every=1, check_nonfinite=0) -> Params:
     q.turb_I, q.seed = p.turb_I, int(p.seed)
     q.diag_every, q.check_nonfinite = int(diag_every), int(check_nonfinite)
     q.force_mode = int(getattr(p, "force_mode", 0))
+    q.fd_share = float(getattr(p, "fd_share", 0.0))
     return q
 
 
@@ -402,6 +403,8 @@ def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=Non
     from . import workloads as W
     if getattr(w.params, "force_mode", 0) & 1:
         flags |= WITH_MOMENTUM_EXCHANGE
+    if getattr(w.params, "fd_share", 0.0) > 0:
+        flags |= WITH_FD_STRAIN
     lat = Lattice(w.nx, w.ny, w.nz, storage=storage, bc_x=w.bc_x, rotors=w.rotors, flags=flags, device=device,
                   history=history, q=getattr(w, "q", 27), static_workspace=static_workspace)
     lat.set_params(w.params, diag_every=diag_every, check_nonfinite=check_nonfinite)

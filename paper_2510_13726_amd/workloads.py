@@ -42,6 +42,7 @@ class Params:
     turb_I: float = 0.0
     seed: int = 0
     force_mode: int = 0         # 1: also record the momentum-exchange force
+    fd_share: float = 0.0       # 1 - sigma off the wall in element cells (hybrid f~(1))
 
 
 @dataclasses.dataclass

@@ -17,6 +17,7 @@ struct or_params {
   double u_in[3];
   double turb_I;
   uint64_t seed;
+  double fd_share;
 };
 struct or_rotor {
   double center[3], axis[3];

@@ -1,0 +1,75 @@
+"""Hybrid non-equilibrium off the wall (Sec. 2.2, f~(1) = sigma f(1) -
+(1 - sigma) f(1,FD) with the central-difference strain in element cells that
+are not active wall cells; fd_share = 1 - sigma) against the oracle on the
+same seeded inputs: FP64 1e-12, FP32 2e-5 on populations, forces and
+torques."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_13726_amd import workloads as W
+from parity_metrics import force_torque_error, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def _hl():
+    from paper_2510_13726_amd import hlbm
+    return hlbm
+
+
+def _run(w, storage, steps):
+    hl = _hl()
+    lat = hl.setup(w, storage=storage, check_nonfinite=1)
+    o = O.setup(w)
+    lat.step(steps)
+    o.step(steps)
+    e = rel(lat.get_populations().cpu().numpy(), o.get_populations())
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    return e, eF, eT, lat, o
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_fd_strain_rotor_with_wall_model(storage):
+    w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    w.params.fd_share = 0.5
+    e, eF, eT, lat, o = _run(w, storage, 16)
+    print(f"[fd] rotor {storage}: h {e:.3e} F {eF:.3e} T {eT:.3e} newton {lat.wall_stats()}/{o.newton_stats()}",
+          flush=True)
+    assert e < TOL[storage] and eF < TOL[storage] and eT < TOL[storage]
+    assert lat.wall_stats()[1] == o.newton_stats()[1]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_fd_strain_static_sphere(storage):
+    w = W.config1(noise=True)
+    w.params.fd_share = 1.0
+    e, eF, eT, _, _ = _run(w, storage, 40)
+    print(f"[fd] sphere {storage}: h {e:.3e} F {eF:.3e} T {eT:.3e}", flush=True)
+    assert e < TOL[storage] and eF < TOL[storage] and eT < TOL[storage]
+
+
+def test_fd_strain_periodic_two_rotors_d3q19():
+    w = W.small_rotor(nx=48, ny=48, nz=48, R=9.0, chord=3.0, hub=2.0, tau0=0.52, wall=0)
+    w.bc_x = W.BC_PERIODIC
+    w.q = 19
+    w.params.fd_share = 0.3
+    w.rotors[0].center = (14.2, 24.4, 24.9)
+    w.rotors.append(W.Rotor(center=(33.3, 24.1, 23.7), axis=(0.2, 1.0, 0.3), R=8.0, r_hub=1.5, chord=3.0,
+                            thick=2.0, omega=0.02, phase0=0.3, n_blades=2, tag=5))
+    w.init, w.u0 = "uniform", 0.03
+    e, eF, eT, _, _ = _run(w, "f64", 12)
+    print(f"[fd] periodic d3q19: h {e:.3e} F {eF:.3e} T {eT:.3e}", flush=True)
+    assert e < 1e-12 and eF < 1e-12 and eT < 1e-12
+
+
+def test_fd_strain_excludes_the_adjoint():
+    hl = _hl()
+    w = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52)
+    w.params.fd_share = 0.5
+    lat = hl.setup(w, storage="f64", flags=hl.WITH_ADJOINT)
+    with pytest.raises(hl.HlbmError) as e:
+        lat.forward_record(4, 1, 4, 0, 2)
+    assert e.value.code == hl.HLBM_ERR_STATE
