@@ -1069,21 +1069,34 @@ double axial_torque(hlbm_handle h, const double* rec, int32_t obj_tag) {
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+// One recorded step of the lattice state (reductions left pending).
+hipError_t step_one(hlbm_handle h) {
+  const bool wall = h->params.wall_model && h->L.nrot > 0;
+  const int a1 = (h->acur + 1) % 3, a2 = (h->acur + 2) % 3;
+  hipError_t e = forward_one(h, h->step, h->pop[h->cur], h->pop[1 - h->cur], h->ut[h->wcur], h->act[h->acur],
+                             h->ut[1 - h->wcur], h->act[a1], wall ? h->act[a2] : nullptr);
+  if (e != hipSuccess) return e;
+  h->cur = 1 - h->cur;
+  if (wall) {
+    h->wcur = 1 - h->wcur;
+    h->acur = a1;
+  }
+  ++h->step;
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
 int hlbm_step(hlbm_handle h, int64_t n) {
   if (!h) return HLBM_ERR_INVALID;
   if (n < 0) return fail(h, HLBM_ERR_INVALID, "n must be >= 0");
-  const bool wall = h->params.wall_model && h->L.nrot > 0;
   for (int64_t k = 0; k < n; ++k) {
-    const int a1 = (h->acur + 1) % 3, a2 = (h->acur + 2) % 3;
-    hipError_t e = forward_one(h, h->step, h->pop[h->cur], h->pop[1 - h->cur], h->ut[h->wcur], h->act[h->acur],
-                               h->ut[1 - h->wcur], h->act[a1], wall ? h->act[a2] : nullptr);
+    hipError_t e = step_one(h);
     if (e != hipSuccess) return hip_fail(h, e, "step");
-    h->cur = 1 - h->cur;
-    if (wall) {
-      h->wcur = 1 - h->wcur;
-      h->acur = a1;
-    }
-    ++h->step;
   }
   hipError_t ef = flush(h);
   if (ef != hipSuccess) return hip_fail(h, ef, "step");
@@ -1114,8 +1127,10 @@ int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, i
     return fail(h, HLBM_ERR_INVALID, "checkpoint buffer too small");
   const StateLayout sl = state_layout(h);
   const int64_t n0 = h->step;
+  // steps run without synchronizing (reductions batched as in hlbm_step);
+  // the window's records are read once per chunk of half the history ring
   const int64_t chunk = std::max<int64_t>(1, h->hist_cap / 2);
-  std::vector<double> rec(kHist);
+  std::vector<double> rec(size_t(std::min(chunk, nsteps)) * kHist);
   double acc = 0.0;
   int64_t done = 0;
   while (done < nsteps) {
@@ -1125,16 +1140,23 @@ int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, i
         hipError_t e = copy_state_out(h, static_cast<char*>(ckpt) + (k / ckpt_every) * sl.bytes);
         if (e != hipSuccess) return hip_fail(h, e, "checkpoint");
       }
-      int rc = hlbm_step(h, 1);
-      if (rc != HLBM_OK) return rc;
+      hipError_t e = step_one(h);
+      if (e != hipSuccess) return hip_fail(h, e, "forward record");
     }
-    // objective from the FP64 history of the chunk
-    for (int64_t k = std::max(done, t0); k < std::min(done + m, t1); ++k) {
-      int rc = hlbm_history(h, n0 + k, n0 + k + 1, rec.data());
+    hipError_t e = flush(h);
+    if (e != hipSuccess) return hip_fail(h, e, "forward record");
+    // objective from the FP64 history of the chunk, summed in step order
+    const int64_t lo = std::max(done, t0), hi = std::min(done + m, t1);
+    if (hi > lo) {
+      int rc = hlbm_history(h, n0 + lo, n0 + hi, rec.data());
       if (rc != HLBM_OK) return rc;
-      acc += axial_torque(h, rec.data(), obj_tag);
+      for (int64_t k = lo; k < hi; ++k) acc += axial_torque(h, rec.data() + (k - lo) * kHist, obj_tag);
     }
     done += m;
+  }
+  if (h->params.check_nonfinite) {
+    const int rc = check_flag(h);
+    if (rc != HLBM_OK) return rc;
   }
   h->rec.valid = true;
   h->rec.n0 = n0;
