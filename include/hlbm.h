@@ -120,11 +120,22 @@ typedef struct {
 /* Rotor of n_blades flat-plate blades (chord x thick, from r_hub to R,
  * pitch twisted linearly from twist_root to twist_tip, radians) and a hub
  * sphere of radius r_hub, turning about axis through center at omega
- * rad/step from phase0; its cells carry tag (1..15). */
+ * rad/step from phase0; its cells carry tag (1..15).
+ * inertia = 0: prescribed rotation, angle phase0 + omega n at step n.
+ * inertia > 0: two-way coupling (the structure update of the FSI time loop,
+ * Sec. 3.2, as a rigid rotation about the fixed axis): from angle phase0
+ * and speed omega at the step hlbm_set_rotors is called, each step n turns
+ * the rotor by theta_{n+1} = theta_n + Omega_n and drives it by the axial
+ * torque e . T_n the fluid handed to it (hlbm_force_torque) against the
+ * generator torque torque_gen: Omega_{n+1} = Omega_n + (e . T_n -
+ * torque_gen) / inertia, all on the device.  The explicit update is stable
+ * while inertia exceeds about half the moment of inertia of the fluid the
+ * blades displace (added mass). */
 typedef struct {
   double center[3], axis[3];
   double R, r_hub, chord, thick, twist_root, twist_tip, omega, phase0;
   int32_t n_blades, tag;
+  double inertia, torque_gen;
 } hlbm_rotor;
 
 /* Bytes of one population buffer.  Its layout is internal (the canonical
@@ -306,6 +317,15 @@ int hlbm_thrust_coefficient(hlbm_handle h, int32_t tag, int64_t from, int64_t to
  * argument exceeded 80 and took the cap (host, syncs).  Both stay zero on
  * well-posed runs. */
 int hlbm_wall_safeguards(hlbm_handle h, int64_t* halvings, int64_t* caps);
+
+/* Angle theta (rad) and angular velocity Omega (rad/step) of each rotor at
+ * the current step, in the order of hlbm_set_rotors: prescribed rotors
+ * phase0 + omega n and omega, coupled ones their state (see hlbm_rotor).
+ * theta, omega: host arrays of at least the number of rotors (syncs).
+ * Returns the number of rotors, or a negative error code.  The state of
+ * coupled rotors travels in hlbm_get_state / hlbm_set_state; hlbm_set_rotors
+ * and hlbm_init_equilibrium restart it from phase0 and omega. */
+int hlbm_rotor_state(hlbm_handle h, double* theta, double* omega);
 
 /* Opt-in kernel timing with HIP events recorded on the lattice's stream
  * around every launch of the given kernel class during hlbm_step

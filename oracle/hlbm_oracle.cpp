@@ -26,6 +26,7 @@ struct or_rotor {
   double center[3], axis[3];
   double R, r_hub, chord, thick, twist_root, twist_tip, omega, phase0;
   int32_t n_blades, tag;
+  double inertia, torque_gen;
 };
 
 static Params to_params(const or_params* q) {
@@ -44,6 +45,7 @@ static Rotor to_rotor(const or_rotor* r) {
   o.R = r->R; o.r_hub = r->r_hub; o.chord = r->chord; o.thick = r->thick;
   o.twist_root = r->twist_root; o.twist_tip = r->twist_tip; o.omega = r->omega; o.phase0 = r->phase0;
   o.n_blades = r->n_blades; o.tag = r->tag;
+  o.inertia = r->inertia; o.torque_gen = r->torque_gen;
   return o;
 }
 
@@ -109,6 +111,15 @@ int oracle_step(void* h, int64_t n) {
   return 0;
 }
 int64_t oracle_get_step(void* h) { return ((SimD*)h)->step; }
+// Angle and angular velocity of each rotor at the current step.
+int oracle_rotor_state(void* h, double* theta, double* omega) {
+  SimD* s = (SimD*)h;
+  for (size_t k = 0; k < s->rotors.size(); ++k) {
+    theta[k] = s->angle(k, s->step);
+    omega[k] = s->speed(k);
+  }
+  return int(s->rotors.size());
+}
 
 // rho, u of the pre-collision populations f(x, n) and the homogenized velocity
 // u_hat of the collision at step n (u_hat = post-collision momentum / rho);

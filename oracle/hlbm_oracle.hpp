@@ -140,6 +140,8 @@ struct Rotor {
   double center[3], axis[3];
   double R, r_hub, chord, thick, twist_root, twist_tip, omega, phase0;
   int n_blades, tag;
+  double inertia;     // moment of inertia about the axis; 0: prescribed rotation
+  double torque_gen;  // opposing (generator) torque of a coupled rotor
 };
 
 // ------------------------------------------------------------ equilibrium
@@ -405,8 +407,16 @@ inline Frame rotor_frame(const Rotor& r) {
   return F;
 }
 
-// Signed distance (positive inside) of rotor r at time step n and its gradient.
+// Signed distance (positive inside) of rotor r turned to angle theta (blade
+// b at theta + 2 pi b / n_blades) and its gradient.
+inline double rotor_phi_at(const Rotor& r, const Frame& F, const double x[3], double theta, double grad[3]);
+
+// Signed distance of rotor r at time step n of its prescribed rotation.
 inline double rotor_phi(const Rotor& r, const Frame& F, const double x[3], int64_t n, double grad[3]) {
+  return rotor_phi_at(r, F, x, r.phase0 + r.omega * double(n), grad);
+}
+
+inline double rotor_phi_at(const Rotor& r, const Frame& F, const double x[3], double theta, double grad[3]) {
   double rel[3] = {x[0] - r.center[0], x[1] - r.center[1], x[2] - r.center[2]};
   double dist = std::sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
   // hub sphere
@@ -415,7 +425,7 @@ inline double rotor_phi(const Rotor& r, const Frame& F, const double x[3], int64
   const double ax = rel[0] * F.e[0] + rel[1] * F.e[1] + rel[2] * F.e[2];
   const double two_pi = 6.283185307179586476925286766559;
   for (int b = 0; b < r.n_blades; ++b) {
-    double th = r.phase0 + r.omega * double(n) + two_pi * double(b) / double(r.n_blades);
+    double th = theta + two_pi * double(b) / double(r.n_blades);
     double ct = std::cos(th), st = std::sin(th);
     double er[3], ep[3];
     for (int a = 0; a < 3; ++a) {

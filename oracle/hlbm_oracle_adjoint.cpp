@@ -212,6 +212,8 @@ int oracle_adjoint_run(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int obj
   if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1) return 1;
   if (s.q != 27) return 1;  // the adjoint is written for the 27-velocity set
   if (s.p.fd_share > 0.0) return 1;  // and for the local non-equilibrium off the wall
+  for (const Rotor& r : s.rotors)
+    if (r.inertia > 0) return 1;     // and for prescribed rotations
   const int64_t n0 = s.step, N = s.N;
   s.obj_on = true;
   s.obj_t0 = n0 + t0;
@@ -259,6 +261,8 @@ int oracle_complex_step_J(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int 
   typedef std::complex<double> C;
   const Sim<double>& s = *(const Sim<double>*)hp;
   if (cell < 0 || cell >= s.N || t1 <= t0 || t0 < 0) return 1;
+  for (const Rotor& r : s.rotors)
+    if (r.inertia > 0) return 1;  // prescribed rotations only
   Sim<C> z(s.nx, s.ny, s.nz, s.bc_x, s.q);
   z.p = s.p;
   z.set_rotors(s.rotors.data(), (int)s.rotors.size());

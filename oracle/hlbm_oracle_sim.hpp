@@ -53,6 +53,9 @@ struct Sim {
   Params p{};
   std::vector<Rotor> rotors;
   std::vector<Frame> frames;
+  // rotation of each rotor: angle and angular velocity of the current step
+  // (prescribed: phase0 + omega n and omega; coupled: the rigid-body state)
+  std::vector<double> theta, Omega;
   std::vector<double> d_static, uB_static;
   std::vector<uint8_t> tag_static;
   std::vector<T> dd;                      // porosity control added to d
@@ -105,11 +108,45 @@ struct Sim {
 
   void set_rotors(const Rotor* r, int n) {
     rotors.assign(r, r + n);
+    reset_rotation();
     frames.clear();
     for (auto& ro : rotors) {
       frames.push_back(rotor_frame(ro));
       const Frame& F = frames.back();
       for (int a = 0; a < 3; ++a) { tag_center[ro.tag][a] = ro.center[a]; tag_axis[ro.tag][a] = F.e[a]; }
+    }
+  }
+
+  // The rotation state at the current step: prescribed angles, coupled
+  // rotors starting from their prescribed angle and speed.
+  void reset_rotation() {
+    theta.assign(rotors.size(), 0.0);
+    Omega.assign(rotors.size(), 0.0);
+    for (size_t k = 0; k < rotors.size(); ++k) {
+      theta[k] = rotors[k].phase0 + rotors[k].omega * double(step);
+      Omega[k] = rotors[k].omega;
+    }
+  }
+  double angle(size_t k, int64_t n) const {
+    return rotors[k].inertia > 0 ? theta[k] : rotors[k].phase0 + rotors[k].omega * double(n);
+  }
+  double speed(size_t k) const { return rotors[k].inertia > 0 ? Omega[k] : rotors[k].omega; }
+
+  // Two-way coupling of a rotor with inertia I (the structure update of the
+  // FSI time loop, Sec. 3.2, for a rigid rotation about the fixed axis):
+  // I dOmega/dt = e . T - T_gen with the torque T the fluid handed to the
+  // rotor in step n, explicit: Omega_{n+1} = Omega_n + (e . T_n - T_gen) / I,
+  // theta_{n+1} = theta_n + Omega_n.
+  void evolve_rotors(const double* rec) {
+    for (size_t k = 0; k < rotors.size(); ++k) {
+      const Rotor& r = rotors[k];
+      if (!(r.inertia > 0)) continue;
+      const double* Tq = rec + 4 + 6 * (r.tag - 1);
+      const double* e = frames[k].e;
+      const double Tax = e[0] * Tq[0] + e[1] * Tq[1] + e[2] * Tq[2];
+      const double Om1 = Omega[k] + (Tax - r.torque_gen) / r.inertia;
+      theta[k] = theta[k] + Omega[k];
+      Omega[k] = Om1;
     }
   }
 
@@ -129,7 +166,7 @@ struct Sim {
           int brot = -1;
           for (size_t k = 0; k < rotors.size(); ++k) {
             double gr[3];
-            double ph = rotor_phi(rotors[k], frames[k], X, n, gr);
+            double ph = rotor_phi_at(rotors[k], frames[k], X, angle(k, n), gr);
             if (ph > best) { best = ph; brot = (int)k; for (int a = 0; a < 3; ++a) bgrad[a] = gr[a]; }
           }
           double drot = brot >= 0 ? transition_s(best, eps, p.transition) : 0.0;
@@ -143,9 +180,10 @@ struct Sim {
             g_tag[c] = (uint8_t)R.tag;
             double rel[3] = {X[0] - R.center[0], X[1] - R.center[1], X[2] - R.center[2]};
             // uB = Omega e x (x - x_c)
-            g_uB[3 * c + 0] = R.omega * (F.e[1] * rel[2] - F.e[2] * rel[1]);
-            g_uB[3 * c + 1] = R.omega * (F.e[2] * rel[0] - F.e[0] * rel[2]);
-            g_uB[3 * c + 2] = R.omega * (F.e[0] * rel[1] - F.e[1] * rel[0]);
+            const double om = speed(brot);
+            g_uB[3 * c + 0] = om * (F.e[1] * rel[2] - F.e[2] * rel[1]);
+            g_uB[3 * c + 1] = om * (F.e[2] * rel[0] - F.e[0] * rel[2]);
+            g_uB[3 * c + 2] = om * (F.e[0] * rel[1] - F.e[1] * rel[0]);
             double gn = std::sqrt(bgrad[0] * bgrad[0] + bgrad[1] * bgrad[1] + bgrad[2] * bgrad[2]);
             if (gn > 0) for (int a = 0; a < 3; ++a) g_n[3 * c + a] = -bgrad[a] / gn;
             if (p.wall_model && best > -0.5 * eps && best < 0.0 && gn > 0) g_wall[c] = 1;
@@ -236,9 +274,10 @@ struct Sim {
       const double X[3] = {double(x), double(y), double(z)};
       for (int a = 0; a < 3; ++a) { xw[a] = X[a] - y1 * nn[a]; xs[a] = xw[a] + p.y_s * nn[a]; }
       double rel[3] = {xw[0] - R.center[0], xw[1] - R.center[1], xw[2] - R.center[2]};
-      double uw[3] = {R.omega * (F.e[1] * rel[2] - F.e[2] * rel[1]),
-                      R.omega * (F.e[2] * rel[0] - F.e[0] * rel[2]),
-                      R.omega * (F.e[0] * rel[1] - F.e[1] * rel[0])};
+      const double om = speed(g_rot[c]);
+      double uw[3] = {om * (F.e[1] * rel[2] - F.e[2] * rel[1]),
+                      om * (F.e[2] * rel[0] - F.e[0] * rel[2]),
+                      om * (F.e[0] * rel[1] - F.e[1] * rel[0])};
       T us[3];
       sample_u(xs, us);
       WallOut<T> o = wall_model_cell(us, uw, nn, y1, utau[c], active[c] != 0, p, nu);
@@ -303,6 +342,7 @@ struct Sim {
         }
     rec[0] = re(mass);
     hist.insert(hist.end(), rec.begin(), rec.end());
+    evolve_rotors(rec.data());
     hist_scale.insert(hist_scale.end(), scl.begin(), scl.end());
     if (with_me) momentum_exchange();
     if (obj_on && step >= obj_t0 && step < obj_t1) J = J + Tax / double(obj_t1 - obj_t0);
@@ -427,6 +467,7 @@ struct Sim {
     std::fill(utau.begin(), utau.end(), T(0.0));
     std::fill(active.begin(), active.end(), 0);
     step = 0;
+    reset_rotation();
     hist.clear();
     hist_scale.clear();
     hist_me.clear();

@@ -28,7 +28,8 @@ class OrRotor(C.Structure):
     _fields_ = [("center", C.c_double * 3), ("axis", C.c_double * 3),
                 ("R", C.c_double), ("r_hub", C.c_double), ("chord", C.c_double), ("thick", C.c_double),
                 ("twist_root", C.c_double), ("twist_tip", C.c_double), ("omega", C.c_double),
-                ("phase0", C.c_double), ("n_blades", C.c_int32), ("tag", C.c_int32)]
+                ("phase0", C.c_double), ("n_blades", C.c_int32), ("tag", C.c_int32),
+                ("inertia", C.c_double), ("torque_gen", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -60,6 +61,8 @@ def lib():
         L.oracle_set_tag_frame.argtypes = [C.c_void_p, C.c_int, _D, _D]
         L.oracle_init_equilibrium.argtypes = [C.c_void_p, _D, _D]
         L.oracle_step.argtypes = [C.c_void_p, C.c_int64]
+        L.oracle_rotor_state.restype = C.c_int
+        L.oracle_rotor_state.argtypes = [C.c_void_p, _D, _D]
         L.oracle_get_step.restype = C.c_int64
         L.oracle_get_step.argtypes = [C.c_void_p]
         L.oracle_moments.argtypes = [C.c_void_p, _D, _D, _D]
@@ -146,6 +149,8 @@ def make_rotor(r) -> OrRotor:
     o.R, o.r_hub, o.chord, o.thick = r.R, r.r_hub, r.chord, r.thick
     o.twist_root, o.twist_tip, o.omega, o.phase0 = r.twist_root, r.twist_tip, r.omega, r.phase0
     o.n_blades, o.tag = int(r.n_blades), int(r.tag)
+    o.inertia = float(getattr(r, "inertia", 0.0))
+    o.torque_gen = float(getattr(r, "torque_gen", 0.0))
     return o
 
 
@@ -207,6 +212,12 @@ class OracleLattice:
     @property
     def step_count(self):
         return self.L.oracle_get_step(self.h)
+
+    def rotor_state(self):
+        """(angle, angular velocity) of each rotor at the current step."""
+        th, om = np.zeros(8), np.zeros(8)
+        n = self.L.oracle_rotor_state(self.h, _p(th), _p(om))
+        return th[:n].copy(), om[:n].copy()
 
     def moments(self, uhat=False):
         rho = np.empty(self.N)

@@ -69,7 +69,7 @@ struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
       wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b,
       trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, fsi_tiles, me_partial, me_l1,
-      hist_me, near_index, fd_u, total;
+      hist_me, near_index, fd_u, dyn, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -117,6 +117,7 @@ Layout layout(const hlbm_desc* d) {
   L.ghostb = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * cs : 0);
   L.ghost64b = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
   L.trig = take(d->bbox_cells > 0 ? int64_t(kTrigSteps) * int64_t(sizeof(BladeTrig)) : 0);
+  L.dyn = take(d->bbox_cells > 0 ? int64_t(sizeof(RotorDyn)) : 0);
   const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
   const int64_t lam_bytes = adj ? pop_elems(d) * cs : 0;
   L.lam0 = take(lam_bytes);
@@ -262,6 +263,7 @@ struct hlbm_lattice {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[4];
   std::vector<hipEvent_t> pool;
   int static_dev = -1;         // device whose static workspace this lattice uses, -1: caller's workspace
+  bool coupled = false;        // a rotor turns with the fluid torque (inertia > 0)
 };
 
 namespace {
@@ -464,8 +466,25 @@ int rebuild_slots(hlbm_handle h) {
   return HLBM_OK;
 }
 
+// Start the coupled rotors at the current step from their phase0 and omega.
+int restart_rotation(hlbm_handle h) {
+  if (!h->L.dyn) return HLBM_OK;
+  double st[2 * kMaxRotors] = {0};
+  for (int k = 0; k < h->rot.n; ++k) {
+    st[k] = h->rot.r[k].phase0 + h->rot.r[k].omega * double(h->step);
+    st[kMaxRotors + k] = h->rot.r[k].omega;
+  }
+  hipError_t e = hipMemcpyAsync(h->L.dyn, st, sizeof(st), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "restart rotor rotation");
+  return HLBM_OK;
+}
+
+// The device rotor table with the coupled rotors' current speed and the
+// blade angles of the current step and the next.
 int upload_rotors(hlbm_handle h) {
   hipError_t e = hipMemcpyAsync(h->L.rot, &h->rot, sizeof(RotorTable), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess && h->coupled) e = launch_couple(h->L, -1, h->step);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "upload rotor table");
   return HLBM_OK;
@@ -484,6 +503,9 @@ int build_rotor_table(hlbm_handle h, const hlbm_rotor* r, int32_t n, RotorTable*
     if (q.n_blades < 0 || q.n_blades > HLBM_MAX_BLADES) return fail(h, HLBM_ERR_INVALID, "n_blades out of range");
     if (!(q.R > q.r_hub) || !(q.r_hub >= 0) || !(q.chord > 0) || !(q.thick > 0))
       return fail(h, HLBM_ERR_INVALID, "rotor needs R > r_hub >= 0, chord > 0, thick > 0");
+    if (!(q.inertia >= 0) || !std::isfinite(q.inertia) || !std::isfinite(q.torque_gen) || !std::isfinite(q.omega) ||
+        !std::isfinite(q.phase0))
+      return fail(h, HLBM_ERR_INVALID, "rotor needs a finite inertia >= 0, torque_gen, omega and phase0");
     RotorBox box;
     std::string why;
     if (!rotor_box(&h->desc, q, 0.5 * h->params.eps_h + 1.0, &box, &why)) return fail(h, HLBM_ERR_INVALID, why);
@@ -503,6 +525,7 @@ int build_rotor_table(hlbm_handle h, const hlbm_rotor* r, int32_t n, RotorTable*
     d.R = q.R; d.r_hub = q.r_hub; d.chord = q.chord; d.thick = q.thick;
     d.tw_root = q.twist_root; d.tw_tip = q.twist_tip; d.omega = q.omega; d.phase0 = q.phase0;
     d.nb = q.n_blades; d.tag = q.tag;
+    d.inertia = q.inertia; d.tgen = q.torque_gen;
     for (int a = 0; a < 3; ++a) { d.b0[a] = box.b0[a]; d.bn[a] = box.bn[a]; }
     // FSI workgroups also cover the wall model's probe corners (reach y_s + 1
     // beyond the box; periodic in y and z), where the adjoint gathers the
@@ -654,6 +677,7 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.ghost = h->ghost[0];
   L.ghost64 = h->ghost64[0];
   L.trig_tab = d->bbox_cells > 0 ? reinterpret_cast<BladeTrig*>(base + Y.trig) : nullptr;
+  L.dyn = d->bbox_cells > 0 ? reinterpret_cast<RotorDyn*>(base + Y.dyn) : nullptr;
   // defaults: Smagorinsky-free BGK-like relaxation at tau0 = 1 until set_params
   hlbm_params p{};
   p.tau0 = 1.0; p.cs_smag = 0.0; p.eps_h = 2.0; p.transition = HLBM_TRANSITION_TANH; p.wall_model = 0;
@@ -779,6 +803,9 @@ int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* r, int32_t n) {
   if (rc != HLBM_OK) return rc;
   h->rot = t;
   h->trig_base = -1;  // the blade angles change with the rotors
+  h->coupled = false;
+  for (int k = 0; k < n; ++k) h->coupled = h->coupled || r[k].inertia > 0;
+  if ((rc = restart_rotation(h)) != HLBM_OK) return rc;
   h->rotors.assign(r, r + n);
   h->L.nrot = n;
   h->L.bbox_total = total;
@@ -855,6 +882,11 @@ int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u) {
   h->step = 0;
   h->hist_start = 0;
   h->rec.valid = false;
+  if (h->coupled) {
+    int rc = restart_rotation(h);
+    if (rc == HLBM_OK) rc = upload_rotors(h);
+    if (rc != HLBM_OK) return rc;
+  }
   return HLBM_OK;
 }
 
@@ -882,6 +914,11 @@ BladeTrig blade_trig(hlbm_handle h, int64_t n) {
 hipError_t trig_of(hlbm_handle h, int64_t n, const BladeTrig** out) {
   *out = nullptr;
   if (h->rot.n == 0 || !h->L.trig_tab) return hipSuccess;
+  if (h->coupled) {
+    // written on the device for steps step and step + 1 (no adjoint with coupling)
+    *out = h->L.dyn->trig + (n & 1);
+    return hipSuccess;
+  }
   if (h->trig_base < 0 || n < h->trig_base || n >= h->trig_base + kTrigSteps) {
     hipError_t e = hipSuccess;
     if (!h->trig_host) {
@@ -1017,6 +1054,11 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
     e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_momentum_exchange(h->L, dst, h->nme, mp); });
   }
   if (e == hipSuccess) ++h->pending;
+  // a coupled rotor turns with this step's torque before the next step starts
+  if (e == hipSuccess && h->coupled) {
+    e = flush(h);
+    if (e == hipSuccess) e = timed(h, HLBM_KERNEL_OTHER, [&] { return launch_couple(h->L, n, n + 1); });
+  }
   return e;
 }
 
@@ -1123,6 +1165,7 @@ int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, i
     return fail(h, HLBM_ERR_INVALID, "need 0 <= t0 < t1 <= nsteps, ckpt_every >= 1, 0 <= obj_tag <= 15");
   if (h->params.fd_share > 0.0)
     return fail(h, HLBM_ERR_STATE, "the adjoint is written for the local non-equilibrium (fd_share = 0)");
+  if (h->coupled) return fail(h, HLBM_ERR_STATE, "the adjoint is written for prescribed rotor rotations");
   if (ckpt_bytes < hlbm_checkpoint_bytes(h, nsteps, ckpt_every))
     return fail(h, HLBM_ERR_INVALID, "checkpoint buffer too small");
   const StateLayout sl = state_layout(h);
@@ -1332,7 +1375,8 @@ int hlbm_get_populations_at(hlbm_handle h, const int64_t* cells, int64_t count, 
   return HLBM_OK;
 }
 
-// state blob: [int64 step, int64 bbox_total, pad to 256][populations][u_tau][active]
+// state blob: [int64 step, int64 bbox_total, magic, coupled, pad to 128, FP64 theta[8] omega[8]]
+// [populations][u_tau][active]
 int64_t hlbm_state_bytes(hlbm_handle h) {
   if (!h) return -1;
   const int64_t B = h->L.bbox_total;
@@ -1348,7 +1392,10 @@ int hlbm_get_state(hlbm_handle h, void* dst) {
   head[0] = h->step;
   head[1] = B;
   head[2] = 0x484c424d;  // "HLBM"
+  head[3] = h->coupled ? 1 : 0;
   hipError_t e = hipMemcpyAsync(p, head, sizeof(head), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess && h->L.dyn)
+    e = hipMemcpyAsync(p + 128, h->L.dyn, 2 * kMaxRotors * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(p + 256, h->pop[h->cur], pb, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess && B)
     e = hipMemcpyAsync(p + 256 + pb, h->ut[h->wcur], B * 8, hipMemcpyDeviceToDevice, h->stream);
@@ -1378,6 +1425,19 @@ int hlbm_set_state(hlbm_handle h, const void* src) {
   h->step = head[0];
   h->hist_start = head[0];
   h->rec.valid = false;
+  if (h->coupled) {
+    // the rotation saved with the state, or a restart from phase0 and omega
+    // for a state saved without coupled rotors
+    int rc = HLBM_OK;
+    if (head[3]) {
+      e = hipMemcpyAsync(h->L.dyn, p + 128, 2 * kMaxRotors * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "set rotor state");
+    } else {
+      rc = restart_rotation(h);
+    }
+    if (rc == HLBM_OK) rc = upload_rotors(h);
+    if (rc != HLBM_OK) return rc;
+  }
   return HLBM_OK;
 }
 
@@ -1464,6 +1524,25 @@ int hlbm_wall_safeguards(hlbm_handle h, int64_t* halvings, int64_t* caps) {
   if (halvings) *halvings = int64_t(s[2]);
   if (caps) *caps = int64_t(s[3]);
   return HLBM_OK;
+}
+
+int hlbm_rotor_state(hlbm_handle h, double* theta, double* omega) {
+  if (!h) return HLBM_ERR_INVALID;
+  const int n = h->rot.n;
+  if (n > 0 && (!theta || !omega)) return fail(h, HLBM_ERR_INVALID, "theta and omega must not be NULL");
+  double st[2 * kMaxRotors] = {0};
+  if (h->coupled) {
+    hipError_t e = hipMemcpyAsync(st, h->L.dyn, sizeof(st), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "rotor state");
+  }
+  for (int k = 0; k < n; ++k) {
+    const RotorDev& r = h->rot.r[k];
+    const bool c = r.inertia > 0;
+    theta[k] = c ? st[k] : r.phase0 + r.omega * double(h->step);
+    omega[k] = c ? st[kMaxRotors + k] : r.omega;
+  }
+  return n;
 }
 
 int hlbm_profile_enable(hlbm_handle h, int32_t enable) {

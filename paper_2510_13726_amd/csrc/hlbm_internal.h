@@ -34,6 +34,7 @@ struct RotorDev {
   int32_t mb0[3], mbn[3]; // FSI marking box (box + probe reach, may wrap in y, z)
   int64_t off;            // first slot of this box in the box pools
   int64_t cells;          // bn[0]*bn[1]*bn[2]
+  double inertia, tgen;   // coupled rotation (inertia > 0) and its generator torque
 };
 
 struct RotorTable {
@@ -118,5 +119,14 @@ struct BladeTrig {
 };
 // Steps of blade angles held on the device at once (uploaded in chunks).
 constexpr int kTrigSteps = 2048;
+
+// Rotation of two-way coupled rotors, on the device: angle and angular
+// velocity of every coupled rotor at the current step, and the blade angles
+// of all rotors for the current step and the next, by step parity.
+struct RotorDyn {
+  double theta[kMaxRotors];
+  double omega[kMaxRotors];
+  BladeTrig trig[2];
+};
 
 }  // namespace hlbm

@@ -2132,6 +2132,56 @@ hipError_t launch_get_populations_at(const Launch& L, const void* src, const int
   });
 }
 
+// Two-way rotor coupling, one lane per rotor (the structure update of the
+// FSI time loop, Sec. 3.2, for a rigid rotation about the fixed axis):
+// I (Omega_{n+1} - Omega_n) = e . T_n - T_gen and theta_{n+1} = theta_n +
+// Omega_n, T_n the torque record of step n.  Writes the speed of step m into
+// the rotor table (read by the solid velocity of the sweep, the wall model
+// and the momentum exchange) and the blade angles of steps m and m + 1 (read
+// by the geometry, which the wall launch of step m computes for m + 1).
+__global__ __launch_bounds__(64) void k_couple(RotorTable* __restrict__ rt, RotorDyn* __restrict__ dyn,
+                                               const double* __restrict__ hist, int64_t hist_cap, int64_t rec,
+                                               int64_t m) {
+  const int k = threadIdx.x;
+  if (k >= rt->n) return;
+  RotorDev& R = rt->r[k];
+  double th0, th1;
+  if (R.inertia > 0.0) {
+    double th = dyn->theta[k], om = dyn->omega[k];
+    if (rec >= 0) {
+      const double* T = hist + (rec % hist_cap) * kHist + 4 + 6 * (R.tag - 1);
+      const double Tax = R.e[0] * T[0] + R.e[1] * T[1] + R.e[2] * T[2];
+      const double om1 = om + (Tax - R.tgen) / R.inertia;
+      th = th + om;
+      om = om1;
+      dyn->theta[k] = th;
+      dyn->omega[k] = om;
+    }
+    R.omega = om;
+    th0 = th;
+    th1 = th + om;
+  } else {
+    th0 = R.phase0 + R.omega * double(m);
+    th1 = R.phase0 + R.omega * double(m + 1);
+  }
+  BladeTrig& a = dyn->trig[m & 1];
+  BladeTrig& b = dyn->trig[(m + 1) & 1];
+  for (int j = 0; j < R.nb; ++j) {
+    const double off = 6.283185307179586476925286766559 * double(j) / double(R.nb);
+    a.c[k][j] = cos(th0 + off);
+    a.s[k][j] = sin(th0 + off);
+    b.c[k][j] = cos(th1 + off);
+    b.s[k][j] = sin(th1 + off);
+  }
+}
+
+hipError_t launch_couple(const Launch& L, int64_t rec, int64_t m) {
+  if (!L.dyn || L.nrot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_couple, dim3(1), dim3(64), 0, L.stream, L.rot, L.dyn, (const double*)L.hist, L.hist_cap, rec,
+                     m);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_rest(const Launch& L, void* dst) {
   return by_types(L.storage, L.compute, [&](auto* st, auto*) {
     using ST = std::remove_pointer_t<decltype(st)>;

@@ -17,6 +17,7 @@ struct Launch {
   Model m;
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
   BladeTrig* trig_tab;       // blade angles of kTrigSteps consecutive steps
+  RotorDyn* dyn;             // coupled rotation state (nullable)
   // fields
   void* d_eff;
   void* d_static;
@@ -107,6 +108,11 @@ hipError_t launch_fd_velocity(const Launch& L, const void* src, int64_t step);
 // Momentum-exchange partials of the step whose post-collision state is
 // `state`, into me_partial (one slot per FSI tile).
 hipError_t launch_momentum_exchange(const Launch& L, const void* state, int32_t nslots, double* me_partial);
+// Rotor rotation for step m: rec >= 0 first advances every coupled rotor by
+// the axial torque of history record rec; then each coupled rotor's speed
+// goes into the rotor table and every rotor's blade angles of steps m and
+// m + 1 into the parity slots of L.dyn.
+hipError_t launch_couple(const Launch& L, int64_t rec, int64_t m);
 hipError_t launch_moments(const Launch& L, const void* src, int64_t step, void* rho, void* u, void* uhat);
 hipError_t launch_init_equilibrium(const Launch& L, void* dst, const void* rho, const void* u);
 hipError_t launch_get_populations(const Launch& L, const void* src, double* dst);

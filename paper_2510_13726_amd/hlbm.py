@@ -49,7 +49,8 @@ class Rotor(C.Structure):
     _fields_ = [("center", C.c_double * 3), ("axis", C.c_double * 3),
                 ("R", C.c_double), ("r_hub", C.c_double), ("chord", C.c_double), ("thick", C.c_double),
                 ("twist_root", C.c_double), ("twist_tip", C.c_double), ("omega", C.c_double),
-                ("phase0", C.c_double), ("n_blades", C.c_int32), ("tag", C.c_int32)]
+                ("phase0", C.c_double), ("n_blades", C.c_int32), ("tag", C.c_int32),
+                ("inertia", C.c_double), ("torque_gen", C.c_double)]
 
 
 _lib = None
@@ -87,6 +88,7 @@ SIGNATURES = [
     ("hlbm_thrust_coefficient", C.c_int, [_H, C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_double,
                                           C.c_double, C.POINTER(C.c_double)]),
     ("hlbm_wall_safeguards", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hlbm_rotor_state", C.c_int, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("hlbm_checkpoint_bytes", C.c_int64, [_H, C.c_int64, C.c_int32]),
     ("hlbm_adjoint_stack_bytes", C.c_int64, [_H, C.c_int32]),
     ("hlbm_forward_record", C.c_int, [_H, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _V, C.c_int64,
@@ -136,6 +138,8 @@ def make_rotor(r) -> Rotor:
     o.R, o.r_hub, o.chord, o.thick = r.R, r.r_hub, r.chord, r.thick
     o.twist_root, o.twist_tip, o.omega, o.phase0 = r.twist_root, r.twist_tip, r.omega, r.phase0
     o.n_blades, o.tag = int(r.n_blades), int(r.tag)
+    o.inertia = float(getattr(r, "inertia", 0.0))
+    o.torque_gen = float(getattr(r, "torque_gen", 0.0))
     return o
 
 
@@ -374,6 +378,15 @@ class Lattice:
         b = C.c_int64()
         self._check(self.L.hlbm_wall_safeguards(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def rotor_state(self):
+        """(angle, angular velocity) of each rotor at the current step."""
+        th = (C.c_double * 8)()
+        om = (C.c_double * 8)()
+        n = self.L.hlbm_rotor_state(self.h, th, om)
+        if n < 0:
+            self._check(n)
+        return np.array(th[:n]), np.array(om[:n])
 
 
 KERNEL_SWEEP, KERNEL_WALL, KERNEL_RASTERIZE, KERNEL_OTHER = range(4)

@@ -59,6 +59,8 @@ class Rotor:
     phase0: float = 0.0
     n_blades: int = 3
     tag: int = 1
+    inertia: float = 0.0        # > 0: rotation driven by the fluid torque (two-way coupling)
+    torque_gen: float = 0.0     # opposing generator torque of a coupled rotor
 
 
 @dataclasses.dataclass

@@ -23,6 +23,7 @@ struct or_rotor {
   double center[3], axis[3];
   double R, r_hub, chord, thick, twist_root, twist_tip, omega, phase0;
   int32_t n_blades, tag;
+  double inertia, torque_gen;
 };
 void* oracle_create(int nx, int ny, int nz, int bc_x);
 void oracle_destroy(void* h);

@@ -31,7 +31,7 @@ def test_struct_sizes_match_header_layout():
     # hlbm_desc: 8 int32 + 2 int64 + pointer; hlbm_params / hlbm_rotor as declared
     assert C.sizeof(hlbm.Desc) == 8 * 4 + 2 * 8 + 8
     assert C.sizeof(hlbm.Params) == 3 * 8 + 2 * 4 + 4 * 8 + 2 * 4 + 3 * 8 + 8 + 8 + 2 * 4 + 8
-    assert C.sizeof(hlbm.Rotor) == 14 * 8 + 2 * 4
+    assert C.sizeof(hlbm.Rotor) == 14 * 8 + 2 * 4 + 2 * 8
 
 
 def test_host_size_helpers():
