@@ -124,7 +124,7 @@ Layout layout(const hlbm_desc* d) {
   L.lam1 = take(lam_bytes);
   L.utb0 = take(adj ? B * 8 : 0);
   L.utb1 = take(adj ? B * 8 : 0);
-  L.ubar = take(adj ? 3 * N * 8 : 0);
+  L.ubar = take(adj ? 9 * N * 8 : 0);
   L.side = take(adj ? 9 * plane * cs : 0);
   L.sideb = take(adj ? 9 * plane * cs : 0);
   L.scr_ut = take(adj ? B * 8 : 0);
@@ -187,8 +187,12 @@ uint32_t tile_band(const hlbm_desc* d, int32_t nty) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 1) return uint32_t(std::min<long>(v, nty));
   }
+  // bands of 8 tile rows on large planes (measured on one fixed allocation:
+  // 1.1 % faster than single rows at 1536 x 768 x 256 and 0.9 % at
+  // 1024 x 512 x 384, 6 % faster than whole planes there); whole planes
+  // (z-major order) on small ones (5 % faster than bands at 256 x 128 x 128)
   const int64_t ntx = (d->nx + kTileX - 1) / kTileX;
-  return ntx * nty > 1024 ? 1u : uint32_t(nty);
+  return ntx * nty > 1024 ? uint32_t(std::min<int32_t>(8, nty)) : uint32_t(nty);
 }
 
 void set_tile_band(Geometry* g, uint32_t band) {
@@ -1226,7 +1230,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
   char* ws = h->ws;
   void* lam[2] = {ws + Y.lam0, ws + Y.lam1};
   double* utb[2] = {reinterpret_cast<double*>(ws + Y.utb0), reinterpret_cast<double*>(ws + Y.utb1)};
-  double* ubar = reinterpret_cast<double*>(ws + Y.ubar);
+  unsigned long long* ubar = reinterpret_cast<unsigned long long*>(ws + Y.ubar);
   void* side[2] = {ws + Y.side, ws + Y.sideb};
   double* scr_ut = reinterpret_cast<double*>(ws + Y.scr_ut);
   // activity written by the wall model of a reverse step, by step parity
@@ -1239,7 +1243,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
   if (e == hipSuccess) e = hipMemsetAsync(lam[0], 0, lam_bytes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(utb[0], 0, B * 8, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(utb[1], 0, B * 8, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(ubar, 0, 3 * N * 8, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ubar, 0, 9 * N * 8, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(G, 0, N * 8, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint init");
   const int64_t nseg = (h->rec.nsteps + ce - 1) / ce;
@@ -1322,8 +1326,14 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
     }
   }
   h->ahead_step = -1;
-  e = hipStreamSynchronize(h->stream);
+  int32_t flag = 0;
+  e = hipMemcpyAsync(&flag, h->L.flag, 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint");
+  if (flag & 2) {
+    (void)hipMemsetAsync(h->L.flag, 0, 4, h->stream);
+    return fail(h, HLBM_ERR_NONFINITE, "a probe-velocity adjoint is non-finite or beyond 2^40");
+  }
   return HLBM_OK;
 }
 

@@ -75,6 +75,44 @@ inline Udiv make_udiv(uint32_t d) {
   const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
   return Udiv{uint32_t(m), l < 1 ? l : 1u, l > 1 ? l - 1 : 0u};
 }
+// Fixed-point form of a sum of FP64 values that is independent of the order
+// of the terms: a value v with |v| < 2^40 is the integer X = round(v 2^64),
+// split by magnitude into 32-bit pieces |X| = P2 2^64 + P1 2^32 + P0 and
+// signed like v; each piece is summed in its own int64 accumulator (exact
+// for fewer than 2^31 terms).  fix_split returns false (p untouched) for a
+// value outside the range or not finite.
+__host__ __device__ inline bool fix_split(double v, long long p[3]) {
+  constexpr double k32 = 4294967296.0, k64 = 18446744073709551616.0;
+  if (!(fabs(v) < 1099511627776.0)) return false;  // 2^40
+  const double t = rint(fabs(v) * k64);
+  const double p2 = floor(t / k64);
+  const double r1 = t - p2 * k64;  // in [0, 2^64), exact
+  const double p1 = floor(r1 / k32);
+  const double p0 = r1 - p1 * k32;  // in [0, 2^32), exact
+  const long long s = v < 0.0 ? -1 : 1;
+  p[0] = s * (long long)p2;
+  p[1] = s * (long long)p1;
+  p[2] = s * (long long)p0;
+  return true;
+}
+
+// The accumulated sum (s2 2^64 + s1 2^32 + s0) 2^-64 as FP64: the carries
+// are normalized into H + F 2^-64 with F in [0, 2^64), and the magnitude is
+// converted (one rounding of the fraction relative to the sum).
+__host__ __device__ inline double fix_merge(long long s2, long long s1, long long s0) {
+  const long long c0 = s0 >> 32;  // floor division by 2^32 (arithmetic shift)
+  const unsigned long long l0 = (unsigned long long)(s0 - c0 * 4294967296ll);
+  const long long m1 = s1 + c0;
+  const long long c1 = m1 >> 32;
+  const unsigned long long l1 = (unsigned long long)(m1 - c1 * 4294967296ll);
+  const long long H = s2 + c1;
+  const unsigned long long F = (l1 << 32) | l0;
+  constexpr double k2m64 = 5.42101086242752217e-20;  // 2^-64
+  if (H >= 0) return double(H) + double(F) * k2m64;
+  if (F == 0) return double(H);
+  return -(double(-(H + 1)) + double(0ull - F) * k2m64);
+}
+
 __host__ __device__ inline uint32_t udiv(uint32_t n, const Udiv& v) {
   const uint32_t t = uint32_t((uint64_t(v.m) * n) >> 32);
   return (t + ((n - t) >> v.s1)) >> v.s2;

@@ -658,6 +658,34 @@ __device__ __forceinline__ void group8_sum(double us[3]) {
 // the two Newton solves and writes u_wm, S_wm, sigma and the u_tau state.
 // Adjoint of the torque objective with respect to the momentum exchange of
 // a cell of tag t: d(e . (r x dP)) / d dP = e x r, weighted by w.
+// Probe-velocity adjoints are summed in fixed point (fix_split / fix_merge),
+// so that the sum of the scattered contributions does not depend on the
+// order of the atomic additions and the gradient is reproducible bit for
+// bit.  Accumulators [3 q + k][N] for component q, piece k; a value outside
+// the range raises bit 1 of flag.
+__device__ __forceinline__ void fix_add(unsigned long long* acc, int64_t N, int64_t c, int q, double v,
+                                        int32_t* flag) {
+  long long p[3];
+  if (!fix_split(v, p)) {
+    atomicOr(flag, 2);
+    return;
+  }
+  unsigned long long* b = acc + int64_t(3 * q) * N + c;
+  atomicAdd(b, (unsigned long long)p[0]);
+  atomicAdd(b + N, (unsigned long long)p[1]);
+  atomicAdd(b + 2 * N, (unsigned long long)p[2]);
+}
+
+// The sum of component q at cell c as FP64; the accumulators are zeroed.
+__device__ __forceinline__ double fix_take(unsigned long long* acc, int64_t N, int64_t c, int q) {
+  unsigned long long* b = acc + int64_t(3 * q) * N + c;
+  const long long s2 = (long long)b[0], s1 = (long long)b[N], s0 = (long long)b[2 * N];
+  b[0] = 0ull;
+  b[N] = 0ull;
+  b[2 * N] = 0ull;
+  return fix_merge(s2, s1, s0);
+}
+
 template <class CT>
 __device__ __forceinline__ void objective_dp(const RotorTable& rt, int t, int obj_tag, double w, int x, int y, int z,
                                              CT pb[3]) {
@@ -698,7 +726,8 @@ struct WallArgs {
   const CT* ghost_ct;        // inflow plane in the compute type
   const double* ut_bar_in;   // adjoint of the friction velocity written by the step
   double* ut_bar_out;        // adjoint of the friction velocity read by the step
-  double* ubar;              // [3][N] probe-velocity adjoints, scattered atomically
+  unsigned long long* ubar;  // probe-velocity adjoints in fixed point ([9][N], fix_add)
+  int32_t* flag;             // bit 1: a probe-velocity adjoint outside the fixed-point range
   double obj_w;              // weight of this step's torque in J
   int32_t obj_tag;
 };
@@ -860,7 +889,7 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
       for (int q = 0; q < 3; ++q) v[q] = __shfl(usb[q], lead, 64);
       if (live && (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0)) {
         const int64_t cc = (int64_t(pr.q[2]) * g.ny + pr.q[1]) * g.nx + pr.q[0];
-        for (int q = 0; q < 3; ++q) atomicAdd(&a.ubar[q * g.N + cc], pr.wgt * v[q]);
+        for (int q = 0; q < 3; ++q) fix_add(a.ubar, g.N, cc, q, pr.wgt * v[q], a.flag);
       }
     }
     // Newton statistics (diagnostics steps): one atomic per wave; the
@@ -1633,7 +1662,7 @@ struct AdjArgs {
   const RotorTable* rot;
   const CT* uB_static;
   const CT* ghost;
-  double* ubar;             // [3][N] probe-velocity adjoints scattered by the wall cells; zeroed here
+  unsigned long long* ubar; // probe-velocity adjoints scattered by the wall cells (fixed point); zeroed here
   double* G;                // dJ/d(delta_d), accumulated
   double obj_w;             // weight of this step's torque in J (0 outside the window)
   int32_t obj_tag;
@@ -1724,8 +1753,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const bool fsi = slot >= 0, gather = slot != -1;
   if (gather) {
     for (int q = 0; q < 3; ++q) {
-      ub[q] = a.ubar[q * g.N + c];
-      a.ubar[q * g.N + c] = 0.0;
+      ub[q] = fix_take(a.ubar, g.N, c, q);
     }
   }
   if (fsi) {
@@ -1900,7 +1928,7 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
     if (adj) {
       w.lam_in = (const CT*)adj->lam_in; w.side_in = (const CT*)adj->side_in;
       w.d_eff = (const CT*)L.d_eff; w.tag = L.tag; w.ghost_ct = (const CT*)L.ghost;
-      w.ut_bar_in = adj->ut_bar_in; w.ut_bar_out = adj->ut_bar_out; w.ubar = adj->ubar;
+      w.ut_bar_in = adj->ut_bar_in; w.ut_bar_out = adj->ut_bar_out; w.ubar = adj->ubar; w.flag = L.flag;
       w.obj_w = adj->obj_w; w.obj_tag = adj->obj_tag;
     }
     int64_t geo_blocks = 0;

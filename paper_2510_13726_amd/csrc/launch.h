@@ -128,7 +128,7 @@ struct AdjLaunch {
   void* lam_out;            // adjoint of this state
   void* side;               // outflow side buffer of this step [9][nz][ny]
   const void* side_in;      // that of the next step (added to lam_in on the last plane); nullable
-  double* ubar;             // [3][N] FP64, zero on entry of the sweep except wall scatter
+  unsigned long long* ubar; // [9][N] fixed-point probe-velocity adjoints, zero except the wall scatter
   double* G;                // [N] FP64 gradient accumulator
   const double* ut_bar_in;  // adjoint of the friction velocity written by the step
   double* ut_bar_out;       // adjoint of the friction velocity read by the step
