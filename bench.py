@@ -15,7 +15,6 @@ FP16 / BF16 storage variants, and the FP64 CPU oracle timed on a bounded
 sample of the same workload on the host.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -33,15 +32,7 @@ ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 def bytes_per_cell(storage, q=27):
     """Algorithmic bytes of one cell update: q populations read, q written."""
     return 2 * q * ELEM_BYTES[storage]
-KERNEL_SOURCES = ["paper_2510_13726_amd/csrc/kernels.hip", "paper_2510_13726_amd/csrc/lbm_cell.h"]
-
-
-def kernel_hash():
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+from paper_2510_13726_amd.provenance import kernel_hash  # noqa: E402
 
 
 def log(msg):
