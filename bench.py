@@ -148,6 +148,32 @@ def copy_bandwidth(gib=2.0, reps=20):
     return {"bytes_per_copy": 2 * n * 4, "avg_ms": round(ms, 4), "GB_s": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
+def stream_copy_bandwidth(nbytes, reps=10):
+    """Bandwidth of the library's plain streaming copy (16 B per lane,
+    non-temporal stores) over buffers of the sweep's population size: the
+    streaming rate the sweep's HBM traffic is compared with."""
+    import torch
+    from paper_2510_13726_amd import hlbm
+    n = (int(nbytes) + 15) // 16 * 16
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    hlbm.stream_copy(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(reps):
+        if k % 2:
+            hlbm.stream_copy(b, a)
+        else:
+            hlbm.stream_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * n, "avg_ms": round(ms, 4), "GB_s": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+
+
 CACHE_RESIDENT_BYTES = 256 << 20   # MI355X Infinity Cache
 
 
@@ -266,6 +292,16 @@ def main():
     copy_ref = copy_bandwidth() if args.copy_reference else None
     if copy_ref:
         log(f"copy reference: {copy_ref}")
+    stream_ref = None
+    if args.copy_reference:
+        from paper_2510_13726_amd import hlbm as _hl
+        d = _hl.make_desc(w.nx, w.ny, w.nz, _hl.DTYPES[args.storage], None, w.bc_x)
+        import ctypes as _C
+        pb = _hl.lib().hlbm_population_bytes(_C.byref(d))
+        stream_ref = stream_copy_bandwidth(pb)
+        main_rl = roofline(w, args.storage, main_run["sweep_avg_ms"], main_run["sweep_cells"])
+        stream_ref["sweep_over_copy"] = round(main_rl["achieved"] / stream_ref["GB_s"], 4)
+        log(f"stream copy of the population size: {stream_ref}")
     cpu = None
     if args.cpu_seconds > 0:
         log(f"cpu baseline: {args.cpu_seconds} s of the oracle")
@@ -296,6 +332,7 @@ def main():
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,
         "copy_reference": copy_ref,
+        "stream_copy": stream_ref,
         "finite": main_run["finite"],
         "mass_per_cell": main_run["mass_per_cell"],
         "wall_cells_processed": main_run["wall_cells"],

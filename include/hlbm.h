@@ -151,7 +151,10 @@ int64_t hlbm_rotor_bbox_cells(const hlbm_desc* desc, const hlbm_rotor* rotors, i
 /* Create a lattice on the current HIP device.  pop_a, pop_b: device buffers of
  * hlbm_population_bytes each; workspace: device buffer of
  * hlbm_workspace_bytes.  The handle borrows them until destroy.  The
- * lattice starts at rest (f* = w), step 0, no solids. */
+ * lattice starts at rest (f* = w), step 0, no solids.  The environment
+ * variable HLBM_TILE_BAND (a positive integer), read here, overrides the
+ * number of tile rows per band of the sweep's tile order (for
+ * measurements); results do not depend on it. */
 int hlbm_lattice_create(const hlbm_desc* desc, void* pop_a, void* pop_b, void* workspace,
                         hlbm_handle* out);
 /* Destroy a handle; never frees caller memory.  NULL is a no-op. */
@@ -318,6 +321,19 @@ int hlbm_thrust_coefficient(hlbm_handle h, int32_t tag, int64_t from, int64_t to
  * well-posed runs. */
 int hlbm_wall_safeguards(hlbm_handle h, int64_t* halvings, int64_t* caps);
 
+/* Rotor geometry work since creation (host, syncs): box slots whose rotor
+ * distance was evaluated, and box slots visited, over all geometry
+ * launches.  The rasterization (Sec. 3.1) evaluates the distance only on the
+ * growth layer of Fig. fsialgo, the cells within one cell of those whose
+ * distance lay within one cell of the transition band at the previous step,
+ * while every rotor rotates as prescribed with |omega| (R + eps_h/2 + 1)
+ * <= 1/2 (the surface moves at most half a cell per step) and the previous
+ * step's geometry was computed under the same rotors and parameters;
+ * otherwise on every box slot.  The result is the same either way.  The
+ * environment variable HLBM_GROWTH_LAYER=0, read at creation, turns the
+ * layer off. */
+int hlbm_geometry_stats(hlbm_handle h, int64_t* evaluated, int64_t* visited);
+
 /* Angle theta (rad) and angular velocity Omega (rad/step) of each rotor at
  * the current step, in the order of hlbm_set_rotors: prescribed rotors
  * phase0 + omega n and omega, coupled ones their state (see hlbm_rotor).
@@ -345,6 +361,13 @@ int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* 
  * and wall-model velocities and reduce the per-tag momentum, and of its
  * plain workgroups (host, syncs). */
 int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells);
+/* A plain streaming copy of `bytes` bytes from src to dst (device, 16-byte
+ * aligned, bytes a multiple of 16, not overlapping), 16 B per lane with
+ * non-temporal stores, enqueued on `stream` (hipStream_t, NULL = the null
+ * stream): the reference of the streaming bandwidth the sweep is measured
+ * against in benchmarks.  HLBM_ERR_INVALID for a misaligned or negative
+ * size; asynchronous. */
+int hlbm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
 /* Message of the last error of this handle (or of the last failed create
  * when h is NULL).  Valid until the next call on the handle. */

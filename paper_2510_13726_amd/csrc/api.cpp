@@ -69,7 +69,7 @@ struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
       wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b,
       trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, fsi_tiles, me_partial, me_l1,
-      hist_me, near_index, fd_u, dyn, total;
+      hist_me, near_index, fd_u, dyn, gmark, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -118,6 +118,7 @@ Layout layout(const hlbm_desc* d) {
   L.ghost64b = take(d->bc_x == HLBM_BC_INFLOW_OUTFLOW ? 9 * plane * 8 : 0);
   L.trig = take(d->bbox_cells > 0 ? int64_t(kTrigSteps) * int64_t(sizeof(BladeTrig)) : 0);
   L.dyn = take(d->bbox_cells > 0 ? int64_t(sizeof(RotorDyn)) : 0);
+  L.gmark = take(2 * B * 8);
   const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
   const int64_t lam_bytes = adj ? pop_elems(d) * cs : 0;
   L.lam0 = take(lam_bytes);
@@ -268,6 +269,14 @@ struct hlbm_lattice {
   std::vector<hipEvent_t> pool;
   int static_dev = -1;         // device whose static workspace this lattice uses, -1: caller's workspace
   bool coupled = false;        // a rotor turns with the fluid torque (inertia > 0)
+  // growth layer of the rotor geometry: allowed by the environment, usable
+  // for the current rotors, generation of the rotor / parameter state, and
+  // the step and generation of the last geometry launch
+  bool growth_env = true, growth_ok = false;
+  long long gen = 1;
+  int64_t geo_prev = -2;
+  long long geo_prev_gen = 0;
+  long long* gmark = nullptr;
 };
 
 namespace {
@@ -339,8 +348,42 @@ int next_epoch(hlbm_handle h) {
 }
 
 // Static porosity and tags (plus the control field) into both buffer sets.
+// Growth layer of the rotor geometry (Sec. 3.1, Fig. fsialgo): a geometry
+// launch of step n evaluates the rotor distance only on the box slots that
+// the launch of step n - 1 marked (the cells within one cell of those whose
+// distance lay within one cell of the transition band), when that launch ran
+// under the same rotors and parameters.  Every launch marks for the next.
+void growth_for(hlbm_handle h, Launch* L, int64_t n) {
+  if (!h->growth_ok) {
+    L->gmark = nullptr;
+    L->guse = 0;
+    return;
+  }
+  L->gmark = h->gmark;
+  L->ggen = h->gen;
+  L->guse = (h->geo_prev == n - 1 && h->geo_prev_gen == h->gen) ? 1 : 0;
+  h->geo_prev = n;
+  h->geo_prev_gen = h->gen;
+}
+
+// After a change of the rotors or parameters: the marks of earlier launches
+// no longer apply.  The layer is used for prescribed rotations whose surface
+// moves at most half a cell per step (|omega| (R + eps_h/2 + 1) <= 1/2): the
+// best of the 26 neighbours of a cell then lies at least 0.88 cells deeper
+// in the transition band, more than the motion.
+void growth_update(hlbm_handle h) {
+  ++h->gen;
+  bool ok = h->growth_env && h->gmark && h->rot.n > 0;
+  for (int k = 0; k < h->rot.n && ok; ++k) {
+    const RotorDev& r = h->rot.r[k];
+    if (r.inertia > 0 || !(std::fabs(r.omega) * (r.R + 0.5 * h->params.eps_h + 1.0) <= 0.5)) ok = false;
+  }
+  h->growth_ok = ok;
+}
+
 hipError_t refill_porosity(hlbm_handle h) {
   h->ahead_step = -1;
+  ++h->gen;
   for (int p = 0; p < 2; ++p) {
     hipError_t e = launch_refill_porosity(launch_of(h, p));
     if (e != hipSuccess) return e;
@@ -682,6 +725,11 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.ghost64 = h->ghost64[0];
   L.trig_tab = d->bbox_cells > 0 ? reinterpret_cast<BladeTrig*>(base + Y.trig) : nullptr;
   L.dyn = d->bbox_cells > 0 ? reinterpret_cast<RotorDyn*>(base + Y.dyn) : nullptr;
+  h->gmark = d->bbox_cells > 0 ? reinterpret_cast<long long*>(base + Y.gmark) : nullptr;
+  L.gmark = nullptr;
+  L.ggen = 0;
+  L.guse = 0;
+  if (const char* g = std::getenv("HLBM_GROWTH_LAYER")) h->growth_env = std::strcmp(g, "0") != 0;
   // defaults: Smagorinsky-free BGK-like relaxation at tau0 = 1 until set_params
   hlbm_params p{};
   p.tau0 = 1.0; p.cs_smag = 0.0; p.eps_h = 2.0; p.transition = HLBM_TRANSITION_TANH; p.wall_model = 0;
@@ -792,6 +840,7 @@ int hlbm_set_params(hlbm_handle h, const hlbm_params* p) {
     if ((rc = rebuild_slots(h)) != HLBM_OK) return rc;
   }
   set_model(h);
+  growth_update(h);
   h->have_params = true;
   h->ahead_step = -1;
   h->rec.valid = false;
@@ -813,6 +862,7 @@ int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* r, int32_t n) {
   h->rotors.assign(r, r + n);
   h->L.nrot = n;
   h->L.bbox_total = total;
+  growth_update(h);
   // reset cells of the old boxes to the static field, then re-mark
   hipError_t e = refill_porosity(h);
   if (e != hipSuccess) return hip_fail(h, e, "refill porosity");
@@ -886,6 +936,7 @@ int hlbm_init_equilibrium(hlbm_handle h, const void* rho, const void* u) {
   h->step = 0;
   h->hist_start = 0;
   h->rec.valid = false;
+  ++h->gen;
   if (h->coupled) {
     int rc = restart_rotation(h);
     if (rc == HLBM_OK) rc = upload_rotors(h);
@@ -1015,7 +1066,10 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
     if (e == hipSuccess) e = trig_of(h, n, &trig);
     epoch = next_epoch(h);
     if (e == hipSuccess)
-      e = timed(h, HLBM_KERNEL_RASTERIZE, [&] { return launch_geometry(h->L, n, trig, epoch, act_new, !inlet); });
+      e = timed(h, HLBM_KERNEL_RASTERIZE, [&] {
+        growth_for(h, &h->L, n);
+        return launch_geometry(h->L, n, trig, epoch, act_new, !inlet);
+      });
   }
   h->ahead_step = -1;
   if (e == hipSuccess && wall) {
@@ -1025,6 +1079,7 @@ hipError_t forward_one(hlbm_handle h, int64_t n, const void* src, void* dst, con
       const BladeTrig* trig1 = nullptr;
       e = trig_of(h, n + 1, &trig1);
       L1 = launch_of(h, n + 1);
+      growth_for(h, &L1, n + 1);
       ng = NextGeometry{&L1, n + 1, trig1, next_epoch(h), act_ahead, !inlet};
     }
     if (e == hipSuccess)
@@ -1300,6 +1355,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
         const BladeTrig* trig = nullptr;
         if (e == hipSuccess) e = trig_of(h, n, &trig);
         epoch = next_epoch(h);
+        growth_for(h, &h->L, n);
         if (e == hipSuccess) e = launch_geometry(h->L, n, trig, epoch, scr_act[n & 1], !inlet);
       }
       h->ahead_step = -1;
@@ -1310,6 +1366,7 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
           const BladeTrig* trig1 = nullptr;
           e = trig_of(h, n - 1, &trig1);
           L1 = launch_of(h, n - 1);
+          growth_for(h, &L1, n - 1);
           ng = NextGeometry{&L1, n - 1, trig1, next_epoch(h), scr_act[(n - 1) & 1], !inlet};
         }
         if (e == hipSuccess)
@@ -1353,6 +1410,7 @@ int hlbm_moments(hlbm_handle h, void* rho, void* u, void* uhat) {
   h->ahead_step = -1;
   uint8_t* act_next = h->act[(h->acur + 1) % 3];
   const int epoch = next_epoch(h);
+  growth_for(h, &h->L, h->step);
   if (e == hipSuccess) e = launch_geometry(h->L, h->step, trig, epoch, act_next, !inlet);
   if (e == hipSuccess && wall)
     e = launch_wall(h->L, h->pop[h->cur], h->ut[h->wcur], h->act[h->acur], h->ut[1 - h->wcur], act_next, epoch,
@@ -1435,6 +1493,7 @@ int hlbm_set_state(hlbm_handle h, const void* src) {
   h->step = head[0];
   h->hist_start = head[0];
   h->rec.valid = false;
+  ++h->gen;
   if (h->coupled) {
     // the rotation saved with the state, or a restart from phase0 and omega
     // for a state saved without coupled rotors
@@ -1511,6 +1570,17 @@ int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]) {
   int rc = hlbm_history(h, h->step - 1, h->step, rec);
   if (rc != HLBM_OK) return rc;
   for (int a = 0; a < 3; ++a) { F[a] = rec[1 + 6 * (tag - 1) + a]; T[a] = rec[4 + 6 * (tag - 1) + a]; }
+  return HLBM_OK;
+}
+
+int hlbm_geometry_stats(hlbm_handle h, int64_t* evaluated, int64_t* visited) {
+  if (!h) return HLBM_ERR_INVALID;
+  unsigned long long s[6];
+  hipError_t e = hipMemcpyAsync(s, h->L.stats, sizeof(s), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "geometry stats");
+  if (evaluated) *evaluated = int64_t(s[4]);
+  if (visited) *visited = int64_t(s[5]);
   return HLBM_OK;
 }
 
@@ -1604,6 +1674,14 @@ int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells)
   if (fsi_cells) *fsi_cells = cnt[0];
   if (bulk_cells) *bulk_cells = cnt[1];
   return HLBM_OK;
+}
+
+int hlbm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+  if (bytes < 0 || bytes % 16 || (bytes > 0 && (!src || !dst)) || (reinterpret_cast<uintptr_t>(src) & 15) ||
+      (reinterpret_cast<uintptr_t>(dst) & 15) || (bytes / 16 + 1023) / 1024 > int64_t(0x7fffffff))
+    return HLBM_ERR_INVALID;
+  hipError_t e = launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HLBM_OK : HLBM_ERR_HIP;
 }
 
 const char* hlbm_last_error(hlbm_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }

@@ -947,6 +947,14 @@ struct GeoArgs {
   CT* ghost;
   double* ghost64;
   int32_t ghost_blocks;
+  // growth layer (nullable): evaluate the rotor distance only on the slots
+  // with mark_in == key; mark for the next step (key + 1) the slots within
+  // one cell of every evaluated slot whose distance exceeds -mark_cut
+  const long long* mark_in;
+  long long* mark_out;
+  long long key;
+  double mark_cut;
+  unsigned long long* stats;  // [4] rotor distances evaluated, [5] box slots visited
 };
 
 // Workgroup `bid` of the geometry work: box slots first, then the extra
@@ -979,7 +987,9 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
   double best = -1e300, gr[3] = {0, 0, 0};
   int br = -1;
   RotorPhi win{};
-  for (int j = 0; j < rt.n; ++j) {
+  // growth layer: a slot outside it is fluid for every rotor at this step
+  const bool eval = !a.mark_in || a.mark_in[s] == a.key;
+  for (int j = 0; eval && j < rt.n; ++j) {
     if (!in_box(rt.r[j], x, y, z)) continue;
     RotorPhi p = rotor_phi(rt.r[j], a.trig->c[j], a.trig->s[j], double(x), double(y), double(z), 0.5 * m.eps_h + 1.0);
     if (p.phi > best) {
@@ -987,6 +997,33 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
       br = j;
       win = p;
     }
+  }
+  if (a.stats) {
+    // one atomic pair per workgroup
+    __shared__ int n_eval, n_live;
+    if (threadIdx.x == 0) { n_eval = 0; n_live = 0; }
+    __syncthreads();
+    if (live) {
+      atomicAdd(&n_live, 1);
+      if (eval) atomicAdd(&n_eval, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      atomicAdd(&a.stats[4], (unsigned long long)n_eval);
+      atomicAdd(&a.stats[5], (unsigned long long)n_live);
+    }
+  }
+  if (live && a.mark_out && best > -a.mark_cut) {
+    // the slots of this box within one cell form the next step's layer
+    const RotorDev& R = rt.r[k];
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int xn = x + dx, yn = y + dy, zn = z + dz;
+          if (!in_box(R, xn, yn, zn)) continue;
+          const int64_t sn = R.off + (int64_t(zn - R.b0[2]) * R.bn[1] + (yn - R.b0[1])) * R.bn[0] + (xn - R.b0[0]);
+          a.mark_out[sn] = a.key + 1;
+        }
   }
   // the normal is needed by wall-cell candidates only (band -eps_h/2 < phi < 0)
   if (br >= 0 && m.wall_model && best > -0.5 * m.eps_h && best < 0.0)
@@ -1889,6 +1926,15 @@ static GeoArgs<CT> geo_args(const Launch& L, int64_t step, const BladeTrig* trig
   // the wall model samples in FP64: also fill the FP64 plane when it differs
   a.ghost64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
   a.ghost_blocks = int32_t(nghost);
+  a.stats = L.stats;
+  if (L.gmark && nbw > 0) {
+    // two mark arrays by step parity: a launch reads the marks of the
+    // previous step's launch and writes those of the next step
+    a.mark_in = L.guse ? L.gmark + (step & 1) * L.bbox_total : nullptr;
+    a.mark_out = L.gmark + ((step + 1) & 1) * L.bbox_total;
+    a.key = (L.ggen << 40) | (long long)(step & ((1ll << 40) - 1));
+    a.mark_cut = 0.5 * L.m.eps_h + 1.0;
+  }
   *blocks = nbw + nghost;
   return a;
 }
@@ -2207,6 +2253,33 @@ hipError_t launch_couple(const Launch& L, int64_t rec, int64_t m) {
   if (!L.dyn || L.nrot <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_couple, dim3(1), dim3(64), 0, L.stream, L.rot, L.dyn, (const double*)L.hist, L.hist_cap, rec,
                      m);
+  return hipGetLastError();
+}
+
+// Plain streaming copy, 16 B per lane, four per thread, non-temporal stores.
+typedef float float4v __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const float4v* __restrict__ src, float4v* __restrict__ dst,
+                                                     int64_t n16) {
+  const int64_t i0 = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  float4v v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < n16) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < n16) __builtin_nontemporal_store(v[k], dst + i);
+  }
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t stream) {
+  const int64_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  const int64_t grid = (n16 + 1023) / 1024;
+  hipLaunchKernelGGL(k_stream_copy, dim3(unsigned(grid)), dim3(256), 0, stream, (const float4v*)src, (float4v*)dst,
+                     n16);
   return hipGetLastError();
 }
 

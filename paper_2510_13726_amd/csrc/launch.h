@@ -18,6 +18,12 @@ struct Launch {
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
   BladeTrig* trig_tab;       // blade angles of kTrigSteps consecutive steps
   RotorDyn* dyn;             // coupled rotation state (nullable)
+  // growth layer of the rotor geometry: marks [2][bbox_total] by step
+  // parity (null: every box slot is evaluated), the generation of the rotor
+  // and parameter state they belong to, and whether this launch reads them
+  long long* gmark;
+  long long ggen;
+  int32_t guse;
   // fields
   void* d_eff;
   void* d_static;
@@ -140,6 +146,8 @@ struct AdjLaunch {
 // The adjoint wall step runs inside launch_wall (adj); then this sweep.
 hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A);
 hipError_t launch_refill_porosity(const Launch& L);
+// Plain streaming copy (bytes a multiple of 16, 16-byte aligned pointers).
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t stream);
 hipError_t launch_fill_rest(const Launch& L, void* dst);
 
 // Workspace for lattices created without a caller buffer: a file-scope

@@ -89,6 +89,7 @@ SIGNATURES = [
                                           C.c_double, C.POINTER(C.c_double)]),
     ("hlbm_wall_safeguards", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("hlbm_rotor_state", C.c_int, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("hlbm_geometry_stats", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("hlbm_checkpoint_bytes", C.c_int64, [_H, C.c_int64, C.c_int32]),
     ("hlbm_adjoint_stack_bytes", C.c_int64, [_H, C.c_int32]),
     ("hlbm_forward_record", C.c_int, [_H, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _V, C.c_int64,
@@ -97,6 +98,7 @@ SIGNATURES = [
     ("hlbm_profile_enable", C.c_int, [_H, C.c_int32]),
     ("hlbm_profile_read", C.c_int, [_H, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     ("hlbm_sweep_partition", C.c_int, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hlbm_stream_copy", C.c_int, [_V, _V, C.c_int64, _V]),
     ("hlbm_last_error", C.c_char_p, [_H]),
 ]
 
@@ -379,6 +381,13 @@ class Lattice:
         self._check(self.L.hlbm_wall_safeguards(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def geometry_stats(self):
+        """(rotor distances evaluated, box slots visited) since creation."""
+        a = C.c_int64()
+        b = C.c_int64()
+        self._check(self.L.hlbm_geometry_stats(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def rotor_state(self):
         """(angle, angular velocity) of each rotor at the current step."""
         th = (C.c_double * 8)()
@@ -408,6 +417,19 @@ def sweep_partition(lat):
     b = C.c_int64()
     lat._check(lat.L.hlbm_sweep_partition(lat.h, C.byref(f), C.byref(b)))
     return f.value, b.value
+
+
+def stream_copy(src, dst, stream=None):
+    """Plain streaming copy of src into dst (torch uint8 device tensors of
+    equal size, a multiple of 16 bytes) by the library's reference kernel."""
+    import torch
+    if src.numel() != dst.numel() or src.dtype != torch.uint8 or dst.dtype != torch.uint8:
+        raise HlbmError(HLBM_ERR_INVALID, "src and dst must be uint8 tensors of equal size")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib().hlbm_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), src.numel(),
+                                C.c_void_p(s.cuda_stream))
+    if rc:
+        raise HlbmError(rc, "hlbm_stream_copy: misaligned or invalid size")
 
 
 def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=None, history=1024,

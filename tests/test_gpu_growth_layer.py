@@ -1,0 +1,79 @@
+"""The rotor rasterization on the growth layer (Sec. 3.1, Fig. fsialgo):
+each step evaluates the rotor distance only on the cells within one cell of
+those whose distance lay within one cell of the transition band at the
+previous step.  Against the rasterization of every box slot
+(HLBM_GROWTH_LAYER=0) the runs are identical bit for bit, with a small part
+of the distance evaluations; the layer stays off where its speed bound or
+prescribed rotation does not hold."""
+import numpy as np
+import pytest
+
+from paper_2510_13726_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _hl():
+    from paper_2510_13726_amd import hlbm
+    return hlbm
+
+
+def _two_rotors_overlapping_boxes():
+    """Two rotors 25.5 cells apart: their boxes overlap, their blades do not."""
+    w = W.small_rotor(nx=80, ny=72, nz=36, R=11.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    r0 = w.rotors[0]
+    r0.center = (24.3, 21.6, 18.2)
+    r0.phase0 = 0.3
+    w.rotors.append(W.Rotor(center=(24.8, 47.1, 17.7), R=11.0, r_hub=2.0, chord=4.0, thick=3.0, omega=r0.omega,
+                            phase0=1.7, tag=2))
+    return w
+
+
+CASES = {
+    "small": lambda: W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05),
+    "two_rotors": _two_rotors_overlapping_boxes,
+    "channel": W.config2,
+}
+
+
+def _pair(w, monkeypatch, steps, storage="f32"):
+    hl = _hl()
+    monkeypatch.setenv("HLBM_GROWTH_LAYER", "0")
+    full = hl.setup(w, storage=storage, check_nonfinite=1)
+    monkeypatch.delenv("HLBM_GROWTH_LAYER")
+    grow = hl.setup(w, storage=storage, check_nonfinite=1)
+    full.step(steps)
+    grow.step(steps)
+    return full, grow
+
+
+@pytest.mark.parametrize("case,steps", [("small", 60), ("two_rotors", 40), ("channel", 30)])
+def test_growth_layer_equals_full_rasterization(case, steps, monkeypatch):
+    w = CASES[case]()
+    print(f"[growth] {w.name} steps={steps}", flush=True)
+    full, grow = _pair(w, monkeypatch, steps)
+    ev_f, vis_f = full.geometry_stats()
+    ev_g, vis_g = grow.geometry_stats()
+    print(f"[growth] {w.name}: distances evaluated {ev_g} of {vis_g} box slots visited "
+          f"({ev_g / vis_g:.3f}); full rasterization {ev_f} of {vis_f}", flush=True)
+    assert ev_f == vis_f and vis_g == vis_f
+    assert ev_g < 0.5 * vis_g
+    assert np.array_equal(grow.get_populations().cpu().numpy(), full.get_populations().cpu().numpy())
+    assert np.array_equal(grow.history(), full.history())
+    assert grow.wall_stats() == full.wall_stats()
+
+
+def test_growth_layer_off_beyond_its_speed_bound_and_for_coupled_rotors():
+    hl = _hl()
+    fast = CASES["small"]()
+    fast.rotors[0].omega = 0.05      # 0.05 (12 + 2) = 0.7 cells per step
+    lat = hl.setup(fast, storage="f32")
+    lat.step(4)
+    ev, vis = lat.geometry_stats()
+    assert ev == vis > 0
+    coupled = CASES["small"]()
+    coupled.rotors[0].inertia = 1e6
+    lat = hl.setup(coupled, storage="f32")
+    lat.step(4)
+    ev, vis = lat.geometry_stats()
+    assert ev == vis > 0
