@@ -323,15 +323,16 @@ int hlbm_wall_safeguards(hlbm_handle h, int64_t* halvings, int64_t* caps);
 
 /* Rotor geometry work since creation (host, syncs): box slots whose rotor
  * distance was evaluated, and box slots visited, over all geometry
- * launches.  The rasterization (Sec. 3.1) evaluates the distance only on the
- * growth layer of Fig. fsialgo, the cells within one cell of those whose
- * distance lay within one cell of the transition band at the previous step,
- * while every rotor rotates as prescribed with |omega| (R + eps_h/2 + 1)
- * <= 1/2 (the surface moves at most half a cell per step) and the previous
- * step's geometry was computed under the same rotors and parameters;
- * otherwise on every box slot.  The result is the same either way.  The
- * environment variable HLBM_GROWTH_LAYER=0, read at creation, turns the
- * layer off. */
+ * launches.  The rasterization (Sec. 3.1) evaluates the distance on every
+ * slot of the rotor boxes; with the environment variable
+ * HLBM_GROWTH_LAYER=1, read at creation, only on the growth layer of Fig.
+ * fsialgo: the cells within one cell of those whose distance lay within one
+ * cell of the transition band at the previous step, while every rotor
+ * rotates as prescribed with |omega| (R + eps_h/2 + 1) <= 1/2 (the surface
+ * moves at most half a cell per step) and the previous step's geometry was
+ * computed under the same rotors and parameters.  The result is the same
+ * either way; the layer is off by default because marking it costs more
+ * than the evaluations it saves. */
 int hlbm_geometry_stats(hlbm_handle h, int64_t* evaluated, int64_t* visited);
 
 /* Angle theta (rad) and angular velocity Omega (rad/step) of each rotor at

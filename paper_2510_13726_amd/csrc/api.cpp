@@ -69,7 +69,7 @@ struct Layout {
   int64_t d_eff, d_effb, d_static, tag, tagb, tag_static, uB, dd, blk, partial, partl1, mass, massl1, wlist, wlistb,
       wcount, flag, stats, rot, geo, geob, ut0, ut1, act0, act1, act2, wall, hist, ghost, ghost64, ghostb, ghost64b,
       trig, lam0, lam1, utb0, utb1, ubar, side, sideb, scr_ut, scr_act, scr_actb, fsi_tiles, me_partial, me_l1,
-      hist_me, near_index, fd_u, dyn, gmark, total;
+      hist_me, near_index, fd_u, dyn, gmark, gstats, total;
 };
 
 Layout layout(const hlbm_desc* d) {
@@ -119,6 +119,7 @@ Layout layout(const hlbm_desc* d) {
   L.trig = take(d->bbox_cells > 0 ? int64_t(kTrigSteps) * int64_t(sizeof(BladeTrig)) : 0);
   L.dyn = take(d->bbox_cells > 0 ? int64_t(sizeof(RotorDyn)) : 0);
   L.gmark = take(2 * B * 8);
+  L.gstats = take(2 * ((B + 255) / 256) * 8);
   const bool adj = (d->flags & HLBM_WITH_ADJOINT) != 0;
   const int64_t lam_bytes = adj ? pop_elems(d) * cs : 0;
   L.lam0 = take(lam_bytes);
@@ -178,20 +179,19 @@ bool rotor_box(const hlbm_desc* d, const hlbm_rotor& r, double margin, RotorBox*
 // 1024 tiles (about four per CU) fits in the workgroups in flight, so plane
 // after plane already sweeps the three z planes that read a source row
 // together, and the plain lattice order (one band) is fastest; a larger
-// plane is swept one row of tiles at a time through all z (band 1).
-// Measured on MI355X: 256x128x128 (128 tiles per plane) 72.5 % of 8 TB/s
-// with one band, 65 % with band 1; 1536x768x256 (4608 tiles per plane)
-// 75.4 % with band 1, 70.6 % with one band.  HLBM_TILE_BAND overrides the
-// choice (measurement runs).
+// plane is swept in bands of 8 tile rows through all z.  Measured on one
+// fixed allocation on MI355X (the population buffers reused, so that the
+// spread between allocations drops out): 256x128x128 (128 tiles per plane)
+// 154.7 us with one band against 163-166 us with bands of 1-16 rows;
+// 1536x768x256 (4608 tiles per plane) 11.74 ms with bands of 8 rows against
+// 11.87 ms (1 row) and 11.96 ms (one band); 1024x512x384 7.41 ms against
+// 7.51 ms and 7.88 ms.  HLBM_TILE_BAND overrides the choice (measurement
+// runs).
 uint32_t tile_band(const hlbm_desc* d, int32_t nty) {
   if (const char* e = std::getenv("HLBM_TILE_BAND")) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 1) return uint32_t(std::min<long>(v, nty));
   }
-  // bands of 8 tile rows on large planes (measured on one fixed allocation:
-  // 1.1 % faster than single rows at 1536 x 768 x 256 and 0.9 % at
-  // 1024 x 512 x 384, 6 % faster than whole planes there); whole planes
-  // (z-major order) on small ones (5 % faster than bands at 256 x 128 x 128)
   const int64_t ntx = (d->nx + kTileX - 1) / kTileX;
   return ntx * nty > 1024 ? uint32_t(std::min<int32_t>(8, nty)) : uint32_t(nty);
 }
@@ -272,7 +272,7 @@ struct hlbm_lattice {
   // growth layer of the rotor geometry: allowed by the environment, usable
   // for the current rotors, generation of the rotor / parameter state, and
   // the step and generation of the last geometry launch
-  bool growth_env = true, growth_ok = false;
+  bool growth_env = false, growth_ok = false;
   long long gen = 1;
   int64_t geo_prev = -2;
   long long geo_prev_gen = 0;
@@ -729,7 +729,12 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.gmark = nullptr;
   L.ggen = 0;
   L.guse = 0;
-  if (const char* g = std::getenv("HLBM_GROWTH_LAYER")) h->growth_env = std::strcmp(g, "0") != 0;
+  L.gstats = d->bbox_cells > 0 ? reinterpret_cast<unsigned long long*>(base + Y.gstats) : nullptr;
+  // opt-in: on MI355X marking the layer costs more than the distance
+  // evaluations it saves (the fused wall-and-geometry launch took 31.3 us
+  // with it and 24.5 us without at 256x128x128, 190 and 179 us at
+  // 1536x768x256)
+  if (const char* g = std::getenv("HLBM_GROWTH_LAYER")) h->growth_env = std::strcmp(g, "1") == 0;
   // defaults: Smagorinsky-free BGK-like relaxation at tau0 = 1 until set_params
   hlbm_params p{};
   p.tau0 = 1.0; p.cs_smag = 0.0; p.eps_h = 2.0; p.transition = HLBM_TRANSITION_TANH; p.wall_model = 0;
@@ -1575,12 +1580,21 @@ int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]) {
 
 int hlbm_geometry_stats(hlbm_handle h, int64_t* evaluated, int64_t* visited) {
   if (!h) return HLBM_ERR_INVALID;
-  unsigned long long s[6];
-  hipError_t e = hipMemcpyAsync(s, h->L.stats, sizeof(s), hipMemcpyDeviceToHost, h->stream);
+  const int64_t nwg = (h->desc.bbox_cells + 255) / 256;
+  std::vector<unsigned long long> s(size_t(2 * nwg), 0ull);
+  hipError_t e = hipSuccess;
+  if (nwg > 0 && h->L.gstats)
+    e = hipMemcpyAsync(s.data(), h->L.gstats, sizeof(unsigned long long) * s.size(), hipMemcpyDeviceToHost,
+                       h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "geometry stats");
-  if (evaluated) *evaluated = int64_t(s[4]);
-  if (visited) *visited = int64_t(s[5]);
+  int64_t ev = 0, vis = 0;
+  for (int64_t b = 0; b < nwg; ++b) {
+    ev += int64_t(s[size_t(2 * b)]);
+    vis += int64_t(s[size_t(2 * b + 1)]);
+  }
+  if (evaluated) *evaluated = ev;
+  if (visited) *visited = vis;
   return HLBM_OK;
 }
 

@@ -954,7 +954,10 @@ struct GeoArgs {
   long long* mark_out;
   long long key;
   double mark_cut;
-  unsigned long long* stats;  // [4] rotor distances evaluated, [5] box slots visited
+  // per geometry workgroup: rotor distances evaluated and box slots visited
+  // since creation ([2 bid], [2 bid + 1]; each entry written by one
+  // workgroup per launch, so no atomics)
+  unsigned long long* gstats;
 };
 
 // Workgroup `bid` of the geometry work: box slots first, then the extra
@@ -970,9 +973,11 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
     if (k < plane) inflow_plane_cell<CT, Q>(g, m, a.step, k, a.ghost, a.ghost64);
     return;
   }
-  __shared__ int wl_count, wl_base;
+  __shared__ int wl_count, wl_base, n_eval, n_live;
   if (threadIdx.x == 0) {
     wl_count = 0;
+    n_eval = 0;
+    n_live = 0;
     if (bid == 0) *a.wcount_next = 0;
   }
   __syncthreads();
@@ -998,19 +1003,12 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
       win = p;
     }
   }
-  if (a.stats) {
-    // one atomic pair per workgroup
-    __shared__ int n_eval, n_live;
-    if (threadIdx.x == 0) { n_eval = 0; n_live = 0; }
-    __syncthreads();
-    if (live) {
-      atomicAdd(&n_live, 1);
-      if (eval) atomicAdd(&n_eval, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      atomicAdd(&a.stats[4], (unsigned long long)n_eval);
-      atomicAdd(&a.stats[5], (unsigned long long)n_live);
+  {
+    // counts of the wave into the workgroup's (one LDS atomic per wave)
+    const unsigned long long be = __ballot(live && eval), bl = __ballot(live);
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&n_eval, int(__popcll(be)));
+      atomicAdd(&n_live, int(__popcll(bl)));
     }
   }
   if (live && a.mark_out && best > -a.mark_cut) {
@@ -1050,7 +1048,13 @@ __device__ __forceinline__ void geometry_block(const GeoArgs<CT>& a, uint32_t bi
   int rank = 0;
   if (mine) rank = atomicAdd(&wl_count, 1);
   __syncthreads();
-  if (threadIdx.x == 0) wl_base = wl_count ? atomicAdd(a.wcount, wl_count) : 0;
+  if (threadIdx.x == 0) {
+    wl_base = wl_count ? atomicAdd(a.wcount, wl_count) : 0;
+    if (a.gstats) {
+      a.gstats[2 * bid] += (unsigned long long)n_eval;
+      a.gstats[2 * bid + 1] += (unsigned long long)n_live;
+    }
+  }
   __syncthreads();
   if (!mine) return;
   // the wall cell's distance and normal beside its list entry, so that the
@@ -1926,7 +1930,7 @@ static GeoArgs<CT> geo_args(const Launch& L, int64_t step, const BladeTrig* trig
   // the wall model samples in FP64: also fill the FP64 plane when it differs
   a.ghost64 = (L.compute != 0 && L.nrot > 0) ? L.ghost64 : nullptr;
   a.ghost_blocks = int32_t(nghost);
-  a.stats = L.stats;
+  a.gstats = L.gstats;
   if (L.gmark && nbw > 0) {
     // two mark arrays by step parity: a launch reads the marks of the
     // previous step's launch and writes those of the next step

@@ -24,6 +24,7 @@ struct Launch {
   long long* gmark;
   long long ggen;
   int32_t guse;
+  unsigned long long* gstats;  // [2][geometry workgroups]: distances evaluated, slots visited
   // fields
   void* d_eff;
   void* d_static;

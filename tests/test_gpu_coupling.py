@@ -34,12 +34,13 @@ def _wind(inertia=1e6, torque_gen=2.0):
     return w
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_coupled_rotor_parity(storage):
+@pytest.mark.parametrize("storage,q", [("f64", 27), ("f32", 27), ("f64", 19)])
+def test_coupled_rotor_parity(storage, q):
     hl = _hl()
     w = _wind()
+    w.q = q
     n = 24
-    print(f"[coupling] {w.name} storage={storage} steps={n}", flush=True)
+    print(f"[coupling] {w.name} q={q} storage={storage} steps={n}", flush=True)
     lat = hl.setup(w, storage=storage, check_nonfinite=1)
     o = O.setup(w)
     th_g, om_g, th_o, om_o = [], [], [], []
@@ -58,7 +59,7 @@ def test_coupled_rotor_parity(storage):
     e_th = np.abs(th_g - th_o)
     eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
     ep = rel(lat.get_populations().cpu().numpy(), o.get_populations())
-    print(f"[coupling] {storage}: Omega {om_o[0]:.6f} -> {om_o[-1]:.6f}, speed err {e_om.max():.2e} "
+    print(f"[coupling] D3Q{q} {storage}: Omega {om_o[0]:.6f} -> {om_o[-1]:.6f}, speed err {e_om.max():.2e} "
           f"(bound {om_bound[-1]:.2e}), angle err {e_th.max():.2e}, F {eF:.2e} T {eT:.2e}, pops {ep:.2e}",
           flush=True)
     assert abs(om_o[-1] - om_o[0]) > 0.05 * abs(om_o[0])   # the coupling does act

@@ -1,8 +1,8 @@
 """The rotor rasterization on the growth layer (Sec. 3.1, Fig. fsialgo):
 each step evaluates the rotor distance only on the cells within one cell of
 those whose distance lay within one cell of the transition band at the
-previous step.  Against the rasterization of every box slot
-(HLBM_GROWTH_LAYER=0) the runs are identical bit for bit, with a small part
+previous step (HLBM_GROWTH_LAYER=1).  Against the rasterization of every
+box slot (the default) the runs are identical bit for bit, with a small part
 of the distance evaluations; the layer stays off where its speed bound or
 prescribed rotation does not hold."""
 import numpy as np
@@ -29,8 +29,15 @@ def _two_rotors_overlapping_boxes():
     return w
 
 
+def _small_d3q19():
+    w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    w.q = 19
+    return w
+
+
 CASES = {
     "small": lambda: W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05),
+    "small_d3q19": _small_d3q19,
     "two_rotors": _two_rotors_overlapping_boxes,
     "channel": W.config2,
 }
@@ -38,16 +45,16 @@ CASES = {
 
 def _pair(w, monkeypatch, steps, storage="f32"):
     hl = _hl()
-    monkeypatch.setenv("HLBM_GROWTH_LAYER", "0")
+    monkeypatch.delenv("HLBM_GROWTH_LAYER", raising=False)
     full = hl.setup(w, storage=storage, check_nonfinite=1)
-    monkeypatch.delenv("HLBM_GROWTH_LAYER")
+    monkeypatch.setenv("HLBM_GROWTH_LAYER", "1")
     grow = hl.setup(w, storage=storage, check_nonfinite=1)
     full.step(steps)
     grow.step(steps)
     return full, grow
 
 
-@pytest.mark.parametrize("case,steps", [("small", 60), ("two_rotors", 40), ("channel", 30)])
+@pytest.mark.parametrize("case,steps", [("small", 60), ("small_d3q19", 30), ("two_rotors", 40), ("channel", 30)])
 def test_growth_layer_equals_full_rasterization(case, steps, monkeypatch):
     w = CASES[case]()
     print(f"[growth] {w.name} steps={steps}", flush=True)
@@ -63,8 +70,9 @@ def test_growth_layer_equals_full_rasterization(case, steps, monkeypatch):
     assert grow.wall_stats() == full.wall_stats()
 
 
-def test_growth_layer_off_beyond_its_speed_bound_and_for_coupled_rotors():
+def test_growth_layer_off_beyond_its_speed_bound_and_for_coupled_rotors(monkeypatch):
     hl = _hl()
+    monkeypatch.setenv("HLBM_GROWTH_LAYER", "1")
     fast = CASES["small"]()
     fast.rotors[0].omega = 0.05      # 0.05 (12 + 2) = 0.7 cells per step
     lat = hl.setup(fast, storage="f32")
