@@ -1,5 +1,4 @@
-"""Per-cell instruction and FLOP counts of the sweep from a rocprofv3
-counter pass.
+"""Instruction counts per wave of the sweep from a rocprofv3 counter pass.
 
     python -m paper_2510_13726_amd.profile_counters --csv run_counter_collection.csv \
         --workload rotor_channel_256x128x128 --cells 4194304 --cmd "..." \
@@ -7,9 +6,7 @@ counter pass.
 
 For every storage type and velocity set of k_sweep in the pass, the mean
 value per dispatch of each counter of the steady-state variant (the one
-launched most often), divided by the cells one launch updates.  SQ_INSTS_*
-count wave instructions (64 lanes each); SQ_INSTS_VALU_FLOPS_* count
-floating-point operations (an FMA is two).
+launched most often), per wave of 64 cells.
 """
 import argparse
 import collections
@@ -25,7 +22,10 @@ def main():
     ap.add_argument("--cells", type=int, required=True)
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--skip", default="", help="comma-separated counters to leave out of the table")
+    ap.add_argument("--note", default="")
     a = ap.parse_args()
+    skip = set(x for x in a.skip.split(",") if x)
     vals = collections.defaultdict(lambda: collections.defaultdict(list))  # (st, q) -> name -> counter -> [v]
     counters = []
     with open(a.csv) as fh:
@@ -34,14 +34,16 @@ def main():
             if not c:
                 continue
             name = r["Counter_Name"]
+            if name in skip:
+                continue
             if name not in counters:
                 counters.append(name)
             vals[c][(r["Kernel_Name"], name)].append(float(r["Counter_Value"]))
-    lines = [f"# Instructions and FLOPs per cell of k_sweep, {a.workload} ({a.cells:,} cells per launch)", "",
+    lines = [f"# Vector and scalar instructions per wave of k_sweep, {a.workload} ({a.cells:,} cells per launch)", "",
              "Command (one counter pass):", "", f"    {a.cmd}", "",
-             "Mean per dispatch of the steady-state variant, divided by the cells of one launch. SQ_INSTS_* "
-             "count wave instructions (64 lanes); per cell they are the instructions one lane executes for its "
-             "cell. SQ_INSTS_VALU_FLOPS_* count operations (an FMA is two).", "",
+             "Mean per dispatch of the steady-state variant. SQ_INSTS_* are wave instructions per wave (one wave "
+             "updates 64 cells, one per lane; a vector instruction is executed by every lane).", "",
+             *([a.note, ""] if a.note else []),
              "| storage | velocities | " + " | ".join(counters) + " |",
              "|---|---|" + "---|" * len(counters)]
     for key in sorted(vals):
@@ -61,7 +63,7 @@ def main():
                 continue
             per = mean / a.cells
             if cn.startswith("SQ_INSTS") and "FLOPS" not in cn:
-                per *= 64.0  # wave instructions -> per lane (one cell per lane)
+                per *= 64.0  # per wave: 64 cells
             row.append(f"{per:.1f}")
         lines.append(f"| {st} | D3Q{q} | " + " | ".join(row) + " |")
     with open(a.out, "w") as fh:
