@@ -203,17 +203,19 @@ def config_sweep(keys, storages, main_key, main_results, cpu_seconds):
     return out
 
 
-def cpu_sample(w, seconds):
+def cpu_sample(w, seconds, threads=None, planes=16):
     """The oracle on a bounded part of a workload: the whole lattice if a step
-    fits the budget, else an x-slab of 16 planes through the first rotor."""
+    fits the budget, else an x-slab of `planes` planes through the first
+    rotor."""
     from oracle import oracle as O
     from paper_2510_13726_amd import workloads as W
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     s, what = w, "whole lattice"
-    if w.cells > 5_000_000:
-        x0 = max(0, int(w.rotors[0].center[0]) - 8) if w.rotors else 0
-        s = W.x_slab(w, x0, 16)
-        what = f"x-slab [{x0}, {x0 + 16}) through the first rotor ({s.cells} cells)"
+    if w.cells * 16 > 5_000_000 * planes:
+        x0 = max(0, int(w.rotors[0].center[0]) - planes // 2) if w.rotors else 0
+        s = W.x_slab(w, x0, planes)
+        what = f"x-slab [{x0}, {x0 + planes}) through the first rotor ({s.cells} cells)"
     o = O.setup(s, threads=threads)
     o.step(1)
     t0 = time.perf_counter()
@@ -302,11 +304,13 @@ def main():
         main_rl = roofline(w, args.storage, main_run["sweep_avg_ms"], main_run["sweep_cells"])
         stream_ref["sweep_over_copy"] = round(main_rl["achieved"] / stream_ref["GB_s"], 4)
         log(f"stream copy of the population size: {stream_ref}")
-    cpu = None
+    cpu = cpu1 = None
     if args.cpu_seconds > 0:
         log(f"cpu baseline: {args.cpu_seconds} s of the oracle")
         cpu = cpu_sample(w, args.cpu_seconds)
         log(f"cpu: {cpu}")
+        cpu1 = cpu_sample(w, max(1.0, args.cpu_seconds / 5), threads=1, planes=2)
+        log(f"cpu, one thread: {cpu1}")
     out = {
         "metric": METRIC,
         "value": round(main_run["mlups"], 1),
@@ -326,6 +330,7 @@ def main():
                    "diag_every": args.diag_every, "check_nonfinite": True},
         "roofline": roofline(w, args.storage, main_run["sweep_avg_ms"], main_run["sweep_cells"]),
         "cpu_baseline": cpu,
+        "cpu_oracle_one_thread": cpu1,
         "storage_variants": variants,
         "d3q19": d3q19 or None,
         "per_config": per_config,
