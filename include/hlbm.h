@@ -73,7 +73,7 @@ typedef struct hlbm_lattice* hlbm_handle;
  * only with compute = HLBM_F32); compute: arithmetic type of the sweep
  * (HLBM_F64 or HLBM_F32).  bc_x: x faces periodic, or equilibrium inflow at
  * x = 0 and zero-gradient outflow at x = nx-1 (y and z are periodic).
- * velocities: 27 (or 0) for D3Q27, 19 for D3Q19 (no HLBM_WITH_ADJOINT).
+ * velocities: 27 (or 0) for D3Q27, 19 for D3Q19.
  * bbox_cells: total cells of the rotors' bounding boxes the workspace must
  * hold (from hlbm_rotor_bbox_cells); history: steps kept in the force ring. */
 typedef struct {
@@ -264,7 +264,8 @@ int hlbm_force_torque(hlbm_handle h, int32_t tag, double F[3], double T[3]);
 int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
 
 /* Discrete adjoint of the time stepping (gradient of the time-averaged
- * rotor torque with respect to the porosity control delta_d), D3Q27 only.
+ * rotor torque with respect to the porosity control delta_d), on either
+ * velocity set.
  * Objective: J = 1/(t1-t0) sum over steps k in [t0, t1) of the record of
  * the axial torque e_tag . T_tag (obj_tag 0 = all tags), with T from the
  * momentum handed to the solid (Sec. 2.2.2).  Needs HLBM_WITH_ADJOINT.

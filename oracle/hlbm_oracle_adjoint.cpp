@@ -47,7 +47,8 @@ typedef Dual<4> D4;
 void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, const std::vector<double>& lam,
                   const std::vector<double>& UT, std::vector<double>& lam_out, std::vector<double>& UT_out,
                   double* G) {
-  const Lattice& L = lat();
+  const Lattice& L = *s.lat_;
+  const int q = s.q;
   const int64_t N = s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   s.geometry(n);
@@ -87,9 +88,9 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
       sig[c] = 0.0;
       wcells.push_back(c);
       xs_of.push_back({xs[0], xs[1], xs[2]});
-      for (int a = 0; a < 3; ++a) for (int q = 0; q < 4; ++q) Jw.push_back(o.uwm[a].g[q]);
-      for (int k = 0; k < 6; ++k) for (int q = 0; q < 4; ++q) Jw.push_back(o.S[k].g[q]);
-      for (int q = 0; q < 4; ++q) Jw.push_back(o.utau.g[q]);
+      for (int a = 0; a < 3; ++a) for (int r = 0; r < 4; ++r) Jw.push_back(o.uwm[a].g[r]);
+      for (int k = 0; k < 6; ++k) for (int r = 0; r < 4; ++r) Jw.push_back(o.S[k].g[r]);
+      for (int r = 0; r < 4; ++r) Jw.push_back(o.utau.g[r]);
     }
   }
   // ---- collision adjoint per cell
@@ -98,7 +99,7 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
   for (int64_t c = 0; c < N; ++c) {
     const int x = int(c % nx), y = int((c / nx) % ny), z = int(c / ((int64_t)nx * ny));
     double fbar[Q];
-    for (int i = 0; i < Q; ++i) fbar[i] = lam[(size_t)i * N + c];
+    for (int i = 0; i < q; ++i) fbar[i] = lam[(size_t)i * N + c];
     double pbar[3] = {0, 0, 0};
     const int t = s.g_tag[c];
     if (obj_weight != 0.0 && t != 0 && (obj_tag == 0 || obj_tag == t)) {
@@ -114,13 +115,13 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
     dd.g[10] = 1.0;
     for (int a = 0; a < 3; ++a) { uw3[a] = D20(uwm[(size_t)a * N + c]); uw3[a].g[11 + a] = 1.0; }
     for (int k = 0; k < 6; ++k) { S6[k] = D20(Swm[(size_t)k * N + c]); S6[k].g[14 + k] = 1.0; }
-    collide_cell(m, dd, &s.g_uB[3 * c], uw3, S6, sig[c], p.tau0, p.cs_smag, fs, dp);
+    collide_cell(m, dd, &s.g_uB[3 * c], uw3, S6, sig[c], p.tau0, p.cs_smag, fs, dp, L);
     double xbar[20] = {0};
-    for (int q = 0; q < 20; ++q) {
+    for (int r = 0; r < 20; ++r) {
       double acc = 0.0;
-      for (int i = 0; i < Q; ++i) acc += fbar[i] * fs[i].g[q];
-      for (int a = 0; a < 3; ++a) acc += pbar[a] * dp[a].g[q];
-      xbar[q] = acc;
+      for (int i = 0; i < q; ++i) acc += fbar[i] * fs[i].g[r];
+      for (int a = 0; a < 3; ++a) acc += pbar[a] * dp[a].g[r];
+      xbar[r] = acc;
     }
     for (int k = 0; k < 10; ++k) mbar[(size_t)k * N + c] = xbar[k];
     G[c] += xbar[10];
@@ -139,7 +140,7 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
     out_bar[9] = UT[c];
     double in_bar[4] = {0, 0, 0, 0};
     for (int o = 0; o < 10; ++o)
-      for (int q = 0; q < 4; ++q) in_bar[q] += out_bar[o] * J[o * 4 + q];
+      for (int r = 0; r < 4; ++r) in_bar[r] += out_bar[o] * J[o * 4 + r];
     UT_out[c] += in_bar[3];
     // trilinear weights of the probe, as in Sim::sample_u
     const double* X = xs_of[w].data();
@@ -176,7 +177,7 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
       mb[0] -= ub * j / (rho * rho);
       mb[1 + a] += ub / rho;
     }
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < q; ++i) {
       const int* ci = L.c[i];
       mu[(size_t)i * N + c] = mb[0] + ci[0] * mb[1] + ci[1] * mb[2] + ci[2] * mb[3] + ci[0] * ci[0] * mb[4] +
                               ci[1] * ci[1] * mb[5] + ci[2] * ci[2] * mb[6] + ci[0] * ci[1] * mb[7] +
@@ -188,7 +189,7 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const int64_t c = s.idx(x, y, z);
-        for (int i = 0; i < Q; ++i) {
+        for (int i = 0; i < q; ++i) {
           int xs = x - L.c[i][0];
           const int ys = Sim<double>::wrap(y - L.c[i][1], ny), zs = Sim<double>::wrap(z - L.c[i][2], nz);
           if (s.bc_x == 0) xs = Sim<double>::wrap(xs, nx);
@@ -210,7 +211,6 @@ int oracle_adjoint_run(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int obj
                        double* G) {
   Sim<double>& s = *(Sim<double>*)hp;
   if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1) return 1;
-  if (s.q != 27) return 1;  // the adjoint is written for the 27-velocity set
   if (s.p.fd_share > 0.0) return 1;  // and for the local non-equilibrium off the wall
   for (const Rotor& r : s.rotors)
     if (r.inertia > 0) return 1;     // and for prescribed rotations

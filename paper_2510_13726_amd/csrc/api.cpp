@@ -39,10 +39,6 @@ bool desc_ok(const hlbm_desc* d, std::string* why) {
     *why = "velocities must be 27 (or 0) or 19";
     return false;
   }
-  if (d->velocities == 19 && (d->flags & HLBM_WITH_ADJOINT)) {
-    *why = "the discrete adjoint is available on the 27-velocity set only";
-    return false;
-  }
   return true;
 }
 

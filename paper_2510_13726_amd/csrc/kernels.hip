@@ -740,7 +740,6 @@ struct WallArgs {
 // the eight probe corners with the trilinear weights) and of u_tau^prev.
 template <class ST, class CT, bool kPeriodicX, bool kAdj, int Q = 27>
 __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, uint32_t nblk) {
-  static_assert(!kAdj || Q == 27, "the adjoint wall step is written for the 27-velocity set");
   const RotorTable& rt = *a.rot;
   const Geometry& g = a.g;
   const Model& m = a.m;
@@ -843,18 +842,18 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
         if (active) {
           const int x = pr.x, y = pr.y, z = pr.z;
           const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
-          CT hc[27];
-          pull_cell<ST, CT, kPeriodicX>(src, g, x, y, z, a.ghost_ct, hc);
-          const Moments<CT> mc = moments_of<CT>(hc);
+          CT hc[Q];
+          pull_cell<ST, CT, kPeriodicX, Q>(src, g, x, y, z, a.ghost_ct, hc);
+          const Moments<CT> mc = moments_q<Q, CT>(hc);
           // adjoint of the state after the step at this cell; on the last
           // x plane lam_in also holds the outflow share of the c_x = -1 states
           const bool fix = !kPeriodicX && a.side_in && x == g.nx - 1;
           const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
-          CT gb[27];
-          for (int i = 0; i < 27; ++i) {
-            CT l = a.lam_in[pop_at(g, i, x, y, z)];
-            if (fix && i < 9) l += a.side_in[i * plane + k];
-            gb[i] = CT(w_of(i)) * l;
+          CT gb[Q];
+          for (int i = 0; i < Q; ++i) {
+            CT l = a.lam_in[pop_at<Q>(g, i, x, y, z)];
+            if (fix && i < xgroup_of<Q>(1)) l += a.side_in[i * plane + k];
+            gb[i] = CT(wq<Q>(i)) * l;
           }
           // the FSI inputs of the cell as the sweep of the step read them
           const uint8_t tb = a.tag[c];
@@ -869,7 +868,7 @@ __device__ __forceinline__ void wall_cells(const WallArgs<CT>& a, uint32_t blk, 
           objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
           Moments<CT> mb;
           CT db, bb[3], Sb[6];
-          collide_vjp<CT>(mc, d, b[0], b[1], b[2], CT(0), S, CT(m.tau0), CT(m.smag), gb, pb, mb, db, bb, Sb);
+          collide_vjp<CT, Q>(mc, d, b[0], b[1], b[2], CT(0), S, CT(m.tau0), CT(m.smag), gb, pb, mb, db, bb, Sb);
           double ob[10];
           for (int q = 0; q < 3; ++q) ob[q] = double(bb[q]);
           for (int q = 0; q < 6; ++q) ob[3 + q] = double(Sb[q]);
@@ -1748,7 +1747,7 @@ __device__ __forceinline__ void fsi_inputs(const AdjArgs<CT>& a, const RotorTabl
 // clamped read of (nx-1, .); the second share goes to `side`, and the reader
 // of lam (this sweep of the previous step, and the adjoint wall step) adds
 // it on the last plane.  Workgroups past nblocks zero `zero`.
-template <class ST, class CT, bool kPeriodicX>
+template <class ST, class CT, bool kPeriodicX, int Q = 27>
 __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const Geometry& g = a.g;
   if (int64_t(blockIdx.x) >= a.nblocks) {
@@ -1765,27 +1764,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   if (xr >= g.nx || yr >= g.ny) return;
   const int x = xr, y = yr;
   const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
-  CT h[27];
-  pull_row<ST, CT, kPeriodicX>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
-  const Moments<CT> mo = moments_of<CT>(h);
+  CT h[Q];
+  pull_row<ST, CT, kPeriodicX, Q>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+  const Moments<CT> mo = moments_q<Q, CT>(h);
   // lam in the blocked layout of the populations: this wave's block, and the
   // nine rows the transposed pull writes into
   constexpr uint32_t cs = sizeof(CT);
   const uint64_t rs = uint64_t(g.row) * cs;
-  const uint32_t o4 = pop_x(x) * cs;
-  CT gb[27];
+  const uint32_t o4 = pop_x<Q>(x) * cs;
+  CT gb[Q];
   {
     typedef __attribute__((address_space(1))) const char* gcb;
     gcb q = (gcb)a.lam_in + (uint64_t(z) * g.ny + y) * rs;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) gb[i] = *(const CT*)(q + (o4 + uint32_t(i * kTileX) * cs));
+    for (int i = 0; i < Q; ++i) gb[i] = *(const CT*)(q + (o4 + uint32_t(i * kTileX) * cs));
   }
   if (!kPeriodicX && a.side_in && x == g.nx - 1) {
     const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
-    for (int i = 0; i < 9; ++i) gb[i] += a.side_in[i * plane + k];
+    for (int i = 0; i < xgroup_of<Q>(1); ++i) gb[i] += a.side_in[i * plane + k];
   }
 #pragma unroll
-  for (int i = 0; i < 27; ++i) gb[i] *= CT(w_of(i));
+  for (int i = 0; i < Q; ++i) gb[i] *= CT(wq<Q>(i));
   const RotorTable& rt = *a.rot;
   CT d = CT(0), b[3] = {CT(0), CT(0), CT(0)}, S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)}, sigma = CT(1);
   CT pb[3] = {CT(0), CT(0), CT(0)};
@@ -1806,7 +1805,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   }
   Moments<CT> mb;
   CT db, bb[3], Sb[6];
-  collide_vjp<CT>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
+  collide_vjp<CT, Q>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
   if (gather) {
     // probe velocity u = j / rho at this cell, sampled by wall cells
     const CT rho = CT(1) + mo.drho, irho = rcp_ct(rho);
@@ -1830,11 +1829,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   }
   const uint64_t rz[3] = {uint64_t(zp) * g.ny, uint64_t(z) * g.ny, uint64_t(zm) * g.ny};
   const uint32_t ry[3] = {uint32_t(yp), uint32_t(y), uint32_t(ym)};
-  const uint32_t ox[3] = {pop_x(xp) * cs, pop_x(x) * cs, pop_x(xm) * cs};
+  const uint32_t ox[3] = {pop_x<Q>(xp) * cs, pop_x<Q>(x) * cs, pop_x<Q>(xm) * cs};
   const int64_t plane = int64_t(g.ny) * g.nz;
 #pragma unroll
-  for (int i = 0; i < 27; ++i) {
-    const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+  for (int i = 0; i < Q; ++i) {
+    const int cx = cxq<Q>(i), cy = cyq<Q>(i), cz = czq<Q>(i);
     const CT mu = mb.drho + CT(cx) * mb.jx + CT(cy) * mb.jy + CT(cz) * mb.jz + CT(cx * cx) * mb.pxx +
                   CT(cy * cy) * mb.pyy + CT(cz * cz) * mb.pzz + CT(cx * cy) * mb.pxy + CT(cx * cz) * mb.pxz +
                   CT(cy * cz) * mb.pyz;
@@ -1856,9 +1855,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   if (!kPeriodicX) {
     // states nobody reads: (nx-1, *) for c_x = +1 and (0, *) for c_x = -1
     if (x == g.nx - 1)
-      for (int i = 18; i < 27; ++i) a.lam_out[pop_at(g, i, x, y, z)] = CT(0);
+      for (int i = xgroup_of<Q>(2); i < Q; ++i) a.lam_out[pop_at<Q>(g, i, x, y, z)] = CT(0);
     if (x == 0)
-      for (int i = 0; i < 9; ++i) a.lam_out[pop_at(g, i, x, y, z)] = CT(0);
+      for (int i = 0; i < xgroup_of<Q>(1); ++i) a.lam_out[pop_at<Q>(g, i, x, y, z)] = CT(0);
   }
 }
 
@@ -1992,17 +1991,17 @@ hipError_t launch_wall(const Launch& L, const void* src, const double* ut_prev, 
         hipLaunchKernelGGL(fused_kernel, dim3(unsigned(wall_blocks + geo_blocks)), dim3(256), 0, L.stream, w, ga,
                            uint32_t(wall_blocks));
     };
-    if (adj && L.q != 27) return hipErrorInvalidValue;  // the adjoint needs the 27-velocity set
-    if (L.q == 19) {
-      if (L.g.bc_x == 0) go(k_wall<ST, CT, true, false, 19>, k_wall_geometry<ST, CT, true, false, 19>);
-      else go(k_wall<ST, CT, false, false, 19>, k_wall_geometry<ST, CT, false, false, 19>);
-    } else if (L.g.bc_x == 0) {
-      if (adj) go(k_wall<ST, CT, true, true, 27>, k_wall_geometry<ST, CT, true, true, 27>);
-      else go(k_wall<ST, CT, true, false, 27>, k_wall_geometry<ST, CT, true, false, 27>);
-    } else {
-      if (adj) go(k_wall<ST, CT, false, true, 27>, k_wall_geometry<ST, CT, false, true, 27>);
-      else go(k_wall<ST, CT, false, false, 27>, k_wall_geometry<ST, CT, false, false, 27>);
-    }
+    (void)by_q(L.q, [&](auto QC) {
+      constexpr int Q = QC.value;
+      if (L.g.bc_x == 0) {
+        if (adj) go(k_wall<ST, CT, true, true, Q>, k_wall_geometry<ST, CT, true, true, Q>);
+        else go(k_wall<ST, CT, true, false, Q>, k_wall_geometry<ST, CT, true, false, Q>);
+      } else {
+        if (adj) go(k_wall<ST, CT, false, true, Q>, k_wall_geometry<ST, CT, false, true, Q>);
+        else go(k_wall<ST, CT, false, false, Q>, k_wall_geometry<ST, CT, false, false, Q>);
+      }
+      return hipSuccess;
+    });
     return hipGetLastError();
   });
 }
@@ -2151,16 +2150,18 @@ static AdjArgs<CT> adj_args(const Launch& L, const AdjLaunch& A) {
 }
 
 hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A) {
-  if (L.q != 27) return hipErrorInvalidValue;  // the adjoint is written for the 27-velocity set
   return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
     using ST = std::remove_pointer_t<decltype(st)>;
     using CT = std::remove_pointer_t<decltype(ct)>;
     AdjArgs<CT> a = adj_args<CT>(L, A);
     const int64_t nzb = A.zero ? (A.nzero + kBlock - 1) / kBlock : 0;
     const dim3 grid(unsigned(L.nblocks + nzb));
-    if (L.g.bc_x == 0) hipLaunchKernelGGL((k_adj_sweep<ST, CT, true>), grid, dim3(kBlock), 0, L.stream, a);
-    else hipLaunchKernelGGL((k_adj_sweep<ST, CT, false>), grid, dim3(kBlock), 0, L.stream, a);
-    return hipGetLastError();
+    return by_q(L.q, [&](auto QC) {
+      constexpr int Q = QC.value;
+      if (L.g.bc_x == 0) hipLaunchKernelGGL((k_adj_sweep<ST, CT, true, Q>), grid, dim3(kBlock), 0, L.stream, a);
+      else hipLaunchKernelGGL((k_adj_sweep<ST, CT, false, Q>), grid, dim3(kBlock), 0, L.stream, a);
+      return hipGetLastError();
+    });
   });
 }
 

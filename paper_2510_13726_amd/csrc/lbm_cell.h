@@ -454,14 +454,56 @@ __device__ __forceinline__ Coef<CT> reconstruct_transpose(const CT gb[27]) {
   return c;
 }
 
+// Adjoints of the inputs of reconstruct19 (its transpose): E0, the
+// odd-moment scale U = 3 rho u, B2 and the third-order coefficients B3_aab.
+// Faces: g = (E0 + B_aa) +- (U_a - 2 sum_{c != a} B3_cca); edges (a, b):
+// g = (E0 + B_aa + B_bb +- 2 B_ab) +- (U_a + 2 B3_bba) +- (U_b + 2 B3_aab).
+template <class CT>
+__device__ __forceinline__ void reconstruct19_transpose(const CT gb[19], CT& E0b, CT b2db[3], CT b2ob[3], CT Ub[3],
+                                                        CT b3b[6]) {
+  const CT exb = gb[kq<19>(1, 0, 0)] + gb[kq<19>(-1, 0, 0)], vxb = gb[kq<19>(1, 0, 0)] - gb[kq<19>(-1, 0, 0)];
+  const CT eyb = gb[kq<19>(0, 1, 0)] + gb[kq<19>(0, -1, 0)], vyb = gb[kq<19>(0, 1, 0)] - gb[kq<19>(0, -1, 0)];
+  const CT ezb = gb[kq<19>(0, 0, 1)] + gb[kq<19>(0, 0, -1)], vzb = gb[kq<19>(0, 0, 1)] - gb[kq<19>(0, 0, -1)];
+  // edge (a, b): g_pp = ep + op, g_mm = ep - op, g_pm = em + om, g_mp = em - om
+  auto edge_t = [&](int ipp, int imm, int ipm, int imp, CT& eb, CT& Db, CT& Wab, CT& Wbb) {
+    const CT epb = gb[ipp] + gb[imm], opb = gb[ipp] - gb[imm];
+    const CT emb = gb[ipm] + gb[imp], omb = gb[ipm] - gb[imp];
+    eb = epb + emb;
+    Db = epb - emb;
+    Wab = opb + omb;
+    Wbb = opb - omb;
+  };
+  CT exyb, Dxyb, Wx_xy, Wy_xy, exzb, Dxzb, Wx_xz, Wz_xz, eyzb, Dyzb, Wy_yz, Wz_yz;
+  edge_t(kq<19>(1, 1, 0), kq<19>(-1, -1, 0), kq<19>(1, -1, 0), kq<19>(-1, 1, 0), exyb, Dxyb, Wx_xy, Wy_xy);
+  edge_t(kq<19>(1, 0, 1), kq<19>(-1, 0, -1), kq<19>(1, 0, -1), kq<19>(-1, 0, 1), exzb, Dxzb, Wx_xz, Wz_xz);
+  edge_t(kq<19>(0, 1, 1), kq<19>(0, -1, -1), kq<19>(0, 1, -1), kq<19>(0, -1, 1), eyzb, Dyzb, Wy_yz, Wz_yz);
+  E0b = gb[kq<19>(0, 0, 0)] + exb + eyb + ezb + exyb + exzb + eyzb;
+  b2db[0] = exb + exyb + exzb;
+  b2db[1] = eyb + exyb + eyzb;
+  b2db[2] = ezb + exzb + eyzb;
+  b2ob[0] = CT(2) * Dxyb;
+  b2ob[1] = CT(2) * Dxzb;
+  b2ob[2] = CT(2) * Dyzb;
+  Ub[0] = vxb + Wx_xy + Wx_xz;
+  Ub[1] = vyb + Wy_xy + Wy_yz;
+  Ub[2] = vzb + Wz_xz + Wz_yz;
+  // b3 order xxy, xxz, yyx, yyz, zzx, zzy
+  b3b[0] = CT(-2) * vyb + CT(2) * Wy_xy;
+  b3b[1] = CT(-2) * vzb + CT(2) * Wz_xz;
+  b3b[2] = CT(-2) * vxb + CT(2) * Wx_xy;
+  b3b[3] = CT(-2) * vzb + CT(2) * Wz_yz;
+  b3b[4] = CT(-2) * vxb + CT(2) * Wx_xz;
+  b3b[5] = CT(-2) * vyb + CT(2) * Wy_yz;
+}
+
 // Vector-Jacobian product of `collide` (with the homogenized velocity
 // u_hat = u + d (b - u), b = u^B + u_wm) and of the momentum handed to the
 // solid dP = j - rho u_hat.  gb = adjoint of the normalized post-collision
 // deviations (w_i times the adjoint of f*_i), pb = adjoint of dP.  Returns
 // the adjoints of the deviation moments, of d and of b (= of u_wm) and S.
-template <class CT>
+template <class CT, int NQ = 27>
 __device__ __forceinline__ void collide_vjp(const Moments<CT>& m, CT d, CT bx, CT by, CT bz, CT sigma, const CT S[6],
-                                            CT tau0, CT smag, const CT gb[27], const CT pb[3], Moments<CT>& mb,
+                                            CT tau0, CT smag, const CT gb[NQ], const CT pb[3], Moments<CT>& mb,
                                             CT& db, CT bb[3], CT Sb[6]) {
   const CT third = CT(1.0 / 3.0), c45 = CT(4.5);
   // ---- forward intermediates
@@ -483,20 +525,35 @@ __device__ __forceinline__ void collide_vjp(const Moments<CT>& m, CT d, CT bx, C
   const CT os = om * sigma;
   const CT fd = om * CT(3) * (CT(1) - sigma) * rho * tau;
   const CT pi = c45 * os, t = c45 * os;
-  // ---- coefficient adjoints
-  const Coef<CT> k = reconstruct_transpose(gb);
-  // E0 = drho - tr(B2)/3; B_aa = b2_aa; D_ab = 2 b2_ab; T_ab = 3 b3_aab;
-  // V_b = 3 rho uh_b - sum_{a != b} b3_aab; X = 6 b3_xyz
-  CT b2b[6] = {k.Bxx - k.E0 * third, k.Byy - k.E0 * third, k.Bzz - k.E0 * third,
-               CT(2) * k.Dxy, CT(2) * k.Dxz, CT(2) * k.Dyz};
-  // b3 adjoints, indexed (a twice, b once): xxy, xxz, yyx, yyz, zzx, zzy
-  const CT b3xxy = CT(3) * k.Txy - k.Vy, b3xxz = CT(3) * k.Txz - k.Vz;
-  const CT b3yyx = CT(3) * k.Tyx - k.Vx, b3yyz = CT(3) * k.Tyz - k.Vz;
-  const CT b3zzx = CT(3) * k.Tzx - k.Vx, b3zzy = CT(3) * k.Tzy - k.Vy;
-  const CT b3xyz = CT(6) * k.X;
-  CT drho_b = k.E0;
-  CT rho_b = CT(3) * (k.Vx * uh[0] + k.Vy * uh[1] + k.Vz * uh[2]);
-  CT uh_b[3] = {CT(3) * rho * k.Vx, CT(3) * rho * k.Vy, CT(3) * rho * k.Vz};
+  // ---- coefficient adjoints: E0 = drho - tr(B2)/3, the odd scale
+  // U = 3 rho uh, B2 and B3 (b3 indexed (a twice, b once): xxy, xxz, yyx,
+  // yyz, zzx, zzy, and xyz on D3Q27)
+  CT b2b[6], b3xxy, b3xxz, b3yyx, b3yyz, b3zzx, b3zzy, b3xyz, drho_b, Ub[3];
+  if constexpr (NQ == 27) {
+    const Coef<CT> k = reconstruct_transpose(gb);
+    // B_aa = b2_aa; D_ab = 2 b2_ab; T_ab = 3 b3_aab; V_b = U_b - sum_{a != b}
+    // b3_aab; X = 6 b3_xyz
+    b2b[0] = k.Bxx - k.E0 * third; b2b[1] = k.Byy - k.E0 * third; b2b[2] = k.Bzz - k.E0 * third;
+    b2b[3] = CT(2) * k.Dxy; b2b[4] = CT(2) * k.Dxz; b2b[5] = CT(2) * k.Dyz;
+    b3xxy = CT(3) * k.Txy - k.Vy; b3xxz = CT(3) * k.Txz - k.Vz;
+    b3yyx = CT(3) * k.Tyx - k.Vx; b3yyz = CT(3) * k.Tyz - k.Vz;
+    b3zzx = CT(3) * k.Tzx - k.Vx; b3zzy = CT(3) * k.Tzy - k.Vy;
+    b3xyz = CT(6) * k.X;
+    drho_b = k.E0;
+    Ub[0] = k.Vx; Ub[1] = k.Vy; Ub[2] = k.Vz;
+  } else {
+    CT E0b, b2db[3], b2ob[3], b3b[6];
+    reconstruct19_transpose<CT>(gb, E0b, b2db, b2ob, Ub, b3b);
+    for (int a = 0; a < 3; ++a) {
+      b2b[a] = b2db[a] - E0b * third;
+      b2b[3 + a] = b2ob[a];
+    }
+    b3xxy = b3b[0]; b3xxz = b3b[1]; b3yyx = b3b[2]; b3yyz = b3b[3]; b3zzx = b3b[4]; b3zzy = b3b[5];
+    b3xyz = CT(0);
+    drho_b = E0b;
+  }
+  CT rho_b = CT(3) * (Ub[0] * uh[0] + Ub[1] * uh[1] + Ub[2] * uh[2]);
+  CT uh_b[3] = {CT(3) * rho * Ub[0], CT(3) * rho * Ub[1], CT(3) * rho * Ub[2]};
   CT ru_b[3] = {CT(0), CT(0), CT(0)};
   CT Pb[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)};
   CT t_b = CT(0);

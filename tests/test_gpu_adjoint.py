@@ -28,12 +28,14 @@ def _cases():
     return {"sphere": (a, 12, 4, 12), "rotor": (b, 10, 3, 10)}
 
 
+@pytest.mark.parametrize("q", [27, 19])
 @pytest.mark.parametrize("case", ["sphere", "rotor"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_adjoint_matches_oracle(case, storage):
+def test_adjoint_matches_oracle(case, storage, q):
     hl = _hl()
     w, n, t0, t1 = _cases()[case]
-    print(f"[adjoint] {case} {storage}", flush=True)
+    w.q = q
+    print(f"[adjoint] {case} D3Q{q} {storage}", flush=True)
     o = O.setup(w)
     J_or, G_or = o.adjoint_run(n, t0, t1, obj_tag=0, ckpt_every=4)
     lat = hl.setup(w, storage=storage, flags=hl.WITH_ADJOINT)
@@ -43,7 +45,8 @@ def test_adjoint_matches_oracle(case, storage):
     # scale of the summed |(x - x_c) x dP| over the window
     eJ = abs(J - J_or) / _torque_scale(o, t0, t1)
     eG = np.abs(G - G_or).max() / np.abs(G_or).max()
-    print(f"[adjoint] {case} {storage}: J {J:.6e} vs {J_or:.6e} (rel {eJ:.2e}); G rel err {eG:.2e}", flush=True)
+    print(f"[adjoint] {case} D3Q{q} {storage}: J {J:.6e} vs {J_or:.6e} (rel {eJ:.2e}); G rel err {eG:.2e}",
+          flush=True)
     tol = {"f64": 1e-12, "f32": 2e-5}[storage]
     assert eJ < tol
     assert eG < tol

@@ -109,8 +109,21 @@ def test_d3q19_full_channel_fp32():
     assert e < TOL["f32"]
 
 
-def test_d3q19_refuses_the_adjoint():
+def test_d3q19_adjoint_checkpoint_spacing_and_repeat():
+    """The D3Q19 adjoint (parity with the oracle in test_gpu_adjoint) gives
+    the same gradient bit for bit for checkpoint spacings 1, 3 and the whole
+    run, and on a repeated run."""
     hl = _hl()
-    with pytest.raises(hl.HlbmError) as e:
-        hl.Lattice(16, 8, 8, storage="f64", flags=hl.WITH_ADJOINT, q=19)
-    assert e.value.code == hl.HLBM_ERR_INVALID
+    w = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52, turb=0.05)
+    w.q = 19
+    lat = hl.setup(w, storage="f64", flags=hl.WITH_ADJOINT)
+    state0 = lat.get_state().clone()
+    ref = None
+    for ce in (1, 3, 10, 3):
+        lat.set_state(state0)
+        J = lat.forward_record(10, 3, 10, obj_tag=0, ckpt_every=ce)
+        G = lat.adjoint(1.0).cpu().numpy()
+        if ref is None:
+            ref = (J, G)
+        assert J == ref[0] and np.array_equal(G, ref[1]), ce
+    assert np.abs(ref[1]).max() > 0

@@ -1,7 +1,8 @@
 """Pin of the oracle's discrete adjoint: dJ/d(delta_d) from the reverse sweep
 equals the complex-step derivative of the forward oracle (step h = 1e-30, no
 subtractive cancellation) to rounding, for a static porous sphere and for a
-rotating rotor with the wall model, inflow turbulence and outflow."""
+rotating rotor with the wall model, inflow turbulence and outflow, on the
+D3Q27 and the D3Q19 velocity sets."""
 import numpy as np
 import pytest
 
@@ -26,12 +27,16 @@ def _check(w, nsteps, t0, t1, ncells=6, seed=0):
     assert np.array_equal(o.get_populations(), o2.get_populations())
 
 
-def test_adjoint_static_sphere_complex_step():
+@pytest.mark.parametrize("q", [27, 19])
+def test_adjoint_static_sphere_complex_step(q):
     w = W.config1(noise=True, n=12)
     w.params.cs_smag = 0.15
+    w.q = q
     _check(w, 12, 4, 12)
 
 
-def test_adjoint_rotor_wall_model_complex_step():
+@pytest.mark.parametrize("q", [27, 19])
+def test_adjoint_rotor_wall_model_complex_step(q):
     w = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52, turb=0.05)
+    w.q = q
     _check(w, 10, 3, 10)
