@@ -223,3 +223,63 @@ def test_light_cone_of_an_x_slab(x0):
     assert np.abs(hf - hs).max() <= 1e-13 * np.abs(hf).max()
     # the compared planes hold the rotor's disturbance, not only free stream
     assert np.abs(hf - hf[:, :1, :1, :1]).max() > 1e-4 * np.abs(hf).max()
+
+
+@pytest.mark.parametrize("case", ["poiseuille", "brinkman"])
+def test_channel_driven_by_a_weak_porosity(case):
+    """A periodic channel between two porous walls (a d = 1 slab with the
+    tanh band; its d = 1/2 level set 17 cells from the axis, Def. Lattice
+    Porosity), the fluid held by a weak uniform porosity delta toward the
+    solid velocity V: each step the collision hands rho delta (V - u) to the
+    fluid (eq. convexVelocity), a body force.  The steady profile solves
+    nu u'' + delta (V - u) = 0 with u = 0 at the walls,
+    u = V (1 - cosh(k y) / cosh(k h)), k = sqrt(delta / nu), nu =
+    cs^2 (tau0 - 1/2): the Poiseuille parabola u = delta V (h^2 - y^2) /
+    (2 nu) for k h -> 0 (delta = 2e-5), a distinctly flatter profile for
+    k h = 1.9 (delta = 2e-3).  The wall position h is fitted; it must lie
+    within 0.6 cells of the level set, as for the Couette flow."""
+    from scipy.optimize import brentq
+    delta, V, steps = {"poiseuille": (2e-5, 1.0, 18000), "brinkman": (2e-3, 0.01, 6000)}[case]
+    n, tau0 = 40, 1.0
+    o = O.OracleLattice(2, n, 1, 0)
+    o.set_params(W.Params(tau0=tau0, cs_smag=0.0, eps_h=2.0))
+    o.set_rotors([])
+    y = np.arange(n)
+    phi = 3.0 - np.minimum(y, n - y)
+
+    def s(p):
+        v = 0.5 * (1 + np.tanh(4 * p / 2.0) / np.tanh(2.0))
+        return np.where(p <= -1, 0.0, np.where(p >= 1, 1.0, v))
+
+    dw = s(phi)
+    d = np.tile(np.maximum(dw, delta)[:, None], (1, 2)).reshape(-1)
+    uBx = np.tile(np.where(dw > 0, 0.0, V)[:, None], (1, 2)).reshape(-1)
+    o.set_porosity_field(d, np.zeros(2 * n, dtype=np.uint8))
+    o.set_solid_velocity(np.stack([uBx, 0 * uBx, 0 * uBx]))
+    o.init_equilibrium(None, None)
+    o.step(steps)
+    ux = o.moments()[1][0].reshape(n, 2)[:, 0]
+    o.step(100)
+    assert np.abs(o.moments()[1][0].reshape(n, 2)[:, 0] - ux).max() < 1e-9 * V   # steady
+    nu = CS2 * (tau0 - 0.5)
+    k = np.sqrt(delta / nu)
+    yc, h_set = 20.0, 17.0
+    ys = np.array([v for v in range(5, 36) if dw[v] == 0.0])
+
+    def model(h):
+        return V * (1 - np.cosh(k * (ys - yc)) / np.cosh(k * h))
+
+    h = brentq(lambda hh: np.sum((ux[ys] - model(hh)) * np.cosh(k * (ys - yc))), 15.0, 19.0)
+    umax = ux[ys].max()
+    resid = np.abs(ux[ys] - model(h)).max() / umax
+    par = np.polyfit(ys, ux[ys], 2)
+    par_resid = np.abs(ux[ys] - np.polyval(par, ys)).max() / umax
+    print(f"{case}: wall at {h:.3f} (level set {h_set}), residual {resid:.1e} of u_max {umax:.4e}, "
+          f"parabola residual {par_resid:.1e}")
+    assert abs(h - h_set) < 0.6
+    assert resid < 1e-3
+    if case == "poiseuille":
+        assert par_resid < 1e-3
+        assert abs(umax / (delta * V * h ** 2 / (2 * nu)) - 1) < 0.02
+    else:
+        assert par_resid > 1e-2
