@@ -129,3 +129,23 @@ def test_tile_order_does_not_change_results(band, monkeypatch):
     lat.step(12)
     assert np.array_equal(lat.get_populations().cpu().numpy(), ref.get_populations().cpu().numpy())
     assert np.array_equal(lat.history(), ref.history())
+
+
+def test_profiling_and_sweep_partition():
+    """Opt-in event timing counts one sweep and one wall-model launch per
+    step (the wall launch also computes the next geometry), and the sweep's
+    porous and plain workgroups cover every cell once."""
+    hl = _hl()
+    w = W.small_rotor(nx=72, ny=44, nz=40, R=12.0, chord=4.0, hub=2.0, tau0=0.51, turb=0.05)
+    lat = hl.setup(w, storage="f32")
+    lat.step(2)
+    hl.profile_enable(lat, True)
+    lat.step(7)
+    n_sw, ms_sw = hl.profile_read(lat, hl.KERNEL_SWEEP)
+    n_wall, ms_wall = hl.profile_read(lat, hl.KERNEL_WALL)
+    n_geo, _ = hl.profile_read(lat, hl.KERNEL_RASTERIZE)
+    hl.profile_enable(lat, False)
+    assert (n_sw, n_wall, n_geo) == (7, 7, 0)
+    assert ms_sw > 0 and ms_wall > 0
+    fsi, bulk = hl.sweep_partition(lat)
+    assert fsi > 0 and bulk > 0 and fsi + bulk == w.nx * w.ny * w.nz
