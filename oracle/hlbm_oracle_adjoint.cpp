@@ -93,6 +93,19 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
       for (int r = 0; r < 4; ++r) Jw.push_back(o.utau.g[r]);
     }
   }
+  // ---- hybrid non-equilibrium off the wall: sigma = 1 - fd_share and the
+  // central-difference strain of the pre-collision velocity in the element
+  // cells that are not active wall cells (as in the forward step)
+  std::vector<int64_t> fdcells;
+  if (p.fd_share > 0.0) {
+    s.sigma = sig;
+    s.Swm = Swm;
+    s.fd_strain();
+    for (int64_t c = 0; c < N; ++c)
+      if (s.sigma[c] != sig[c]) fdcells.push_back(c);
+    sig = s.sigma;
+    Swm = s.Swm;
+  }
   // ---- collision adjoint per cell
   std::vector<double> mbar(10 * N, 0.0), uwbar(3 * N, 0.0), Sbar(6 * N, 0.0);
 #pragma omp parallel for num_threads(s.nthreads) schedule(static)
@@ -163,6 +176,30 @@ void adjoint_step(Sim<double>& s, int64_t n, double obj_weight, int obj_tag, con
       for (int a = 0; a < 3; ++a) ubar[(size_t)a * N + cc] += wgt * in_bar[a];
     }
   }
+  // ---- the strain of the hybrid cells: S_ab = (d_a u_b + d_b u_a) / 2 with
+  // d_b u_a = (u_a(x + e_b) - u_a(x - e_b)) / 2 -> velocity adjoints of the
+  // neighbours (the same neighbour rules as the forward strain)
+  for (const int64_t c : fdcells) {
+    const int x = int(c % nx), y = int((c / nx) % ny), z = int(c / ((int64_t)nx * ny));
+    const int xm = s.bc_x == 0 ? Sim<double>::wrap(x - 1, nx) : (x > 0 ? x - 1 : 0);
+    const int xp = s.bc_x == 0 ? Sim<double>::wrap(x + 1, nx) : (x < nx - 1 ? x + 1 : nx - 1);
+    int64_t nb[3][2];
+    nb[0][0] = s.idx(xm, y, z);
+    nb[0][1] = s.idx(xp, y, z);
+    nb[1][0] = s.idx(x, Sim<double>::wrap(y - 1, ny), z);
+    nb[1][1] = s.idx(x, Sim<double>::wrap(y + 1, ny), z);
+    nb[2][0] = s.idx(x, y, Sim<double>::wrap(z - 1, nz));
+    nb[2][1] = s.idx(x, y, Sim<double>::wrap(z + 1, nz));
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        int k;
+        sym_index(a, b, k);
+        // adjoint of d_b u_a: S_aa = d_a u_a; S_ab = (d_b u_a + d_a u_b) / 2
+        const double dub = (a == b ? 1.0 : 0.5) * Sbar[(size_t)k * N + c];
+        ubar[(size_t)a * N + nb[b][1]] += 0.5 * dub;
+        ubar[(size_t)a * N + nb[b][0]] -= 0.5 * dub;
+      }
+  }
   // ---- u = j / rho into the moment adjoints, then moments -> populations
   std::fill(lam_out.begin(), lam_out.end(), 0.0);
   std::vector<double> mu((size_t)Q * N);
@@ -211,7 +248,6 @@ int oracle_adjoint_run(void* hp, int64_t nsteps, int64_t t0, int64_t t1, int obj
                        double* G) {
   Sim<double>& s = *(Sim<double>*)hp;
   if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1) return 1;
-  if (s.p.fd_share > 0.0) return 1;  // and for the local non-equilibrium off the wall
   for (const Rotor& r : s.rotors)
     if (r.inertia > 0) return 1;     // and for prescribed rotations
   const int64_t n0 = s.step, N = s.N;

@@ -40,3 +40,19 @@ def test_adjoint_rotor_wall_model_complex_step(q):
     w = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52, turb=0.05)
     w.q = q
     _check(w, 10, 3, 10)
+
+
+@pytest.mark.parametrize("case", ["sphere", "rotor"])
+def test_adjoint_with_hybrid_strain_complex_step(case):
+    """fd_share > 0: the hybrid non-equilibrium off the wall, whose strain is
+    the central difference of the neighbours' velocities (Sec. 2.2), enters
+    the adjoint through those neighbours."""
+    if case == "sphere":
+        w = W.config1(noise=True, n=12)
+        w.params.cs_smag = 0.15
+        w.params.fd_share = 0.4
+        _check(w, 12, 4, 12)
+    else:
+        w = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52, turb=0.05)
+        w.params.fd_share = 0.3
+        _check(w, 10, 3, 10)
