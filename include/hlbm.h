@@ -104,7 +104,7 @@ typedef struct {
  * cells, with sigma = 1 - fd_share and f(1,FD) from the central-difference
  * strain of the pre-collision velocity (y, z periodic; x periodic or clamped
  * to the first and last plane); 0 (the default) keeps sigma = 1 there;
- * fd_share > 0 needs HLBM_WITH_FD_STRAIN and excludes the adjoint. */
+ * fd_share > 0 needs HLBM_WITH_FD_STRAIN. */
 typedef struct {
   double tau0, cs_smag, eps_h;
   int32_t transition, wall_model;
@@ -275,7 +275,11 @@ int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst);
  * writes G = gJ dJ/d(delta_d) (device FP64, N values): it recomputes each
  * segment of ckpt_every steps into stack (device, hlbm_adjoint_stack_bytes)
  * and runs the reverse steps; Newton iterations of the wall model are
- * differentiated as executed.  The lattice state is left unchanged. */
+ * differentiated as executed, and with fd_share > 0 the central differences
+ * of the hybrid cells' strain carry its adjoint to the neighbours'
+ * velocities.  Prescribed rotations only: forward_record refuses a coupled
+ * rotor (inertia > 0) with HLBM_ERR_STATE.  The lattice state is left
+ * unchanged. */
 int64_t hlbm_checkpoint_bytes(hlbm_handle h, int64_t nsteps, int32_t ckpt_every);
 int64_t hlbm_adjoint_stack_bytes(hlbm_handle h, int32_t ckpt_every);
 /* A record is invalidated by any call that steps the lattice or changes its

@@ -483,6 +483,11 @@ int rebuild_slots(hlbm_handle h) {
   }
   int32_t n = 0;
   for (auto& f : flags) f = (f & 1) ? n++ : (f & 2) ? -2 : -1;
+  // the finite-difference strain of an FSI tile's cells reads the velocity
+  // of the neighbouring tiles' cells: the adjoint gathers there too
+  if (h->L.near_index)
+    for (const int32_t b : tiles)
+      if (flags[size_t(b)] == -1) flags[size_t(b)] = -2;
   h->nslots = n;
   h->nme = (h->desc.flags & HLBM_WITH_MOMENTUM_EXCHANGE) ? int32_t(tiles.size()) : 0;
   h->L.nnear = h->L.near_index ? int32_t(tiles.size()) : 0;
@@ -1223,8 +1228,6 @@ int hlbm_forward_record(hlbm_handle h, int64_t nsteps, int64_t t0, int64_t t1, i
   if (!(h->desc.flags & HLBM_WITH_ADJOINT)) return fail(h, HLBM_ERR_STATE, "created without HLBM_WITH_ADJOINT");
   if (nsteps < 1 || t0 < 0 || t1 <= t0 || t1 > nsteps || ckpt_every < 1 || obj_tag < 0 || obj_tag > 15 || !ckpt || !J)
     return fail(h, HLBM_ERR_INVALID, "need 0 <= t0 < t1 <= nsteps, ckpt_every >= 1, 0 <= obj_tag <= 15");
-  if (h->params.fd_share > 0.0)
-    return fail(h, HLBM_ERR_STATE, "the adjoint is written for the local non-equilibrium (fd_share = 0)");
   if (h->coupled) return fail(h, HLBM_ERR_STATE, "the adjoint is written for prescribed rotor rotations");
   if (ckpt_bytes < hlbm_checkpoint_bytes(h, nsteps, ckpt_every))
     return fail(h, HLBM_ERR_INVALID, "checkpoint buffer too small");
@@ -1376,6 +1379,11 @@ int hlbm_adjoint(hlbm_handle h, double gJ, double* G, void* stack, int64_t stack
           h->ahead_step = n - 1;
           h->ahead_epoch = ng.epoch;
         }
+      }
+      // the strain of the hybrid cells: velocity adjoints of their neighbours
+      if (e == hipSuccess && h->params.fd_share > 0.0) {
+        e = launch_fd_velocity(h->L, s0, n);
+        if (e == hipSuccess) e = launch_adjoint_fd(h->L, A);
       }
       if (e == hipSuccess) e = launch_adjoint_sweep(h->L, A);
       if (e != hipSuccess) return hip_fail(h, e, "adjoint step");

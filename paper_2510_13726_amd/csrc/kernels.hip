@@ -1111,24 +1111,28 @@ struct SweepArgs {
   CT fd_share;
 };
 
+// The velocity field of the finite-difference strain: the pre-collision
+// velocity of the cells of the listed tiles ([index][3][kBlock]).
+template <class CT>
+struct FdField {
+  const CT* fd_u;
+  const int32_t* near_index;
+};
+
 // Pre-collision velocity component a of cell (x, y, z) from the velocity
 // buffer of the listed tiles.
 template <class CT>
-__device__ __forceinline__ CT fd_velocity(const SweepArgs<CT>& s, int a, int x, int y, int z) {
-  const Geometry& g = s.g;
+__device__ __forceinline__ CT fd_velocity(const Geometry& g, const FdField<CT>& f, int a, int x, int y, int z) {
   const int64_t canon = (int64_t(z) * g.nty + y / kTileY) * g.ntx + x / kTileX;
-  const int32_t k = s.near_index[canon];
-  return s.fd_u[(int64_t(k) * 3 + a) * kBlock + (y % kTileY) * kTileX + (x % kTileX)];
+  const int32_t k = f.near_index[canon];
+  return f.fd_u[(int64_t(k) * 3 + a) * kBlock + (y % kTileY) * kTileX + (x % kTileX)];
 }
 
-// Central-difference strain S_ab = (d_a u_b + d_b u_a) / 2 of the
-// pre-collision velocity at (x, y, z), d_b u_a = (u_a(x + e_b) - u_a(x - e_b))
-// / 2; y, z periodic, x periodic or clamped to the first and last plane.
-// Order xx, yy, zz, xy, xz, yz.
-template <class CT, bool kPeriodicX>
-__device__ __forceinline__ void fd_strain(const SweepArgs<CT>& s, int x, int y, int z, CT S[6]) {
-  const Geometry& g = s.g;
-  int xm, xp;
+// Neighbours of the central differences: y, z periodic, x periodic or
+// clamped to the first and last plane.
+template <bool kPeriodicX>
+__device__ __forceinline__ void fd_stencil(const Geometry& g, int x, int y, int z, int& xm, int& xp, int& ym, int& yp,
+                                           int& zm, int& zp) {
   if (kPeriodicX) {
     xm = x == 0 ? g.nx - 1 : x - 1;
     xp = x + 1 == g.nx ? 0 : x + 1;
@@ -1136,14 +1140,25 @@ __device__ __forceinline__ void fd_strain(const SweepArgs<CT>& s, int x, int y, 
     xm = x == 0 ? 0 : x - 1;
     xp = x + 1 == g.nx ? x : x + 1;
   }
-  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
-  const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z + 1 == g.nz ? 0 : z + 1;
+  ym = y == 0 ? g.ny - 1 : y - 1;
+  yp = y + 1 == g.ny ? 0 : y + 1;
+  zm = z == 0 ? g.nz - 1 : z - 1;
+  zp = z + 1 == g.nz ? 0 : z + 1;
+}
+
+// Central-difference strain S_ab = (d_a u_b + d_b u_a) / 2 of the
+// pre-collision velocity at (x, y, z), d_b u_a = (u_a(x + e_b) - u_a(x - e_b))
+// / 2.  Order xx, yy, zz, xy, xz, yz.
+template <class CT, bool kPeriodicX>
+__device__ __forceinline__ void fd_strain(const Geometry& g, const FdField<CT>& f, int x, int y, int z, CT S[6]) {
+  int xm, xp, ym, yp, zm, zp;
+  fd_stencil<kPeriodicX>(g, x, y, z, xm, xp, ym, yp, zm, zp);
   CT d[3][3];  // d[a][b] = d_b u_a
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    d[a][0] = CT(0.5) * (fd_velocity(s, a, xp, y, z) - fd_velocity(s, a, xm, y, z));
-    d[a][1] = CT(0.5) * (fd_velocity(s, a, x, yp, z) - fd_velocity(s, a, x, ym, z));
-    d[a][2] = CT(0.5) * (fd_velocity(s, a, x, y, zp) - fd_velocity(s, a, x, y, zm));
+    d[a][0] = CT(0.5) * (fd_velocity(g, f, a, xp, y, z) - fd_velocity(g, f, a, xm, y, z));
+    d[a][1] = CT(0.5) * (fd_velocity(g, f, a, x, yp, z) - fd_velocity(g, f, a, x, ym, z));
+    d[a][2] = CT(0.5) * (fd_velocity(g, f, a, x, y, zp) - fd_velocity(g, f, a, x, y, zm));
   }
   S[0] = d[0][0];
   S[1] = d[1][1];
@@ -1233,7 +1248,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<CT>& a, uint32_t blk,
     // active wall cells take sigma = 1 - fd_share and the non-local strain
     if (!kMoments && a.fd_u && t != 0 && sigma == CT(1) && valid) {
       sigma = CT(1) - a.fd_share;
-      fd_strain<CT, kPeriodicX>(a, x, y, z, S);
+      fd_strain<CT, kPeriodicX>(g, FdField<CT>{a.fd_u, a.near_index}, x, y, z, S);
     }
     const CT hx = ux + d * (bx - ux), hy = uy + d * (by - uy), hz = uz + d * (bz - uz);
     if (kMoments) {
@@ -1709,6 +1724,12 @@ struct AdjArgs {
   int64_t nblocks;
   double* zero;             // zeroed by the workgroups past nblocks
   int64_t nzero;
+  // finite-difference strain of the step (nullable fd_u: off)
+  const CT* fd_u;
+  const int32_t* near_index;
+  CT fd_share;
+  const int32_t* tiles;     // the FSI tiles and their neighbours
+  int32_t* flag;
 };
 
 // Homogenization inputs of an FSI cell: porosity, b = u^B + u_wm, S, sigma.
@@ -1740,13 +1761,109 @@ __device__ __forceinline__ void fsi_inputs(const AdjArgs<CT>& a, const RotorTabl
   }
 }
 
+// Local part of a reverse step at cell (x, y, z) (index c): the moments of
+// the state and the collision VJP from the adjoint of the next state at the
+// cell (with the outflow share on the last plane), under the FSI inputs of
+// the forward step when the tile is an FSI tile.  Returns whether the cell
+// took the finite-difference strain (sigma = 1 - fd_share): the element
+// cells that are not active wall cells.
+template <class ST, class CT, bool kPeriodicX, int Q>
+__device__ __forceinline__ bool adj_local(const AdjArgs<CT>& a, int x, int y, int z, int64_t c, bool fsi,
+                                          Moments<CT>& mo, Moments<CT>& mb, CT& db, CT Sb[6]) {
+  const Geometry& g = a.g;
+  CT h[Q];
+  pull_row<ST, CT, kPeriodicX, Q>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
+  mo = moments_q<Q, CT>(h);
+  // lam in the blocked layout of the populations: this wave's block
+  constexpr uint32_t cs = sizeof(CT);
+  const uint64_t rs = uint64_t(g.row) * cs;
+  const uint32_t o4 = pop_x<Q>(x) * cs;
+  CT gb[Q];
+  {
+    typedef __attribute__((address_space(1))) const char* gcb;
+    gcb q = (gcb)a.lam_in + (uint64_t(z) * g.ny + y) * rs;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gb[i] = *(const CT*)(q + (o4 + uint32_t(i * kTileX) * cs));
+  }
+  if (!kPeriodicX && a.side_in && x == g.nx - 1) {
+    const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
+    for (int i = 0; i < xgroup_of<Q>(1); ++i) gb[i] += a.side_in[i * plane + k];
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) gb[i] *= CT(wq<Q>(i));
+  CT d = CT(0), b[3] = {CT(0), CT(0), CT(0)}, S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)}, sigma = CT(1);
+  CT pb[3] = {CT(0), CT(0), CT(0)};
+  bool fd = false;
+  if (fsi) {
+    const RotorTable& rt = *a.rot;
+    const uint8_t tb = a.tag[c];
+    fsi_inputs(a, rt, c, x, y, z, tb, d, b, S, sigma);
+    if (a.fd_u && (tb & kTagMask) != 0 && sigma == CT(1)) {
+      sigma = CT(1) - a.fd_share;
+      fd_strain<CT, kPeriodicX>(g, FdField<CT>{a.fd_u, a.near_index}, x, y, z, S);
+      fd = true;
+    }
+    objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
+  } else if (a.uB_static) {
+    b[0] = a.uB_static[c]; b[1] = a.uB_static[g.N + c]; b[2] = a.uB_static[2 * g.N + c];
+  }
+  CT bb[3];
+  collide_vjp<CT, Q>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
+  return fd;
+}
+
+// Velocity adjoints of the finite-difference strain, one workgroup per
+// listed tile (the FSI tiles and their neighbours; the neighbours exit).  At
+// a cell that took the strain, the collision VJP gives the adjoint of S;
+// S_ab = (d_a u_b + d_b u_a) / 2 with d_b u_a = (u_a(x + e_b) - u_a(x - e_b))
+// / 2 hands it to the pre-collision velocities of the six neighbours, summed
+// in fixed point with the probe-velocity adjoints; the adjoint sweep of the
+// step gathers them.
+template <class ST, class CT, bool kPeriodicX, int Q>
+__global__ __launch_bounds__(kBlock) void k_adj_fd(AdjArgs<CT> a) {
+  const Geometry& g = a.g;
+  const uint32_t canon = uint32_t(a.tiles[blockIdx.x]);
+  if (a.blk_slot[canon] < 0) return;
+  const uint32_t ntx = uint32_t(g.ntx), tpz = ntx * uint32_t(g.nty);
+  const int z = int(canon / tpz);
+  const uint32_t rem = canon - uint32_t(z) * tpz;
+  const int ty = int(rem / ntx), tx = int(rem - uint32_t(ty) * ntx);
+  const int xr = tx * kTileX + int(threadIdx.x & (kTileX - 1));
+  const int yr = __builtin_amdgcn_readfirstlane(ty * kTileY + int(threadIdx.x >> 6));
+  if (xr >= g.nx || yr >= g.ny) return;
+  const int x = xr, y = yr;
+  const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
+  if ((a.tag[c] & kTagMask) == 0) return;
+  Moments<CT> mo, mb;
+  CT db, Sb[6];
+  if (!adj_local<ST, CT, kPeriodicX, Q>(a, x, y, z, c, true, mo, mb, db, Sb)) return;
+  int xm, xp, ym, yp, zm, zp;
+  fd_stencil<kPeriodicX>(g, x, y, z, xm, xp, ym, yp, zm, zp);
+  const int64_t cp[3] = {(int64_t(z) * g.ny + y) * g.nx + xp, (int64_t(z) * g.ny + yp) * g.nx + x,
+                         (int64_t(zp) * g.ny + y) * g.nx + x};
+  const int64_t cm[3] = {(int64_t(z) * g.ny + y) * g.nx + xm, (int64_t(z) * g.ny + ym) * g.nx + x,
+                         (int64_t(zm) * g.ny + y) * g.nx + x};
+  // adjoint of d_b u_a: S_aa = d_a u_a, S_ab = (d_b u_a + d_a u_b) / 2
+  const double s0 = double(Sb[0]), s1 = double(Sb[1]), s2 = double(Sb[2]);
+  const double s3 = 0.5 * double(Sb[3]), s4 = 0.5 * double(Sb[4]), s5 = 0.5 * double(Sb[5]);
+  const double dbar[3][3] = {{s0, s3, s4}, {s3, s1, s5}, {s4, s5, s2}};
+  for (int q = 0; q < 3; ++q)
+    for (int e = 0; e < 3; ++e) {
+      const double v = 0.5 * dbar[q][e];
+      if (v == 0.0) continue;
+      fix_add(a.ubar, g.N, cp[e], q, v, a.flag);
+      fix_add(a.ubar, g.N, cm[e], q, -v, a.flag);
+    }
+}
+
 // Adjoint sweep over all cells: collision VJP from the local adjoint of the
-// next state, the probe-velocity adjoints gathered from the wall cells, and
-// the transpose of the pull (lam_out_i(x - c_i) = mu_i(x)).  Outflow: the
-// state at (nx-1, y', z') with c_x = -1 is read by (nx-2, .) and by the
-// clamped read of (nx-1, .); the second share goes to `side`, and the reader
-// of lam (this sweep of the previous step, and the adjoint wall step) adds
-// it on the last plane.  Workgroups past nblocks zero `zero`.
+// next state, the probe-velocity adjoints gathered from the wall cells (and
+// from the finite-difference strain), and the transpose of the pull
+// (lam_out_i(x - c_i) = mu_i(x)).  Outflow: the state at (nx-1, y', z') with
+// c_x = -1 is read by (nx-2, .) and by the clamped read of (nx-1, .); the
+// second share goes to `side`, and the reader of lam (this sweep of the
+// previous step, and the adjoint wall step) adds it on the last plane.
+// Workgroups past nblocks zero `zero`.
 template <class ST, class CT, bool kPeriodicX, int Q = 27>
 __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   const Geometry& g = a.g;
@@ -1764,30 +1881,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
   if (xr >= g.nx || yr >= g.ny) return;
   const int x = xr, y = yr;
   const int64_t c = (int64_t(z) * g.ny + y) * g.nx + x;
-  CT h[Q];
-  pull_row<ST, CT, kPeriodicX, Q>(static_cast<const ST*>(a.src), g, x, y, z, a.ghost, h);
-  const Moments<CT> mo = moments_q<Q, CT>(h);
-  // lam in the blocked layout of the populations: this wave's block, and the
-  // nine rows the transposed pull writes into
-  constexpr uint32_t cs = sizeof(CT);
-  const uint64_t rs = uint64_t(g.row) * cs;
-  const uint32_t o4 = pop_x<Q>(x) * cs;
-  CT gb[Q];
-  {
-    typedef __attribute__((address_space(1))) const char* gcb;
-    gcb q = (gcb)a.lam_in + (uint64_t(z) * g.ny + y) * rs;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) gb[i] = *(const CT*)(q + (o4 + uint32_t(i * kTileX) * cs));
-  }
-  if (!kPeriodicX && a.side_in && x == g.nx - 1) {
-    const int64_t k = int64_t(z) * g.ny + y, plane = int64_t(g.ny) * g.nz;
-    for (int i = 0; i < xgroup_of<Q>(1); ++i) gb[i] += a.side_in[i * plane + k];
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) gb[i] *= CT(wq<Q>(i));
-  const RotorTable& rt = *a.rot;
-  CT d = CT(0), b[3] = {CT(0), CT(0), CT(0)}, S[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)}, sigma = CT(1);
-  CT pb[3] = {CT(0), CT(0), CT(0)};
   double ub[3] = {0.0, 0.0, 0.0};
   const int32_t slot = a.blk_slot[ti.canon];
   const bool fsi = slot >= 0, gather = slot != -1;
@@ -1796,18 +1889,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
       ub[q] = fix_take(a.ubar, g.N, c, q);
     }
   }
-  if (fsi) {
-    const uint8_t tb = a.tag[c];
-    fsi_inputs(a, rt, c, x, y, z, tb, d, b, S, sigma);
-    objective_dp<CT>(rt, tb & kTagMask, a.obj_tag, a.obj_w, x, y, z, pb);
-  } else if (a.uB_static) {
-    b[0] = a.uB_static[c]; b[1] = a.uB_static[g.N + c]; b[2] = a.uB_static[2 * g.N + c];
-  }
-  Moments<CT> mb;
-  CT db, bb[3], Sb[6];
-  collide_vjp<CT, Q>(mo, d, b[0], b[1], b[2], sigma, S, CT(a.m.tau0), CT(a.m.smag), gb, pb, mb, db, bb, Sb);
+  Moments<CT> mo, mb;
+  CT db, Sb[6];
+  (void)adj_local<ST, CT, kPeriodicX, Q>(a, x, y, z, c, fsi, mo, mb, db, Sb);
   if (gather) {
-    // probe velocity u = j / rho at this cell, sampled by wall cells
+    // velocity u = j / rho at this cell, sampled by wall-cell probes and
+    // by the finite-difference strain of its neighbours
     const CT rho = CT(1) + mo.drho, irho = rcp_ct(rho);
     const CT ju = CT(ub[0]) * mo.jx + CT(ub[1]) * mo.jy + CT(ub[2]) * mo.jz;
     mb.drho -= ju * irho * irho;
@@ -1815,6 +1902,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs<CT> a) {
     mb.jy += CT(ub[1]) * irho;
     mb.jz += CT(ub[2]) * irho;
   }
+  constexpr uint32_t cs = sizeof(CT);
+  const uint64_t rs = uint64_t(g.row) * cs;
   a.G[c] += double(db);
   // transpose of the pull: the state read by f_i(x) is at x - c_i
   const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
@@ -2146,7 +2235,31 @@ static AdjArgs<CT> adj_args(const Launch& L, const AdjLaunch& A) {
   a.uB_static = (const CT*)L.uB_static; a.ghost = (const CT*)L.ghost; a.ubar = A.ubar; a.G = A.G;
   a.obj_w = A.obj_w; a.obj_tag = A.obj_tag; a.nblocks = L.nblocks;
   a.zero = A.zero; a.nzero = A.zero ? A.nzero : 0;
+  if (L.m.fd_share > 0.0 && L.fd_u) {
+    a.fd_u = (const CT*)L.fd_u;
+    a.near_index = L.near_index;
+    a.fd_share = CT(L.m.fd_share);
+  }
+  a.tiles = L.fsi_tiles;
+  a.flag = L.flag;
   return a;
+}
+
+hipError_t launch_adjoint_fd(const Launch& L, const AdjLaunch& A) {
+  if (!(L.m.fd_share > 0.0) || !L.fd_u || L.nnear <= 0) return hipSuccess;
+  return by_types(L.storage, L.compute, [&](auto* st, auto* ct) {
+    using ST = std::remove_pointer_t<decltype(st)>;
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    AdjArgs<CT> a = adj_args<CT>(L, A);
+    return by_q(L.q, [&](auto QC) {
+      constexpr int Q = QC.value;
+      if (L.g.bc_x == 0)
+        hipLaunchKernelGGL((k_adj_fd<ST, CT, true, Q>), dim3(unsigned(L.nnear)), dim3(kBlock), 0, L.stream, a);
+      else
+        hipLaunchKernelGGL((k_adj_fd<ST, CT, false, Q>), dim3(unsigned(L.nnear)), dim3(kBlock), 0, L.stream, a);
+      return hipGetLastError();
+    });
+  });
 }
 
 hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A) {

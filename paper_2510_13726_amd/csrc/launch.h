@@ -144,7 +144,10 @@ struct AdjLaunch {
   double* zero;             // zeroed by the adjoint sweep (nullable), nzero doubles
   int64_t nzero;
 };
-// The adjoint wall step runs inside launch_wall (adj); then this sweep.
+// The adjoint wall step runs inside launch_wall (adj); with fd_share > 0,
+// the velocity adjoints of the finite-difference strain (launch_adjoint_fd,
+// after launch_fd_velocity of the step's state); then this sweep.
+hipError_t launch_adjoint_fd(const Launch& L, const AdjLaunch& A);
 hipError_t launch_adjoint_sweep(const Launch& L, const AdjLaunch& A);
 hipError_t launch_refill_porosity(const Launch& L);
 // Plain streaming copy (bytes a multiple of 16, 16-byte aligned pointers).

@@ -64,12 +64,3 @@ def test_fd_strain_periodic_two_rotors_d3q19():
     print(f"[fd] periodic d3q19: h {e:.3e} F {eF:.3e} T {eT:.3e}", flush=True)
     assert e < 1e-12 and eF < 1e-12 and eT < 1e-12
 
-
-def test_fd_strain_excludes_the_adjoint():
-    hl = _hl()
-    w = W.small_rotor(nx=24, ny=20, nz=20, R=6.0, chord=3.0, hub=1.5, tau0=0.52)
-    w.params.fd_share = 0.5
-    lat = hl.setup(w, storage="f64", flags=hl.WITH_ADJOINT)
-    with pytest.raises(hl.HlbmError) as e:
-        lat.forward_record(4, 1, 4, 0, 2)
-    assert e.value.code == hl.HLBM_ERR_STATE
