@@ -368,8 +368,8 @@ int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* 
  * plain workgroups (host, syncs). */
 int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells);
 /* A plain streaming copy of `bytes` bytes from src to dst (device, 16-byte
- * aligned, bytes a multiple of 16, not overlapping), 16 B per lane with
- * non-temporal stores, enqueued on `stream` (hipStream_t, NULL = the null
+ * aligned, bytes a multiple of 16, not overlapping), one 16 B element per
+ * thread with non-temporal loads and stores, enqueued on `stream` (hipStream_t, NULL = the null
  * stream): the reference of the streaming bandwidth the sweep is measured
  * against in benchmarks.  HLBM_ERR_INVALID for a misaligned or negative
  * size; asynchronous. */

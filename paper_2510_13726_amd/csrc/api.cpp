@@ -192,6 +192,25 @@ uint32_t tile_band(const hlbm_desc* d, int32_t nty) {
   return ntx * nty > 1024 ? uint32_t(std::min<int32_t>(8, nty)) : uint32_t(nty);
 }
 
+// Dynamic LDS of a sweep workgroup, which caps the workgroups resident on a
+// CU (160 KB of LDS each; the sweep itself holds under 4 KB).  Without a
+// cap, the FP32 sweep runs five per CU (its registers allow five waves per
+// SIMD).  On lattices of more than 2^18 tiles fewer stream faster, measured
+// against no cap on the same allocation (the time differs between
+// allocations by more than the gain): D3Q27 with three per CU by 0.6-1.6 %
+// on six allocations at 1536x768x256 and by 2 % at 1024x512x384; D3Q19 with
+// four per CU by 0.4-1.5 % on four allocations.  At 256x128x128 the cap
+// gains nothing, and FP16 and BF16 storage, closer to the ALU bound, slow
+// down with any cap.  HLBM_SWEEP_WG_PER_CU = 3 or 4 sets the cap, 0 removes
+// it (measurement runs).
+uint32_t sweep_lds(const hlbm_desc* d, int64_t tiles) {
+  int cap = 0;
+  if (d->storage == HLBM_F32 && tiles > (int64_t(1) << 18)) cap = vel_of(d) == 19 ? 4 : 3;
+  if (const char* e = std::getenv("HLBM_SWEEP_WG_PER_CU")) cap = int(std::strtol(e, nullptr, 10));
+  if (cap != 3 && cap != 4) return 0;
+  return uint32_t(163840 / cap - 4096);
+}
+
 void set_tile_band(Geometry* g, uint32_t band) {
   const uint32_t ntx = uint32_t(g->ntx), nz = uint32_t(g->nz), nty = uint32_t(g->nty);
   g->band = band;
@@ -670,6 +689,7 @@ int hlbm_lattice_create(const hlbm_desc* d, void* pop_a, void* pop_b, void* ws, 
   L.nblocks = int64_t(L.g.ntx) * L.g.nty * d->nz;
   L.g.by_ntx = make_udiv(uint32_t(L.g.ntx));
   set_tile_band(&L.g, tile_band(d, L.g.nty));
+  L.sweep_lds = sweep_lds(d, int64_t(L.g.ntx) * L.g.nty * L.g.nz);
   L.g.by_span = make_udiv(8u * uint32_t(L.g.ntx));
   L.g.grouped = uint32_t(L.nblocks / (8 * int64_t(L.g.ntx)) * (8 * int64_t(L.g.ntx)));
   const Layout& Y = h->lay;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 #include <utility>
@@ -2123,10 +2124,11 @@ hipError_t launch_sweep(const Launch& L, const void* src, void* dst, int64_t ste
     return by_q(L.q, [&](auto QC) {
       constexpr int Q = QC.value;
       if (L.g.bc_x == 0)
-        hipLaunchKernelGGL((k_sweep<ST, CT, true, false, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream, a);
+        hipLaunchKernelGGL((k_sweep<ST, CT, true, false, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), L.sweep_lds,
+                           L.stream, a);
       else
-        hipLaunchKernelGGL((k_sweep<ST, CT, false, false, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), 0, L.stream,
-                           a);
+        hipLaunchKernelGGL((k_sweep<ST, CT, false, false, Q>), dim3(unsigned(L.nblocks)), dim3(kBlock), L.sweep_lds,
+                           L.stream, a);
       return hipGetLastError();
     });
   });
@@ -2374,31 +2376,28 @@ hipError_t launch_couple(const Launch& L, int64_t rec, int64_t m) {
   return hipGetLastError();
 }
 
-// Plain streaming copy, 16 B per lane, four per thread, non-temporal stores.
+// Plain streaming copy: one 16 B element per thread, non-temporal loads and
+// stores.  This is the fastest copy form measured here (32.6 GB buffers:
+// 82 % of 8 TB/s, against 78 % with plain loads and stores and 70 % with
+// four elements per thread).  Launched in chunks of 2^30 elements.
 typedef float float4v __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_stream_copy(const float4v* __restrict__ src, float4v* __restrict__ dst,
                                                      int64_t n16) {
-  const int64_t i0 = int64_t(blockIdx.x) * 1024 + threadIdx.x;
-  float4v v[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int64_t i = i0 + k * 256;
-    if (i < n16) v[k] = src[i];
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int64_t i = i0 + k * 256;
-    if (i < n16) __builtin_nontemporal_store(v[k], dst + i);
-  }
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t stream) {
+  constexpr int64_t kChunk = int64_t(1) << 30;
   const int64_t n16 = bytes / 16;
-  if (n16 == 0) return hipSuccess;
-  const int64_t grid = (n16 + 1023) / 1024;
-  hipLaunchKernelGGL(k_stream_copy, dim3(unsigned(grid)), dim3(256), 0, stream, (const float4v*)src, (float4v*)dst,
-                     n16);
-  return hipGetLastError();
+  for (int64_t o = 0; o < n16; o += kChunk) {
+    const int64_t m = std::min(kChunk, n16 - o);
+    hipLaunchKernelGGL(k_stream_copy, dim3(unsigned((m + 255) / 256)), dim3(256), 0, stream,
+                       static_cast<const float4v*>(src) + o, static_cast<float4v*>(dst) + o, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_fill_rest(const Launch& L, void* dst) {

@@ -16,6 +16,7 @@ struct Launch {
   Geometry g;
   Model m;
   int64_t nblocks;           // sweep workgroups = ntx * nty * nz
+  uint32_t sweep_lds;        // dynamic LDS of a sweep workgroup: caps the resident workgroups per CU
   BladeTrig* trig_tab;       // blade angles of kTrigSteps consecutive steps
   RotorDyn* dyn;             // coupled rotation state (nullable)
   // growth layer of the rotor geometry: marks [2][bbox_total] by step
