@@ -303,6 +303,26 @@ double oracle_rotor_phi(const or_rotor* r, const double* x, int64_t n, double* g
   return rotor_phi(ro, F, x, n, grad);
 }
 double oracle_transition(double phi, double eps, int kind) { return transition_s(phi, eps, kind); }
+int oracle_set_rotor_grid(void* h, int k, const double* phi, int n0, int n1, int n2, double spacing,
+                          const double* origin) {
+  if (k < 0 || k >= 8) return 1;
+  if (phi && (n0 < 2 || n1 < 2 || n2 < 2 || !(spacing > 0) || !origin)) return 1;
+  const int n[3] = {n0, n1, n2};
+  ((SimD*)h)->set_grid(k, phi, n, spacing, origin);
+  return 0;
+}
+// Distance and gradient of a reference-grid body of rotor r at angle theta.
+double oracle_grid_rotor_phi(const or_rotor* r, const double* phi, int n0, int n1, int n2, double spacing,
+                             const double* origin, const double* x, double theta, double* grad) {
+  RefGrid G;
+  G.phi.assign(phi, phi + (size_t)n0 * n1 * n2);
+  G.n[0] = n0; G.n[1] = n1; G.n[2] = n2;
+  G.h = spacing;
+  for (int a = 0; a < 3; ++a) G.o[a] = origin[a];
+  Rotor ro = to_rotor(r);
+  ro.grid = &G;
+  return rotor_phi_at(ro, rotor_frame(ro), x, theta, grad);
+}
 double oracle_gaussian(uint64_t seed, int64_t n, int y, int z, int comp, int ny, int nz) {
   return inflow_gaussian(seed, n, y, z, comp, ny, nz);
 }

@@ -136,12 +136,25 @@ struct Params {
   double fd_share;    // 1 - sigma in an element's cells off the wall (hybrid f~(1)); 0: sigma = 1
 };
 
+// Reference grid of a moving element (Sec. 3.1: the element is voxelized
+// once in its own inertial reference grid, and that grid is embedded into
+// the lattice porosity at the element's position and orientation each
+// step): the signed distance phi (positive inside) at body coordinates
+// o + h (i, j, k), stored [k][j][i], body axes the radial direction of blade
+// 0, the tangential direction e x e_r and the rotor axis e.
+struct RefGrid {
+  std::vector<double> phi;
+  int n[3];
+  double h, o[3];
+};
+
 struct Rotor {
   double center[3], axis[3];
   double R, r_hub, chord, thick, twist_root, twist_tip, omega, phase0;
   int n_blades, tag;
   double inertia;     // moment of inertia about the axis; 0: prescribed rotation
   double torque_gen;  // opposing (generator) torque of a coupled rotor
+  const RefGrid* grid = nullptr;  // replaces the flat-plate blades and hub when set
 };
 
 // ------------------------------------------------------------ equilibrium
@@ -416,8 +429,53 @@ inline double rotor_phi(const Rotor& r, const Frame& F, const double x[3], int64
   return rotor_phi_at(r, F, x, r.phase0 + r.omega * double(n), grad);
 }
 
+// The body of a reference grid at rotor angle theta: the point's body
+// coordinates p (projections on blade 0's radial and tangential directions
+// and on the axis), grid coordinates u = (p - o) / h, and the trilinear
+// interpolant of the eight surrounding samples; its gradient is that of the
+// interpolant, taken back to the lattice frame.  A point outside the grid
+// is not in the body (phi = -1e300, gradient zero).
+inline double grid_phi_at(const RefGrid& G, const Frame& F, const double rel[3], double theta, double grad[3]) {
+  for (int a = 0; a < 3; ++a) grad[a] = 0.0;
+  const double ct = std::cos(theta), st = std::sin(theta);
+  double axes[3][3];
+  for (int a = 0; a < 3; ++a) {
+    axes[0][a] = ct * F.e1[a] + st * F.e2[a];
+    axes[1][a] = -st * F.e1[a] + ct * F.e2[a];
+    axes[2][a] = F.e[a];
+  }
+  int i0[3];
+  double f[3];
+  for (int k = 0; k < 3; ++k) {
+    const double p = rel[0] * axes[k][0] + rel[1] * axes[k][1] + rel[2] * axes[k][2];
+    const double u = (p - G.o[k]) / G.h;
+    if (!(u >= 0.0 && u <= double(G.n[k] - 1))) return -1e300;
+    int i = int(std::floor(u));
+    if (i > G.n[k] - 2) i = G.n[k] - 2;
+    i0[k] = i;
+    f[k] = u - double(i);
+  }
+  double phi = 0.0, du[3] = {0.0, 0.0, 0.0};
+  for (int corner = 0; corner < 8; ++corner) {
+    const int b[3] = {corner & 1, (corner >> 1) & 1, (corner >> 2) & 1};
+    const double v = G.phi[((size_t)(i0[2] + b[2]) * G.n[1] + (i0[1] + b[1])) * G.n[0] + (i0[0] + b[0])];
+    double w[3], dw[3];
+    for (int k = 0; k < 3; ++k) {
+      w[k] = b[k] ? f[k] : 1.0 - f[k];
+      dw[k] = b[k] ? 1.0 : -1.0;
+    }
+    phi += w[0] * w[1] * w[2] * v;
+    du[0] += dw[0] * w[1] * w[2] * v;
+    du[1] += w[0] * dw[1] * w[2] * v;
+    du[2] += w[0] * w[1] * dw[2] * v;
+  }
+  for (int a = 0; a < 3; ++a) grad[a] = (du[0] * axes[0][a] + du[1] * axes[1][a] + du[2] * axes[2][a]) / G.h;
+  return phi;
+}
+
 inline double rotor_phi_at(const Rotor& r, const Frame& F, const double x[3], double theta, double grad[3]) {
   double rel[3] = {x[0] - r.center[0], x[1] - r.center[1], x[2] - r.center[2]};
+  if (r.grid) return grid_phi_at(*r.grid, F, rel, theta, grad);
   double dist = std::sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
   // hub sphere
   double best = r.r_hub - dist;

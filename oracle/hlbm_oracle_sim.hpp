@@ -52,6 +52,7 @@ struct Sim {
   int64_t N = 0;
   Params p{};
   std::vector<Rotor> rotors;
+  std::vector<RefGrid> grids = std::vector<RefGrid>(8);  // reference grid per rotor index (empty: none)
   std::vector<Frame> frames;
   // rotation of each rotor: angle and angular velocity of the current step
   // (prescribed: phase0 + omega n and omega; coupled: the rigid-body state)
@@ -106,8 +107,22 @@ struct Sim {
   int64_t idx(int x, int y, int z) const { return ((int64_t)z * ny + y) * nx + x; }
   static int wrap(int a, int n) { a %= n; return a < 0 ? a + n : a; }
 
+  // Reference grid of rotor index k (copied); an empty phi removes it.
+  void set_grid(int k, const double* phi, const int n[3], double h, const double o[3]) {
+    RefGrid& G = grids[k];
+    G.phi.clear();
+    if (phi) {
+      G.phi.assign(phi, phi + (size_t)n[0] * n[1] * n[2]);
+      for (int a = 0; a < 3; ++a) { G.n[a] = n[a]; G.o[a] = o[a]; }
+      G.h = h;
+    }
+    if ((size_t)k < rotors.size()) rotors[k].grid = G.phi.empty() ? nullptr : &G;
+  }
+
   void set_rotors(const Rotor* r, int n) {
     rotors.assign(r, r + n);
+    for (size_t k = 0; k < rotors.size() && k < grids.size(); ++k)
+      rotors[k].grid = grids[k].phi.empty() ? nullptr : &grids[k];
     reset_rotation();
     frames.clear();
     for (auto& ro : rotors) {

@@ -102,6 +102,11 @@ def lib():
                                        C.POINTER(C.c_int)]
         L.oracle_rotor_phi.restype = C.c_double
         L.oracle_rotor_phi.argtypes = [C.POINTER(OrRotor), _D, C.c_int64, _D]
+        L.oracle_set_rotor_grid.restype = C.c_int
+        L.oracle_set_rotor_grid.argtypes = [C.c_void_p, C.c_int, _D, C.c_int, C.c_int, C.c_int, C.c_double, _D]
+        L.oracle_grid_rotor_phi.restype = C.c_double
+        L.oracle_grid_rotor_phi.argtypes = [C.POINTER(OrRotor), _D, C.c_int, C.c_int, C.c_int, C.c_double, _D, _D,
+                                            C.c_double, _D]
         L.oracle_transition.restype = C.c_double
         L.oracle_transition.argtypes = [C.c_double, C.c_double, C.c_int]
         L.oracle_gaussian.restype = C.c_double
@@ -182,6 +187,18 @@ class OracleLattice:
         arr = (OrRotor * max(1, len(rotors)))(*[make_rotor(r) for r in rotors])
         if self.L.oracle_set_rotors(self.h, arr, len(rotors)):
             raise ValueError("invalid rotor")
+
+    def set_rotor_grid(self, k, grid):
+        """Reference grid (workloads.RefGrid, or None to remove) of rotor index k."""
+        if grid is None:
+            rc = self.L.oracle_set_rotor_grid(self.h, int(k), None, 0, 0, 0, 0.0, None)
+        else:
+            phi = _f64(grid.phi)
+            n2, n1, n0 = phi.shape
+            o = _f64(np.asarray(grid.origin, dtype=np.float64))
+            rc = self.L.oracle_set_rotor_grid(self.h, int(k), _p(phi), n0, n1, n2, float(grid.spacing), _p(o))
+        if rc:
+            raise ValueError("invalid reference grid")
 
     def set_porosity_field(self, d, tag):
         d = _f64(d)
@@ -333,6 +350,9 @@ def setup(w, threads=None) -> OracleLattice:
     o.set_params(w.params)
     o.set_force_mode(getattr(w.params, "force_mode", 0))
     o.set_rotors(w.rotors)
+    for k, r in enumerate(w.rotors):
+        if getattr(r, "grid", None) is not None:
+            o.set_rotor_grid(k, r.grid)
     d, tag = W.static_porosity(w)
     if d is not None:
         o.set_porosity_field(d, tag)
@@ -399,6 +419,19 @@ def rotor_phi(rotor, x, n=0):
     g = np.empty(3)
     phi = lib().oracle_rotor_phi(C.byref(r), _p(x), int(n), _p(g))
     return phi, g
+
+
+def grid_rotor_phi(rotor, grid, x, theta):
+    """Distance and gradient of the reference-grid body of `rotor` at angle theta."""
+    r = make_rotor(rotor)
+    phi = _f64(grid.phi)
+    n2, n1, n0 = phi.shape
+    o = _f64(np.asarray(grid.origin, dtype=np.float64))
+    x = _f64(np.asarray(x, dtype=np.float64))
+    g = np.empty(3)
+    v = lib().oracle_grid_rotor_phi(C.byref(r), _p(phi), n0, n1, n2, float(grid.spacing), _p(o), _p(x),
+                                    float(theta), _p(g))
+    return v, g
 
 
 def trilinear(q, shape, bc_x, X):

@@ -46,6 +46,17 @@ class Params:
 
 
 @dataclasses.dataclass
+class RefGrid:
+    """A moving element on its own reference grid: signed distance phi
+    (positive inside), shape (n2, n1, n0), at body coordinates
+    origin + spacing (i0, i1, i2); body axes the radial direction of blade 0,
+    the tangential direction (axis x radial) and the rotor axis."""
+    phi: np.ndarray
+    spacing: float
+    origin: Tuple[float, float, float]
+
+
+@dataclasses.dataclass
 class Rotor:
     center: Tuple[float, float, float]
     axis: Tuple[float, float, float] = (1.0, 0.0, 0.0)
@@ -61,6 +72,7 @@ class Rotor:
     tag: int = 1
     inertia: float = 0.0        # > 0: rotation driven by the fluid torque (two-way coupling)
     torque_gen: float = 0.0     # opposing generator torque of a coupled rotor
+    grid: Optional[RefGrid] = None  # reference-grid body replacing the flat-plate blades and hub
 
 
 @dataclasses.dataclass
@@ -83,6 +95,38 @@ class Workload:
     @property
     def cells(self) -> int:
         return self.nx * self.ny * self.nz
+
+
+def capsule_rotor_grid(r: Rotor, spacing: float = 0.5, eps_h: float = 2.0) -> RefGrid:
+    """A synthetic element on a reference grid of `spacing` lattice units
+    (the paper resolves its reference grid at twice the lattice resolution,
+    Sec. 3.1), standing in for the voxelized STL rotor: a hub sphere of
+    radius r_hub and n_blades capsule blades of radius thick/2 whose axes
+    run from r_hub/2 to R - thick/2 along each blade's radial direction,
+    tilted axially by +-chord/4 from root to tip.  The body lies within the
+    flat-plate rotor's envelope (radius R, axial half extent
+    max(sqrt((chord/2)^2 + (thick/2)^2), r_hub)); the grid reaches
+    eps_h/2 + 2 cells beyond it."""
+    rad = 0.5 * r.thick
+    tilt = 0.25 * r.chord
+    ha = max(math.sqrt(0.25 * r.chord ** 2 + 0.25 * r.thick ** 2), r.r_hub)
+    m = 0.5 * eps_h + 2.0
+    lo = np.array([-(r.R + m), -(r.R + m), -(ha + m)])
+    n = [int(math.ceil(-2.0 * lo[k] / spacing)) + 1 for k in range(3)]
+    ax = [lo[k] + spacing * np.arange(n[k]) for k in range(3)]
+    p2, p1, p0 = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    P = np.stack([p0, p1, p2], axis=-1)
+    phi = r.r_hub - np.linalg.norm(P, axis=-1)
+    for b in range(max(r.n_blades, 1)):
+        a = 2.0 * math.pi * b / max(r.n_blades, 1)
+        d = np.array([math.cos(a), math.sin(a), 0.0])
+        A = 0.5 * r.r_hub * d + np.array([0.0, 0.0, -tilt])
+        B = (r.R - rad) * d + np.array([0.0, 0.0, tilt])
+        AB = B - A
+        t = np.clip(((P - A) @ AB) / (AB @ AB), 0.0, 1.0)
+        dist = np.linalg.norm(P - (A + t[..., None] * AB), axis=-1)
+        phi = np.maximum(phi, rad - dist)
+    return RefGrid(phi=np.ascontiguousarray(phi), spacing=spacing, origin=(float(lo[0]), float(lo[1]), float(lo[2])))
 
 
 # ----------------------------------------------------------------- configs
