@@ -186,6 +186,31 @@ int hlbm_set_params(hlbm_handle h, const hlbm_params* p);
  * domain and within desc->bbox_cells.  n = 0 removes all rotors. */
 int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* rotors, int32_t n);
 
+/* Reference grid of rotor index `rotor` (Sec. 3.1: a moving element is
+ * voxelized once on its own reference grid, which is embedded into the
+ * lattice porosity at the element's position and orientation every step).
+ * The grid replaces that rotor's flat-plate blades and hub sphere; its
+ * axis, center, rotation, tag and the other rotor fields keep their meaning.
+ * phi: device FP64 array [n2][n1][n0] (borrowed until replaced, removed or
+ * the handle is destroyed), the signed distance (positive inside) at body
+ * coordinates origin + spacing (i0, i1, i2).  Body axes: 0 the radial
+ * direction of blade 0, cos(theta) e1 + sin(theta) e2 at rotor angle theta
+ * (e1 the unit projection of x onto the plane normal to the axis, of y when
+ * |axis_x| >= 0.9, e2 = axis x e1); 1 the tangential direction axis x
+ * (axis 0); 2 the axis.  Each step the geometry samples phi trilinearly at
+ * the body coordinates of the box cells and takes the wall normal from the
+ * gradient of that interpolant; a cell off the grid is not in the body.
+ * The solid (phi >= 0) must lie within the rotor's envelope (radius
+ * sqrt(R^2 + (chord/2)^2 + (thick/2)^2) about the axis, axial half extent
+ * max(sqrt((chord/2)^2 + (thick/2)^2), r_hub)), which sizes its box, and the
+ * grid must reach eps_h/2 + 1 beyond the solid.  n0, n1, n2 >= 2, spacing >
+ * 0, the rotor needs n_blades >= 1 (blade 0 orients the body).  phi = NULL
+ * removes the grid.  The grid stays with the rotor index across
+ * hlbm_set_rotors calls; when the index holds a rotor, this call re-applies
+ * the rotors as hlbm_set_rotors does.  HLBM_ERR_INVALID for bad arguments. */
+int hlbm_set_rotor_grid(hlbm_handle h, int32_t rotor, const double* phi, int32_t n0, int32_t n1, int32_t n2,
+                        double spacing, const double* origin);
+
 /* Static porosity field: the lattice porosity d of Def. Lattice Porosity
  * (Sec. 2.2.2) entering eq. convexVelocity, device, compute type, N values,
  * 0 <= d <= 1 (1 solid, 0 fluid), and the tag of the solid element each cell

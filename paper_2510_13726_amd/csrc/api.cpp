@@ -249,6 +249,12 @@ struct hlbm_lattice {
   int acur = 0;
   RotorTable rot{};
   std::vector<hlbm_rotor> rotors;
+  // reference grids by rotor index (caller memory)
+  struct GridRef {
+    const double* phi = nullptr;
+    int32_t n[3] = {0, 0, 0};
+    double h = 0.0, o[3] = {0.0, 0.0, 0.0};
+  } grids[kMaxRotors];
   hlbm_params params{};
   bool have_params = false;
   int32_t nslots = 0;
@@ -594,6 +600,13 @@ int build_rotor_table(hlbm_handle h, const hlbm_rotor* r, int32_t n, RotorTable*
     d.tw_root = q.twist_root; d.tw_tip = q.twist_tip; d.omega = q.omega; d.phase0 = q.phase0;
     d.nb = q.n_blades; d.tag = q.tag;
     d.inertia = q.inertia; d.tgen = q.torque_gen;
+    const auto& G = h->grids[k];
+    if (G.phi && q.n_blades < 1)
+      return fail(h, HLBM_ERR_INVALID, "a rotor with a reference grid needs n_blades >= 1 (blade 0 orients it)");
+    d.grid = G.phi;
+    for (int a = 0; a < 3; ++a) { d.gn[a] = G.n[a]; d.go[a] = G.o[a]; }
+    d.gpad = 0;
+    d.gh = G.h;
     for (int a = 0; a < 3; ++a) { d.b0[a] = box.b0[a]; d.bn[a] = box.bn[a]; }
     // FSI workgroups also cover the wall model's probe corners (reach y_s + 1
     // beyond the box; periodic in y and z), where the adjoint gathers the
@@ -899,6 +912,34 @@ int hlbm_set_rotors(hlbm_handle h, const hlbm_rotor* r, int32_t n) {
   h->rec.valid = false;
   if ((rc = upload_rotors(h)) != HLBM_OK) return rc;
   return rebuild_slots(h);
+}
+
+int hlbm_set_rotor_grid(hlbm_handle h, int32_t rotor, const double* phi, int32_t n0, int32_t n1, int32_t n2,
+                        double spacing, const double* origin) {
+  if (!h) return HLBM_ERR_INVALID;
+  if (rotor < 0 || rotor >= HLBM_MAX_ROTORS) return fail(h, HLBM_ERR_INVALID, "rotor index out of range");
+  hlbm_lattice::GridRef G;
+  if (phi) {
+    if (n0 < 2 || n1 < 2 || n2 < 2 || int64_t(n0) * n1 * n2 > (int64_t(1) << 31))
+      return fail(h, HLBM_ERR_INVALID, "reference grid needs 2 <= n0, n1, n2 and fewer than 2^31 samples");
+    if (!(spacing > 0.0) || !std::isfinite(spacing) || !origin)
+      return fail(h, HLBM_ERR_INVALID, "reference grid needs spacing > 0 and an origin");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(origin[a])) return fail(h, HLBM_ERR_INVALID, "reference grid origin not finite");
+    G.phi = phi;
+    G.n[0] = n0; G.n[1] = n1; G.n[2] = n2;
+    G.h = spacing;
+    for (int a = 0; a < 3; ++a) G.o[a] = origin[a];
+  }
+  const hlbm_lattice::GridRef old = h->grids[rotor];
+  h->grids[rotor] = G;
+  if (rotor < int32_t(h->rotors.size())) {
+    const std::vector<hlbm_rotor> r = h->rotors;
+    const int rc = hlbm_set_rotors(h, r.data(), int32_t(r.size()));
+    if (rc != HLBM_OK) h->grids[rotor] = old;
+    return rc;
+  }
+  return HLBM_OK;
 }
 
 int hlbm_set_porosity_field(hlbm_handle h, const void* d, const uint8_t* tag) {

@@ -35,6 +35,11 @@ struct RotorDev {
   int64_t off;            // first slot of this box in the box pools
   int64_t cells;          // bn[0]*bn[1]*bn[2]
   double inertia, tgen;   // coupled rotation (inertia > 0) and its generator torque
+  // reference grid of the body (nullable): signed distance [gn2][gn1][gn0]
+  // at body coordinates go + gh (i0, i1, i2)
+  const double* grid;
+  int32_t gn[3], gpad;
+  double gh, go[3];
 };
 
 struct RotorTable {

@@ -260,10 +260,94 @@ __device__ __forceinline__ void blade_box(const RotorDev& r, BladeFrame& f, bool
   f.p[2] = f.cb * f.ax + f.sb * f.qq;
 }
 
+// Reference-grid body (Sec. 3.1: the element voxelized once on its own
+// grid, embedded at its current position and orientation every step).  The
+// body frame turns with blade 0: e_r = cos(theta) e1 + sin(theta) e2, e_t =
+// e x e_r, and the axis e.  A point's body coordinates, divided into grid
+// units, give its cell (the last cell for a point on the far face) and the
+// fractions inside it; a point off the grid is not in the body.
+struct GridCell {
+  const double* v;  // sample of the cell's lowest corner
+  double f[3];
+  double ax[3][3];  // e_r, e_t, e
+};
+__device__ __forceinline__ bool grid_cell(const RotorDev& r, double ct, double st, const double rel[3], GridCell& s) {
+  for (int a = 0; a < 3; ++a) {
+    s.ax[0][a] = ct * r.e1[a] + st * r.e2[a];
+    s.ax[1][a] = -st * r.e1[a] + ct * r.e2[a];
+    s.ax[2][a] = r.e[a];
+  }
+  int i[3];
+  for (int k = 0; k < 3; ++k) {
+    const double p = rel[0] * s.ax[k][0] + rel[1] * s.ax[k][1] + rel[2] * s.ax[k][2];
+    const double u = (p - r.go[k]) / r.gh;
+    if (!(u >= 0.0 && u <= double(r.gn[k] - 1))) return false;
+    const int c = min(int(floor(u)), r.gn[k] - 2);
+    i[k] = c;
+    s.f[k] = u - double(c);
+  }
+  s.v = r.grid + (int64_t(i[2]) * r.gn[1] + i[1]) * r.gn[0] + i[0];
+  return true;
+}
+// The eight corner samples of a cell, v[z][y][x].
+__device__ __forceinline__ void grid_corners(const RotorDev& r, const GridCell& s, double v[2][2][2]) {
+  const int64_t sy = r.gn[0], sz = int64_t(r.gn[0]) * r.gn[1];
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy) {
+      v[dz][dy][0] = s.v[dz * sz + dy * sy];
+      v[dz][dy][1] = s.v[dz * sz + dy * sy + 1];
+    }
+}
+// Trilinear interpolant: along the first axis, then the second, the third.
+__device__ __forceinline__ double grid_value(const RotorDev& r, const GridCell& s) {
+  double v[2][2][2];
+  grid_corners(r, s, v);
+  double w[2];
+  for (int dz = 0; dz < 2; ++dz) {
+    const double a0 = v[dz][0][0] + s.f[0] * (v[dz][0][1] - v[dz][0][0]);
+    const double a1 = v[dz][1][0] + s.f[0] * (v[dz][1][1] - v[dz][1][0]);
+    w[dz] = a0 + s.f[1] * (a1 - a0);
+  }
+  return w[0] + s.f[2] * (w[1] - w[0]);
+}
+// Gradient of that interpolant in the lattice frame.
+__device__ __forceinline__ void grid_gradient(const RotorDev& r, const GridCell& s, double grad[3]) {
+  double v[2][2][2];
+  grid_corners(r, s, v);
+  const double fx = s.f[0], fy = s.f[1], fz = s.f[2];
+  double d[3] = {0.0, 0.0, 0.0};  // derivatives with respect to the three fractions
+  for (int dz = 0; dz < 2; ++dz) {
+    const double wz = dz ? fz : 1.0 - fz, sz = dz ? 1.0 : -1.0;
+    for (int dy = 0; dy < 2; ++dy) {
+      const double wy = dy ? fy : 1.0 - fy, sy = dy ? 1.0 : -1.0;
+      const double lo = v[dz][dy][0], hi = v[dz][dy][1];
+      const double along = lo + fx * (hi - lo);
+      d[0] += wy * wz * (hi - lo);
+      d[1] += sy * wz * along;
+      d[2] += wy * sz * along;
+    }
+  }
+  const double ih = 1.0 / r.gh;
+  for (int a = 0; a < 3; ++a) grad[a] = (d[0] * s.ax[0][a] + d[1] * s.ax[1][a] + d[2] * s.ax[2][a]) * ih;
+}
+
 __device__ __forceinline__ RotorPhi rotor_phi(const RotorDev& r, const double* ctab, const double* stab, double x,
                                               double y, double z, double cut) {
   RotorPhi o;
   const double rel[3] = {x - r.c[0], y - r.c[1], z - r.c[2]};
+  if (r.grid) {
+    GridCell s;
+    o.sb = 0.0;
+    o.cb = 1.0;
+    if (grid_cell(r, ctab[0], stab[0], rel, s)) {
+      o.phi = grid_value(r, s);
+      o.piece = 0;
+    } else {
+      o.phi = -1e300;
+      o.piece = -2;
+    }
+    return o;
+  }
   const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
   o.phi = r.r_hub - dist;
   o.piece = -1;
@@ -307,6 +391,12 @@ __device__ __forceinline__ void rotor_grad(const RotorDev& r, const double* ctab
                                            double y, double z, const RotorPhi& w, double grad[3]) {
   const int piece = w.piece;
   const double rel[3] = {x - r.c[0], y - r.c[1], z - r.c[2]};
+  if (r.grid) {
+    GridCell s;
+    if (grid_cell(r, ctab[0], stab[0], rel, s)) grid_gradient(r, s, grad);
+    else grad[0] = grad[1] = grad[2] = 0.0;
+    return;
+  }
   const double dist = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
   if (piece < 0) {
     for (int a = 0; a < 3; ++a) grad[a] = dist > 0 ? -rel[a] / dist : 0.0;

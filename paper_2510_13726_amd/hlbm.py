@@ -67,6 +67,8 @@ SIGNATURES = [
     ("hlbm_lattice_destroy", None, [_H]),
     ("hlbm_set_params", C.c_int, [_H, C.POINTER(Params)]),
     ("hlbm_set_rotors", C.c_int, [_H, C.POINTER(Rotor), C.c_int32]),
+    ("hlbm_set_rotor_grid", C.c_int, [_H, C.c_int32, _V, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                      C.POINTER(C.c_double)]),
     ("hlbm_set_porosity_field", C.c_int, [_H, _V, _V]),
     ("hlbm_set_solid_velocity", C.c_int, [_H, _V]),
     ("hlbm_set_control", C.c_int, [_H, _V]),
@@ -247,6 +249,21 @@ class Lattice:
 
     def set_rotors(self, rotors):
         self._check(self.L.hlbm_set_rotors(self.h, _rotor_array(rotors), len(rotors)))
+
+    def set_rotor_grid(self, k, grid):
+        """Reference grid (workloads.RefGrid, or None to remove) of rotor index k;
+        the device copy of its samples is kept alive with the lattice."""
+        if not hasattr(self, "_grids"):
+            self._grids = {}
+        if grid is None:
+            self._check(self.L.hlbm_set_rotor_grid(self.h, int(k), None, 0, 0, 0, 0.0, None))
+            self._grids.pop(int(k), None)
+            return
+        t, p = self._dev(grid.phi, dtype=self.torch.float64)
+        n2, n1, n0 = t.shape
+        o = (C.c_double * 3)(*[float(v) for v in grid.origin])
+        self._check(self.L.hlbm_set_rotor_grid(self.h, int(k), p, n0, n1, n2, float(grid.spacing), o))
+        self._grids[int(k)] = t
 
     def set_porosity_field(self, d, tag=None):
         dt, dp = self._dev(d, shape=(self.N,))
@@ -444,6 +461,9 @@ def setup(w, storage="f32", diag_every=1, check_nonfinite=0, flags=0, device=Non
                   history=history, q=getattr(w, "q", 27), static_workspace=static_workspace)
     lat.set_params(w.params, diag_every=diag_every, check_nonfinite=check_nonfinite)
     lat.set_rotors(w.rotors)
+    for k, r in enumerate(w.rotors):
+        if getattr(r, "grid", None) is not None:
+            lat.set_rotor_grid(k, r.grid)
     d, tag = W.static_porosity(w)
     if d is not None:
         lat.set_porosity_field(d, tag)
