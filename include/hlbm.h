@@ -359,7 +359,8 @@ int hlbm_wall_safeguards(hlbm_handle h, int64_t* halvings, int64_t* caps);
  * fsialgo: the cells within one cell of those whose distance lay within one
  * cell of the transition band at the previous step, while every rotor
  * rotates as prescribed with |omega| (R + eps_h/2 + 1) <= 1/2 (the surface
- * moves at most half a cell per step) and the previous step's geometry was
+ * moves at most half a cell per step), no rotor has a reference grid (whose
+ * interpolant may be steeper than a distance), and the previous step's geometry was
  * computed under the same rotors and parameters.  The result is the same
  * either way; the layer is off by default because marking it costs more
  * than the evaluations it saves. */

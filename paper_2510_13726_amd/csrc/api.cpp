@@ -398,7 +398,9 @@ void growth_update(hlbm_handle h) {
   bool ok = h->growth_env && h->gmark && h->rot.n > 0;
   for (int k = 0; k < h->rot.n && ok; ++k) {
     const RotorDev& r = h->rot.r[k];
-    if (r.inertia > 0 || !(std::fabs(r.omega) * (r.R + 0.5 * h->params.eps_h + 1.0) <= 0.5)) ok = false;
+    // the layer's reach assumes a distance that changes by at most one per
+    // cell; the interpolant of a reference grid can be steeper near creases
+    if (r.inertia > 0 || r.grid || !(std::fabs(r.omega) * (r.R + 0.5 * h->params.eps_h + 1.0) <= 0.5)) ok = false;
   }
   h->growth_ok = ok;
 }

@@ -103,13 +103,15 @@ def capsule_rotor_grid(r: Rotor, spacing: float = 0.5, eps_h: float = 2.0) -> Re
     Sec. 3.1), standing in for the voxelized STL rotor: a hub sphere of
     radius r_hub and n_blades capsule blades of radius thick/2 whose axes
     run from r_hub/2 to R - thick/2 along each blade's radial direction,
-    tilted axially by +-chord/4 from root to tip.  The body lies within the
+    tilted axially from root to tip by +-min(chord/4, h_c - thick/2), h_c =
+    sqrt((chord/2)^2 + (thick/2)^2).  The body lies within the
     flat-plate rotor's envelope (radius R, axial half extent
     max(sqrt((chord/2)^2 + (thick/2)^2), r_hub)); the grid reaches
     eps_h/2 + 2 cells beyond it."""
     rad = 0.5 * r.thick
-    tilt = 0.25 * r.chord
-    ha = max(math.sqrt(0.25 * r.chord ** 2 + 0.25 * r.thick ** 2), r.r_hub)
+    hc = math.sqrt(0.25 * r.chord ** 2 + 0.25 * r.thick ** 2)
+    tilt = max(0.0, min(0.25 * r.chord, hc - rad))
+    ha = max(hc, r.r_hub)
     m = 0.5 * eps_h + 2.0
     lo = np.array([-(r.R + m), -(r.R + m), -(ha + m)])
     n = [int(math.ceil(-2.0 * lo[k] / spacing)) + 1 for k in range(3)]

@@ -70,7 +70,7 @@ def test_growth_layer_equals_full_rasterization(case, steps, monkeypatch):
     assert grow.wall_stats() == full.wall_stats()
 
 
-def test_growth_layer_off_beyond_its_speed_bound_and_for_coupled_rotors(monkeypatch):
+def test_growth_layer_off_beyond_its_speed_bound_and_for_coupled_and_grid_rotors(monkeypatch):
     hl = _hl()
     monkeypatch.setenv("HLBM_GROWTH_LAYER", "1")
     fast = CASES["small"]()
@@ -82,6 +82,13 @@ def test_growth_layer_off_beyond_its_speed_bound_and_for_coupled_rotors(monkeypa
     coupled = CASES["small"]()
     coupled.rotors[0].inertia = 1e6
     lat = hl.setup(coupled, storage="f32")
+    lat.step(4)
+    ev, vis = lat.geometry_stats()
+    assert ev == vis > 0
+    # a reference-grid body: its interpolant is not held to the layer's reach
+    grid = CASES["small"]()
+    grid.rotors[0].grid = W.capsule_rotor_grid(grid.rotors[0], spacing=0.5, eps_h=grid.params.eps_h)
+    lat = hl.setup(grid, storage="f32")
     lat.step(4)
     ev, vis = lat.geometry_stats()
     assert ev == vis > 0

@@ -50,6 +50,35 @@ def test_reference_grid_rotor_parity(storage, q):
     assert lat.wall_safeguards() == (0, 0)
 
 
+def test_coupled_reference_grid_rotor_parity():
+    """Two-way coupling (Sec. 3.2) turns the grid body with the torque it
+    receives: the angle and speed follow the oracle within the torque
+    tolerance carried through the rotor ODE."""
+    hl = _hl()
+    w = _grid_rotor()
+    w.rotors[0].inertia = 1e6
+    w.rotors[0].torque_gen = 2.0
+    n = 24
+    lat = hl.setup(w, storage="f64", check_nonfinite=1)
+    o = O.setup(w)
+    om_g, om_o = [], []
+    for _ in range(n):
+        lat.step(1)
+        o.step(1)
+        om_g.append(lat.rotor_state()[1][0])
+        om_o.append(o.rotor_state()[1][0])
+    om_g, om_o = np.array(om_g), np.array(om_o)
+    scale = o.history_scale()[:, 0, 1]
+    bound = np.cumsum(1e-12 * scale) / w.rotors[0].inertia + 4e-16 * np.abs(om_o)
+    ep = rel(lat.get_populations().cpu().numpy(), o.get_populations())
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    print(f"[refgrid] coupled: Omega {om_o[0]:.6f} -> {om_o[-1]:.6f}, speed err {np.abs(om_g - om_o).max():.2e}, "
+          f"pops {ep:.2e} F {eF:.2e} T {eT:.2e}", flush=True)
+    assert om_o[-1] != om_o[0]
+    assert np.all(np.abs(om_g - om_o) <= bound)
+    assert ep < 1e-12 and eF < 1e-12 and eT < 1e-12
+
+
 def test_reference_grid_differs_from_the_flat_plates_and_removal_restores_them():
     """The grid body is another solid than the flat-plate rotor of the same
     parameters; removing the grid gives back the flat-plate run bit for bit."""
