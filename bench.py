@@ -57,6 +57,7 @@ def time_storage(w, storage, steps, warmup, diag_every=1):
     hlbm.profile_enable(lat, True)
     lat.step(steps)
     n, ms = hlbm.profile_read(lat, hlbm.KERNEL_SWEEP)
+    nw, msw = hlbm.profile_read(lat, hlbm.KERNEL_WALL)
     hlbm.profile_enable(lat, False)
     fsi_cells, bulk_cells = hlbm.sweep_partition(lat)
     # one launch sweeps every cell
@@ -69,6 +70,7 @@ def time_storage(w, storage, steps, warmup, diag_every=1):
     torch.cuda.empty_cache()
     return dict(mlups=w.cells * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, sweep_launches=n,
                 sweep_avg_ms=ms / max(n, 1), sweep_cells=sweep_cells, fsi_cells=fsi_cells, finite=ok,
+                wall_geometry_avg_ms=msw / nw if nw else None,
                 wall_cells=cells, newton_iters=it, mass_per_cell=None if mass is None else mass / w.cells)
 
 
@@ -125,6 +127,30 @@ def adjoint_ratio(storage, steps, window, ckpt_every):
             "ckpt_every": ckpt_every, "forward_s": round(t_fwd, 4), "forward_record_s": round(t_rec, 4),
             "adjoint_s": round(t_adj, 4), "ratio": round(t_adj / t_fwd, 3), "J": J, "grad_max": gmax,
             "grad_finite": finite}
+
+
+def reference_grid_run(w, storage, steps, warmup, diag_every, flat):
+    """The same workload with every rotor's body on a reference grid (Sec.
+    3.1; a capsule-blade rotor of the same parameters on a half-cell grid):
+    step rate and the fused wall-model / geometry launch against the
+    flat-plate run."""
+    import copy
+    from paper_2510_13726_amd import workloads as W
+    wg = copy.deepcopy(w)
+    grids = {}
+    for r in wg.rotors:
+        key = (r.R, r.r_hub, r.chord, r.thick, r.n_blades)
+        if key not in grids:
+            grids[key] = W.capsule_rotor_grid(r, spacing=0.5, eps_h=wg.params.eps_h)
+        r.grid = grids[key]
+    res = time_storage(wg, storage, steps, warmup, diag_every)
+    g = next(iter(grids.values()))
+    return {"value": round(res["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(res["ms_per_step"], 5),
+            "wall_geometry_ms": None if res["wall_geometry_avg_ms"] is None else round(res["wall_geometry_avg_ms"], 4),
+            "flat_plate_wall_geometry_ms": None if flat["wall_geometry_avg_ms"] is None
+            else round(flat["wall_geometry_avg_ms"], 4),
+            "wall_cells": res["wall_cells"], "grid_samples_per_rotor": int(g.phi.size), "grid_spacing": g.spacing,
+            "body": "hub sphere and capsule blades", "finite": res["finite"]}
 
 
 def copy_bandwidth(gib=2.0, reps=20):
@@ -246,6 +272,8 @@ def main():
     ap.add_argument("--copy-reference", type=int, default=1, help="time a plain copy kernel (0 = skip)")
     ap.add_argument("--configs", default="1,2,3,4,5", help="workloads timed for the per-config table ('' = skip)")
     ap.add_argument("--config-cpu-seconds", type=float, default=3.0, help="oracle seconds per config (0 = skip)")
+    ap.add_argument("--grid-rotors", type=int, default=1,
+                    help="also time the workload with reference-grid rotor bodies (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -282,6 +310,10 @@ def main():
         d3q19[st] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
                      "bytes_per_cell": bytes_per_cell(st, 19),
                      "roofline": roofline(w19, st, r["sweep_avg_ms"], r["sweep_cells"]), "finite": r["finite"]}
+    grid_run = None
+    if args.grid_rotors and w.rotors:
+        grid_run = reference_grid_run(w, args.storage, args.steps, args.warmup, args.diag_every, main_run)
+        log(f"reference grid: {grid_run}")
     per_config = None
     keys = [k for k in args.configs.split(",") if k]
     if keys:
@@ -333,6 +365,7 @@ def main():
         "cpu_oracle_one_thread": cpu1,
         "storage_variants": variants,
         "d3q19": d3q19 or None,
+        "reference_grid": grid_run,
         "per_config": per_config,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,

@@ -395,8 +395,8 @@ int hlbm_profile_read(hlbm_handle h, int32_t kernel, int64_t* launches, double* 
 int hlbm_sweep_partition(hlbm_handle h, int64_t* fsi_cells, int64_t* bulk_cells);
 /* A plain streaming copy of `bytes` bytes from src to dst (device, 16-byte
  * aligned, bytes a multiple of 16, not overlapping), one 16 B element per
- * thread with non-temporal loads and stores, enqueued on `stream` (hipStream_t, NULL = the null
- * stream): the reference of the streaming bandwidth the sweep is measured
+ * thread with non-temporal loads and stores, enqueued on `stream`
+ * (hipStream_t, NULL = the null stream): the reference of the streaming bandwidth the sweep is measured
  * against in benchmarks.  HLBM_ERR_INVALID for a misaligned or negative
  * size; asynchronous. */
 int hlbm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
