@@ -149,6 +149,7 @@ def reference_grid_run(w, storage, steps, warmup, diag_every, flat):
             "wall_geometry_ms": None if res["wall_geometry_avg_ms"] is None else round(res["wall_geometry_avg_ms"], 4),
             "flat_plate_wall_geometry_ms": None if flat["wall_geometry_avg_ms"] is None
             else round(flat["wall_geometry_avg_ms"], 4),
+            "sweep_avg_ms": round(res["sweep_avg_ms"], 5),
             "wall_cells": res["wall_cells"], "grid_samples_per_rotor": int(g.phi.size), "grid_spacing": g.spacing,
             "body": "hub sphere and capsule blades", "finite": res["finite"]}
 
