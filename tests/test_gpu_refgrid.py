@@ -79,6 +79,28 @@ def test_coupled_reference_grid_rotor_parity():
     assert ep < 1e-12 and eF < 1e-12 and eT < 1e-12
 
 
+def test_reference_grid_kept_across_a_parameter_change():
+    """eps_h raised from 2 to 3 mid-run rebuilds the rotor boxes; the grid
+    stays with its rotor and the run continues as the oracle's (the grid
+    reaches eps_h/2 + 2 = 3 cells beyond the body, enough for eps_h = 3)."""
+    hl = _hl()
+    w = _grid_rotor()
+    lat = hl.setup(w, storage="f64", check_nonfinite=1)
+    o = O.setup(w)
+    lat.step(6)
+    o.step(6)
+    w.params.eps_h = 3.0
+    lat.set_params(w.params, check_nonfinite=1)
+    o.set_params(w.params)
+    lat.step(6)
+    o.step(6)
+    ep = rel(lat.get_populations().cpu().numpy(), o.get_populations())
+    eF, eT = force_torque_error(lat.history(), o.history(), o.history_scale())
+    print(f"[refgrid] eps_h 2 -> 3: pops {ep:.2e} F {eF:.2e} T {eT:.2e}", flush=True)
+    assert ep < 1e-12 and eF < 1e-12 and eT < 1e-12
+    assert lat.wall_stats() == o.newton_stats()
+
+
 def test_reference_grid_differs_from_the_flat_plates_and_removal_restores_them():
     """The grid body is another solid than the flat-plate rotor of the same
     parameters; removing the grid gives back the flat-plate run bit for bit."""
