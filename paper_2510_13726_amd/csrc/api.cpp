@@ -1583,6 +1583,26 @@ int hlbm_set_state(hlbm_handle h, const void* src) {
   return HLBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Records [from, to) of a device ring of `cap` records of `width` doubles
+// into dst: one copy per contiguous piece of the ring (at most two).
+hipError_t copy_ring(hipStream_t stream, const double* ring, int64_t cap, int width, int64_t from, int64_t to,
+                     double* dst) {
+  for (int64_t s = from; s < to;) {
+    const int64_t slot = s % cap, n = std::min(to - s, cap - slot);
+    const hipError_t e = hipMemcpyAsync(dst + (s - from) * width, ring + slot * width, n * width * 8,
+                                        hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return e;
+    s += n;
+  }
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
 int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst) {
   if (!h) return HLBM_ERR_INVALID;
   const int64_t lo = std::max(h->hist_start, h->step - h->hist_cap);
@@ -1590,12 +1610,8 @@ int hlbm_history(hlbm_handle h, int64_t from, int64_t to, double* dst) {
     return fail(h, HLBM_ERR_INVALID, "steps [" + std::to_string(from) + ", " + std::to_string(to) +
                                          ") not in the history ring [" + std::to_string(lo) + ", " +
                                          std::to_string(h->step) + ")");
-  for (int64_t s = from; s < to; ++s) {
-    hipError_t e = hipMemcpyAsync(dst + (s - from) * kHist, h->L.hist + (s % h->hist_cap) * kHist, kHist * 8,
-                                  hipMemcpyDeviceToHost, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "history");
-  }
-  hipError_t e = hipStreamSynchronize(h->stream);
+  hipError_t e = copy_ring(h->stream, h->L.hist, h->hist_cap, kHist, from, to, dst);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "history");
   return HLBM_OK;
 }
@@ -1607,9 +1623,7 @@ int hlbm_history_me(hlbm_handle h, int64_t from, int64_t to, double* dst) {
   if (from < lo || to > h->step || from > to || (to > from && !dst))
     return fail(h, HLBM_ERR_INVALID, "steps not in the history ring");
   hipError_t e = flush(h);
-  for (int64_t s = from; e == hipSuccess && s < to; ++s)
-    e = hipMemcpyAsync(dst + (s - from) * kHistMe, h->L.hist_me + (s % h->hist_cap) * kHistMe, kHistMe * 8,
-                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = copy_ring(h->stream, h->L.hist_me, h->hist_cap, kHistMe, from, to, dst);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "momentum-exchange history");
   return HLBM_OK;

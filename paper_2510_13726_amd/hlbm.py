@@ -344,6 +344,19 @@ class Lattice:
         return out
 
     # ------------------------------------------------------------ adjoint
+    def reserve(self, nsteps, ckpt_every=100):
+        """Allocate the checkpoint buffer of a forward_record of nsteps and the
+        recompute stack of its adjoint ahead of time (both are kept and
+        reused by later calls)."""
+        nb = self.L.hlbm_checkpoint_bytes(self.h, nsteps, ckpt_every)
+        ns = self.L.hlbm_adjoint_stack_bytes(self.h, ckpt_every)
+        if nb < 0 or ns < 0:
+            raise HlbmError(HLBM_ERR_INVALID, "bad checkpoint request")
+        if getattr(self, "_ckpt", None) is None or self._ckpt.numel() < nb:
+            self._ckpt = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        if getattr(self, "_stack", None) is None or self._stack.numel() < ns:
+            self._stack = self.torch.empty(ns, dtype=self.torch.uint8, device=self.device)
+
     def forward_record(self, nsteps, t0, t1, obj_tag=0, ckpt_every=100):
         """Advance nsteps recording checkpoints; returns J (mean axial torque
         over steps [t0, t1) of the run)."""
