@@ -284,7 +284,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}, "
+        print(f"bench.py measures one GPU: this library has no multi-GPU path (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 

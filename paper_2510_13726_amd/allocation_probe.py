@@ -48,7 +48,7 @@ def summary(csv_path, log_path, kernel, title, cmd, out):
     ids = sorted(rows)
     per = len(ids) // max(len(trials), 1)
     names = sorted({k for v in rows.values() for k in v})
-    lines = [f"# {title}", "", "Command (repository root on the GPU box, MI355X):", "", f"    {cmd}", "",
+    lines = [f"# {title}", "", "Command (from the repository root, MI355X):", "", f"    {cmd}", "",
              f"Sweep dispatches `{kernel}`: {len(ids)}, {per} per allocation; counters as the mean per dispatch.", "",
              "| allocation | buffer a | sweep ms (HIP events) | " + " | ".join(names) + " |",
              "|---|---|---|" + "---|" * len(names)]

@@ -20,7 +20,7 @@ def main():
     a = ap.parse_args()
     with open(a.stats) as fh:
         rows = list(csv.DictReader(fh))
-    lines = [f"# {a.title}", "", "Command (repository root on the GPU box, MI355X):", "", f"    {a.cmd}", ""]
+    lines = [f"# {a.title}", "", "Command (from the repository root, MI355X):", "", f"    {a.cmd}", ""]
     if a.note:
         lines += [a.note, ""]
     lines += ["run_kernel_stats.csv, kernels above 0.1 % of the GPU time (durations in microseconds):", "",
