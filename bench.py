@@ -93,12 +93,13 @@ def roofline(w, storage, sweep_avg_ms, sweep_cells):
             "avg_launch_ms": round(sweep_avg_ms, 5)}
 
 
-def adjoint_ratio(storage, steps, window, ckpt_every):
-    """Adjoint cost of the rotor-torque gradient relative to the forward run
-    on the adjoint workload (128 x 64 x 64 channel, rotor R = 20)."""
+def adjoint_ratio(storage, steps, window, ckpt_every, config="4"):
+    """Adjoint cost of the rotor-torque gradient relative to the forward run,
+    on the adjoint workload (128 x 64 x 64 channel, rotor R = 20) unless
+    another workload is named."""
     import torch
     from paper_2510_13726_amd import hlbm, workloads as W
-    w = W.config4()
+    w = W.ALL[config]()
     lat = hlbm.setup(w, storage=storage, diag_every=0, flags=hlbm.WITH_ADJOINT)
     state0 = lat.get_state().clone()
     # the checkpoint buffer and the recompute stack are allocated once, before
@@ -275,6 +276,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="seconds of the FP64 oracle on a sample of the workload (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint ratio run (0 = skip)")
+    ap.add_argument("--adjoint-config", default="4", help="workload of the adjoint ratio run (1..5)")
     ap.add_argument("--copy-reference", type=int, default=1, help="time a plain copy kernel (0 = skip)")
     ap.add_argument("--configs", default="1,2,3,4,5", help="workloads timed for the per-config table ('' = skip)")
     ap.add_argument("--config-cpu-seconds", type=float, default=3.0, help="oracle seconds per config (0 = skip)")
@@ -327,7 +329,7 @@ def main():
     adj = None
     if args.adjoint_steps > 0:
         adj = adjoint_ratio(args.storage if args.storage in ("f32", "f64") else "f32", args.adjoint_steps,
-                            args.adjoint_steps // 2, 100)
+                            args.adjoint_steps // 2, min(100, args.adjoint_steps), args.adjoint_config)
         log(f"adjoint: {adj}")
     copy_ref = copy_bandwidth() if args.copy_reference else None
     if copy_ref:
