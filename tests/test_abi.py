@@ -73,3 +73,22 @@ def test_create_rejects_null_buffers():
     rc = L.hlbm_lattice_create(C.byref(d), None, None, None, C.byref(h))
     assert rc == hlbm.HLBM_ERR_INVALID and not h.value
     assert b"NULL" in L.hlbm_last_error(None)
+
+
+def test_size_limits_of_the_descriptor():
+    # tile and cell indices are 32-bit: the last accepted lattice has
+    # 2^31 - 2^21 cells, one more z plane reaches 2^31 and is refused
+    L = hlbm.lib()
+    top = hlbm.make_desc(2048, 1024, 1023, hlbm.F16)
+    assert L.hlbm_population_bytes(C.byref(top)) == 27 * 2048 * 1024 * 1023 * 2
+    assert L.hlbm_workspace_bytes(C.byref(top)) > 0
+    over = hlbm.make_desc(2048, 1024, 1024, hlbm.F16)
+    assert L.hlbm_population_bytes(C.byref(over)) == -1
+    assert L.hlbm_workspace_bytes(C.byref(over)) == -1
+    # D3Q19 rows hold 19 runs per block of 64 cells; other velocity sets are refused
+    q19 = hlbm.make_desc(100, 3, 2, hlbm.F32)
+    q19.velocities = 19
+    assert L.hlbm_population_bytes(C.byref(q19)) == 19 * 128 * 3 * 2 * 4
+    q15 = hlbm.make_desc(100, 3, 2, hlbm.F32)
+    q15.velocities = 15
+    assert L.hlbm_population_bytes(C.byref(q15)) == -1
