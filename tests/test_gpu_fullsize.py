@@ -1,5 +1,7 @@
-"""HIP path vs the FP64 oracle at the full sizes of the rotor workloads, in
-the launch configuration the benchmark times (no per-step diagnostics).
+"""HIP path vs the FP64 oracle at the full sizes of the rotor workloads.  The
+slab cases run the launch configuration the benchmark times (mass reduction
+and finite check every step) and also compare the force and torque records
+of the rotors inside the compared window.
 
 The 256x128x128 channel fits the oracle whole.  The 1024x512x384 wake and the
 1536x768x256 rotor array do not; there the oracle runs an x-slab of the
@@ -40,7 +42,7 @@ def _free(lat):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("storage,diag", [("f64", 1), ("f32", 0)])
+@pytest.mark.parametrize("storage,diag", [("f64", 1), ("f32", 0), ("f32", 1)])
 def test_rotor_channel_full_domain(storage, diag):
     """256x128x128 channel, rotor R = 40 with the wall model, 6 steps."""
     hl = _hl()
@@ -69,13 +71,18 @@ def test_rotor_channel_full_domain(storage, diag):
               flush=True)
         assert eF < TOL[storage] and eT < TOL[storage]
         assert safe_g == (0, 0)
-        assert (it_g, nw_g) == o.newton_stats()
+        # equal Newton counts are an FP64 property: FP32 probe velocities
+        # may flip a stop decision
+        if storage == "f64":
+            assert (it_g, nw_g) == o.newton_stats()
         assert nw_g > 1000
 
 
 def _slab_case(w, x0, length, n, storage, box):
     """Run `w` on the GPU for n steps and the x-slab [x0, x0 + length) on the
-    oracle; compare the slab's interior cells inside the y-z window `box`."""
+    oracle; compare the slab's interior cells inside the y-z window `box`, and
+    the force / torque records of the rotors whose boxes lie in the slab's
+    interior (their cells hold the same values in both runs)."""
     hl = _hl()
     m = 6 * n + 2
     lo = x0 + (m if x0 != 0 else 0)
@@ -86,9 +93,10 @@ def _slab_case(w, x0, length, n, storage, box):
     cells = ((zz * w.ny + yy) * w.nx + xx).reshape(-1).astype(np.int64)
     print(f"[fullsize] {w.name} {storage}: {n} steps, slab x [{x0}, {x0 + length}), "
           f"compare x [{lo}, {hi}) ({cells.size} cells)", flush=True)
-    lat = hl.setup(w, storage=storage, diag_every=0)
+    lat = hl.setup(w, storage=storage, diag_every=1, check_nonfinite=1)
     lat.step(n)
     hg = lat.get_populations_at(cells).cpu().numpy()          # [cells][27]
+    hist_g = lat.history()
     _free(lat)
     s = W.x_slab(w, x0, length)
     o = O.setup(s, threads=THREADS)
@@ -113,7 +121,14 @@ def _slab_case(w, x0, length, n, storage, box):
             print(f"[fullsize]   cell ({x},{y},{z}) err {err[b]:.3e} dist to nearest rotor centre {near:.1f}",
                   flush=True)
         print(f"[fullsize]   cells above tolerance: {(err > TOL[storage] * np.abs(ho).max()).sum()}", flush=True)
-    return e, o
+    # rotors whose marking boxes (centre +- 6 cells along the x axis) lie in
+    # the compared planes
+    tags = {r.tag for r in w.rotors if lo + 6 <= r.center[0] < hi - 6}
+    if tags:
+        eF, eT = force_torque_error(hist_g, o.history(), o.history_scale(), tags)
+        print(f"[fullsize] {w.name} {storage}: tags {sorted(tags)} F err {eF:.3e} T err {eT:.3e}", flush=True)
+        assert eF < TOL[storage] and eT < TOL[storage]
+    return e, o, tags
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -123,8 +138,8 @@ def test_wake_rotor_slab(storage):
     w = W.config3()
     n = 4
     xc = int(w.rotors[0].center[0])
-    e, o = _slab_case(w, xc - 16 - (6 * n + 2), 32 + 2 * (6 * n + 2), n, storage, ((128, 384), (64, 320)))
-    assert o.newton_stats()[1] > 1000
+    e, o, tags = _slab_case(w, xc - 16 - (6 * n + 2), 32 + 2 * (6 * n + 2), n, storage, ((128, 384), (64, 320)))
+    assert o.newton_stats()[1] > 1000 and tags == {1}
     assert e < TOL[storage]
 
 
@@ -133,7 +148,7 @@ def test_wake_inflow_slab():
     inflow drawn from the counter-based generator of every (step, y, z))."""
     w = W.config3()
     n = 4
-    e, _ = _slab_case(w, 0, 24 + 6 * n + 2, n, "f32", ((0, 512), (100, 160)))
+    e, _, _ = _slab_case(w, 0, 24 + 6 * n + 2, n, "f32", ((0, 512), (100, 160)))
     assert e < TOL["f32"]
 
 
@@ -143,6 +158,6 @@ def test_rotor_array_slab():
     w = W.config5()
     n = 4
     xc = int(w.rotors[0].center[0])
-    e, o = _slab_case(w, xc - 10 - (6 * n + 2), 20 + 2 * (6 * n + 2), n, "f32", ((250, 520), (70, 190)))
-    assert o.newton_stats()[1] > 1000
+    e, o, tags = _slab_case(w, xc - 10 - (6 * n + 2), 20 + 2 * (6 * n + 2), n, "f32", ((250, 520), (70, 190)))
+    assert o.newton_stats()[1] > 1000 and len(tags) == 2
     assert e < TOL["f32"]
