@@ -139,7 +139,7 @@ def _slab_case(w, x0, length, n, storage, box):
     return e, o, tags
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 def test_wake_rotor_slab(storage):
     """1024x512x384 wake workload (rotor R = 120, inflow turbulence), slab
     around the rotor plane."""
@@ -148,7 +148,7 @@ def test_wake_rotor_slab(storage):
     xc = int(w.rotors[0].center[0])
     e, o, tags = _slab_case(w, xc - 16 - (6 * n + 2), 32 + 2 * (6 * n + 2), n, storage, ((128, 384), (64, 320)))
     assert o.newton_stats()[1] > 1000 and tags == {1}
-    assert e < TOL[storage]
+    assert e < _tol(storage, n)
 
 
 def test_wake_inflow_slab():
