@@ -98,7 +98,7 @@ def _slab_case(w, x0, length, n, storage, box):
     (y0, y1), (z0, z1) = box
     zz, yy, xx = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(lo, hi), indexing="ij")
     cells = ((zz * w.ny + yy) * w.nx + xx).reshape(-1).astype(np.int64)
-    print(f"[fullsize] {w.name} {storage}: {n} steps, slab x [{x0}, {x0 + length}), "
+    print(f"[fullsize] {w.name} D3Q{getattr(w, 'q', 27)} {storage}: {n} steps, slab x [{x0}, {x0 + length}), "
           f"compare x [{lo}, {hi}) ({cells.size} cells)", flush=True)
     lat = hl.setup(w, storage=storage, diag_every=1, check_nonfinite=1)
     lat.step(n)
@@ -160,12 +160,13 @@ def test_wake_inflow_slab():
     assert e < TOL["f32"]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_rotor_array_slab(storage):
+@pytest.mark.parametrize("storage,q", [("f32", 27), ("f16", 27), ("bf16", 27), ("f32", 19), ("f16", 19)])
+def test_rotor_array_slab(storage, q):
     """1536x768x256 array of 8 rotors (R = 48): slab around the first column
-    of two rotors with different phases, in each storage type the benchmark
-    times."""
+    of two rotors with different phases, in each storage type and velocity
+    set the benchmark times."""
     w = W.config5()
+    w.q = q
     n = 4
     xc = int(w.rotors[0].center[0])
     e, o, tags = _slab_case(w, xc - 10 - (6 * n + 2), 20 + 2 * (6 * n + 2), n, storage, ((250, 520), (70, 190)))
