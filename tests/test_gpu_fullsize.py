@@ -172,3 +172,18 @@ def test_rotor_array_slab(storage, q):
     e, o, tags = _slab_case(w, xc - 10 - (6 * n + 2), 20 + 2 * (6 * n + 2), n, storage, ((250, 520), (70, 190)))
     assert o.newton_stats()[1] > 1000 and len(tags) == 2
     assert e < _tol(storage, n)
+
+
+def test_rotor_array_slab_reference_grid():
+    """The same slab with every rotor's body on a half-cell reference grid
+    (hub sphere and capsule blades of the same parameters), as the benchmark
+    times it: one grid shared by the eight rotors."""
+    w = W.config5()
+    g = W.capsule_rotor_grid(w.rotors[0], spacing=0.5, eps_h=w.params.eps_h)
+    for r in w.rotors:
+        r.grid = g
+    n = 4
+    xc = int(w.rotors[0].center[0])
+    e, o, tags = _slab_case(w, xc - 10 - (6 * n + 2), 20 + 2 * (6 * n + 2), n, "f32", ((250, 520), (70, 190)))
+    assert o.newton_stats()[1] > 1000 and len(tags) == 2
+    assert e < TOL["f32"]
