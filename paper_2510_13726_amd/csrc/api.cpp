@@ -195,18 +195,18 @@ uint32_t tile_band(const hlbm_desc* d, int32_t nty) {
 // Dynamic LDS of a sweep workgroup, which caps the workgroups resident on a
 // CU (160 KB of LDS each; the sweep itself holds under 4 KB).  Without a
 // cap, the FP32 sweep runs five per CU (its registers allow five waves per
-// SIMD).  Measured in sustained runs (bench processes of 410 launches per
-// lattice, capped and uncapped processes alternating): on lattices of more
-// than 2^18 tiles the D3Q19 FP32 sweep is faster with four per CU (8.05 and
-// 8.09 against 8.22 and 8.30 ms at 1536x768x256), while the D3Q27 FP32 sweep
-// is slower with three (12.08 and 12.34 against 11.35 and 11.37 ms; 67.6-69.5
-// against 71.1 % of 8 TB/s at 1024x512x384), although switching the cap
-// every 17 steps on one lattice favoured it.  FP16 and BF16 storage, closer
-// to the ALU bound, slow down with any cap.  HLBM_SWEEP_WG_PER_CU = 3 or 4
-// sets the cap, 0 removes it (measurement runs).
+// SIMD).  On lattices of more than 2^18 tiles the FP32 sweep is faster with
+// four per CU, measured on one lattice with the cap switched every 43-83 steps
+// (four rounds, two allocations): D3Q27 at 1536x768x256 11.56-11.58 against
+// 11.72-11.73 ms and 10.94-10.99 against 11.07-11.11 ms, at 1024x512x384
+// 7.72 against 7.83 ms; D3Q19 at 1536x768x256 7.73-7.76 against 7.86-7.91
+// ms.  Three per CU is slower (D3Q27 12.32 and 11.79 ms on the same two
+// allocations).  FP16 and BF16 storage, closer to the ALU bound, gain
+// nothing or slow down with a cap.  HLBM_SWEEP_WG_PER_CU = 3 or 4 sets the
+// cap, 0 removes it (measurement runs).
 uint32_t sweep_lds(const hlbm_desc* d, int64_t tiles) {
   int cap = 0;
-  if (d->storage == HLBM_F32 && vel_of(d) == 19 && tiles > (int64_t(1) << 18)) cap = 4;
+  if (d->storage == HLBM_F32 && tiles > (int64_t(1) << 18)) cap = 4;
   if (const char* e = std::getenv("HLBM_SWEEP_WG_PER_CU")) cap = int(std::strtol(e, nullptr, 10));
   if (cap != 3 && cap != 4) return 0;
   return uint32_t(163840 / cap - 4096);
